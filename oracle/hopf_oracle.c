@@ -1,0 +1,459 @@
+/*
+ * Plain FP64 CPU oracle for Darbon & Osher, arXiv:1605.01799.
+ *
+ * TEST INFRASTRUCTURE ONLY (see hopf_oracle.h).  It is deliberately slow and
+ * literal: one point at a time, dense triangular solves, the split-Bregman
+ * updates in the order the paper gives them, Neumaier-compensated sums.
+ */
+#include "hopf_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Compensated summation (Neumaier).                                          */
+/* ------------------------------------------------------------------------- */
+typedef struct { double s, c; } ksum;
+static void ks_add(ksum* k, double v) {
+  double t = k->s + v;
+  if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+  else k->c += (v - t) + k->s;
+  k->s = t;
+}
+static double ks_val(const ksum* k) { return k->s + k->c; }
+
+static double dot(int n, const double* a, const double* b) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i) ks_add(&k, a[i] * b[i]);
+  return ks_val(&k);
+}
+static double sqdist(int n, const double* a, const double* b) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i) { double d = a[i] - b[i]; ks_add(&k, d * d); }
+  return ks_val(&k);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense SPD factorisation and solves (used for the quadratic prox, which is  */
+/* the resolvent (I + alpha A)^{-1} of section 4.1; here in the form          */
+/* (A + lambda I)^{-1} that update (3.4a) needs).                             */
+/* ------------------------------------------------------------------------- */
+/* Cholesky of S = A + shift*I into lower-triangular L (row-major).  Returns -2 if not SPD. */
+static int cholesky(int n, const double* A, double shift, double* L) {
+  memset(L, 0, sizeof(double) * (size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    ksum k = {0, 0};
+    ks_add(&k, A[(size_t)j * n + j] + shift);
+    for (int m = 0; m < j; ++m) ks_add(&k, -L[(size_t)j * n + m] * L[(size_t)j * n + m]);
+    double djj = ks_val(&k);
+    if (!(djj > 0.0)) return -2;
+    double ljj = sqrt(djj);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      ksum q = {0, 0};
+      ks_add(&q, A[(size_t)i * n + j]);
+      for (int m = 0; m < j; ++m) ks_add(&q, -L[(size_t)i * n + m] * L[(size_t)j * n + m]);
+      L[(size_t)i * n + j] = ks_val(&q) / ljj;
+    }
+  }
+  return 0;
+}
+/* Solve L L^T out = rhs. */
+static void chol_solve(int n, const double* L, const double* rhs, double* tmp, double* out) {
+  for (int i = 0; i < n; ++i) {
+    ksum k = {0, 0};
+    ks_add(&k, rhs[i]);
+    for (int m = 0; m < i; ++m) ks_add(&k, -L[(size_t)i * n + m] * tmp[m]);
+    tmp[i] = ks_val(&k) / L[(size_t)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    ksum k = {0, 0};
+    ks_add(&k, tmp[i]);
+    for (int m = i + 1; m < n; ++m) ks_add(&k, -L[(size_t)m * n + i] * out[m]);
+    out[i] = ks_val(&k) / L[(size_t)i * n + i];
+  }
+}
+/* p^T A p */
+static double quad(int n, const double* A, const double* p) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) ks_add(&k, p[i] * A[(size_t)i * n + j] * p[j]);
+  return ks_val(&k);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hamiltonians and their proximal maps.                                      */
+/* ------------------------------------------------------------------------- */
+static double wgt(const double* w, int i) { return w ? w[i] : 1.0; }
+
+/* Soft thresholding, eq. (shrink1_def) / section 4.1: sign(z)max(|z|-a,0), sign(0)=1. */
+static double shrink1(double z, double a) {
+  double m = fabs(z) - a;
+  if (m <= 0.0) return 0.0;
+  return z >= 0.0 ? m : -m;
+}
+
+/* H(p) for the supported family (support functions of a box, a ball, and their Minkowski sum). */
+static double ham(int n, int hkind, const double* w, const double* p) {
+  double h = 0.0;
+  if (hkind == OH_WL1 || hkind == OH_L2_WL1) {
+    ksum k = {0, 0};
+    for (int i = 0; i < n; ++i) ks_add(&k, wgt(w, i) * fabs(p[i]));
+    h += ks_val(&k);
+  }
+  if (hkind == OH_L2 || hkind == OH_L2_WL1) h += sqrt(dot(n, p, p));
+  return h;
+}
+
+/* d = argmin_d { theta*H(d) + 1/2 ||d - z||^2 }, i.e. update (3.4b) with theta = t/lambda.
+ * WL1: componentwise shrink1 with thresholds theta*w_i (eq. shrink1_def).
+ * L2:  shrink2(z, theta) (eq. shrink2_def).
+ * L2 + WL1: shrink2(shrink1(z, theta*w), theta), the composition of the two maps
+ * (the prox of a sum of a group norm and a separable norm that both act on
+ * the same single group). */
+static void prox_h(int n, int hkind, const double* w, double theta, const double* z, double* d) {
+  if (hkind == OH_WL1 || hkind == OH_L2_WL1) {
+    for (int i = 0; i < n; ++i) d[i] = shrink1(z[i], theta * wgt(w, i));
+  } else {
+    memcpy(d, z, sizeof(double) * (size_t)n);
+  }
+  if (hkind == OH_L2 || hkind == OH_L2_WL1) {
+    double nr = sqrt(dot(n, d, d));
+    if (nr == 0.0) {
+      for (int i = 0; i < n; ++i) d[i] = 0.0;
+    } else {
+      double f = (nr - theta > 0.0 ? nr - theta : 0.0) / nr;
+      for (int i = 0; i < n; ++i) d[i] *= f;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One Hopf evaluation by split Bregman, eqs. (3.4a)-(3.4c), with the         */
+/* initial values v0 = d0 = x', b0 = 0 and the stopping test of section 4.5   */
+/* (all three squared norms <= tol).                                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int n;
+  double *v, *d, *b, *rhs, *vn, *dn, *z, *tmp, *y;
+} scratch;
+
+static int scratch_alloc(scratch* s, int n) {
+  s->n = n;
+  double* buf = (double*)calloc((size_t)9 * n, sizeof(double));
+  if (!buf) return -1;
+  s->v = buf; s->d = buf + n; s->b = buf + 2 * n; s->rhs = buf + 3 * n; s->vn = buf + 4 * n;
+  s->dn = buf + 5 * n; s->z = buf + 6 * n; s->tmp = buf + 7 * n; s->y = buf + 8 * n;
+  return 0;
+}
+static void scratch_free(scratch* s) { free(s->v); }
+
+/* Solves min_p F(p) = 1/2 p^T A p + t H(p) - <xp, p>.  Writes p (= d^K) into out_p,
+ * returns -F(p) (the Hopf value of eq. (3.3) without any constant offset).
+ * *iters = number of v-updates, or -2 if max_iter was reached.
+ * gap (nullable): J(xp - lambda b) + F(p) with J(y) = 1/2 y^T A^{-1} y (needs LA = chol(A)). */
+static double hopf_solve(const oh_problem* pb, int hkind, const double* LS, const double* LA,
+                         const double* xp, double t, scratch* s, double* out_p, int32_t* iters,
+                         double* gap) {
+  const int n = pb->n;
+  const double lam = pb->lambda;
+  memcpy(s->v, xp, sizeof(double) * (size_t)n);
+  memcpy(s->d, xp, sizeof(double) * (size_t)n);
+  memset(s->b, 0, sizeof(double) * (size_t)n);
+  int k = 0, conv = 0;
+  while (k < pb->max_iter) {
+    ++k;
+    /* (3.4a): v = argmin J*(v) - <x,v> + lambda/2 ||d - v - b||^2  <=>  (A + lambda I) v = x + lambda (d - b) */
+    for (int i = 0; i < n; ++i) s->rhs[i] = xp[i] + lam * (s->d[i] - s->b[i]);
+    chol_solve(n, LS, s->rhs, s->tmp, s->vn);
+    /* (3.4b): d = prox_{(t/lambda) H}(v + b) */
+    for (int i = 0; i < n; ++i) s->z[i] = s->vn[i] + s->b[i];
+    prox_h(n, hkind, pb->w, t / lam, s->z, s->dn);
+    /* (3.4c): b = b + v - d */
+    for (int i = 0; i < n; ++i) s->b[i] = s->b[i] + s->vn[i] - s->dn[i];
+    double r1 = sqdist(n, s->vn, s->v);
+    double r2 = sqdist(n, s->dn, s->d);
+    double r3 = sqdist(n, s->dn, s->vn);
+    memcpy(s->v, s->vn, sizeof(double) * (size_t)n);
+    memcpy(s->d, s->dn, sizeof(double) * (size_t)n);
+    if (r1 <= pb->tol && r2 <= pb->tol && r3 <= pb->tol) { conv = 1; break; }
+  }
+  *iters = conv ? k : -2;
+  const double* p = s->d;
+  memcpy(out_p, p, sizeof(double) * (size_t)n);
+  ksum F = {0, 0};
+  ks_add(&F, 0.5 * quad(n, pb->A, p));
+  ks_add(&F, t * ham(n, hkind, pb->w, p));
+  ks_add(&F, -dot(n, xp, p));
+  double Fv = ks_val(&F);
+  if (gap) {
+    /* Hopf-Lax feasible point y = x' - lambda b: lambda b / t lies in t^{-1} * t dH(d) within the Wulff shape. */
+    for (int i = 0; i < n; ++i) s->y[i] = xp[i] - lam * s->b[i];
+    chol_solve(n, LA, s->y, s->tmp, s->z); /* z = A^{-1} y */
+    *gap = 0.5 * dot(n, s->y, s->z) + Fv;
+  }
+  return -Fv;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Threading over points.                                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const oh_problem* pb;
+  const double *LS, *LA;
+  int64_t begin, end;
+  const double *x, *t;
+  double *phi, *grad, *dphidt, *gap;
+  int32_t *iters, *kstar;
+  int rc;
+} eval_job;
+
+static void* eval_worker(void* arg) {
+  eval_job* J = (eval_job*)arg;
+  const oh_problem* pb = J->pb;
+  const int n = pb->n;
+  scratch s;
+  if (scratch_alloc(&s, n)) { J->rc = -1; return NULL; }
+  double* xp = (double*)malloc(sizeof(double) * (size_t)n * 2);
+  double* p = xp + n;
+  for (int64_t j = J->begin; j < J->end; ++j) {
+    const double* x = J->x + (size_t)j * n;
+    double t = J->t[j];
+    double best = INFINITY;
+    int kb = -1;
+    for (int k = 0; k < pb->K; ++k) {
+      for (int i = 0; i < n; ++i) xp[i] = x[i] - (pb->centres ? pb->centres[(size_t)k * n + i] : 0.0);
+      int32_t it;
+      double g = 0.0;
+      double val = hopf_solve(pb, pb->hkind, J->LS, J->LA, xp, t, &s, p, &it, J->gap ? &g : NULL);
+      if (pb->level_set) val -= 0.5; /* J_k* carries the constant +1/2 */
+      /* min over initial data (section 2): phi = min_k phi_k, lowest k on ties */
+      if (val < best || kb < 0) {
+        best = val; kb = k;
+        memcpy(J->grad + (size_t)j * n, p, sizeof(double) * (size_t)n);
+        J->iters[j] = it;
+        if (J->gap) J->gap[j] = g;
+      }
+    }
+    J->phi[j] = best;
+    J->kstar[j] = kb;
+    /* dphi/dt = -H(grad phi), from (1.1a) */
+    J->dphidt[j] = -ham(n, pb->hkind, pb->w, J->grad + (size_t)j * n);
+  }
+  free(xp);
+  scratch_free(&s);
+  return NULL;
+}
+
+static int check_problem(const oh_problem* pb) {
+  if (!pb || pb->n < 1 || !pb->A || pb->K < 1 || !(pb->lambda > 0) || pb->max_iter < 1) return -1;
+  if (pb->hkind < OH_WL1 || pb->hkind > OH_L2_WL1) return -1;
+  if (pb->w)
+    for (int i = 0; i < pb->n; ++i)
+      if (!(pb->w[i] >= 0)) return -1;
+  return 0;
+}
+
+int oh_eval(const oh_problem* pb, int64_t npts, const double* x, const double* t, double* phi,
+            double* grad, double* dphidt, int32_t* iters, int32_t* kstar, double* gap,
+            int nthreads) {
+  if (check_problem(pb) || npts < 0) return -1;
+  for (int64_t j = 0; j < npts; ++j)
+    if (!(t[j] > 0)) return -1;
+  const int n = pb->n;
+  double* LS = (double*)malloc(sizeof(double) * (size_t)n * n * 2);
+  double* LA = LS + (size_t)n * n;
+  if (!LS) return -1;
+  int rc = cholesky(n, pb->A, pb->lambda, LS);
+  if (rc == 0 && gap) rc = cholesky(n, pb->A, 0.0, LA);
+  if (rc) { free(LS); return rc; }
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > npts) nthreads = npts > 0 ? (int)npts : 1;
+  eval_job* jobs = (eval_job*)calloc((size_t)nthreads, sizeof(eval_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  for (int i = 0; i < nthreads; ++i) {
+    eval_job* J = &jobs[i];
+    J->pb = pb; J->LS = LS; J->LA = LA; J->x = x; J->t = t;
+    J->phi = phi; J->grad = grad; J->dphidt = dphidt; J->gap = gap; J->iters = iters; J->kstar = kstar;
+    J->begin = npts * i / nthreads; J->end = npts * (i + 1) / nthreads;
+    if (nthreads == 1) eval_worker(J);
+    else pthread_create(&th[i], NULL, eval_worker, J);
+  }
+  rc = 0;
+  for (int i = 0; i < nthreads; ++i) {
+    if (nthreads > 1) pthread_join(th[i], NULL);
+    if (jobs[i].rc) rc = jobs[i].rc;
+  }
+  free(jobs); free(th); free(LS);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Closest point / distance by the level-set route of section 3.2:            */
+/* psi solves the eikonal equation with psi(.,0) = L_k (the quadratic level-  */
+/* set function of ellipsoid k), psi(y, s) is a Hopf evaluation with          */
+/* H = ||.||_2 (split Bregman (3.9) is (3.4) with H = ||.||_2), and Newton on */
+/* s uses d psi / ds = -||grad_x psi|| (eq. Newton_zero).                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  const oh_problem* pb;
+  const double *LS, *LA;
+  int64_t begin, end;
+  const double* y;
+  double s_tol;
+  int32_t max_newton;
+  double *dist, *cp;
+  int32_t *kstar, *inside, *newton;
+  int rc;
+} dist_job;
+
+static void* dist_worker(void* arg) {
+  dist_job* J = (dist_job*)arg;
+  const oh_problem* pb = J->pb;
+  const int n = pb->n;
+  scratch s;
+  if (scratch_alloc(&s, n)) { J->rc = -1; return NULL; }
+  double* buf = (double*)malloc(sizeof(double) * (size_t)n * 4);
+  double *yp = buf, *g = buf + n, *p = buf + 2 * n, *tmp = buf + 3 * n;
+  for (int64_t j = J->begin; j < J->end; ++j) {
+    const double* y = J->y + (size_t)j * n;
+    double best = INFINITY;
+    int kb = -1, ins = 0, nb = 0;
+    double* cpj = J->cp + (size_t)j * n;
+    for (int k = 0; k < pb->K && !ins; ++k) {
+      for (int i = 0; i < n; ++i) yp[i] = y[i] - (pb->centres ? pb->centres[(size_t)k * n + i] : 0.0);
+      chol_solve(n, J->LA, yp, tmp, g); /* g = A^{-1}(y - c_k) = grad L_k(y) */
+      double Ly = 0.5 * (dot(n, yp, g) - 1.0);
+      if (Ly <= 0.0) { /* y lies in ellipsoid k: distance 0, closest point y */
+        ins = 1; kb = k; best = 0.0;
+        memcpy(cpj, y, sizeof(double) * (size_t)n);
+        break;
+      }
+      double sv = Ly / sqrt(dot(n, g, g)); /* a lower bound of the distance */
+      int l = 0;
+      double pn = 0.0;
+      while (l < J->max_newton) {
+        ++l;
+        int32_t it;
+        double psi = hopf_solve(pb, OH_L2, J->LS, J->LA, yp, sv, &s, p, &it, NULL) - 0.5;
+        pn = sqrt(dot(n, p, p));
+        if (pn == 0.0) break;
+        double ds = psi / pn; /* s_{l+1} = s_l - psi / (d psi/ds), d psi/ds = -||grad psi|| */
+        sv += ds;
+        if (fabs(ds) <= J->s_tol * (sv > 1.0 ? sv : 1.0)) break;
+      }
+      if (sv < best) {
+        best = sv; kb = k; nb = l;
+        /* pi(y) = y - s * grad psi / ||grad psi||  (eq. projection_when_s_known) */
+        for (int i = 0; i < n; ++i) cpj[i] = y[i] - (pn > 0 ? sv * p[i] / pn : 0.0);
+      }
+    }
+    J->dist[j] = best;
+    J->kstar[j] = kb;
+    J->inside[j] = ins;
+    if (J->newton) J->newton[j] = nb;
+  }
+  free(buf);
+  scratch_free(&s);
+  return NULL;
+}
+
+int oh_distance_newton(const oh_problem* pb, int64_t npts, const double* y, double s_tol,
+                       int32_t max_newton, double* dist, double* cp, int32_t* kstar,
+                       int32_t* inside, int32_t* newton, int nthreads) {
+  if (check_problem(pb) || npts < 0 || max_newton < 1) return -1;
+  const int n = pb->n;
+  double* LS = (double*)malloc(sizeof(double) * (size_t)n * n * 2);
+  double* LA = LS + (size_t)n * n;
+  int rc = cholesky(n, pb->A, pb->lambda, LS);
+  if (rc == 0) rc = cholesky(n, pb->A, 0.0, LA);
+  if (rc) { free(LS); return rc; }
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > npts) nthreads = npts > 0 ? (int)npts : 1;
+  dist_job* jobs = (dist_job*)calloc((size_t)nthreads, sizeof(dist_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  for (int i = 0; i < nthreads; ++i) {
+    dist_job* J = &jobs[i];
+    J->pb = pb; J->LS = LS; J->LA = LA; J->y = y; J->s_tol = s_tol; J->max_newton = max_newton;
+    J->dist = dist; J->cp = cp; J->kstar = kstar; J->inside = inside; J->newton = newton;
+    J->begin = npts * i / nthreads; J->end = npts * (i + 1) / nthreads;
+    if (nthreads == 1) dist_worker(J);
+    else pthread_create(&th[i], NULL, dist_worker, J);
+  }
+  rc = 0;
+  for (int i = 0; i < nthreads; ++i) {
+    if (nthreads > 1) pthread_join(th[i], NULL);
+    if (jobs[i].rc) rc = jobs[i].rc;
+  }
+  free(jobs); free(th); free(LS);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Textbook projection onto an ellipsoid (section 4.3): in the eigenbasis the  */
+/* projection of u is sigma_i u_i / (sigma_i + mu) with mu > 0 the root of     */
+/* sum sigma_i u_i^2 / (sigma_i + mu)^2 = 1, found by Newton from mu = 0.      */
+/* ------------------------------------------------------------------------- */
+int oh_distance_secular(int32_t n, const double* Q, const double* sigma, int32_t K,
+                        const double* centres, int64_t npts, const double* y, double* dist,
+                        double* cp, int32_t* kstar, int32_t* inside) {
+  if (n < 1 || !Q || !sigma || K < 1 || npts < 0) return -1;
+  for (int i = 0; i < n; ++i)
+    if (!(sigma[i] > 0)) return -2;
+  double* buf = (double*)malloc(sizeof(double) * (size_t)n * 3);
+  double *u = buf, *us = buf + n, *col = buf + 2 * n;
+  for (int64_t j = 0; j < npts; ++j) {
+    const double* yj = y + (size_t)j * n;
+    double* cpj = cp + (size_t)j * n;
+    double best = INFINITY;
+    int kb = -1, ins = 0;
+    for (int k = 0; k < K && !ins; ++k) {
+      const double* c = centres ? centres + (size_t)k * n : NULL;
+      for (int a = 0; a < n; ++a) { /* u = Q^T (y - c) */
+        ksum s = {0, 0};
+        for (int i = 0; i < n; ++i) ks_add(&s, Q[(size_t)i * n + a] * (yj[i] - (c ? c[i] : 0.0)));
+        u[a] = ks_val(&s);
+      }
+      ksum q = {0, 0};
+      for (int a = 0; a < n; ++a) ks_add(&q, u[a] * u[a] / sigma[a]);
+      if (ks_val(&q) <= 1.0) {
+        ins = 1; kb = k; best = 0.0;
+        memcpy(cpj, yj, sizeof(double) * (size_t)n);
+        break;
+      }
+      double mu = 0.0;
+      for (int it = 0; it < 500; ++it) {
+        ksum g = {0, 0}, gp = {0, 0};
+        ks_add(&g, -1.0);
+        for (int a = 0; a < n; ++a) {
+          double den = sigma[a] + mu;
+          double e = sigma[a] * u[a] * u[a] / (den * den);
+          ks_add(&g, e);
+          ks_add(&gp, -2.0 * e / den);
+        }
+        double dmu = -ks_val(&g) / ks_val(&gp);
+        mu += dmu;
+        if (fabs(dmu) <= 1e-15 * (mu > 1.0 ? mu : 1.0)) break;
+      }
+      ksum d2 = {0, 0};
+      for (int a = 0; a < n; ++a) {
+        us[a] = sigma[a] * u[a] / (sigma[a] + mu);
+        double e = u[a] - us[a];
+        ks_add(&d2, e * e);
+      }
+      double dk = sqrt(ks_val(&d2));
+      if (dk < best) {
+        best = dk; kb = k;
+        for (int i = 0; i < n; ++i) { /* cp = c + Q u* */
+          for (int a = 0; a < n; ++a) col[a] = Q[(size_t)i * n + a];
+          cpj[i] = (c ? c[i] : 0.0) + dot(n, col, us);
+        }
+      }
+    }
+    dist[j] = best; kstar[j] = kb; inside[j] = ins;
+  }
+  free(buf);
+  return 0;
+}

@@ -1,0 +1,194 @@
+"""ctypes wrapper of the C oracle plus the parts that are library primitives.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* ``oracle_eval``: Hopf value, gradient and time derivative by split Bregman
+  (paper eqs. (3.3), (3.4a)-(3.4c), stopping test of section 4.5), min over
+  translated initial data (section 2, min over initial data), in C.
+* ``oracle_distance_newton``: distance / closest point to a union of
+  ellipsoids by the level-set route of section 3.2 (eikonal Hopf evaluation
+  and Newton on s, eq. (Newton_zero)), in C.
+* ``oracle_distance_secular``: the same distance by the textbook ellipsoid
+  projection of section 4.3 (Lagrange multiplier, Newton on mu); the
+  eigendecomposition A = Q diag(sigma) Q^T is a library primitive
+  (``numpy.linalg.eigh``).
+* ``oracle_backward``: envelope-theorem gradients of phi with respect to x, t,
+  A and the centres (phi is the optimal value of eq. (3.3), whose objective is
+  affine in x, t, A and c at fixed p).  Parity unpinned by any printed value:
+  pinned by central finite differences of ``oracle_eval``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hopf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_hopf.so")
+
+OH_WL1, OH_L2, OH_L2_WL1 = 0, 1, 2
+_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE double, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def available() -> bool:
+    return os.path.exists(_LIB)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("A", ctypes.c_void_p), ("K", ctypes.c_int32),
+        ("centres", ctypes.c_void_p), ("level_set", ctypes.c_int32), ("hkind", ctypes.c_int32),
+        ("w", ctypes.c_void_p), ("lam", ctypes.c_double), ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str):
+    """Load an oracle shared library built from hopf_oracle.c and declare its signatures."""
+    lib = ctypes.CDLL(path)
+    P, V, I64, I32, D = (ctypes.POINTER(_Problem), ctypes.c_void_p, ctypes.c_int64,
+                         ctypes.c_int32, ctypes.c_double)
+    lib.oh_eval.argtypes = [P, I64, V, V, V, V, V, V, V, V, ctypes.c_int]
+    lib.oh_distance_newton.argtypes = [P, I64, V, D, I32, V, V, V, V, V, ctypes.c_int]
+    lib.oh_distance_secular.argtypes = [I32, V, V, I32, V, I64, V, V, V, V, V]
+    for f in (lib.oh_eval, lib.oh_distance_newton, lib.oh_distance_secular):
+        f.restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = load_library(_LIB)
+    return _lib
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter):
+    A = _f64(A)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be n x n")
+    w = _f64(w)
+    centres = None if centres is None else _f64(centres).reshape(-1, n)
+    K = 1 if centres is None else centres.shape[0]
+    hk = _HKIND[hkind] if isinstance(hkind, str) else int(hkind)
+    pb = _Problem(n, _ptr(A), K, _ptr(centres), int(bool(level_set)), hk, _ptr(w),
+                  float(lam), float(tol), int(max_iter))
+    return pb, (A, w, centres), n, K
+
+
+def _threads(nthreads):
+    if nthreads is None or nthreads <= 0:
+        return os.cpu_count() or 1
+    return int(nthreads)
+
+
+def oracle_eval(A, x, t, hkind="wl1", w=None, centres=None, level_set=False, lam=1.0,
+                tol=1e-28, max_iter=100000, nthreads=None, with_gap=False):
+    """Hopf evaluation of every point of x (npts x n) at times t (npts)."""
+    lib = _load()
+    pb, keep, n, K = _problem(A, hkind, w, centres, level_set, lam, tol, max_iter)
+    x = _f64(x).reshape(-1, n)
+    t = _f64(t).reshape(-1)
+    m = x.shape[0]
+    if t.shape[0] != m:
+        raise ValueError("t must have one entry per point")
+    phi = np.empty(m); grad = np.empty((m, n)); dphidt = np.empty(m)
+    iters = np.empty(m, np.int32); kstar = np.empty(m, np.int32)
+    gap = np.empty(m) if with_gap else None
+    rc = lib.oh_eval(ctypes.byref(pb), m, _ptr(x), _ptr(t), _ptr(phi), _ptr(grad), _ptr(dphidt),
+                     _ptr(iters), _ptr(kstar), _ptr(gap), _threads(nthreads))
+    if rc == -2:
+        raise np.linalg.LinAlgError("A + lambda I (or A) is not symmetric positive definite")
+    if rc:
+        raise ValueError("oracle_eval: invalid arguments")
+    out = dict(phi=phi, grad=grad, dphidt=dphidt, iters=iters, kstar=kstar)
+    if with_gap:
+        out["gap"] = gap
+    return out
+
+
+def oracle_distance_newton(A, y, centres=None, lam=1.0, tol=1e-28, max_iter=100000,
+                           s_tol=1e-13, max_newton=100, nthreads=None):
+    """Distance / closest point from each y to the union of ellipsoids c_k + {u^T A^{-1} u <= 1}."""
+    lib = _load()
+    pb, keep, n, K = _problem(A, "l2", None, centres, True, lam, tol, max_iter)
+    y = _f64(y).reshape(-1, n)
+    m = y.shape[0]
+    dist = np.empty(m); cp = np.empty((m, n))
+    kstar = np.empty(m, np.int32); inside = np.empty(m, np.int32); newton = np.empty(m, np.int32)
+    rc = lib.oh_distance_newton(ctypes.byref(pb), m, _ptr(y), float(s_tol), int(max_newton),
+                                _ptr(dist), _ptr(cp), _ptr(kstar), _ptr(inside), _ptr(newton),
+                                _threads(nthreads))
+    if rc:
+        raise ValueError("oracle_distance_newton failed (%d)" % rc)
+    return dict(dist=dist, cp=cp, kstar=kstar, inside=inside, newton=newton)
+
+
+def oracle_distance_secular(A, y, centres=None):
+    """Same distance via the eigenbasis projection (section 4.3)."""
+    lib = _load()
+    A = _f64(A)
+    n = A.shape[0]
+    sigma, Q = np.linalg.eigh(0.5 * (A + A.T))
+    Q = np.ascontiguousarray(Q)
+    sigma = np.ascontiguousarray(sigma)
+    centres = None if centres is None else _f64(centres).reshape(-1, n)
+    K = 1 if centres is None else centres.shape[0]
+    y = _f64(y).reshape(-1, n)
+    m = y.shape[0]
+    dist = np.empty(m); cp = np.empty((m, n))
+    kstar = np.empty(m, np.int32); inside = np.empty(m, np.int32)
+    rc = lib.oh_distance_secular(n, _ptr(Q), _ptr(sigma), K, _ptr(centres), m, _ptr(y),
+                                 _ptr(dist), _ptr(cp), _ptr(kstar), _ptr(inside))
+    if rc:
+        raise ValueError("oracle_distance_secular failed (%d)" % rc)
+    return dict(dist=dist, cp=cp, kstar=kstar, inside=inside)
+
+
+def oracle_backward(grad, kstar, t_h, gphi, K=1):
+    """Envelope-theorem gradients of L = sum_j gphi_j phi_j.
+
+    phi_j = -F_j(p_j) with F_j(p) = 1/2 p^T A p + <c_k, p> + t_j H(p) - <x_j, p> (+ const),
+    which is affine in (x_j, t_j, A, c_k) at fixed p, so at the minimiser p_j (= grad phi_j):
+      d phi_j / d x_j = p_j,  d phi_j / d t_j = -H(p_j),
+      d phi_j / d A = -1/2 p_j p_j^T,  d phi_j / d c_{k*} = -p_j  (0 for the other k).
+    ``t_h`` carries H(p_j) (i.e. -dphidt).
+    """
+    grad = np.asarray(grad, np.float64)
+    gphi = np.asarray(gphi, np.float64).reshape(-1)
+    m, n = grad.shape
+    gx = gphi[:, None] * grad
+    gt = -gphi * np.asarray(t_h, np.float64).reshape(-1)
+    gA = -0.5 * (grad * gphi[:, None]).T @ grad
+    gc = np.zeros((K, n))
+    for k in range(K):
+        sel = np.asarray(kstar) == k
+        gc[k] = -(gphi[sel, None] * grad[sel]).sum(0)
+    return dict(gx=gx, gt=gt, gA=gA, gc=gc)

@@ -1,0 +1,134 @@
+"""Planted mistakes: each mutant of the oracle source (a dropped term, a flipped sign, a
+transposed operand, a wrong index or comparison) must fail at least one pin.  The mutants
+are compiled into a temporary directory on the CPU and never touch the real oracle."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+
+SRC = os.path.join(os.path.dirname(O.__file__), "hopf_oracle.c")
+
+MUTANTS = {
+    "bregman_update_sign": ("s->b[i] + s->vn[i] - s->dn[i]", "s->b[i] - s->vn[i] + s->dn[i]"),
+    "rhs_drops_lambda": ("xp[i] + lam * (s->d[i] - s->b[i])", "xp[i] + (s->d[i] - s->b[i])"),
+    "rhs_sign_b": ("lam * (s->d[i] - s->b[i])", "lam * (s->d[i] + s->b[i])"),
+    "threshold_times_lambda": ("t / lam, s->z, s->dn", "t * lam, s->z, s->dn"),
+    "shrink2_sign": ("(nr - theta > 0.0 ? nr - theta : 0.0) / nr", "(nr + theta > 0.0 ? nr + theta : 0.0) / nr"),
+    "shrink1_ignores_weights": ("d[i] = shrink1(z[i], theta * wgt(w, i));", "d[i] = shrink1(z[i], theta);"),
+    "backsolve_transposed": ("ks_add(&k, -L[(size_t)m * n + i] * out[m]);", "ks_add(&k, -L[(size_t)i * n + m] * out[m]);"),
+    "cholesky_sign": ("ks_add(&k, -L[(size_t)j * n + m] * L[(size_t)j * n + m]);", "ks_add(&k, L[(size_t)j * n + m] * L[(size_t)j * n + m]);"),
+    "value_drops_H": ("ks_add(&F, t * ham(n, hkind, pb->w, p));", "ks_add(&F, 0.0);"),
+    "value_half_missing": ("ks_add(&F, 0.5 * quad(n, pb->A, p));", "ks_add(&F, quad(n, pb->A, p));"),
+    "union_max_not_min": ("if (val < best || kb < 0)", "if (val > best || kb < 0)"),
+    "level_set_offset_sign": ("if (pb->level_set) val -= 0.5;", "if (pb->level_set) val += 0.5;"),
+    "newton_step_sign": ("sv += ds;", "sv -= ds;"),
+    "dphidt_sign": ("J->dphidt[j] = -ham(", "J->dphidt[j] = ham("),
+    "centre_sign": ("xp[i] = x[i] - (pb->centres", "xp[i] = x[i] + (pb->centres"),
+    "secular_projection_index": ("us[a] = sigma[a] * u[a] / (sigma[a] + mu);", "us[a] = sigma[a] * u[a] / (sigma[a] + mu * mu);"),
+}
+
+
+def battery(lib):
+    """Quick pins; returns the names of those that fail."""
+    old = O._lib
+    O._lib = lib
+    fails = []
+    rng = np.random.default_rng(0)
+    try:
+        def check(name, fn):
+            try:
+                if not fn():
+                    fails.append(name)
+            except Exception:
+                fails.append(name)
+
+        n = 6
+        a = rng.uniform(0.5, 3, n)
+        w = rng.uniform(0.5, 2, n)
+        x = rng.normal(0, 3, (8, n))
+        t = rng.uniform(0.1, 2, 8)
+
+        def ellipsoid_cf():
+            r = O.oracle_eval(np.diag(a * a), x, t, "wl1", w=w, level_set=True, tol=1e-26, max_iter=20000)
+            ex = np.maximum(np.abs(x) - t[:, None] * w, 0)
+            ok = np.allclose(r["phi"], -0.5 + 0.5 * ((ex / a) ** 2).sum(1), atol=1e-9)
+            ok &= np.allclose(r["dphidt"], -(w * np.abs(r["grad"])).sum(1), atol=1e-9)
+            return ok and np.allclose(r["grad"], np.sign(x) * ex / (a * a), atol=1e-9)
+        check("ellipsoid_cf", ellipsoid_cf)
+
+        def sphere_cf():
+            r = O.oracle_eval(np.eye(n), x, t, "l2", level_set=True, tol=1e-26, max_iter=20000)
+            nx = np.linalg.norm(x, axis=1)
+            return np.allclose(r["phi"], np.where(nx > t, 0.5 * (nx - t) ** 2 - 0.5, -0.5), atol=1e-9)
+        check("sphere_cf", sphere_cf)
+
+        Q = np.linalg.qr(rng.normal(size=(n, n)))[0]
+        A = (Q * rng.uniform(0.2, 5, n)) @ Q.T
+        A = 0.5 * (A + A.T)
+
+        def kkt():
+            from tests.test_oracle_pins import kkt_residual
+            ok = True
+            for hk in ("wl1", "l2", "l2_wl1"):
+                for lam in (1.0, 0.4):
+                    r = O.oracle_eval(A, x, t, hk, w=w, lam=lam, tol=1e-26, max_iter=20000)
+                    ok &= all(kkt_residual(A, x[j], t[j], r["grad"][j], hk, w) < 1e-7 for j in range(8))
+            return ok
+        check("kkt", kkt)
+
+        def union_translation():
+            C = rng.normal(0, 2, (2, n))
+            r = O.oracle_eval(A, x, t, "wl1", w=w, centres=C, tol=1e-26, max_iter=20000)
+            r0 = O.oracle_eval(A, x - C[0], t, "wl1", w=w, tol=1e-26, max_iter=20000)
+            r1 = O.oracle_eval(A, x - C[1], t, "wl1", w=w, tol=1e-26, max_iter=20000)
+            return np.allclose(r["phi"], np.minimum(r0["phi"], r1["phi"]), atol=1e-9)
+        check("union_translation", union_translation)
+
+        def distances():
+            C = rng.normal(0, 3, (2, n))
+            y = rng.normal(0, 5, (6, n))
+            r1 = O.oracle_distance_newton(A, y, centres=C, tol=1e-26, max_iter=20000, max_newton=60)
+            yb = rng.normal(0, 3, (6, n))
+            yb = yb[np.linalg.norm(yb, axis=1) > 1.1]
+            rb = O.oracle_distance_newton(np.eye(n), yb, tol=1e-26, max_iter=20000, max_newton=60)
+            ok = np.allclose(rb["dist"], np.linalg.norm(yb, axis=1) - 1, atol=1e-8)
+            r2 = O.oracle_distance_secular(A, y, centres=C)
+            ok &= np.array_equal(r1["inside"], r2["inside"])
+            ok &= np.allclose(r1["dist"], r2["dist"], atol=1e-8)
+            out = r2["inside"] == 0
+            for j in np.nonzero(out)[0]:  # closest point on the boundary of its ellipsoid
+                u = r2["cp"][j] - C[r2["kstar"][j]]
+                ok &= abs(u @ np.linalg.solve(A, u) - 1) < 1e-8
+            return ok
+        check("distances", distances)
+    finally:
+        O._lib = old
+    return fails
+
+
+def _compile(src_text, d, name):
+    c = os.path.join(d, name + ".c")
+    so = os.path.join(d, name + ".so")
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-I", os.path.dirname(SRC), "-o", so, c, "-lm", "-lpthread"])
+    return O.load_library(so)
+
+
+def test_unmutated_passes_battery(oracle_lib):
+    assert battery(O._load()) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(oracle_lib, name):
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, name
+    with tempfile.TemporaryDirectory() as d:
+        lib = _compile(src.replace(old, new), d, "m_" + name)
+        assert battery(lib), "planted mistake %s not caught" % name
