@@ -1,0 +1,179 @@
+/*
+ * hopf.h -- C ABI of the MI355X (gfx950) Hopf-formula library.
+ *
+ * Method: Darbon & Osher, "Algorithms for overcoming the curse of
+ * dimensionality for certain Hamilton-Jacobi equations arising in control
+ * theory and elsewhere", arXiv:1605.01799.
+ *
+ * For every query point (x, t) the library evaluates the Hopf formula
+ * (eqs. (1.2)/(3.3))
+ *     phi(x, t) = -min_p { J*(p) + t H(p) - <x, p> }
+ * for the initial data J(y) = 1/2 y^T A^{-1} y (A symmetric positive definite,
+ * so J*(p) = 1/2 p^T A p), or for the non-convex initial data
+ * J = min_k J_k over K translated copies / ellipsoid level-set functions
+ * (section 2, "min over initial data": phi = min_k phi_k), with the convex,
+ * positively 1-homogeneous Hamiltonians H = sum_i w_i |p_i|, ||p||_2, or their
+ * sum.  The minimiser is found by split Bregman (eqs. (3.4a)-(3.4c)); the
+ * library returns phi, grad_x phi = p* (the minimiser, section 1) and
+ * d phi / d t = -H(p*) (eq. (1.1a)).  It also computes the distance from a
+ * point to a union of ellipsoids and the closest point on it (section 3.2,
+ * level-set eikonal evaluation with Newton on s, eq. (Newton_zero)), and the
+ * envelope-theorem gradients of phi with respect to x, t, A and the centres.
+ *
+ * Conventions (all entry points):
+ *  - Host pointers are marked "host"; every other array argument is a DEVICE
+ *    pointer owned by the caller (e.g. allocated by PyTorch).  The library
+ *    owns only what a problem handle holds (the factored matrices on device)
+ *    and an internal workspace per device (grown on demand with hipMalloc).
+ *  - Array element type: double for precision HOPF_F64, float for HOPF_F32
+ *    and HOPF_BF16_REFINED ("real" below).  Points are stored point-major:
+ *    x[j*n + i] is coordinate i of point j.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    stream-ordered: returning HOPF_OK means the work was enqueued, not that
+ *    it finished.  Host arrays passed in are copied before the call returns.
+ *  - Errors: argument checks happen synchronously on the host and return a
+ *    status; no state is changed on error.  hopf_last_error() returns a
+ *    thread-local description of the last non-OK status.  Per-point problems
+ *    are reported in iters[]: >= 1 converged after that many v-updates, -2
+ *    the iteration cap was hit (outputs come from the last iterate), -1 a
+ *    non-finite input or t <= 0 (outputs are NaN).
+ *  - Calls that share a problem handle may run concurrently on different
+ *    streams; calls on one device share the workspace and are serialised by
+ *    the library's per-device lock around enqueueing (not around execution:
+ *    use one stream per device, or synchronise between streams).
+ */
+#ifndef HOPF_H
+#define HOPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOPF_OK = 0,
+  HOPF_EINVAL = -1,   /* bad argument */
+  HOPF_ENOTSPD = -2,  /* A + lambda I (or A) is not symmetric positive definite */
+  HOPF_ENOMEM = -3,   /* device allocation failed */
+  HOPF_EDEVICE = -4   /* HIP runtime error or missing gfx950 device */
+} hopf_status;
+
+typedef enum {
+  HOPF_H_WL1 = 0,     /* H(p) = sum_i w_i |p_i|            (support function of a box)  */
+  HOPF_H_L2 = 1,      /* H(p) = ||p||_2                    (support function of a ball) */
+  HOPF_H_L2_WL1 = 2   /* H(p) = ||p||_2 + sum_i w_i |p_i|  (their Minkowski sum)        */
+} hopf_hkind;
+
+typedef enum {
+  HOPF_F64 = 0,          /* double I/O and arithmetic (diagonal A only) */
+  HOPF_F32 = 1,          /* float I/O; FP32 state and FP32 MFMA products */
+  HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined to
+                            FP64-exact anchor products every few iterations */
+} hopf_precision;
+
+typedef struct {
+  int32_t n;                 /* dimension, 1 <= n <= 2048 */
+  const double* A;           /* host. n*n row-major SPD matrix, or n entries if A_is_diagonal.
+                                NULL means A = I.  J(y) = 1/2 y^T A^{-1} y. */
+  int32_t A_is_diagonal;     /* 1: A holds the n diagonal entries (elementwise path) */
+  int32_t K;                 /* number of translated copies of J, K >= 1 */
+  const double* centres;     /* host, K*n, or NULL (all centres 0) */
+  int32_t level_set;         /* 1: J_k(y) = 1/2((y-c_k)^T A^{-1} (y-c_k) - 1), ellipsoid k */
+  hopf_hkind hkind;
+  const double* w;           /* host, n weights >= 0, or NULL (all 1); ignored for HOPF_H_L2 */
+  double lambda;             /* split-Bregman penalty > 0 (the paper uses 1) */
+  double tol;                /* stopping tolerance on squared norms (see hopf_eval) */
+  int32_t max_iter;          /* iteration cap >= 1 */
+  hopf_precision precision;
+} hopf_problem_desc;
+
+typedef struct hopf_problem* hopf_problem_t;
+
+/* Creates a problem: validates the descriptor, copies the host data, and
+ * enqueues on `stream` the FP64 factorisation of A + lambda I on the device
+ * (block Gauss-Jordan inverse M = (A + lambda I)^{-1} with a Cholesky test of
+ * every pivot block; section 4.1 states that the quadratic prox is
+ * (I + alpha A)^{-1}), followed by the rounded copies the kernels read.
+ * Returns HOPF_ENOTSPD (after synchronising `stream`) if a pivot block is not
+ * positive definite.  *out is owned by the caller until hopf_problem_destroy. */
+hopf_status hopf_problem_create(const hopf_problem_desc* desc, void* stream, hopf_problem_t* out);
+
+/* Creates nprob problems at once (descs[i] -> out[i]); the dense factorisations of
+ * the batch run together (problems sorted by size, one launch sequence), which is
+ * how a ragged batch of many problems should be set up.  On error no handle is
+ * returned (all out[i] are NULL) and the message names the failing problem. */
+hopf_status hopf_problem_create_batch(int32_t nprob, const hopf_problem_desc* descs, void* stream,
+                                      hopf_problem_t* out);
+
+/* Releases the device memory of a problem (synchronises the device first). */
+hopf_status hopf_problem_destroy(hopf_problem_t problem);
+
+/* Evaluates npts points (eq. (3.3), split Bregman (3.4a)-(3.4c) with
+ * v0 = d0 = x - c_k, b0 = 0).  Inputs: x (npts*n), t (npts, > 0).  Outputs:
+ * phi (npts), grad (npts*n) = p* of the attaining copy, dphidt (npts) =
+ * -H(p*), iters (npts, nullable), kstar (npts, nullable; lowest index
+ * attaining the min over k).  A point stops when the squared change of the
+ * split-Bregman iterate between two iterations, summed over the last two
+ * iterations as (sqrt(a) + sqrt(b))^2, is <= tol; this bounds all three
+ * squared norms of the stopping test of section 4.5 by tol.  npts == 0 is a
+ * no-op. */
+hopf_status hopf_eval(hopf_problem_t problem, int64_t npts, const void* x, const void* t,
+                      void* phi, void* grad, void* dphidt, int32_t* iters, int32_t* kstar,
+                      void* stream);
+
+/* Distance from each y (npts*n) to the union of the K ellipsoids
+ * {u : (u-c_k)^T A^{-1} (u-c_k) <= 1} of the problem (level_set must be 1;
+ * H = ||.||_2 is used whatever the problem's hkind), by Newton on s for
+ * psi_k(y, s) = 0 with psi_k the eikonal Hopf evaluation (section 3.2).
+ * Outputs: dist (npts), cp (npts*n) closest point, kstar (npts, nearest
+ * ellipsoid), inside (npts, nullable: 1 if y lies in the union, then dist = 0
+ * and cp = y), newton (npts, nullable: Newton steps of the nearest ellipsoid,
+ * -2 if a cap was hit, -1 for a non-finite y).  s_tol: Newton stops when
+ * |s_{l+1} - s_l| <= s_tol * max(1, s). */
+hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void* y, double s_tol,
+                               void* dist, void* cp, int32_t* kstar, int32_t* inside,
+                               int32_t* newton, void* stream);
+
+/* Ragged batch: nprob problems (any n, K, A, w; one precision for all, not
+ * HOPF_F64) evaluated in one launch sequence.  pt_offset (host, nprob+1)
+ * gives the points of problem q as [pt_offset[q], pt_offset[q+1]); x_packed
+ * holds the points of problem q contiguously starting at element
+ * sum_{r<q} (pt_offset[r+1]-pt_offset[r]) * n_r, and grad_packed likewise.
+ * t, phi, dphidt, iters, kstar are indexed by the global point index. */
+hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* problems,
+                             const int64_t* pt_offset, const void* x_packed, const void* t,
+                             void* phi, void* grad_packed, void* dphidt, int32_t* iters,
+                             int32_t* kstar, void* stream);
+
+/* Envelope-theorem gradients of L = sum_j gphi_j phi_j (phi is the optimal
+ * value of eq. (3.3), an objective affine in x, t, A and c_k at fixed p):
+ *   gx[j] = gphi_j p*_j,  gt[j] = gphi_j dphidt_j (= -gphi_j H(p*_j)),
+ *   gA = -1/2 sum_j gphi_j p*_j p*_j^T (n*n, row-major),
+ *   gc[k] = -sum_{j: kstar_j = k} gphi_j p*_j (K*n).
+ * grad_saved, dphidt_saved, kstar_saved are hopf_eval's outputs.  Any output
+ * may be NULL.  gA and gc are overwritten (not accumulated).  kstar_saved may
+ * be NULL when K == 1. */
+hopf_status hopf_backward(hopf_problem_t problem, int64_t npts, const void* gphi,
+                          const void* grad_saved, const void* dphidt_saved,
+                          const int32_t* kstar_saved, void* gx, void* gt, void* gA, void* gc,
+                          void* stream);
+
+/* Device-side factor of the problem, for inspection and tests: copies
+ * M = (A + lambda I)^{-1} (n*n, row-major, FP64) to the host array out. */
+hopf_status hopf_problem_get_inverse(hopf_problem_t problem, double* out);
+
+/* Problem dimension, padded dimension, K, precision; any pointer may be NULL. */
+hopf_status hopf_problem_info(hopf_problem_t problem, int32_t* n, int32_t* n_pad, int32_t* K,
+                              int32_t* precision);
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char* hopf_last_error(void);
+
+/* Library version string. */
+const char* hopf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOPF_H */

@@ -1,0 +1,559 @@
+// C ABI of the library (declared in include/hopf.h): argument checking,
+// problem setup, tiling of query columns, workspace management, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hopf.h"
+#include "backward.hpp"
+#include "common.hpp"
+#include "dense.hpp"
+#include "diag.hpp"
+#include "setup.hpp"
+
+using namespace hopf;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static hopf_status fail(hopf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail(_e == hipErrorOutOfMemory ? HOPF_ENOMEM : HOPF_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(_e), __FILE__, __LINE__);                     \
+  } while (0)
+
+extern "C" const char* hopf_last_error(void) { return g_err.c_str(); }
+extern "C" const char* hopf_version(void) { return "hopf-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// problem handle
+// ---------------------------------------------------------------------------
+struct hopf_problem {
+  int device = 0;
+  int n = 0, n_pad = 0, K = 1, level_set = 0, hkind = 0, precision = 0, diagonal = 0, max_iter = 1;
+  double lambda = 1.0, tol = 0.0;
+  double* d_w = nullptr;        // n_pad
+  double* d_centres = nullptr;  // K*n_pad (null if all centres are 0 and K == 1)
+  double* d_Md = nullptr;       // n_pad^2
+  float* d_Mf = nullptr;        // n_pad^2 (F32 precision)
+  __bf16* d_Mb = nullptr;       // n_pad^2 (BF16_REFINED precision)
+  double* d_adiag = nullptr;    // n (diagonal A)
+  double* d_minv = nullptr;     // n (diagonal A)
+};
+
+// ---------------------------------------------------------------------------
+// per-device workspace
+// ---------------------------------------------------------------------------
+struct Workspace {
+  std::mutex mu;
+  float* state = nullptr; size_t state_bytes = 0;
+  unsigned char* meta = nullptr; size_t meta_bytes = 0;
+  double* scratch = nullptr; size_t scratch_bytes = 0;
+  unsigned char* pinned = nullptr; size_t pinned_bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool ev_pending = false;
+  int ncu = 0;
+};
+static Workspace g_ws[64];
+
+static hopf_status ws_grow(void** p, size_t* cur, size_t need) {
+  if (need <= *cur) return HOPF_OK;
+  size_t sz = std::max(need, *cur + *cur / 4);
+  if (*p) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(*p));
+    *p = nullptr; *cur = 0;
+  }
+  HIP_TRY(hipMalloc(p, sz));
+  *cur = sz;
+  return HOPF_OK;
+}
+
+static hopf_status ws_get(int dev, Workspace** out) {
+  if (dev < 0 || dev >= 64) return fail(HOPF_EDEVICE, "device index %d out of range", dev);
+  Workspace* w = &g_ws[dev];
+  if (w->ncu == 0) {
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(HOPF_EDEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    w->ncu = prop.multiProcessorCount;
+    HIP_TRY(hipEventCreateWithFlags(&w->ev, hipEventDisableTiming));
+  }
+  *out = w;
+  return HOPF_OK;
+}
+
+// Upload small metadata (problem views, tile lists) through a pinned staging buffer.
+// The staging buffer is reused only after the previous upload has been consumed.
+static hopf_status ws_upload(Workspace* w, const void* src, size_t bytes, hipStream_t stream, void** dst) {
+  if (w->ev_pending) { HIP_TRY(hipEventSynchronize(w->ev)); w->ev_pending = false; }
+  if (bytes > w->pinned_bytes) {
+    if (w->pinned) HIP_TRY(hipHostFree(w->pinned));
+    w->pinned = nullptr;
+    size_t sz = std::max(bytes, (size_t)1 << 16);
+    HIP_TRY(hipHostMalloc((void**)&w->pinned, sz, hipHostMallocDefault));
+    w->pinned_bytes = sz;
+  }
+  hopf_status st = ws_grow((void**)&w->meta, &w->meta_bytes, bytes);
+  if (st) return st;
+  std::memcpy(w->pinned, src, bytes);
+  HIP_TRY(hipMemcpyAsync(w->meta, w->pinned, bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(w->ev, stream));
+  w->ev_pending = true;
+  *dst = w->meta;
+  return HOPF_OK;
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy
+// ---------------------------------------------------------------------------
+static hopf_status validate(const hopf_problem_desc* d) {
+  if (!d) return fail(HOPF_EINVAL, "desc is NULL");
+  if (d->n < 1 || d->n > 2048) return fail(HOPF_EINVAL, "n = %d outside [1, 2048]", d->n);
+  if (d->K < 1 || d->K > 64) return fail(HOPF_EINVAL, "K = %d outside [1, 64]", d->K);
+  if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) return fail(HOPF_EINVAL, "lambda must be finite and > 0");
+  if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return fail(HOPF_EINVAL, "tol must be finite and >= 0");
+  if (d->max_iter < 1) return fail(HOPF_EINVAL, "max_iter must be >= 1");
+  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_L2_WL1) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
+  if (d->precision < HOPF_F64 || d->precision > HOPF_BF16_REFINED)
+    return fail(HOPF_EINVAL, "unknown precision %d", (int)d->precision);
+  const int n = d->n;
+  if (d->w)
+    for (int i = 0; i < n; ++i)
+      if (!(d->w[i] >= 0.0) || !std::isfinite(d->w[i])) return fail(HOPF_EINVAL, "w[%d] must be finite and >= 0", i);
+  if (d->centres)
+    for (int64_t i = 0; i < (int64_t)d->K * n; ++i)
+      if (!std::isfinite(d->centres[i])) return fail(HOPF_EINVAL, "centres[%lld] is not finite", (long long)i);
+  const bool diag = d->A == nullptr || d->A_is_diagonal;
+  if (d->A) {
+    const int64_t m = d->A_is_diagonal ? n : (int64_t)n * n;
+    for (int64_t i = 0; i < m; ++i)
+      if (!std::isfinite(d->A[i])) return fail(HOPF_EINVAL, "A[%lld] is not finite", (long long)i);
+    if (d->A_is_diagonal) {
+      for (int i = 0; i < n; ++i)
+        if (!(d->A[i] > 0.0)) return fail(HOPF_ENOTSPD, "diagonal A[%d] = %g is not > 0", i, d->A[i]);
+    } else {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) {
+          double a = d->A[(size_t)i * n + j], b = d->A[(size_t)j * n + i];
+          if (std::fabs(a - b) > 1e-12 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))))
+            return fail(HOPF_EINVAL, "A is not symmetric at (%d, %d)", i, j);
+        }
+    }
+  }
+  if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
+    return fail(HOPF_EINVAL, "HOPF_F64 supports diagonal A with n <= %d; use HOPF_F32 or HOPF_BF16_REFINED", kDiagMaxN);
+  return HOPF_OK;
+}
+
+static void free_problem(hopf_problem* p) {
+  hipFree(p->d_w); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
+  hipFree(p->d_adiag); hipFree(p->d_minv);
+  delete p;
+}
+
+static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, hopf_problem** out,
+                              std::vector<double*>* pending_S) {
+  hopf_status st = validate(d);
+  if (st) return st;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace* w;
+  if ((st = ws_get(dev, &w))) return st;
+  hopf_problem* p = new hopf_problem;
+  p->device = dev;
+  p->n = d->n; p->K = d->K; p->level_set = d->level_set ? 1 : 0; p->hkind = d->hkind;
+  p->precision = d->precision; p->lambda = d->lambda; p->tol = d->tol; p->max_iter = d->max_iter;
+  p->diagonal = (d->A == nullptr || d->A_is_diagonal) ? 1 : 0;
+  const int n = d->n;
+  const int n_pad = (n + 31) / 32 * 32;
+  p->n_pad = n_pad;
+  auto bail = [&](hopf_status s) { free_problem(p); return s; };
+  std::vector<double> hw(n_pad, 0.0);
+  for (int i = 0; i < n; ++i) hw[i] = d->w ? d->w[i] : 1.0;
+  hipError_t e = hipMalloc(&p->d_w, sizeof(double) * n_pad);
+  if (e) return bail(fail(HOPF_ENOMEM, "hipMalloc w"));
+  e = hipMemcpy(p->d_w, hw.data(), sizeof(double) * n_pad, hipMemcpyHostToDevice);
+  if (e) return bail(fail(HOPF_EDEVICE, "copy w: %s", hipGetErrorString(e)));
+  if (d->centres) {
+    std::vector<double> hc((size_t)d->K * n_pad, 0.0);
+    for (int k = 0; k < d->K; ++k)
+      for (int i = 0; i < n; ++i) hc[(size_t)k * n_pad + i] = d->centres[(size_t)k * n + i];
+    if (hipMalloc(&p->d_centres, sizeof(double) * hc.size())) return bail(fail(HOPF_ENOMEM, "hipMalloc centres"));
+    if (hipMemcpy(p->d_centres, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice))
+      return bail(fail(HOPF_EDEVICE, "copy centres"));
+  }
+  const size_t mm = (size_t)n_pad * n_pad;
+  if (hipMalloc(&p->d_Md, sizeof(double) * mm)) return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP64)"));
+  if (d->precision != HOPF_BF16_REFINED && hipMalloc(&p->d_Mf, sizeof(float) * mm))
+    return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP32)"));
+  if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
+    return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
+  if (p->diagonal) {
+    std::vector<double> a(n, 1.0);
+    if (d->A) for (int i = 0; i < n; ++i) a[i] = d->A[i];
+    if (hipMalloc(&p->d_adiag, sizeof(double) * n) || hipMalloc(&p->d_minv, sizeof(double) * n))
+      return bail(fail(HOPF_ENOMEM, "hipMalloc diagonal"));
+    if (hipMemcpy(p->d_adiag, a.data(), sizeof(double) * n, hipMemcpyHostToDevice))
+      return bail(fail(HOPF_EDEVICE, "copy A"));
+    e = launch_diag_inverse(p->d_adiag, n, n_pad, d->lambda, p->d_Md, p->d_Mf, p->d_Mb, p->d_minv, stream);
+    if (e) return bail(fail(HOPF_EDEVICE, "diag inverse: %s", hipGetErrorString(e)));
+  } else {
+    // A + lambda I in FP64 on the device; the Gauss-Jordan batch is run by the caller
+    double* dA = nullptr;
+    double* S = nullptr;
+    if (hipMalloc(&dA, sizeof(double) * (size_t)n * n) || hipMalloc(&S, sizeof(double) * mm)) {
+      hipFree(dA);
+      return bail(fail(HOPF_ENOMEM, "hipMalloc setup"));
+    }
+    if (hipMemcpy(dA, d->A, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice)) {
+      hipFree(dA); hipFree(S);
+      return bail(fail(HOPF_EDEVICE, "copy A"));
+    }
+    e = launch_build_shifted(dA, n, n_pad, d->lambda, S, stream);
+    hipStreamSynchronize(stream);
+    hipFree(dA);
+    if (e) { hipFree(S); return bail(fail(HOPF_EDEVICE, "build A + lambda I: %s", hipGetErrorString(e))); }
+    pending_S->push_back(S);
+  }
+  *out = p;
+  return HOPF_OK;
+}
+
+// Runs the batched block Gauss-Jordan inverse for the dense problems of `probs`
+// (pending_S[i] belongs to the i-th dense problem in order), writes the M copies.
+static hopf_status factor_batch(std::vector<hopf_problem*>& dense, std::vector<double*>& S,
+                                hipStream_t stream) {
+  const int np = (int)dense.size();
+  if (np == 0) return HOPF_OK;
+  std::vector<int> order(np);
+  for (int i = 0; i < np; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return dense[a]->n_pad > dense[b]->n_pad; });
+  std::vector<SetupProb> hp(np);
+  std::vector<int> nblocks(np);
+  size_t scratch = 0;
+  for (int r = 0; r < np; ++r) scratch += 32 * 32 + 2 * (size_t)dense[order[r]]->n_pad * 32;
+  double* d_scr = nullptr;
+  int* d_status = nullptr;
+  SetupProb* d_probs = nullptr;
+  const int steps = dense[order[0]]->n_pad / 32;
+  int* d_prefix = nullptr;
+  std::vector<int> h_prefix((size_t)steps * 2 * (np + 1));
+  auto cleanup = [&]() {
+    hipFree(d_scr); hipFree(d_status); hipFree(d_probs); hipFree(d_prefix);
+  };
+  if (hipMalloc(&d_scr, sizeof(double) * scratch) || hipMalloc(&d_status, sizeof(int) * np) ||
+      hipMalloc(&d_probs, sizeof(SetupProb) * np) ||
+      hipMalloc(&d_prefix, sizeof(int) * h_prefix.size())) {
+    cleanup();
+    return fail(HOPF_ENOMEM, "hipMalloc setup scratch");
+  }
+  double* q = d_scr;
+  for (int r = 0; r < np; ++r) {
+    hopf_problem* p = dense[order[r]];
+    SetupProb& sp = hp[r];
+    sp.S = S[order[r]]; sp.n_pad = p->n_pad; sp.status = d_status + r;
+    sp.P = q; q += 32 * 32;
+    sp.T = q; q += (size_t)p->n_pad * 32;
+    sp.R = q; q += (size_t)p->n_pad * 32;
+    nblocks[r] = p->n_pad / 32;
+  }
+  hipError_t e = hipMemsetAsync(d_status, 0, sizeof(int) * np, stream);
+  if (!e) e = hipMemcpyAsync(d_probs, hp.data(), sizeof(SetupProb) * np, hipMemcpyHostToDevice, stream);
+  if (!e) e = run_gauss_jordan(d_probs, nblocks.data(), np, d_prefix, h_prefix.data(), stream);
+  for (int r = 0; r < np && !e; ++r) {
+    hopf_problem* p = dense[order[r]];
+    e = launch_finalize_copies(S[order[r]], p->n, p->n_pad, p->d_Md, p->d_Mf, p->d_Mb, stream);
+  }
+  std::vector<int> status(np, 0);
+  if (!e) e = hipMemcpyAsync(status.data(), d_status, sizeof(int) * np, hipMemcpyDeviceToHost, stream);
+  if (!e) e = hipStreamSynchronize(stream);
+  cleanup();
+  if (e) return fail(HOPF_EDEVICE, "factorisation: %s", hipGetErrorString(e));
+  for (int r = 0; r < np; ++r)
+    if (status[r]) return fail(HOPF_ENOTSPD, "A + lambda I is not positive definite (problem %d)", order[r]);
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_problem_create(const hopf_problem_desc* desc, void* stream, hopf_problem_t* out) {
+  if (!out) return fail(HOPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  return hopf_problem_create_batch(1, desc, stream, out);
+}
+
+extern "C" hopf_status hopf_problem_create_batch(int32_t nprob, const hopf_problem_desc* descs, void* stream,
+                                                 hopf_problem_t* out) {
+  if (nprob < 0 || (nprob > 0 && (!descs || !out))) return fail(HOPF_EINVAL, "bad batch arguments");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<hopf_problem*> made, dense;
+  std::vector<double*> S;
+  for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+  auto undo = [&]() {
+    for (double* x : S) hipFree(x);
+    for (hopf_problem* p : made) free_problem(p);
+  };
+  for (int i = 0; i < nprob; ++i) {
+    hopf_problem* p = nullptr;
+    size_t before = S.size();
+    hopf_status st = create_one(&descs[i], s, &p, &S);
+    if (st) {
+      std::string m = g_err;
+      undo();
+      return fail(st, "problem %d: %s", i, m.c_str());
+    }
+    made.push_back(p);
+    if (S.size() > before) dense.push_back(p);
+  }
+  hopf_status st = factor_batch(dense, S, s);
+  for (double* x : S) hipFree(x);
+  S.clear();
+  if (st) {
+    std::string m = g_err;
+    for (hopf_problem* p : made) free_problem(p);
+    return fail(st, "%s", m.c_str());
+  }
+  for (int i = 0; i < nprob; ++i) out[i] = made[i];
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_problem_destroy(hopf_problem_t p) {
+  if (!p) return HOPF_OK;
+  hipDeviceSynchronize();
+  free_problem(p);
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_problem_info(hopf_problem_t p, int32_t* n, int32_t* n_pad, int32_t* K,
+                                         int32_t* precision) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (n) *n = p->n;
+  if (n_pad) *n_pad = p->n_pad;
+  if (K) *K = p->K;
+  if (precision) *precision = p->precision;
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_problem_get_inverse(hopf_problem_t p, double* out) {
+  if (!p || !out) return fail(HOPF_EINVAL, "NULL argument");
+  std::vector<double> h((size_t)p->n_pad * p->n_pad);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(h.data(), p->d_Md, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i < p->n; ++i)
+    for (int j = 0; j < p->n; ++j) out[(size_t)i * p->n + j] = h[(size_t)i * p->n_pad + j];
+  return HOPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dense launches (one problem or a ragged batch)
+// ---------------------------------------------------------------------------
+struct DenseCall {
+  hopf_problem* p;
+  DenseProb view;
+};
+
+static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distance, hipStream_t stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace* w;
+  hopf_status st = ws_get(dev, &w);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(w->mu);
+  const int warmup = std::max(1, env_int("HOPF_WARMUP", 32));
+  const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
+  // tiles per column-width class
+  std::vector<int> classes;
+  for (auto& c : calls) {
+    int pt = dense_cols_per_tile(mode, c.p->n_pad);
+    if (std::find(classes.begin(), classes.end(), pt) == classes.end()) classes.push_back(pt);
+  }
+  std::sort(classes.begin(), classes.end(), [](int a, int b) { return a > b; });
+  for (int pt : classes) {
+    struct T { DenseTile t; double cost; };
+    std::vector<T> tl;
+    std::vector<DenseProb> views;
+    int max_npad = 32;
+    for (auto& c : calls) {
+      if (dense_cols_per_tile(mode, c.p->n_pad) != pt || c.view.npts == 0) continue;
+      const int q = (int)views.size();
+      views.push_back(c.view);
+      max_npad = std::max(max_npad, c.p->n_pad);
+      const int ppt = std::max(1, pt / c.p->K);
+      for (int64_t p0 = 0; p0 < c.view.npts; p0 += ppt) {
+        DenseTile t;
+        t.prob = q; t.pt0 = (int)p0; t.npt = (int)std::min<int64_t>(ppt, c.view.npts - p0); t.pad = 0;
+        tl.push_back({t, (double)c.p->n_pad * c.p->n_pad * t.npt * c.p->K});
+      }
+    }
+    if (tl.empty()) continue;
+    std::stable_sort(tl.begin(), tl.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+    const int ntiles = (int)tl.size();
+    const size_t vbytes = sizeof(DenseProb) * views.size();
+    const size_t off_t = (vbytes + 255) / 256 * 256;
+    std::vector<unsigned char> blob(off_t + sizeof(DenseTile) * ntiles);
+    std::memcpy(blob.data(), views.data(), vbytes);
+    for (int i = 0; i < ntiles; ++i) std::memcpy(blob.data() + off_t + i * sizeof(DenseTile), &tl[i].t, sizeof(DenseTile));
+    void* dmeta = nullptr;
+    if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
+    const int grid = std::min(ntiles, w->ncu);
+    const int64_t ws_per_wg = 4 * (int64_t)pt * max_npad;
+    if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
+    size_t lds = 0;
+    for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
+    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta,
+                                (const DenseTile*)((unsigned char*)dmeta + off_t), ntiles, w->state, ws_per_wg,
+                                grid, lds, distance, warmup, anchor_every, stream);
+    if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
+    // the next class reuses the metadata/staging buffers: wait for this launch to be enqueued
+    // and its metadata consumed before overwriting them
+    if (classes.size() > 1) HIP_TRY(hipStreamSynchronize(stream));
+  }
+  return HOPF_OK;
+}
+
+static DenseProb make_view(hopf_problem* p) {
+  DenseProb v;
+  std::memset(&v, 0, sizeof v);
+  v.n = p->n; v.n_pad = p->n_pad; v.K = p->K; v.level_set = p->level_set; v.hkind = p->hkind;
+  v.max_iter = p->max_iter; v.lambda = p->lambda; v.tol = p->tol;
+  v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.w = p->d_w; v.centres = p->d_centres;
+  v.max_newton = 50;
+  return v;
+}
+
+static int mode_of(hopf_problem* p) { return p->precision == HOPF_BF16_REFINED ? 1 : 0; }
+
+extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, const void* t, void* phi,
+                                 void* grad, void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (npts == 0) return HOPF_OK;
+  if (!x || !t || !phi || !grad || !dphidt) return fail(HOPF_EINVAL, "NULL array argument");
+  if (npts > ((int64_t)1 << 31) - 1) return fail(HOPF_EINVAL, "npts too large");
+  hipStream_t s = (hipStream_t)stream;
+  if (p->diagonal && p->n <= kDiagMaxN) {
+    DiagProb dp;
+    dp.n = p->n; dp.ld = p->n_pad; dp.K = p->K; dp.level_set = p->level_set; dp.hkind = p->hkind;
+    dp.max_iter = p->max_iter; dp.lambda = p->lambda; dp.tol = p->tol;
+    dp.minv = p->d_minv; dp.adiag = p->d_adiag; dp.w = p->d_w; dp.centres = p->d_centres;
+    dp.x = x; dp.t = t; dp.npts = npts; dp.phi = phi; dp.grad = grad; dp.dphidt = dphidt;
+    dp.iters = iters; dp.kstar = kstar;
+    hipError_t e = launch_diag(dp, p->precision == HOPF_F64, s);
+    if (e) return fail(HOPF_EDEVICE, "diag launch: %s", hipGetErrorString(e));
+    return HOPF_OK;
+  }
+  std::vector<DenseCall> calls(1);
+  calls[0].p = p;
+  DenseProb& v = calls[0].view;
+  v = make_view(p);
+  v.x = (const float*)x; v.t = (const float*)t; v.npts = npts;
+  v.phi = (float*)phi; v.grad = (float*)grad; v.dphidt = (float*)dphidt; v.iters = iters; v.kstar = kstar;
+  return run_dense(calls, mode_of(p), 0, s);
+}
+
+extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const void* y, double s_tol,
+                                          void* dist, void* cp, int32_t* kstar, int32_t* inside,
+                                          int32_t* newton, void* stream) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (!p->level_set) return fail(HOPF_EINVAL, "closest point needs an ellipsoid level-set problem (level_set = 1)");
+  if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "closest point needs HOPF_F32 or HOPF_BF16_REFINED");
+  if (!(s_tol > 0.0) || !std::isfinite(s_tol)) return fail(HOPF_EINVAL, "s_tol must be finite and > 0");
+  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (npts == 0) return HOPF_OK;
+  if (!y || !dist || !cp || !kstar) return fail(HOPF_EINVAL, "NULL array argument");
+  std::vector<DenseCall> calls(1);
+  calls[0].p = p;
+  DenseProb& v = calls[0].view;
+  v = make_view(p);
+  v.x = (const float*)y; v.npts = npts; v.grad = (float*)cp; v.kstar = kstar;
+  v.dist = (float*)dist; v.inside = inside; v.newton = newton; v.s_tol = s_tol;
+  return run_dense(calls, mode_of(p), 1, (hipStream_t)stream);
+}
+
+extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
+                                        const void* x_packed, const void* t, void* phi, void* grad_packed,
+                                        void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!probs || !pt_offset))) return fail(HOPF_EINVAL, "bad ragged arguments");
+  if (nprob == 0) return HOPF_OK;
+  if (!x_packed || !t || !phi || !grad_packed || !dphidt) return fail(HOPF_EINVAL, "NULL array argument");
+  const int prec = probs[0] ? probs[0]->precision : -1;
+  if (pt_offset[0] != 0) return fail(HOPF_EINVAL, "pt_offset[0] must be 0");
+  std::vector<DenseCall> calls;
+  int64_t xoff = 0;
+  for (int q = 0; q < nprob; ++q) {
+    hopf_problem* p = probs[q];
+    if (!p) return fail(HOPF_EINVAL, "problem %d is NULL", q);
+    if (p->precision != prec) return fail(HOPF_EINVAL, "problems of a ragged batch must share one precision");
+    if (prec == HOPF_F64) return fail(HOPF_EINVAL, "ragged batches need HOPF_F32 or HOPF_BF16_REFINED");
+    const int64_t np = pt_offset[q + 1] - pt_offset[q];
+    if (np < 0) return fail(HOPF_EINVAL, "pt_offset must be nondecreasing");
+    DenseCall c;
+    c.p = p;
+    c.view = make_view(p);
+    const int64_t g0 = pt_offset[q];
+    c.view.x = (const float*)x_packed + xoff;
+    c.view.t = (const float*)t + g0;
+    c.view.npts = np;
+    c.view.phi = (float*)phi + g0;
+    c.view.grad = (float*)grad_packed + xoff;
+    c.view.dphidt = (float*)dphidt + g0;
+    c.view.iters = iters ? iters + g0 : nullptr;
+    c.view.kstar = kstar ? kstar + g0 : nullptr;
+    xoff += np * p->n;
+    calls.push_back(c);
+  }
+  return run_dense(calls, prec == HOPF_BF16_REFINED ? 1 : 0, 0, (hipStream_t)stream);
+}
+
+extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void* gphi, const void* grad_saved,
+                                     const void* dphidt_saved, const int32_t* kstar_saved, void* gx, void* gt,
+                                     void* gA, void* gc, void* stream) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "backward needs HOPF_F32 or HOPF_BF16_REFINED");
+  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (npts > 0 && (!gphi || !grad_saved)) return fail(HOPF_EINVAL, "gphi and grad_saved are required");
+  if (gt && !dphidt_saved) return fail(HOPF_EINVAL, "gt needs dphidt_saved");
+  if (gc && p->K > 1 && !kstar_saved) return fail(HOPF_EINVAL, "gc needs kstar_saved when K > 1");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace* w;
+  hopf_status st = ws_get(dev, &w);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(w->mu);
+  const int nsplit = backward_splits(npts);
+  const size_t need = sizeof(double) * (size_t)nsplit * ((size_t)p->n * p->n + (size_t)p->K * p->n);
+  if ((st = ws_grow((void**)&w->scratch, &w->scratch_bytes, need))) return st;
+  BackwardArgs a;
+  a.npts = npts; a.n = p->n; a.K = p->K;
+  a.g = (const float*)gphi; a.grad = (const float*)grad_saved; a.dphidt = (const float*)dphidt_saved;
+  a.kstar = kstar_saved; a.gx = (float*)gx; a.gt = (float*)gt; a.gA = (float*)gA; a.gc = (float*)gc;
+  hipError_t e = launch_backward(a, w->scratch, (hipStream_t)stream);
+  if (e) return fail(HOPF_EDEVICE, "backward launch: %s", hipGetErrorString(e));
+  return HOPF_OK;
+}

@@ -1,0 +1,59 @@
+// Shared device/host definitions of the HIP library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hopf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;  // 4 waves per workgroup in every kernel of the library
+
+// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
+__device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
+
+// Per-column states of the dense solver.
+enum ColState : int {
+  COL_EMPTY = 0,    // padding column
+  COL_ACTIVE = 1,   // iterating
+  COL_WAITING = 2,  // converged (or capped): frozen, waits for an exact product before its value
+  COL_PHI = 3,      // this iteration evaluates phi from the exact product identity
+  COL_DONE = 4,     // value and gradient staged
+  COL_INVALID = 5   // non-finite input or t <= 0
+};
+
+// Hamiltonian kinds (same numbering as the public header).
+enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2 };
+__host__ __device__ inline bool hk_has_l1(int hk) { return hk == HK_WL1 || hk == HK_L2_WL1; }
+__host__ __device__ inline bool hk_has_l2(int hk) { return hk == HK_L2 || hk == HK_L2_WL1; }
+
+// Device-side view of one problem for the dense solver (one entry per problem of a launch).
+struct DenseProb {
+  int n, n_pad, K, level_set, hkind, max_iter;
+  double lambda, tol;
+  const __bf16* Mb;      // n_pad*n_pad BF16 copy of M = (A + lambda I)^{-1}
+  const float* Mf;       // n_pad*n_pad FP32 copy
+  const double* Md;      // n_pad*n_pad FP64
+  const double* w;       // n_pad weights (0 beyond n)
+  const double* centres; // K*n_pad (0 beyond n), or null
+  // per-call arrays (already offset to this problem's first point)
+  const float* x;        // npts*n
+  const float* t;        // npts (eval) ; unused for distance
+  int64_t npts;
+  float* phi; float* grad; float* dphidt; int32_t* iters; int32_t* kstar;
+  float* dist; int32_t* inside; int32_t* newton;
+  double s_tol;
+  int max_newton;
+};
+
+struct DenseTile {
+  int prob;   // index into the problem array
+  int pt0;    // first point of the tile (within the problem)
+  int npt;    // points in the tile
+  int pad;
+};
+
+}  // namespace hopf

@@ -1,0 +1,22 @@
+#pragma once
+#include "common.hpp"
+
+namespace hopf {
+
+constexpr int kDiagMaxN = 32;
+
+struct DiagProb {
+  int n, ld, K, level_set, hkind, max_iter;  // ld: stride of the centre rows
+  double lambda, tol;
+  const double* minv;     // n: 1 / (a_i + lambda)
+  const double* adiag;    // n: a_i
+  const double* w;        // n or null
+  const double* centres;  // K*ld or null
+  const void* x; const void* t;
+  int64_t npts;
+  void* phi; void* grad; void* dphidt; int32_t* iters; int32_t* kstar;
+};
+
+hipError_t launch_diag(const DiagProb& pb, bool f64, hipStream_t stream);
+
+}  // namespace hopf

@@ -1,0 +1,247 @@
+// Per-problem FP64 setup: M = (A + lambda I)^{-1} on the device.
+//
+// Update (3.4a) is the resolvent of the quadratic J*(p) = 1/2 p^T A p, i.e. a
+// solve with A + lambda I (section 4.1 gives the quadratic prox as
+// (I + alpha A)^{-1}).  The solver applies it to many right-hand sides per
+// iteration, so the inverse is formed once: block Gauss-Jordan elimination in
+// FP64 on S = A + lambda I (symmetric positive definite, so no pivoting is
+// needed and every pivot block is SPD), 32x32 blocks.  Each pivot block is
+// inverted through its Cholesky factor, which doubles as the positive-
+// definiteness test.  Problems of a batch are sorted by size so that the
+// problems still active at step s form a prefix of the list.
+#include "common.hpp"
+#include "setup.hpp"
+
+namespace hopf {
+
+constexpr int NB = 32;
+
+// Pivot block: P = S_KK^{-1} via Cholesky, one workgroup per problem.
+__global__ void __launch_bounds__(kBlock) gj_pivot_kernel(const SetupProb* probs, int nprob, int step) {
+  const int q = blockIdx.x;
+  if (q >= nprob) return;
+  const SetupProb pb = probs[q];
+  if (step * NB >= pb.n_pad) return;
+  __shared__ double a[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int k0 = step * NB;
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    a[i][j] = pb.S[(size_t)(k0 + i) * pb.n_pad + k0 + j];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double d = a[j][j];
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      a[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    if (tid > j && tid < NB) a[tid][j] /= a[j][j];
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += kBlock) {
+      int i = e / NB, k = e % NB;
+      if (k > j && i >= k) a[i][k] -= a[i][j] * a[k][j];
+    }
+    __syncthreads();
+  }
+  // X = L^{-1}, column c by forward substitution
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int m = c; m < i; ++m) s -= a[i][m] * X[m][c];
+      X[i][c] = (i < c) ? 0.0 : s / a[i][i];
+    }
+  }
+  __syncthreads();
+  // P = X^T X
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    double s = 0.0;
+    for (int m = 0; m < NB; ++m) s += X[m][i] * X[m][j];
+    pb.P[i * NB + j] = s;
+  }
+  if (tid == 0 && bad) *pb.status = 1;
+}
+
+// Panels: T = S[:, K] (copy of the old column panel), R = P * S[K, :] (new row panel).
+// Grid: one workgroup per (problem, 32-block b) flattened; problems sorted by size.
+__global__ void __launch_bounds__(kBlock) gj_panel_kernel(const SetupProb* probs, const int* blk_prefix,
+                                                          int nactive, int step) {
+  // find the problem of this block: blk_prefix[q] = sum_{r<q} nblocks_r over active problems
+  int b = blockIdx.x;
+  int lo = 0, hi = nactive;  // largest q with blk_prefix[q] <= b
+  while (hi - lo > 1) { int mid = (lo + hi) / 2; if (blk_prefix[mid] <= b) lo = mid; else hi = mid; }
+  const SetupProb pb = probs[lo];
+  b -= blk_prefix[lo];
+  const int ld = pb.n_pad, k0 = step * NB, r0 = b * NB;
+  __shared__ double P[NB][NB + 1];
+  __shared__ double Sk[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    P[i][j] = pb.P[i * NB + j];
+    Sk[i][j] = pb.S[(size_t)(k0 + i) * ld + r0 + j];     // S[K rows][block b cols]
+    pb.T[(size_t)(r0 + i) * NB + j] = pb.S[(size_t)(r0 + i) * ld + k0 + j];  // S[block b rows][K cols]
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    double s = 0.0;
+    for (int m = 0; m < NB; ++m) s += P[i][m] * Sk[m][j];
+    pb.R[(size_t)i * ld + r0 + j] = s;
+  }
+}
+
+// Trailing update of every 32x32 tile (bi, bj):
+//   bi != K, bj != K : S_ij -= T_i R_j ;  bj == K : S_iK = -T_i P ;  bi == K : S_Kj = R_j ;  S_KK = P.
+__global__ void __launch_bounds__(kBlock) gj_update_kernel(const SetupProb* probs, const int* tile_prefix,
+                                                           int nactive, int step) {
+  int b = blockIdx.x;
+  int lo = 0, hi = nactive;
+  while (hi - lo > 1) { int mid = (lo + hi) / 2; if (tile_prefix[mid] <= b) lo = mid; else hi = mid; }
+  const SetupProb pb = probs[lo];
+  b -= tile_prefix[lo];
+  const int ld = pb.n_pad, nb = pb.n_pad / NB, K = step;
+  const int bi = b / nb, bj = b % nb;
+  const int tid = threadIdx.x;
+  __shared__ double Ti[NB][NB + 1];
+  __shared__ double Rj[NB][NB + 1];
+  if (bi == K && bj == K) {
+    for (int e = tid; e < NB * NB; e += kBlock) {
+      int i = e / NB, j = e % NB;
+      pb.S[(size_t)(K * NB + i) * ld + K * NB + j] = pb.P[i * NB + j];
+    }
+    return;
+  }
+  if (bi == K) {
+    for (int e = tid; e < NB * NB; e += kBlock) {
+      int i = e / NB, j = e % NB;
+      pb.S[(size_t)(K * NB + i) * ld + bj * NB + j] = pb.R[(size_t)i * ld + bj * NB + j];
+    }
+    return;
+  }
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    Ti[i][j] = pb.T[(size_t)(bi * NB + i) * NB + j];
+    Rj[i][j] = (bj == K) ? pb.P[i * NB + j] : pb.R[(size_t)i * ld + bj * NB + j];
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += kBlock) {
+    int i = e / NB, j = e % NB;
+    double s = 0.0;
+    for (int m = 0; m < NB; ++m) s += Ti[i][m] * Rj[m][j];
+    double* dst = &pb.S[(size_t)(bi * NB + i) * ld + bj * NB + j];
+    *dst = (bj == K) ? -s : (*dst - s);
+  }
+}
+
+// S = A + lambda I (identity on the padding) from a dense FP64 A (n x n, row-major).
+__global__ void build_shifted_kernel(const double* A, int n, int n_pad, double lambda, double* S) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_pad * n_pad) return;
+  int i = (int)(e / n_pad), j = (int)(e % n_pad);
+  double v;
+  if (i < n && j < n) v = A[(size_t)i * n + j] + (i == j ? lambda : 0.0);
+  else v = (i == j) ? 1.0 : 0.0;
+  S[e] = v;
+}
+
+// M copies from the finished inverse: symmetrised, zero outside n x n.
+__global__ void finalize_copies_kernel(const double* S, int n, int n_pad, double* Md, float* Mf,
+                                       __bf16* Mb) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_pad * n_pad) return;
+  int i = (int)(e / n_pad), j = (int)(e % n_pad);
+  double v = 0.0;
+  if (i < n && j < n) v = 0.5 * (S[(size_t)i * n_pad + j] + S[(size_t)j * n_pad + i]);
+  if (Md) Md[e] = v;
+  if (Mf) Mf[e] = (float)v;
+  if (Mb) Mb[e] = to_bf16((float)v);
+}
+
+// Diagonal A: M = diag(1 / (a_i + lambda)).
+__global__ void diag_inverse_kernel(const double* a, int n, int n_pad, double lambda, double* Md,
+                                    float* Mf, __bf16* Mb, double* minv_diag) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_pad * n_pad) return;
+  int i = (int)(e / n_pad), j = (int)(e % n_pad);
+  double v = (i == j && i < n) ? 1.0 / (a[i] + lambda) : 0.0;
+  if (Md) Md[e] = v;
+  if (Mf) Mf[e] = (float)v;
+  if (Mb) Mb[e] = to_bf16((float)v);
+  if (minv_diag && i == j && i < n) minv_diag[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host driver for a batch of dense problems (already sorted by n_pad, descending).
+// ---------------------------------------------------------------------------
+hipError_t run_gauss_jordan(const SetupProb* d_probs, const int* h_nblocks, int nprob, int* d_prefix,
+                            int* h_prefix, hipStream_t stream) {
+  // h_prefix / d_prefix hold, for every step s, the block and tile prefix sums over the
+  // problems still active at s (sizes: steps * 2 * (nprob + 1)).  One blocking copy.
+  if (nprob == 0) return hipSuccess;
+  const int max_steps = h_nblocks[0];
+  const size_t stride = 2 * (size_t)(nprob + 1);
+  for (int s = 0; s < max_steps; ++s) {
+    int* hb = h_prefix + s * stride;
+    int* ht = hb + nprob + 1;
+    hb[0] = 0; ht[0] = 0;
+    for (int q = 0; q < nprob; ++q) {
+      int a = h_nblocks[q] > s ? 1 : 0;
+      hb[q + 1] = hb[q] + a * h_nblocks[q];
+      ht[q + 1] = ht[q] + a * h_nblocks[q] * h_nblocks[q];
+    }
+  }
+  hipError_t e = hipMemcpyAsync(d_prefix, h_prefix, sizeof(int) * stride * max_steps,
+                                hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(stream);  // h_prefix may be reused by the caller after return
+  if (e != hipSuccess) return e;
+  for (int s = 0; s < max_steps; ++s) {
+    int nactive = 0;
+    while (nactive < nprob && h_nblocks[nactive] > s) ++nactive;
+    const int* hb = h_prefix + s * stride;
+    const int* ht = hb + nprob + 1;
+    const int* db = d_prefix + s * stride;
+    const int* dt = db + nprob + 1;
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(nactive), dim3(kBlock), 0, stream, d_probs, nactive, s);
+    hipLaunchKernelGGL(gj_panel_kernel, dim3(hb[nactive]), dim3(kBlock), 0, stream, d_probs, db,
+                       nactive, s);
+    hipLaunchKernelGGL(gj_update_kernel, dim3(ht[nactive]), dim3(kBlock), 0, stream, d_probs, dt,
+                       nactive, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_build_shifted(const double* A, int n, int n_pad, double lambda, double* S,
+                                hipStream_t stream) {
+  int64_t tot = (int64_t)n_pad * n_pad;
+  hipLaunchKernelGGL(build_shifted_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
+                     A, n, n_pad, lambda, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_copies(const double* S, int n, int n_pad, double* Md, float* Mf, __bf16* Mb,
+                                  hipStream_t stream) {
+  int64_t tot = (int64_t)n_pad * n_pad;
+  hipLaunchKernelGGL(finalize_copies_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
+                     S, n, n_pad, Md, Mf, Mb);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_inverse(const double* a, int n, int n_pad, double lambda, double* Md, float* Mf,
+                               __bf16* Mb, double* minv_diag, hipStream_t stream) {
+  int64_t tot = (int64_t)n_pad * n_pad;
+  hipLaunchKernelGGL(diag_inverse_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
+                     a, n, n_pad, lambda, Md, Mf, Mb, minv_diag);
+  return hipGetLastError();
+}
+
+}  // namespace hopf

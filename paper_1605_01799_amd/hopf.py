@@ -1,0 +1,247 @@
+"""Python binding of the C ABI.  PyTorch provides device memory and streams;
+every step of the solver runs in the HIP library (libhopf.so).
+
+    prob = Problem(A, hkind="l2_wl1", w=w, precision="bf16_refined", tol=1e-12)
+    out = prob.eval(x, t)          # x: (npts, n) float32 cuda tensor, t: (npts,)
+    out["phi"], out["grad"], out["dphidt"], out["iters"], out["kstar"]
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _stream_ptr(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _host64(a, shape=None):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _device_array(a: torch.Tensor, dtype, name, shape):
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if a.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, a.dtype))
+    if tuple(a.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(a.shape), tuple(shape)))
+    return a.contiguous()
+
+
+class Problem:
+    """One problem: J(y) = 1/2 y^T A^{-1} y (or the min over K translated copies / ellipsoid
+    level sets c_k + {u^T A^{-1} u <= 1}), H in {"wl1", "l2", "l2_wl1"} with weights w."""
+
+    def __init__(self, A=None, *, n: Optional[int] = None, diagonal: bool = False, centres=None,
+                 level_set: bool = False, hkind: str = "wl1", w=None, lam: float = 1.0,
+                 tol: float = 1e-12, max_iter: int = 20000, precision: str = "bf16_refined",
+                 stream=None, _handle=None):
+        self._lib = _lib.load()
+        A64 = _host64(A)
+        if n is None:
+            if A64 is None:
+                raise ValueError("give A or n")
+            n = A64.shape[0]
+        if A64 is not None:
+            if diagonal:
+                A64 = A64.reshape(n)
+            else:
+                A64 = A64.reshape(n, n)
+        self.n = int(n)
+        self.diagonal = bool(diagonal) or A64 is None
+        self.A = A64
+        self.centres = _host64(centres, (-1, self.n)) if centres is not None else None
+        self.K = 1 if self.centres is None else self.centres.shape[0]
+        self.level_set = bool(level_set)
+        self.hkind = hkind
+        self.w = _host64(w, (self.n,)) if w is not None else None
+        self.lam, self.tol, self.max_iter = float(lam), float(tol), int(max_iter)
+        self.precision = precision
+        self.io_dtype = torch.float64 if precision == "f64" else torch.float32
+        self._handle = None
+        if _handle is not None:
+            self._handle = _handle
+            return
+        h = ctypes.c_void_p()
+        desc = self._desc()
+        check(self._lib.hopf_problem_create(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(h)))
+        self._handle = h
+
+    def _desc(self):
+        return _lib.ProblemDesc(
+            self.n, None if self.A is None else self.A.ctypes.data, int(self.diagonal), self.K,
+            None if self.centres is None else self.centres.ctypes.data, int(self.level_set),
+            _lib.HKIND[self.hkind], None if self.w is None else self.w.ctypes.data, self.lam, self.tol,
+            self.max_iter, _lib.PRECISION[self.precision])
+
+    @classmethod
+    def batch(cls, specs: Sequence[dict], stream=None):
+        """Create many problems with one batched factorisation (ragged batches)."""
+        lib = _lib.load()
+        objs = [cls.__new__(cls) for _ in specs]
+        descs = (_lib.ProblemDesc * len(specs))()
+        for o, s, i in zip(objs, specs, range(len(specs))):
+            cls.__init__(o, **s, _handle=ctypes.c_void_p(0))
+            descs[i] = o._desc()
+        out = (ctypes.c_void_p * len(specs))()
+        check(lib.hopf_problem_create_batch(len(specs), descs, _stream_ptr(stream), out))
+        for o, i in zip(objs, range(len(specs))):
+            o._handle = ctypes.c_void_p(out[i])
+        return objs
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                self._lib.hopf_problem_destroy(h)
+            except Exception:
+                pass
+            self._handle = None
+
+    # ------------------------------------------------------------------ calls
+    def eval(self, x: torch.Tensor, t: torch.Tensor, stream=None, out=None):
+        npts = x.shape[0]
+        x = _device_array(x, self.io_dtype, "x", (npts, self.n))
+        t = _device_array(t, self.io_dtype, "t", (npts,))
+        dev = x.device
+        if out is None:
+            out = dict(
+                phi=torch.empty(npts, dtype=self.io_dtype, device=dev),
+                grad=torch.empty(npts, self.n, dtype=self.io_dtype, device=dev),
+                dphidt=torch.empty(npts, dtype=self.io_dtype, device=dev),
+                iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                kstar=torch.empty(npts, dtype=torch.int32, device=dev),
+            )
+        check(self._lib.hopf_eval(self._handle, npts, _ptr(x), _ptr(t), _ptr(out["phi"]), _ptr(out["grad"]),
+                                  _ptr(out["dphidt"]), _ptr(out["iters"]), _ptr(out["kstar"]),
+                                  _stream_ptr(stream)))
+        return out
+
+    def closest_point(self, y: torch.Tensor, s_tol: float = 1e-6, stream=None):
+        npts = y.shape[0]
+        y = _device_array(y, torch.float32, "y", (npts, self.n))
+        dev = y.device
+        out = dict(
+            dist=torch.empty(npts, dtype=torch.float32, device=dev),
+            cp=torch.empty(npts, self.n, dtype=torch.float32, device=dev),
+            kstar=torch.empty(npts, dtype=torch.int32, device=dev),
+            inside=torch.empty(npts, dtype=torch.int32, device=dev),
+            newton=torch.empty(npts, dtype=torch.int32, device=dev),
+        )
+        check(self._lib.hopf_closest_point(self._handle, npts, _ptr(y), float(s_tol), _ptr(out["dist"]),
+                                           _ptr(out["cp"]), _ptr(out["kstar"]), _ptr(out["inside"]),
+                                           _ptr(out["newton"]), _stream_ptr(stream)))
+        return out
+
+    def backward(self, gphi, grad, dphidt, kstar=None, want=("gx", "gt", "gA", "gc"), stream=None):
+        npts = grad.shape[0]
+        dev = grad.device
+        gphi = _device_array(gphi, torch.float32, "gphi", (npts,))
+        grad = _device_array(grad, torch.float32, "grad", (npts, self.n))
+        dphidt = _device_array(dphidt, torch.float32, "dphidt", (npts,))
+        out = {}
+        if "gx" in want:
+            out["gx"] = torch.empty(npts, self.n, dtype=torch.float32, device=dev)
+        if "gt" in want:
+            out["gt"] = torch.empty(npts, dtype=torch.float32, device=dev)
+        if "gA" in want:
+            out["gA"] = torch.empty(self.n, self.n, dtype=torch.float32, device=dev)
+        if "gc" in want:
+            out["gc"] = torch.empty(self.K, self.n, dtype=torch.float32, device=dev)
+        check(self._lib.hopf_backward(self._handle, npts, _ptr(gphi), _ptr(grad), _ptr(dphidt), _ptr(kstar),
+                                      _ptr(out.get("gx")), _ptr(out.get("gt")), _ptr(out.get("gA")),
+                                      _ptr(out.get("gc")), _stream_ptr(stream)))
+        return out
+
+    def inverse(self) -> np.ndarray:
+        out = np.empty((self.n, self.n))
+        check(self._lib.hopf_problem_get_inverse(self._handle, out.ctypes.data))
+        return out
+
+    def info(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(self._lib.hopf_problem_info(self._handle, *[ctypes.byref(x) for x in v]))
+        return dict(n=v[0].value, n_pad=v[1].value, K=v[2].value, precision=v[3].value)
+
+
+def eval_ragged(problems: Sequence[Problem], xs: Sequence[torch.Tensor], ts: Sequence[torch.Tensor],
+                stream=None):
+    """Evaluate a ragged batch (each problem its own n, A, K, w; points packed) in one call."""
+    lib = _lib.load()
+    nprob = len(problems)
+    counts = [int(x.shape[0]) for x in xs]
+    off = np.zeros(nprob + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    x_packed = torch.cat([x.reshape(-1) for x in xs]).contiguous()
+    t_all = torch.cat(list(ts)).contiguous()
+    dev = x_packed.device
+    tot = int(off[-1])
+    phi = torch.empty(tot, dtype=torch.float32, device=dev)
+    grad = torch.empty_like(x_packed)
+    dphidt = torch.empty(tot, dtype=torch.float32, device=dev)
+    iters = torch.empty(tot, dtype=torch.int32, device=dev)
+    kstar = torch.empty(tot, dtype=torch.int32, device=dev)
+    handles = (ctypes.c_void_p * nprob)(*[p._handle.value for p in problems])
+    offs = (ctypes.c_int64 * (nprob + 1))(*off.tolist())
+    check(lib.hopf_eval_ragged(nprob, handles, offs, _ptr(x_packed), _ptr(t_all), _ptr(phi), _ptr(grad),
+                               _ptr(dphidt), _ptr(iters), _ptr(kstar), _stream_ptr(stream)))
+    grads, o = [], 0
+    for p, c in zip(problems, counts):
+        grads.append(grad[o:o + c * p.n].view(c, p.n))
+        o += c * p.n
+    return dict(phi=phi, grad=grads, dphidt=dphidt, iters=iters, kstar=kstar, offsets=off)
+
+
+class HopfValue(torch.autograd.Function):
+    """phi(x, t; A, centres) with envelope-theorem gradients wrt x, t, A and centres.
+    Only phi is differentiable; grad and dphidt are returned detached."""
+
+    @staticmethod
+    def forward(ctx, x, t, A, centres, problem: Problem):
+        out = problem.eval(x.detach(), t.detach())
+        ctx.problem = problem
+        ctx.save_for_backward(out["grad"], out["dphidt"], out["kstar"])
+        ctx.mark_non_differentiable(out["grad"], out["dphidt"])
+        return out["phi"], out["grad"], out["dphidt"]
+
+    @staticmethod
+    def backward(ctx, gphi, _g1, _g2):
+        grad, dphidt, kstar = ctx.saved_tensors
+        prob = ctx.problem
+        want = []
+        if ctx.needs_input_grad[0]:
+            want.append("gx")
+        if ctx.needs_input_grad[1]:
+            want.append("gt")
+        if ctx.needs_input_grad[2]:
+            want.append("gA")
+        if ctx.needs_input_grad[3]:
+            want.append("gc")
+        b = prob.backward(gphi.contiguous().float(), grad, dphidt, kstar, want=tuple(want))
+        gA = b.get("gA")
+        gc = b.get("gc")
+        return b.get("gx"), b.get("gt"), gA, gc, None
+
+
+def hopf_value(x, t, A, centres, problem: Problem):
+    return HopfValue.apply(x, t, A, centres, problem)
