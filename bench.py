@@ -1,0 +1,153 @@
+"""Benchmark of the Hopf evaluation hot path on one MI355X.
+
+Workload (default): n = 1024, dense SPD A = Q diag(s) Q^T (Q Haar, s log-uniform [0.1, 10]),
+H = ||p||_2 + sum w_i |p_i| (w ~ U(0.5, 2)), 2^16 points x ~ N(0, 4I), t ~ U(0.05, 3), FP32
+inputs, BF16 MFMA products refined by FP64-exact anchor products.  One step = the whole path
+for one batch: problem set-up (FP64 inverse of A + lambda I on the device), the split-Bregman
+evaluation of every point (phi, grad phi, dphi/dt) and the release of the problem.
+
+Prints one JSON line (rank 0) with the throughput, the roofline of the dominant kernel
+(measured with HIP events on the launch stream), the accuracy against the FP64 oracle on a
+sample, and the oracle's own rate on a bounded sample of the same workload (CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (matrix)
+METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % roofline"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "f32"])
+    ap.add_argument("--npts", type=int, default=1 << 16)
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--acc-sample", type=int, default=48)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU only (the workload is one GPU's share; "
+              "see the sharding notes in DESIGN.md); --gpus %d is not supported" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1605_01799_amd import hopf as H
+    from paper_1605_01799_amd import workloads as W
+
+    tol = a.tol if a.tol is not None else (1e-12 if a.precision == "bf16_refined" else 1e-10)
+    p = W.round_inputs(W.workload3(npts=a.npts))
+    n, npts = p.n, p.npts
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(p.x).to(dev)
+    t = torch.from_numpy(p.t).to(dev)
+    stream = torch.cuda.current_stream()
+    out = dict(phi=torch.empty(npts, device=dev), grad=torch.empty(npts, n, device=dev),
+               dphidt=torch.empty(npts, device=dev), iters=torch.empty(npts, dtype=torch.int32, device=dev),
+               kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+    kw = dict(hkind="l2_wl1", w=p.w, tol=tol, max_iter=20000, precision=a.precision)
+
+    def step(ev=None):
+        prob = H.Problem(p.A, **kw)
+        if ev is not None:
+            ev[0].record(stream)
+        prob.eval(x, t, out=out)
+        if ev is not None:
+            ev[1].record(stream)
+        del prob          # hopf_problem_destroy
+        return
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    eval_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    value = npts / (ms_per_step / 1e3)
+
+    iters = out["iters"].cpu().numpy()
+    if np.any(iters <= 0):
+        print("warning: %d points did not converge" % int(np.sum(iters <= 0)), file=sys.stderr)
+    flops = float(np.sum(np.maximum(iters, 0)).astype(np.float64) * 2.0 * n * n)
+    achieved = flops / (eval_ms / 1e3) / 1e12
+    peak = BF16_PEAK_TFLOPS if a.precision == "bf16_refined" else FP32_PEAK_TFLOPS
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "point-evals/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16" if a.precision == "bf16_refined" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "n=1024 dense SPD A, H=l2+weighted l1, 2^16 points x~N(0,4I), t~U(0.05,3), "
+                               "FP32 inputs, split Bregman lambda=1; step = FP64 set-up + evaluation",
+                   "n": n, "npts": npts, "tol": tol, "precision": a.precision,
+                   "products": "BF16 MFMA on increments + FP64 MFMA anchors" if a.precision == "bf16_refined"
+                   else "FP32 MFMA"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "dense_kernel (one launch per step)",
+                     "algorithmic": "sum over points of iterations x 2 n^2 FLOP",
+                     "flop_per_launch": flops, "launch_ms": eval_ms},
+        "eval_only": {"ms": eval_ms, "value": npts / (eval_ms / 1e3)},
+        "iterations": {"mean": float(iters.mean()), "p50": float(np.median(iters)),
+                       "p99": float(np.percentile(iters, 99)), "max": int(iters.max())},
+    }
+
+    # accuracy on a sample against the FP64 oracle (tight tolerance), and the CPU baseline
+    try:
+        import oracle
+        oracle.build(force=not oracle.available())
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample, npts), replace=False))
+        xs = p.x[idx].astype(np.float64)
+        ts = p.t[idx].astype(np.float64)
+        threads = min(16, os.cpu_count() or 1)
+        ref = oracle.oracle_eval(p.A, xs, ts, "l2_wl1", w=p.w, tol=1e-28, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ph = out["phi"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        ef = np.abs(ph - ref["phi"]) / np.maximum(np.abs(ref["phi"]), 1)
+        rec["accuracy"] = {"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()),
+                           "max_rel_err_phi": float(ef.max()), "bound": 1e-6,
+                           "ok": bool(ep.max() <= 1e-6 and ef.max() <= 1e-6)}
+        if not a.no_cpu:
+            m = min(a.cpu_sample, npts)
+            xs = p.x[:m].astype(np.float64)
+            ts = p.t[:m].astype(np.float64)
+            c0 = time.perf_counter()
+            oracle.oracle_eval(p.A, xs, ts, "l2_wl1", w=p.w, tol=tol, nthreads=threads)
+            c1 = time.perf_counter()
+            rec["cpu_baseline"] = {"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads,
+                                   "kind": "oracle",
+                                   "sample": "first %d points of the same workload, same tol (%g), FP64 "
+                                             "oracle (triangular solves, compensated sums), %d threads"
+                                             % (m, tol, threads)}
+    except Exception as e:  # the oracle is test infrastructure; its absence only drops these fields
+        rec["accuracy_error"] = str(e)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

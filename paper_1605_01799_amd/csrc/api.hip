@@ -54,6 +54,7 @@ struct hopf_problem {
   int n = 0, n_pad = 0, K = 1, level_set = 0, hkind = 0, precision = 0, diagonal = 0, max_iter = 1;
   double lambda = 1.0, tol = 0.0;
   double* d_w = nullptr;        // n_pad
+  float* d_wf = nullptr;        // n_pad, FP32 copy
   double* d_centres = nullptr;  // K*n_pad (null if all centres are 0 and K == 1)
   double* d_Md = nullptr;       // n_pad^2
   float* d_Mf = nullptr;        // n_pad^2 (F32 precision)
@@ -68,6 +69,9 @@ struct hopf_problem {
 struct Workspace {
   std::mutex mu;
   float* state = nullptr; size_t state_bytes = 0;
+  double* state64 = nullptr; size_t state64_bytes = 0;
+  unsigned char* best = nullptr; size_t best_bytes = 0;   // per-point best value (double) + copy (int32)
+  int* counter = nullptr;
   unsigned char* meta = nullptr; size_t meta_bytes = 0;
   double* scratch = nullptr; size_t scratch_bytes = 0;
   unsigned char* pinned = nullptr; size_t pinned_bytes = 0;
@@ -174,7 +178,7 @@ static hopf_status validate(const hopf_problem_desc* d) {
 }
 
 static void free_problem(hopf_problem* p) {
-  hipFree(p->d_w); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
+  hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
   hipFree(p->d_adiag); hipFree(p->d_minv);
   delete p;
 }
@@ -202,6 +206,13 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   if (e) return bail(fail(HOPF_ENOMEM, "hipMalloc w"));
   e = hipMemcpy(p->d_w, hw.data(), sizeof(double) * n_pad, hipMemcpyHostToDevice);
   if (e) return bail(fail(HOPF_EDEVICE, "copy w: %s", hipGetErrorString(e)));
+  {
+    std::vector<float> hwf(n_pad);
+    for (int i = 0; i < n_pad; ++i) hwf[i] = (float)hw[i];
+    if (hipMalloc(&p->d_wf, sizeof(float) * n_pad)) return bail(fail(HOPF_ENOMEM, "hipMalloc wf"));
+    if (hipMemcpy(p->d_wf, hwf.data(), sizeof(float) * n_pad, hipMemcpyHostToDevice))
+      return bail(fail(HOPF_EDEVICE, "copy wf"));
+  }
   if (d->centres) {
     std::vector<double> hc((size_t)d->K * n_pad, 0.0);
     for (int k = 0; k < d->K; ++k)
@@ -385,54 +396,82 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   hopf_status st = ws_get(dev, &w);
   if (st) return st;
   std::lock_guard<std::mutex> lk(w->mu);
-  const int warmup = std::max(1, env_int("HOPF_WARMUP", 32));
   const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
-  // tiles per column-width class
+  if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
+  // per-point best arrays for every point of the call
+  int64_t tot = 0;
+  for (auto& c : calls) tot += c.view.npts;
+  if ((st = ws_grow((void**)&w->best, &w->best_bytes, (sizeof(double) + sizeof(int32_t)) * (size_t)std::max<int64_t>(tot, 1))))
+    return st;
+  double* bestv = (double*)w->best;
+  int32_t* bestk = (int32_t*)(w->best + sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
+  {
+    int64_t o = 0;
+    for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
+  }
+  // one launch per column-width class (problems whose padded size gives the same slots per tile)
   std::vector<int> classes;
   for (auto& c : calls) {
     int pt = dense_cols_per_tile(mode, c.p->n_pad);
-    if (std::find(classes.begin(), classes.end(), pt) == classes.end()) classes.push_back(pt);
+    if (c.view.npts > 0 && std::find(classes.begin(), classes.end(), pt) == classes.end()) classes.push_back(pt);
   }
   std::sort(classes.begin(), classes.end(), [](int a, int b) { return a > b; });
+  int cls = 0;
   for (int pt : classes) {
-    struct T { DenseTile t; double cost; };
-    std::vector<T> tl;
     std::vector<DenseProb> views;
+    std::vector<std::pair<double, int>> order;  // (cost, view index)
     int max_npad = 32;
     for (auto& c : calls) {
       if (dense_cols_per_tile(mode, c.p->n_pad) != pt || c.view.npts == 0) continue;
-      const int q = (int)views.size();
+      order.push_back({(double)c.p->n_pad * c.p->n_pad * c.p->K * (double)c.view.npts, (int)views.size()});
       views.push_back(c.view);
       max_npad = std::max(max_npad, c.p->n_pad);
-      const int ppt = std::max(1, pt / c.p->K);
-      for (int64_t p0 = 0; p0 < c.view.npts; p0 += ppt) {
-        DenseTile t;
-        t.prob = q; t.pt0 = (int)p0; t.npt = (int)std::min<int64_t>(ppt, c.view.npts - p0); t.pad = 0;
-        tl.push_back({t, (double)c.p->n_pad * c.p->n_pad * t.npt * c.p->K});
+    }
+    // largest problems first; chunks of whole points, about one tile of columns each
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+      return a.first > b.first;
+    });
+    std::vector<DenseChunk> ch;
+    for (auto& o : order) {
+      const DenseProb& v = views[o.second];
+      const int ppc = std::max(1, pt / v.K);
+      for (int64_t p0 = 0; p0 < v.npts; p0 += ppc) {
+        DenseChunk c;
+        c.prob = o.second;
+        c.col0 = (int)(p0 * v.K);
+        c.ncols = (int)(std::min<int64_t>(ppc, v.npts - p0) * v.K);
+        c.pad = 0;
+        ch.push_back(c);
       }
     }
-    if (tl.empty()) continue;
-    std::stable_sort(tl.begin(), tl.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
-    const int ntiles = (int)tl.size();
+    const int nchunks = (int)ch.size();
     const size_t vbytes = sizeof(DenseProb) * views.size();
-    const size_t off_t = (vbytes + 255) / 256 * 256;
-    std::vector<unsigned char> blob(off_t + sizeof(DenseTile) * ntiles);
+    const size_t off_c = (vbytes + 255) / 256 * 256;
+    std::vector<unsigned char> blob(off_c + sizeof(DenseChunk) * nchunks);
     std::memcpy(blob.data(), views.data(), vbytes);
-    for (int i = 0; i < ntiles; ++i) std::memcpy(blob.data() + off_t + i * sizeof(DenseTile), &tl[i].t, sizeof(DenseTile));
+    std::memcpy(blob.data() + off_c, ch.data(), sizeof(DenseChunk) * nchunks);
     void* dmeta = nullptr;
     if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
-    const int grid = std::min(ntiles, w->ncu);
+    const int grid = std::min(nchunks, w->ncu);
     const int64_t ws_per_wg = 4 * (int64_t)pt * max_npad;
+    const int64_t ws64_per_wg = (int64_t)pt * max_npad;
     if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
+    if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * ws64_per_wg * grid))) return st;
     size_t lds = 0;
     for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
-    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta,
-                                (const DenseTile*)((unsigned char*)dmeta + off_t), ntiles, w->state, ws_per_wg,
-                                grid, lds, distance, warmup, anchor_every, stream);
+    int* counter = w->counter + cls;
+    // reset the counter, and the best arrays of this class's problems
+    for (auto& v : views) {
+      hipError_t e = launch_reset(counter, v.bestv, v.bestk, v.npts, stream);
+      if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
+    }
+    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta, (const DenseChunk*)((unsigned char*)dmeta + off_c),
+                                nchunks, counter, w->state, w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance,
+                                anchor_every, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
-    // the next class reuses the metadata/staging buffers: wait for this launch to be enqueued
-    // and its metadata consumed before overwriting them
-    if (classes.size() > 1) HIP_TRY(hipStreamSynchronize(stream));
+    ++cls;
+    // the next class reuses the metadata/staging buffers and the workspace: wait for this one
+    if (cls < (int)classes.size()) HIP_TRY(hipStreamSynchronize(stream));
   }
   return HOPF_OK;
 }
@@ -442,7 +481,7 @@ static DenseProb make_view(hopf_problem* p) {
   std::memset(&v, 0, sizeof v);
   v.n = p->n; v.n_pad = p->n_pad; v.K = p->K; v.level_set = p->level_set; v.hkind = p->hkind;
   v.max_iter = p->max_iter; v.lambda = p->lambda; v.tol = p->tol;
-  v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.w = p->d_w; v.centres = p->d_centres;
+  v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.w = p->d_w; v.wf = p->d_wf; v.centres = p->d_centres;
   v.max_newton = 50;
   return v;
 }

@@ -10,6 +10,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
+
+// Global-memory views of generic pointers.  Pointers read out of structures in memory are
+// generic ("flat") to the compiler; flat loads count against both the memory and the LDS
+// wait counters, which serialises loads with LDS traffic.  Casting them to the global address
+// space gives global loads, which the compiler can keep in flight.
+#define HOPF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const HOPF_GLOBAL T* gp(const T* p) { return (const HOPF_GLOBAL T*)p; }
+template <typename T>
+__device__ __forceinline__ HOPF_GLOBAL T* gp(T* p) { return (HOPF_GLOBAL T*)p; }
 constexpr int kBlock = 256;  // 4 waves per workgroup in every kernel of the library
 
 // Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
@@ -38,6 +48,7 @@ struct DenseProb {
   const float* Mf;       // n_pad*n_pad FP32 copy
   const double* Md;      // n_pad*n_pad FP64
   const double* w;       // n_pad weights (0 beyond n)
+  const float* wf;       // the same weights in FP32 (thresholds of the per-iteration increments)
   const double* centres; // K*n_pad (0 beyond n), or null
   // per-call arrays (already offset to this problem's first point)
   const float* x;        // npts*n
@@ -47,12 +58,15 @@ struct DenseProb {
   float* dist; int32_t* inside; int32_t* newton;
   double s_tol;
   int max_newton;
+  // per-point best value over the K copies found so far (workspace, reset before every call)
+  double* bestv; int32_t* bestk;
 };
 
-struct DenseTile {
-  int prob;   // index into the problem array
-  int pt0;    // first point of the tile (within the problem)
-  int npt;    // points in the tile
+// A run of columns (col = point * K + k) of one problem; always whole points.
+struct DenseChunk {
+  int prob;
+  int col0;
+  int ncols;
   int pad;
 };
 

@@ -44,24 +44,23 @@ namespace hopf {
 constexpr int kMaxCols = 64;
 constexpr int kNRed = 6;  // step^2, |s|^2 increment, <x',d>, (2d-v).(r-lam v), sum w|d|, |d|^2
 
-struct ColShared {
-  double t[kMaxCols], th1[kMaxCols], th2[kMaxCols], gam[kMaxCols], gama[kMaxCols], dgam[kMaxCols];
-  double ssa2[kMaxCols], ssq[kMaxCols], prev[kMaxCols], s[kMaxCols], phi[kMaxCols], hp[kMaxCols];
-  double pn[kMaxCols];
-  int j[kMaxCols], k[kMaxCols], state[kMaxCols], iters[kMaxCols], newton[kMaxCols], flags[kMaxCols];
-  double red[4][kMaxCols][kNRed];
-  int ctl[8];
-};
-enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8 };
-enum { CTL_ANCHOR = 0, CTL_PHASE = 1, CTL_LAST_ANCHOR = 2, CTL_FINISH = 3 };
-enum { PHASE_WARMUP = 0, PHASE_DELTA = 1 };
+// Per-slot state accesses (global address space; the resident slots' state is sized to stay in
+// the last-level cache, so ordinary cached accesses are used).
+__device__ __forceinline__ f32x4 ld_nt4(const float* p) { return *gp((const f32x4*)p); }
+__device__ __forceinline__ void st_nt4(float* p, f32x4 v) { *gp((f32x4*)p) = v; }
+__device__ __forceinline__ float ld_nt(const float* p) { return *gp(p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { *gp(p) = v; }
+__device__ __forceinline__ double ld_nt(const double* p) { return *gp(p); }
+__device__ __forceinline__ void st_nt(double* p, double v) { *gp(p) = v; }
 
 __device__ __forceinline__ float clampf(float z, float lo, float hi) { return fminf(fmaxf(z, lo), hi); }
-__device__ __forceinline__ float theta_i(double th1, const double* w, int i) { return (float)(th1 * w[i]); }
+// FP32 threshold of coordinate i, used for the per-iteration increments (every use of a slot's
+// threshold goes through this one formula, so all of them agree bit for bit).
+__device__ __forceinline__ float theta_f(float th1f, float wf) { return th1f * wf; }
 // shrink1 of an anchor value in FP64 with the FP64 threshold: the anchor reference d^a must be
 // exact, since every increment of the following iterations is measured from it.
 __device__ __forceinline__ double anchor_shrink(float za, double th1, const double* w, int i) {
-  const double z = (double)za, th = th1 * w[i];
+  const double z = (double)za, th = th1 * *gp(w + i);
   return z - fmin(fmax(z, -th), th);
 }
 
@@ -72,35 +71,47 @@ struct Dense {
 
   // ---------------------------------------------------------------- GEMM pieces
   // acc[r][c] += M[16 rt_r .. , :] * B[:, 16 c ..] over the full contraction.
+  // All RG row tiles are always computed (a row-tile index past the end is clamped to tile 0 and
+  // its result discarded by the caller), so the MFMA stream has no branches.
   static __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pad,
                                                    const __bf16* B, int ldb, const int* rt, int nrt,
                                                    f32x4 (&acc)[RG][CT]) {
+    // A fragments (rows of M, L2-resident) stream with three k-steps in flight; B is in LDS.
     const int l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
-    const __bf16* arow[RG];
+    const HOPF_GLOBAL bf16x8* arow[RG];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) arow[r] = M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 8 * lg;
-    const __bf16* bcol = B + lr * ldb + 8 * lg;
-    bf16x8 a0[RG], a1[RG];
+    for (int r = 0; r < RG; ++r)
+      arow[r] = gp((const bf16x8*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 8 * lg));
+    const bf16x8* bcol = (const bf16x8*)(B + lr * ldb + 8 * lg);
+    const int bstride = 16 * ldb / 8;  // in bf16x8 units
+    const int nk = n_pad >> 5;
+    bf16x8 a[4][RG];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) a0[r] = *(const bf16x8*)(arow[r]);
-    for (int k0 = 0; k0 < n_pad; k0 += 32) {
-      const bool more = k0 + 32 < n_pad;
+    for (int u = 0; u < 3; ++u)
+      if (u < nk) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
-        if (more) a1[r] = *(const bf16x8*)(arow[r] + k0 + 32);
-      bf16x8 b[CT];
+        for (int r = 0; r < RG; ++r) a[u][r] = arow[r][4 * u];
+      }
+    for (int ks = 0; ks < nk; ks += 4) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = *(const bf16x8*)(bcol + 16 * c * ldb + k0);
+      for (int u = 0; u < 4; ++u) {
+        const int kk = ks + u;
+        if (kk < nk) {
+          if (kk + 3 < nk) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
-        if (r < nrt) {
+            for (int r = 0; r < RG; ++r) a[(u + 3) & 3][r] = arow[r][4 * (kk + 3)];
+          }
+          bf16x8 b[CT];
 #pragma unroll
-          for (int c = 0; c < CT; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[r], b[c], acc[r][c], 0, 0, 0);
+          for (int c = 0; c < CT; ++c) b[c] = bcol[c * bstride + 4 * kk];
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][r], b[c], acc[r][c], 0, 0, 0);
         }
-#pragma unroll
-      for (int r = 0; r < RG; ++r) a0[r] = a1[r];
+      }
     }
   }
 
@@ -108,53 +119,69 @@ struct Dense {
                                                   int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
     const int l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
-    const float* arow[RG];
+    const HOPF_GLOBAL f32x4* arow[RG];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) arow[r] = M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 4 * lg;
+    for (int r = 0; r < RG; ++r)
+      arow[r] = gp((const f32x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 4 * lg));
     const float* bcol = B + lr * ldb + 4 * lg;
+    f32x4 an[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) an[r] = arow[r][0];
     for (int k0 = 0; k0 < n_pad; k0 += 16) {
       f32x4 a[RG], b[CT];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) a[r] = *(const f32x4*)(arow[r] + k0);
+      for (int r = 0; r < RG; ++r) a[r] = an[r];
+      if (k0 + 16 < n_pad) {
+#pragma unroll
+        for (int r = 0; r < RG; ++r) an[r] = arow[r][(k0 + 16) / 4];
+      }
 #pragma unroll
       for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + k0);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int r = 0; r < RG; ++r)
-          if (r < nrt) {
 #pragma unroll
-            for (int c = 0; c < CT; ++c)
-              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
-          }
+          for (int c = 0; c < CT; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
     }
   }
 
-  // FP64: one 16-column block. A rows are loaded in the order 4(rho%4) + rho/4 so that the
-  // output lands in the same lane layout as the FP32/BF16 16x16 products:
+  // FP64: the RG row tiles times a K-chunk [k0, k0 + kc) of the right-hand-side block held in
+  // LDS (B[c * ldb + kk], chunk-local kk).  A rows are loaded in the order 4(rho%4) + rho/4 so
+  // that the output lands in the lane layout of the FP32/BF16 16x16 products:
   // lane l, register i -> row 4(l/16) + i, column l%16.
-  static __device__ __forceinline__ void gemm_f64(const double* __restrict__ M, int n_pad, const double* B,
-                                                  int ldb, int bcols, const int* rt, int nrt,
-                                                  f64x4 (&acc)[RG]) {
+  static __device__ __forceinline__ void gemm_f64_chunk(const double* __restrict__ M, int n_pad, int k0, int kc,
+                                                        const double* B, int ldb, const int* rt, int nrt,
+                                                        f64x4 (&acc)[RG][CT]) {
     const int l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
     const int arow_perm = 4 * (lr & 3) + (lr >> 2);
-    const double* arow[RG];
+    const HOPF_GLOBAL f64x4* arow[RG];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) arow[r] = M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + 4 * lg;
-    const bool bon = lr < bcols;
+    for (int r = 0; r < RG; ++r)
+      arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
     const double* bcol = B + lr * ldb + 4 * lg;
-    for (int k0 = 0; k0 < n_pad; k0 += 16) {
-      f64x4 a[RG], b;
+    f64x4 an[RG];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) a[r] = *(const f64x4*)(arow[r] + k0);
-      if (bon) b = *(const f64x4*)(bcol + k0);
-      else b = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r]);
+    for (int kk = 0; kk < kc; kk += 16) {
+      f64x4 a[RG], b[CT];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) a[r] = an[r];
+      if (kk + 16 < kc) {
+#pragma unroll
+        for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r] + (kk + 16) / 4);
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int r = 0; r < RG; ++r)
-          if (r < nrt) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[q], acc[r], 0, 0, 0);
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
     }
   }
 };
@@ -166,10 +193,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Per-column (slot) scalars and the workgroup's control words, in LDS.
+struct ColShared {
+  double t[kMaxCols], th1[kMaxCols], th2[kMaxCols], gam[kMaxCols], gama[kMaxCols], dgam[kMaxCols];
+  double ssa2[kMaxCols], ssq[kMaxCols], prev[kMaxCols], s[kMaxCols], phi[kMaxCols], hp[kMaxCols];
+  double pn[kMaxCols];
+  int col[kMaxCols], j[kMaxCols], k[kMaxCols], state[kMaxCols], phase[kMaxCols], iters[kMaxCols];
+  int newton[kMaxCols], flags[kMaxCols], fresh[kMaxCols];
+  double red[4][kMaxCols][kNRed];
+  int ctl[16];
+};
+enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8 };
+enum {
+  CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
+  CTL_EXIT, CTL_BETTER, CTL_ANY
+};
+enum { PH_WARMUP = 0, PH_DELTA = 1 };
+
 template <int MODE, int CT>
 __global__ void __launch_bounds__(kBlock, 1)
-dense_kernel(const DenseProb* __restrict__ probs, const DenseTile* __restrict__ tiles, int ntiles,
-             float* __restrict__ ws, int64_t ws_per_wg, int distance, int warmup, int anchor_every) {
+dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
+             int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
+             int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every) {
   using D = Dense<MODE, CT>;
   constexpr int PT = D::PT;
   constexpr int RG = D::RG;
@@ -178,549 +223,630 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseTile* __restrict__ 
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, l = tid & 63;
-  float* wsb = ws + (int64_t)blockIdx.x * ws_per_wg;
+  float* const wsb = ws + (int64_t)blockIdx.x * ws_per_wg;
+  (void)ws64; (void)ws64_per_wg;
 
-  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
-    const DenseTile tile = tiles[ti];
-    const DenseProb& pb = probs[tile.prob];
+  if (tid < PT) { S.state[tid] = COL_EMPTY; S.fresh[tid] = 0; }
+  if (tid == 0) {
+    const int c0 = atomicAdd(chunk_counter, 1);
+    if (c0 >= nchunks) {
+      S.ctl[CTL_EXIT] = 1;
+    } else {
+      S.ctl[CTL_EXIT] = 0;
+      S.ctl[CTL_PROB] = chunks[c0].prob;
+      S.ctl[CTL_NEXTCOL] = chunks[c0].col0;
+      S.ctl[CTL_CHUNKEND] = chunks[c0].col0 + chunks[c0].ncols;
+    }
+    S.ctl[CTL_PENDING] = -1; S.ctl[CTL_NOMORE] = 0; S.ctl[CTL_ANCHOR] = 0; S.ctl[CTL_LAST_ANCHOR] = 0;
+  }
+  __syncthreads();
+  if (S.ctl[CTL_EXIT]) return;
+
+  int k_it = 0;
+  while (true) {
+    __syncthreads();  // every control word read in the previous pass is consumed before it changes
+    const DenseProb pb = probs[S.ctl[CTL_PROB]];  // by value: fields stay in registers
     const int n = pb.n, n_pad = pb.n_pad, K = pb.K;
     const double lam = pb.lambda;
+    const float flam = (float)lam;
     const bool has_l1 = !distance && hk_has_l1(pb.hkind);
     const bool has_l2 = distance || hk_has_l2(pb.hkind);
-    const int ncols = tile.npt * K;
-    float* za = wsb;
-    float* dz = wsb + (int64_t)PT * n_pad;
-    float* ea = wsb + 2 * (int64_t)PT * n_pad;
-    float* pout = wsb + 3 * (int64_t)PT * n_pad;
+    float* const za = wsb;
+    float* const dz = wsb + (int64_t)PT * n_pad;
+    float* const ea = wsb + 2 * (int64_t)PT * n_pad;
+    float* const pout = wsb + 3 * (int64_t)PT * n_pad;
     const int nq = n_pad >> 2;
     const int RT = n_pad >> 4;
-    const float flam = (float)lam;
 
-    // ---------------------------------------------------------------- column init
-    if (tid < PT) {
-      const int c = tid;
-      int st = COL_EMPTY;
-      if (c < ncols) {
-        const int jj = tile.pt0 + c / K, kk = c % K;
-        S.j[c] = jj; S.k[c] = kk;
-        double tv = distance ? 0.0 : (double)pb.t[jj];
-        S.t[c] = tv;
-        st = (distance || tv > 0.0) ? COL_ACTIVE : COL_INVALID;
-        S.th1[c] = has_l1 ? tv / lam : 0.0;
-        S.th2[c] = (!distance && has_l2) ? tv / lam : 0.0;
+    // ================================================================ anchor (REFINED mode)
+    if (MODE == 1 && S.ctl[CTL_ANCHOR]) {
+      // pass A (one wave per slot): renormalise z = za + dz, exact anchor reference s_a, norms
+      for (int c = wave; c < PT; c += 4) {
+        const int st = S.state[c];
+        if (st != COL_ACTIVE && st != COL_WAITING) continue;
+        const double th1 = S.th1[c];
+        double pss = 0.0, pinc = 0.0;
+        for (int i = l; i < n_pad; i += 64) {
+          const size_t e = (size_t)c * n_pad + i;
+          const double z = (double)ld_nt(za + e) + (double)ld_nt(dz + e);
+          const float zan = (float)z;
+          const float dzn = (float)(z - (double)zan);
+          st_nt(za + e, zan); st_nt(dz + e, dzn);
+          const float th = theta_f((float)th1, *gp(pb.wf + i));
+          const float ca = clampf(zan, -th, th), sa = zan - ca;
+          const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
+          const double sa64 = anchor_shrink(zan, th1, pb.w, i);
+          pss += sa64 * sa64;
+          pinc += (double)ds * (2.0 * (double)sa + (double)ds);
+        }
+        pss = wave_sum(pss); pinc = wave_sum(pinc);
+        if (l == 0) {
+          S.ssa2[c] = pss;
+          const double ssq = pss + pinc;
+          S.ssq[c] = ssq;
+          double ga = 1.0, g = 1.0;
+          if (has_l2) {
+            const double na = sqrt(pss), nz = sqrt(fmax(ssq, 0.0)), th2 = S.th2[c];
+            ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
+            g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
+          }
+          S.gama[c] = ga; S.gam[c] = g; S.dgam[c] = g - ga;
+          S.phase[c] = PH_DELTA;
+        }
       }
-      S.state[c] = st;
-      S.gam[c] = 1.0; S.gama[c] = 1.0; S.dgam[c] = 0.0; S.ssa2[c] = 0.0; S.ssq[c] = 0.0;
-      S.prev[c] = 1e300; S.s[c] = 0.0; S.phi[c] = 0.0; S.hp[c] = 0.0; S.pn[c] = 0.0;
-      S.iters[c] = 0; S.newton[c] = 0; S.flags[c] = FLAG_FIRST;
+      __syncthreads();
+      // v^a = M r^a (FP64 MFMA), K-chunked through LDS; ea = v^a - d^a
+      {
+        double* B64 = (double*)lds_raw;
+        const int KC = n_pad < (PT == 64 ? 256 : 512) ? n_pad : (PT == 64 ? 256 : 512);
+        const int ldb = KC + 2;
+        for (int rt0 = 0; rt0 < RT; rt0 += 4 * RG) {
+          int rt[RG]; int nrt = 0;
+#pragma unroll
+          for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
+          f64x4 acc[RG][CT];
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+          for (int k0 = 0; k0 < n_pad; k0 += KC) {
+            const int kc = (n_pad - k0) < KC ? (n_pad - k0) : KC;  // multiple of 32: n_pad and KC are
+            __syncthreads();
+            // r^a = x' + lambda (2 d^a - z^a) in FP64 for the anchored slots (0 for the others)
+            for (int g = tid; g < PT * kc; g += kBlock) {
+              const int c = g / kc, kk = g % kc, i = k0 + kk;
+              const int st = S.state[c];
+              double r = 0.0;
+              if ((st == COL_ACTIVE || st == COL_WAITING) && i < n) {
+                const float zan = ld_nt(za + (size_t)c * n_pad + i);
+                const double sa64 = anchor_shrink(zan, S.th1[c], pb.w, i);
+                const double xp = (double)*gp(pb.x + (size_t)S.j[c] * n + i) -
+                                  (pb.centres ? *gp(pb.centres + (size_t)S.k[c] * n_pad + i) : 0.0);
+                r = xp + lam * (2.0 * S.gama[c] * sa64 - (double)zan);
+              }
+              B64[c * ldb + kk] = r;
+            }
+            __syncthreads();
+            D::gemm_f64_chunk(pb.Md, n_pad, k0, kc, B64, ldb, rt, nrt, acc);
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const int c = 16 * ct + (l & 15);
+            const int st = S.state[c];
+            if (st != COL_ACTIVE && st != COL_WAITING) continue;
+            const double ga = S.gama[c];
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+              if (r >= nrt) continue;
+              const int row0 = 16 * rt[r] + 4 * (l >> 4);
+              f32x4 ev;
+              const f32x4 zv = ld_nt4(za + (size_t)c * n_pad + row0);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int row = row0 + i;
+                const double sa64 = anchor_shrink(zv[i], S.th1[c], pb.w, row);
+                ev[i] = (row < n) ? (float)(acc[r][ct][i] - ga * sa64) : 0.f;
+              }
+              st_nt4(ea + (size_t)c * n_pad + row0, ev);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < PT && S.state[tid] == COL_WAITING) S.state[tid] = COL_PHI;
+      if (tid == 0) { S.ctl[CTL_ANCHOR] = 0; S.ctl[CTL_LAST_ANCHOR] = k_it; }
+      __syncthreads();
     }
+    if (MODE == 0) {  // plain mode: converged columns are evaluated right away
+      if (tid < PT && S.state[tid] == COL_WAITING) S.state[tid] = COL_PHI;
+      __syncthreads();
+    }
+
+    // ================================================================ flush finished slots
+    for (int c = 0; c < PT; ++c) {
+      const int st = S.state[c];
+      if (st != COL_DONE && st != COL_INVALID) continue;
+      const int64_t j = S.j[c];
+      const int kk = S.k[c];
+      if (tid == 0) {
+        int better;
+        if (st == COL_INVALID) {
+          better = 2;
+        } else {
+          const double key = distance ? ((S.flags[c] & FLAG_INSIDE) ? -1.0 : S.s[c]) : S.phi[c];
+          const int bk = pb.bestk[j];
+          const double bv = pb.bestv[j];
+          better = (bk < 0 || key < bv || (key == bv && kk < bk)) ? 1 : 0;
+          if (better) { pb.bestv[j] = key; pb.bestk[j] = kk; }
+        }
+        S.ctl[CTL_BETTER] = better;
+        const float qnan = __builtin_nanf("");
+        if (better == 2) {
+          pb.bestk[j] = -2;
+          if (!distance) {
+            pb.phi[j] = qnan; pb.dphidt[j] = qnan;
+            if (pb.iters) pb.iters[j] = -1;
+            if (pb.kstar) pb.kstar[j] = -1;
+          } else {
+            pb.dist[j] = qnan;
+            if (pb.kstar) pb.kstar[j] = -1;
+            if (pb.inside) pb.inside[j] = 0;
+            if (pb.newton) pb.newton[j] = -1;
+          }
+        } else if (better == 1) {
+          if (!distance) {
+            pb.phi[j] = (float)S.phi[c];
+            pb.dphidt[j] = (float)(-S.hp[c]);
+            if (pb.iters) pb.iters[j] = (S.flags[c] & FLAG_CAPPED) ? -2 : S.iters[c];
+            if (pb.kstar) pb.kstar[j] = kk;
+          } else {
+            const bool ins = S.flags[c] & FLAG_INSIDE;
+            pb.dist[j] = ins ? 0.f : (float)S.s[c];
+            if (pb.kstar) pb.kstar[j] = kk;
+            if (pb.inside) pb.inside[j] = ins ? 1 : 0;
+            if (pb.newton) pb.newton[j] = (S.flags[c] & (FLAG_CAPPED | FLAG_NEWTON_CAP)) ? -2 : S.newton[c];
+          }
+        }
+      }
+      __syncthreads();
+      const int better = S.ctl[CTL_BETTER];
+      if (better) {
+        for (int i = tid; i < n; i += kBlock) {
+          float v;
+          if (better == 2) v = __builtin_nanf("");
+          else if (!distance) v = ld_nt(pout + (size_t)c * n_pad + i);
+          else {
+            const float y = pb.x[(size_t)j * n + i];
+            if (S.flags[c] & FLAG_INSIDE) v = y;
+            else v = (float)((double)y - S.s[c] * (double)ld_nt(pout + (size_t)c * n_pad + i) / S.pn[c]);
+          }
+          pb.grad[(size_t)j * n + i] = v;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) S.state[c] = COL_EMPTY;
+      __syncthreads();
+    }
+
+    // ================================================================ refill empty slots
     if (tid == 0) {
-      S.ctl[CTL_ANCHOR] = 0; S.ctl[CTL_PHASE] = PHASE_WARMUP; S.ctl[CTL_LAST_ANCHOR] = 0;
-      S.ctl[CTL_FINISH] = 0;
+      int prob = S.ctl[CTL_PROB], nextcol = S.ctl[CTL_NEXTCOL], cend = S.ctl[CTL_CHUNKEND];
+      int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE];
+      int live = 0;
+      for (int c = 0; c < PT; ++c) {
+        S.fresh[c] = 0;
+        if (S.state[c] != COL_EMPTY) { ++live; continue; }
+        while (nextcol >= cend && pending < 0 && !nomore) {
+          const int nc = atomicAdd(chunk_counter, 1);
+          if (nc >= nchunks) { nomore = 1; break; }
+          if (chunks[nc].prob == prob) { nextcol = chunks[nc].col0; cend = nextcol + chunks[nc].ncols; }
+          else pending = nc;
+        }
+        if (nextcol < cend) {
+          const int col = nextcol++;
+          S.col[c] = col; S.j[c] = col / K; S.k[c] = col % K;
+          S.fresh[c] = 1;
+          ++live;
+        }
+      }
+      int exitf = 0;
+      if (live == 0) {
+        if (pending >= 0) {  // all slots drained: switch to the pending problem
+          prob = chunks[pending].prob;
+          nextcol = chunks[pending].col0;
+          cend = nextcol + chunks[pending].ncols;
+          pending = -1;
+          S.ctl[CTL_ANY] = 1;  // ask for another refill pass with the new problem
+        } else {
+          exitf = 1;
+          S.ctl[CTL_ANY] = 0;
+        }
+      } else {
+        S.ctl[CTL_ANY] = 0;
+      }
+      S.ctl[CTL_PROB] = prob; S.ctl[CTL_NEXTCOL] = nextcol; S.ctl[CTL_CHUNKEND] = cend;
+      S.ctl[CTL_PENDING] = pending; S.ctl[CTL_NOMORE] = nomore; S.ctl[CTL_EXIT] = exitf;
     }
     __syncthreads();
-    // state init + finiteness check, one wave per column
+    if (S.ctl[CTL_EXIT]) break;
+    if (S.ctl[CTL_ANY]) {  // problem switch: restart the loop body with the new problem's view
+      if (tid == 0) { S.ctl[CTL_LAST_ANCHOR] = k_it; S.ctl[CTL_ANCHOR] = 0; }
+      __syncthreads();
+      continue;
+    }
+    // initialise the fresh slots: scalars ...
+    if (tid < PT && S.fresh[tid]) {
+      const int c = tid;
+      const int64_t jj = S.j[c];
+      const double tv = distance ? 0.0 : (double)pb.t[jj];
+      S.t[c] = tv;
+      S.state[c] = (distance || tv > 0.0) ? COL_ACTIVE : COL_INVALID;
+      S.th1[c] = has_l1 ? tv / lam : 0.0;
+      S.th2[c] = (!distance && has_l2) ? tv / lam : 0.0;
+      S.gam[c] = 1.0; S.gama[c] = 1.0; S.dgam[c] = 0.0; S.ssa2[c] = 0.0; S.ssq[c] = 0.0;
+      S.prev[c] = 1e300; S.s[c] = 0.0; S.phi[c] = 0.0; S.hp[c] = 0.0; S.pn[c] = 0.0;
+      S.iters[c] = 0; S.newton[c] = 0; S.flags[c] = FLAG_FIRST; S.phase[c] = PH_WARMUP;
+    }
+    __syncthreads();
+    // ... and state (one wave per slot; also the finiteness check)
     for (int c = wave; c < PT; c += 4) {
+      if (!S.fresh[c]) continue;
       const int st = S.state[c];
       bool bad = false;
-      const double* cen = (pb.centres && st != COL_EMPTY) ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
-      const float* xj = (st != COL_EMPTY) ? pb.x + (size_t)S.j[c] * n : nullptr;
+      const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
+      const float* xj = pb.x + (size_t)S.j[c] * n;
       for (int i = l; i < n_pad; i += 64) {
         float v = 0.f;
-        if (st != COL_EMPTY && i < n) {
-          float xv = xj[i];
+        if (i < n) {
+          const float xv = xj[i];
           if (!isfinite(xv)) bad = true;
           v = (float)((double)xv - (cen ? cen[i] : 0.0));
         }
-        za[(size_t)c * n_pad + i] = (st == COL_ACTIVE) ? v : 0.f;
-        dz[(size_t)c * n_pad + i] = 0.f;
-        ea[(size_t)c * n_pad + i] = 0.f;
+        const size_t e = (size_t)c * n_pad + i;
+        st_nt(za + e, (st == COL_ACTIVE) ? v : 0.f);
+        st_nt(dz + e, 0.f);
+        st_nt(ea + e, 0.f);
       }
-      bool anybad = __any(bad);
+      const bool anybad = __any(bad);
       if (l == 0 && anybad && st == COL_ACTIVE) S.state[c] = COL_INVALID;
     }
     __syncthreads();
-
-    int k_it = 0;
-    while (true) {
-      // ------------------------------------------------------------ anchor (REFINED)
-      if (MODE == 1 && S.ctl[CTL_ANCHOR]) {
-        const bool from_warmup = S.ctl[CTL_PHASE] == PHASE_WARMUP;
-        // pass A: renormalise z = za + dz, anchor d^a = gamma^a shrink1(za), norms
-        for (int c = wave; c < PT; c += 4) {
-          const int st = S.state[c];
-          if (st != COL_ACTIVE && st != COL_WAITING) continue;
-          const double th1 = S.th1[c];
-          double pss = 0.0, pinc = 0.0;
-          for (int i = l; i < n_pad; i += 64) {
-            const size_t e = (size_t)c * n_pad + i;
-            double z = from_warmup ? (double)za[e] : (double)za[e] + (double)dz[e];
-            float zan = (float)z;
-            float dzn = (float)(z - (double)zan);
-            za[e] = zan; dz[e] = dzn;
-            float th = theta_i(th1, pb.w, i);
-            float ca = clampf(zan, -th, th);
-            float sa = zan - ca;
-            float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
-            const double sa64 = anchor_shrink(zan, th1, pb.w, i);
-            pss += sa64 * sa64;
-            pinc += (double)ds * (2.0 * (double)sa + (double)ds);
-          }
-          pss = wave_sum(pss); pinc = wave_sum(pinc);
-          if (l == 0) {
-            S.ssa2[c] = pss;
-            double ssq = pss + pinc;
-            S.ssq[c] = ssq;
-            double ga = 1.0, g = 1.0;
-            if (has_l2) {
-              double na = sqrt(pss), nz = sqrt(fmax(ssq, 0.0)), th2 = S.th2[c];
-              ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
-              g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
-            }
-            if (S.flags[c] & FLAG_FIRST) { ga = 1.0; }  // cannot happen after warm-up; kept for max_iter < 1
-            S.gama[c] = ga; S.gam[c] = g; S.dgam[c] = g - ga;
-          }
-        }
-        __syncthreads();
-        // pass B: v^a = M r^a in FP64, 16 (or 8) columns at a time; ea = v^a - d^a
-        double* B64 = (double*)lds_raw;
-        const int SB = n_pad <= 1024 ? 16 : 8;
-        const int ldb64 = n_pad + 2;
-        for (int c0 = 0; c0 < PT; c0 += SB) {
-          bool any = false;
-          for (int cc = 0; cc < SB; ++cc) {
-            int st = S.state[c0 + cc];
-            any |= (st == COL_ACTIVE || st == COL_WAITING);
-          }
-          if (!any) continue;
-          for (int g = tid; g < SB * n_pad; g += kBlock) {
-            const int cc = g / n_pad, i = g % n_pad, c = c0 + cc;
-            const int st = S.state[c];
-            double r = 0.0;
-            if ((st == COL_ACTIVE || st == COL_WAITING) && i < n) {
-              const size_t e = (size_t)c * n_pad + i;
-              const float zan = za[e];
-              const double sa64 = anchor_shrink(zan, S.th1[c], pb.w, i);
-              double xp = (double)pb.x[(size_t)S.j[c] * n + i] - (pb.centres ? pb.centres[(size_t)S.k[c] * n_pad + i] : 0.0);
-              r = xp + lam * (2.0 * S.gama[c] * sa64 - (double)zan);
-            }
-            B64[cc * ldb64 + i] = r;
-          }
-          __syncthreads();
-          for (int rt0 = wave; rt0 < RT; rt0 += 4 * RG) {
-            int rt[RG]; int nrt = 0;
-#pragma unroll
-            for (int r = 0; r < RG; ++r) { rt[r] = rt0 + 4 * r; if (rt[r] < RT) nrt = r + 1; }
-            f64x4 acc[RG];
-#pragma unroll
-            for (int r = 0; r < RG; ++r) acc[r] = f64x4{0.0, 0.0, 0.0, 0.0};
-            D::gemm_f64(pb.Md, n_pad, B64, ldb64, SB, rt, nrt, acc);
-            const int cc = l & 15;
-            const int c = c0 + cc;
-            if (cc < SB) {
-              const int st = S.state[c];
-              if (st == COL_ACTIVE || st == COL_WAITING) {
-                const double ga = S.gama[c];
-#pragma unroll
-                for (int r = 0; r < RG; ++r) {
-                  if (r >= nrt) continue;
-                  const int row0 = 16 * rt[r] + 4 * (l >> 4);
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) {
-                    const int row = row0 + i;
-                    const size_t e = (size_t)c * n_pad + row;
-                    const double sa64 = anchor_shrink(za[e], S.th1[c], pb.w, row);
-                    ea[e] = (row < n) ? (float)(acc[r][i] - ga * sa64) : 0.f;
-                  }
-                }
-              }
-            }
-          }
-          __syncthreads();
-        }
-        if (tid < PT) {
-          if (S.state[tid] == COL_WAITING) S.state[tid] = COL_PHI;
-        }
-        if (tid == 0) {
-          S.ctl[CTL_ANCHOR] = 0; S.ctl[CTL_PHASE] = PHASE_DELTA; S.ctl[CTL_LAST_ANCHOR] = k_it;
-        }
-        __syncthreads();
-      }
-      if (MODE == 0 && tid < PT) {  // plain mode: converged columns are evaluated right away
-        if (S.state[tid] == COL_WAITING) S.state[tid] = COL_PHI;
-      }
-      __syncthreads();
-      // finished?
+    {  // anything to iterate?  (invalid slots are flushed at the top of the next pass)
       if (tid == 0) {
         int live = 0;
         for (int c = 0; c < PT; ++c) {
-          int st = S.state[c];
-          live |= (st == COL_ACTIVE || st == COL_PHI || st == COL_WAITING);
+          const int st = S.state[c];
+          live |= (st == COL_ACTIVE || st == COL_PHI) ? 1 : (st == COL_INVALID ? 2 : 0);
         }
-        S.ctl[CTL_FINISH] = !live;
+        S.ctl[CTL_ANY] = live;
       }
       __syncthreads();
-      if (S.ctl[CTL_FINISH]) break;
-      const bool delta = (MODE == 1) && S.ctl[CTL_PHASE] == PHASE_DELTA;
+      if (!(S.ctl[CTL_ANY] & 1)) {
+        if (S.ctl[CTL_ANY] & 2) continue;  // only invalid slots: flush them
+        // only waiting slots remain: an anchor (REFINED) makes them evaluable
+        if (tid == 0) S.ctl[CTL_ANCHOR] = 1;
+        __syncthreads();
+        continue;
+      }
+    }
 
-      // ------------------------------------------------------------ prologue: right-hand sides
-      if (MODE == 1) {
-        __bf16* B16 = (__bf16*)lds_raw;
-        const int ldb = n_pad + 8;
-        for (int g = tid; g < PT * nq; g += kBlock) {
-          const int c = g / nq, i0 = (g % nq) * 4;
-          const int st = S.state[c];
-          float rv[4] = {0.f, 0.f, 0.f, 0.f};
-          if (st == COL_ACTIVE || st == COL_PHI) {
-            const size_t e = (size_t)c * n_pad + i0;
-            const f32x4 zav = *(const f32x4*)(za + e);
-            if (delta) {
-              const f32x4 dzv = *(const f32x4*)(dz + e);
-              const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
+    // ================================================================ prologue: right-hand sides
+    // One wave per slot: the slot's scalars are wave-uniform; lane l handles 4 consecutive
+    // coordinates per step.
+    {
+      const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;
+      for (int c = wave; c < PT; c += 4) {
+        const int st = S.state[c];
+        const bool on = st == COL_ACTIVE || st == COL_PHI;
+        const bool deltac = MODE == 1 && S.phase[c] == PH_DELTA;
+        const bool first = S.flags[c] & FLAG_FIRST;
+        const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c], gf = (float)S.gam[c];
+        const float th1f = (float)S.th1[c];
+        const HOPF_GLOBAL float* xj = on ? gp(pb.x + (size_t)S.j[c] * n) : nullptr;
+        const HOPF_GLOBAL double* cen = (on && pb.centres) ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
+        const float* zac = za + (size_t)c * n_pad;
+        const float* dzc = dz + (size_t)c * n_pad;
+        for (int i0 = 4 * l; i0 < n_pad; i0 += 256) {
+          f32x4 rv = {0.f, 0.f, 0.f, 0.f};
+          if (on) {
+            const f32x4 zv = ld_nt4(zac + i0);
+            const f32x4 wv = *gp((const f32x4*)(pb.wf + i0));
+            if (deltac) {
+              const f32x4 dv = ld_nt4(dzc + i0);
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
-                float th = theta_i(S.th1[c], pb.w, i0 + q);
-                float ca = clampf(zav[q], -th, th), sa = zav[q] - ca;
-                float ds = dzv[q] - clampf(dzv[q] + sa, -th - ca, th - ca);
-                float dd = gaf * ds + dgf * (sa + ds);
-                rv[q] = flam * (2.f * dd - dzv[q]);
+                const float th = theta_f(th1f, wv[q]);
+                const float ca = clampf(zv[q], -th, th), sa = zv[q] - ca;
+                const float ds = dv[q] - clampf(dv[q] + sa, -th - ca, th - ca);
+                const float dd = gaf * ds + dgf * (sa + ds);
+                rv[q] = flam * (2.f * dd - dv[q]);
               }
             } else {
-              const bool first = S.flags[c] & FLAG_FIRST;
-              const float gf = (float)S.gam[c];
-              const float* xj = pb.x + (size_t)S.j[c] * n;
-              const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = i0 + q;
-                if (i >= n) continue;
-                float z = zav[q];
-                float d = z;
-                if (!first) { float th = theta_i(S.th1[c], pb.w, i); d = gf * (z - clampf(z, -th, th)); }
-                float xp = (float)((double)xj[i] - (cen ? cen[i] : 0.0));
-                rv[q] = xp + flam * (2.f * d - z);
+                const int ic = i < n ? i : n - 1;  // in-bounds address; value masked below
+                const float xv = xj[ic];
+                const float xp = (i < n) ? (float)((double)xv - (cen ? cen[i] : 0.0)) : 0.f;
+                const float z = zv[q];
+                const float th = theta_f(th1f, wv[q]);
+                const float d = first ? z : gf * (z - clampf(z, -th, th));
+                rv[q] = (i < n) ? xp + flam * (2.f * d - z) : 0.f;
               }
             }
           }
+          if (MODE == 1) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 o;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) B16[c * ldb + i0 + q] = to_bf16(rv[q]);
-        }
-      } else {
-        float* B32 = (float*)lds_raw;
-        const int ldb = n_pad + 4;
-        for (int g = tid; g < PT * nq; g += kBlock) {
-          const int c = g / nq, i0 = (g % nq) * 4;
-          const int st = S.state[c];
-          f32x4 rv = {0.f, 0.f, 0.f, 0.f};
-          if (st == COL_ACTIVE || st == COL_PHI) {
-            const f32x4 zav = *(const f32x4*)(za + (size_t)c * n_pad + i0);
-            const bool first = S.flags[c] & FLAG_FIRST;
-            const float gf = (float)S.gam[c];
-            const float* xj = pb.x + (size_t)S.j[c] * n;
-            const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int i = i0 + q;
-              if (i >= n) continue;
-              float z = zav[q];
-              float d = z;
-              if (!first) { float th = theta_i(S.th1[c], pb.w, i); d = gf * (z - clampf(z, -th, th)); }
-              float xp = (float)((double)xj[i] - (cen ? cen[i] : 0.0));
-              rv[q] = xp + flam * (2.f * d - z);
-            }
+            for (int q = 0; q < 4; ++q) o[q] = to_bf16(rv[q]);
+            *(bf16x4*)((__bf16*)lds_raw + c * ldb + i0) = o;
+          } else {
+            *(f32x4*)((float*)lds_raw + c * ldb + i0) = rv;
           }
-          *(f32x4*)(B32 + c * ldb + i0) = rv;
         }
       }
-      __syncthreads();
+    }
+    __syncthreads();
 
-      // ------------------------------------------------------------ GEMM + epilogue
-      double part[CT][kNRed];
+    // ================================================================ GEMM + epilogue
+    double part[CT][kNRed];
 #pragma unroll
-      for (int c = 0; c < CT; ++c)
+    for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int q = 0; q < kNRed; ++q) part[c][q] = 0.0;
+      for (int q = 0; q < kNRed; ++q) part[c][q] = 0.0;
+    // this lane's CT slots (columns 16 ct + l % 16): scalars hoisted out of the row loop
+    int st_[CT];
+    bool first_[CT], delta_[CT];
+    float th1f_[CT], gaf_[CT], dgf_[CT], gf_[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int c = 16 * ct + (l & 15);
+      st_[ct] = S.state[c];
+      first_[ct] = S.flags[c] & FLAG_FIRST;
+      delta_[ct] = MODE == 1 && S.phase[c] == PH_DELTA;
+      th1f_[ct] = (float)S.th1[c];
+      gaf_[ct] = (float)S.gama[c];
+      dgf_[ct] = (float)S.dgam[c];
+      gf_[ct] = (float)S.gam[c];
+    }
 
-      for (int rt0 = wave; rt0 < RT; rt0 += 4 * RG) {
-        int rt[RG]; int nrt = 0;
+    for (int rt0 = 0; rt0 < RT; rt0 += 4 * RG) {
+      int rt[RG]; int nrt = 0;
 #pragma unroll
-        for (int r = 0; r < RG; ++r) { rt[r] = rt0 + 4 * r; if (rt[r] < RT) nrt = r + 1; }
-        f32x4 acc[RG][CT];
+      for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
+      f32x4 acc[RG][CT];
 #pragma unroll
-        for (int r = 0; r < RG; ++r)
+      for (int r = 0; r < RG; ++r)
 #pragma unroll
-          for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (MODE == 1) D::gemm_bf16(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
-        else D::gemm_f32(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
+        for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (MODE == 1) D::gemm_bf16(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
+      else D::gemm_f32(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
 
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-          const int c = 16 * ct + (l & 15);
-          const int st = S.state[c];
-          if (st != COL_ACTIVE && st != COL_PHI) continue;
-          const bool first = S.flags[c] & FLAG_FIRST;
-          const double th1 = S.th1[c];
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = 16 * ct + (l & 15);
+        const int st = st_[ct];
+        if (st != COL_ACTIVE && st != COL_PHI) continue;
+        const bool delta = delta_[ct];
+        const float th1f = th1f_[ct];
+        // the state of all RG row tiles of this column is requested before any of it is used
+        f32x4 zst[RG], dst[RG], est[RG], wst[RG];
 #pragma unroll
-          for (int r = 0; r < RG; ++r) {
-            if (r >= nrt) continue;
-            const int row0 = 16 * rt[r] + 4 * (l >> 4);
-            const size_t e = (size_t)c * n_pad + row0;
-            const f32x4 v = acc[r][ct];
-            f32x4 zav = *(const f32x4*)(za + e);
-            if (MODE == 1 && delta) {
-              f32x4 dzv = *(const f32x4*)(dz + e);
-              const f32x4 eav = *(const f32x4*)(ea + e);
-              const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
-              // COL_PHI also takes the step: with the fresh anchor it re-runs the stopping test on an
-              // exact product (a column that converged to a stale anchor's fixed point continues).
-              f32x4 pv;
-              const double ga = S.gama[c];
-              const float* xj = pb.x + (size_t)S.j[c] * n;
+        for (int r = 0; r < RG; ++r) {
+          if (r >= nrt) continue;
+          const int row0 = 16 * rt[r] + 4 * (l >> 4);
+          const size_t e = (size_t)c * n_pad + row0;
+          zst[r] = ld_nt4(za + e);
+          wst[r] = *gp((const f32x4*)(pb.wf + row0));
+          if (delta) { dst[r] = ld_nt4(dz + e); est[r] = ld_nt4(ea + e); }
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          if (r >= nrt) continue;
+          const int row0 = 16 * rt[r] + 4 * (l >> 4);
+          const size_t e = (size_t)c * n_pad + row0;
+          const f32x4 v = acc[r][ct];
+          f32x4 zav = zst[r];
+          if (delta) {
+            // COL_PHI also takes the step: with the fresh anchor it re-runs the stopping test on an
+            // exact product (a column that converged to a stale anchor's fixed point continues).
+            f32x4 dzv = dst[r];
+            const f32x4 eav = est[r];
+            const float gaf = gaf_[ct], dgf = dgf_[ct];
+            float s0 = 0.f, s1 = 0.f;
+            f32x4 ddv;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float th = theta_f(th1f, wst[r][q]);
+              const float ca = clampf(zav[q], -th, th), sa = zav[q] - ca;
+              const float lo = -th - ca, hi = th - ca;
+              const float ds = dzv[q] - clampf(dzv[q] + sa, lo, hi);
+              const float dd = gaf * ds + dgf * (sa + ds);
+              const float step = eav[q] + v[q] - dd;      // z^{k+1} - z^k
+              const float dzn = dzv[q] + step;
+              const float dsn = dzn - clampf(dzn + sa, lo, hi);
+              s0 += step * step;
+              s1 += dsn * (2.f * sa + dsn);
+              ddv[q] = dd;
+              dzv[q] = dzn;
+            }
+            part[ct][0] += (double)s0;
+            part[ct][1] += (double)s1;
+            if (st == COL_PHI) {  // value from the exact-product identity at the current iterate
+              const double ga = S.gama[c], th1 = S.th1[c];
+              const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
               const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
+              const f32x4 dz0 = dst[r];
+              f32x4 pv;
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = row0 + q;
-                float th = theta_i(th1, pb.w, i);
-                float ca = clampf(zav[q], -th, th), sa = zav[q] - ca;
-                float lo = -th - ca, hi = th - ca;
-                float ds = dzv[q] - clampf(dzv[q] + sa, lo, hi);
-                float dd = gaf * ds + dgf * (sa + ds);
-                float step = eav[q] + v[q] - dd;      // z^{k+1} - z^k
-                float dzn = dzv[q] + step;
-                float dsn = dzn - clampf(dzn + sa, lo, hi);
-                part[ct][0] += (double)step * (double)step;
-                part[ct][1] += (double)dsn * (2.0 * (double)sa + (double)dsn);
-                if (st == COL_PHI) {  // value from the exact-product identity at the current iterate
-                  double da = ga * anchor_shrink(zav[q], th1, pb.w, i);
-                  double d = da + (double)dd;
-                  double vv = (double)eav[q] + da + (double)v[q];
-                  double xp = (i < n) ? (double)xj[i] - (cen ? cen[i] : 0.0) : 0.0;
-                  double ra = xp + lam * (2.0 * da - (double)zav[q]);
-                  double rr = ra + lam * (2.0 * (double)dd - (double)dzv[q]);
-                  if (i >= n) d = 0.0;
-                  part[ct][2] += xp * d;
-                  part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
-                  part[ct][4] += (i < n ? pb.w[i] : 0.0) * fabs(d);
-                  part[ct][5] += d * d;
-                  pv[q] = (float)d;
-                }
-                dzv[q] = dzn;
+                const double da = ga * anchor_shrink(zav[q], th1, pb.w, i);
+                double d = da + (double)ddv[q];
+                const double vv = (double)eav[q] + da + (double)v[q];
+                const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
+                const double rr = xp + lam * (2.0 * da - (double)zav[q]) + lam * (2.0 * (double)ddv[q] - (double)dz0[q]);
+                if (i >= n) d = 0.0;
+                part[ct][2] += xp * d;
+                part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
+                part[ct][4] += (double)wst[r][q] * fabs(d);
+                part[ct][5] += d * d;
+                pv[q] = (float)d;
               }
-              *(f32x4*)(dz + e) = dzv;
-              if (st == COL_PHI) *(f32x4*)(pout + e) = pv;
-            } else {
-              // plain iteration (F32 mode, or the BF16 warm-up): z^{k+1} = z - d + v
-              const float gf = (float)S.gam[c];
-              if (st == COL_ACTIVE) {
+              st_nt4(pout + e, pv);
+            }
+            st_nt4(dz + e, dzv);
+          } else {
+            // plain iteration (F32 mode, or the BF16 warm-up): z^{k+1} = z - d + v
+            const float gf = gf_[ct];
+            const bool first = first_[ct];
+            if (st == COL_ACTIVE) {
+              float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  float th = theta_i(th1, pb.w, row0 + q);
-                  float z = zav[q];
-                  float d = first ? z : gf * (z - clampf(z, -th, th));
-                  float zn = z - d + v[q];
-                  float step = zn - z;
-                  float sn = zn - clampf(zn, -th, th);
-                  part[ct][0] += (double)step * (double)step;
-                  part[ct][1] += (double)sn * (double)sn;
-                  zav[q] = zn;
-                }
-                *(f32x4*)(za + e) = zav;
-              } else if (MODE == 0) {  // COL_PHI in F32 mode: r is in LDS
-                const float* B32 = (const float*)lds_raw;
-                const int ldb = n_pad + 4;
-                const float* xj = pb.x + (size_t)S.j[c] * n;
-                const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
-                f32x4 pv;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                  const int i = row0 + q;
-                  float th = theta_i(th1, pb.w, i);
-                  float z = zav[q];
-                  double d = (i < n) ? (double)(first ? z : gf * (z - clampf(z, -th, th))) : 0.0;
-                  double vv = (double)v[q];
-                  double rr = (double)B32[c * ldb + i];
-                  double xp = (i < n) ? (double)xj[i] - (cen ? cen[i] : 0.0) : 0.0;
-                  part[ct][2] += xp * d;
-                  part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
-                  part[ct][4] += (i < n ? pb.w[i] : 0.0) * fabs(d);
-                  part[ct][5] += d * d;
-                  pv[q] = (float)d;
-                }
-                *(f32x4*)(pout + e) = pv;
+              for (int q = 0; q < 4; ++q) {
+                const float th = theta_f(th1f, wst[r][q]);
+                const float z = zav[q];
+                const float d = first ? z : gf * (z - clampf(z, -th, th));
+                const float zn = z - d + v[q];
+                const float step = zn - z;
+                const float sn = zn - clampf(zn, -th, th);
+                s0 += step * step;
+                s1 += sn * sn;
+                zav[q] = zn;
               }
+              part[ct][0] += (double)s0;
+              part[ct][1] += (double)s1;
+              st_nt4(za + e, zav);
+            } else if (MODE == 0) {  // COL_PHI in F32 mode: r is in LDS
+              const float* B32 = (const float*)lds_raw;
+              const int ldb = n_pad + 4;
+              const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
+              const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
+              f32x4 pv;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int i = row0 + q;
+                const float th = theta_f(th1f, wst[r][q]);
+                const float z = zav[q];
+                const double d = (i < n) ? (double)(first ? z : gf * (z - clampf(z, -th, th))) : 0.0;
+                const double vv = (double)v[q];
+                const double rr = (double)B32[c * ldb + i];
+                const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
+                part[ct][2] += xp * d;
+                part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
+                part[ct][4] += (double)wst[r][q] * fabs(d);
+                part[ct][5] += d * d;
+                pv[q] = (float)d;
+              }
+              st_nt4(pout + e, pv);
             }
           }
         }
       }
-      // reduce partials: over the 4 lane groups, then across waves through LDS
+    }
+    // reduce partials: over the 4 lane groups, then across waves through LDS
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-        for (int q = 0; q < kNRed; ++q) {
-          double v = part[ct][q];
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
-          if (l < 16) S.red[wave][16 * ct + l][q] = v;
-        }
-      __syncthreads();
+      for (int q = 0; q < kNRed; ++q) {
+        double v = part[ct][q];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (l < 16) S.red[wave][16 * ct + l][q] = v;
+      }
+    __syncthreads();
 
-      // ------------------------------------------------------------ per-column update
-      if (tid < PT) {
-        const int c = tid;
-        const int st = S.state[c];
-        double sm[kNRed];
+    // ================================================================ per-column update
+    if (tid < PT) {
+      const int c = tid;
+      const int st = S.state[c];
+      double sm[kNRed];
 #pragma unroll
-        for (int q = 0; q < kNRed; ++q) sm[q] = S.red[0][c][q] + S.red[1][c][q] + S.red[2][c][q] + S.red[3][c][q];
-        const bool stepped = st == COL_ACTIVE || (MODE == 1 && st == COL_PHI);
-        bool evaluate = (MODE == 0 && st == COL_PHI);
-        if (stepped) {
-          S.iters[c] += 1;
-          const double ssq = delta ? S.ssa2[c] + sm[1] : sm[1];
-          S.ssq[c] = ssq;
-          double g = 1.0;
-          if (has_l2) {
-            double nz = sqrt(fmax(ssq, 0.0));
-            g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
-          }
-          S.gam[c] = g;
-          S.dgam[c] = g - S.gama[c];
-          S.flags[c] &= ~FLAG_FIRST;
-          const bool can_stop = (MODE == 0) || delta;
-          const double a = sqrt(sm[0]), b = sqrt(S.prev[c]);
-          S.prev[c] = sm[0];
-          const bool conv = can_stop && (a + b) * (a + b) <= pb.tol;
-          const bool capped = S.iters[c] >= pb.max_iter;
-          if (st == COL_ACTIVE) {
-            if (conv) S.state[c] = COL_WAITING;
-            else if (capped) { S.state[c] = COL_WAITING; S.flags[c] |= FLAG_CAPPED; }
-          } else {
-            if (capped && !conv) S.flags[c] |= FLAG_CAPPED;
-            if (conv || (S.flags[c] & FLAG_CAPPED)) evaluate = true;
-            else S.state[c] = COL_ACTIVE;
-          }
+      for (int q = 0; q < kNRed; ++q) sm[q] = S.red[0][c][q] + S.red[1][c][q] + S.red[2][c][q] + S.red[3][c][q];
+      const bool delta = MODE == 1 && S.phase[c] == PH_DELTA;
+      const bool stepped = st == COL_ACTIVE || (MODE == 1 && st == COL_PHI);
+      bool evaluate = (MODE == 0 && st == COL_PHI);
+      if (stepped) {
+        S.iters[c] += 1;
+        const double ssq = delta ? S.ssa2[c] + sm[1] : sm[1];
+        S.ssq[c] = ssq;
+        double g = 1.0;
+        if (has_l2) {
+          const double nz = sqrt(fmax(ssq, 0.0));
+          g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
         }
-        if (evaluate) {
-          const double tt = distance ? S.s[c] : S.t[c];
-          const double pn = sqrt(sm[5]);
-          const double H = (has_l1 ? sm[4] : 0.0) + (has_l2 ? pn : 0.0);
-          const double val = sm[2] - 0.5 * sm[3] - tt * H - (pb.level_set ? 0.5 : 0.0);
-          S.phi[c] = val; S.hp[c] = H; S.pn[c] = pn;
-          if (!distance) {
+        S.gam[c] = g;
+        S.dgam[c] = g - S.gama[c];
+        S.flags[c] &= ~FLAG_FIRST;
+        const bool can_stop = (MODE == 0) || delta;
+        const double a = sqrt(sm[0]), b = sqrt(S.prev[c]);
+        S.prev[c] = sm[0];
+        const bool conv = can_stop && (a + b) * (a + b) <= pb.tol;
+        const bool capped = S.iters[c] >= pb.max_iter;
+        if (st == COL_ACTIVE) {
+          if (conv) S.state[c] = COL_WAITING;
+          else if (capped) { S.state[c] = COL_WAITING; S.flags[c] |= FLAG_CAPPED; }
+        } else {
+          if (capped && !conv) S.flags[c] |= FLAG_CAPPED;
+          if (conv || (S.flags[c] & FLAG_CAPPED)) evaluate = true;
+          else S.state[c] = COL_ACTIVE;
+        }
+      }
+      if (evaluate) {
+        const double tt = distance ? S.s[c] : S.t[c];
+        const double pn = sqrt(sm[5]);
+        const double H = (has_l1 ? sm[4] : 0.0) + (has_l2 ? pn : 0.0);
+        const double val = sm[2] - 0.5 * sm[3] - tt * H - (pb.level_set ? 0.5 : 0.0);
+        S.phi[c] = val; S.hp[c] = H; S.pn[c] = pn;
+        if (!distance) {
+          S.state[c] = COL_DONE;
+        } else {
+          if (S.s[c] == 0.0 && val <= 0.0) {  // psi(y, 0) = L_k(y) <= 0: y lies in ellipsoid k
+            S.flags[c] |= FLAG_INSIDE; S.state[c] = COL_DONE;
+          } else if (!(pn > 0.0) || (S.flags[c] & FLAG_CAPPED)) {
             S.state[c] = COL_DONE;
           } else {
-            if (S.s[c] == 0.0 && val <= 0.0) {  // psi(y, 0) = L_k(y) <= 0: y lies in ellipsoid k
-              S.flags[c] |= FLAG_INSIDE; S.state[c] = COL_DONE;
-            } else if (!(pn > 0.0) || (S.flags[c] & FLAG_CAPPED)) {
+            const double ds = val / pn;  // s_{l+1} = s_l - psi / (d psi / ds), d psi/ds = -|grad psi|
+            const double sn = S.s[c] + ds;
+            S.newton[c] += 1;
+            S.s[c] = sn;
+            if (fabs(ds) <= pb.s_tol * fmax(1.0, sn)) {
               S.state[c] = COL_DONE;
+            } else if (S.newton[c] >= pb.max_newton) {
+              S.flags[c] |= FLAG_NEWTON_CAP; S.state[c] = COL_DONE;
             } else {
-              const double ds = val / pn;          // s_{l+1} = s_l - psi / (d psi / ds), d psi/ds = -|grad psi|
-              const double sn = S.s[c] + ds;
-              S.newton[c] += 1;
-              S.s[c] = sn;
-              if (fabs(ds) <= pb.s_tol * fmax(1.0, sn)) {
-                S.state[c] = COL_DONE;
-              } else if (S.newton[c] >= pb.max_newton) {
-                S.flags[c] |= FLAG_NEWTON_CAP; S.state[c] = COL_DONE;
-              } else {
-                S.th2[c] = sn / lam;
-                const double nz = sqrt(fmax(S.ssq[c], 0.0));
-                const double g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
-                S.gam[c] = g; S.dgam[c] = g - S.gama[c];
-                S.prev[c] = 1e300;
-                S.state[c] = COL_ACTIVE;
-              }
+              S.th2[c] = sn / lam;
+              const double nz = sqrt(fmax(S.ssq[c], 0.0));
+              const double g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
+              S.gam[c] = g; S.dgam[c] = g - S.gama[c];
+              S.prev[c] = 1e300;
+              S.state[c] = COL_ACTIVE;
             }
           }
         }
       }
-      __syncthreads();
-      if (tid == 0) {
-        int nact = 0, nwait = 0;
-        for (int c = 0; c < PT; ++c) {
-          nact += S.state[c] == COL_ACTIVE;
-          nwait += S.state[c] == COL_WAITING;
-        }
-        if (MODE == 1) {
-          const int kn = k_it + 1;
-          if (S.ctl[CTL_PHASE] == PHASE_WARMUP) {
-            if (kn >= warmup || (nact == 0 && nwait > 0)) S.ctl[CTL_ANCHOR] = 1;
-          } else {
-            if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0))
-              S.ctl[CTL_ANCHOR] = 1;
-          }
-        }
-      }
-      __syncthreads();
-      ++k_it;
     }
-
-    // ---------------------------------------------------------------- outputs (min over copies)
-    const int npt = tile.npt;
-    __shared__ int win[kMaxCols];
-    if (tid < npt) {
-      int best = -1;
-      double bv = 0.0;
-      bool inside = false;
-      for (int kk = 0; kk < K; ++kk) {
-        const int c = tid * K + kk;
-        if (S.state[c] != COL_DONE) continue;
-        if (distance) {
-          if (S.flags[c] & FLAG_INSIDE) { if (!inside) { inside = true; best = c; } continue; }
-          if (inside) continue;
-          if (best < 0 || S.s[c] < bv) { best = c; bv = S.s[c]; }
-        } else {
-          if (best < 0 || S.phi[c] < bv) { best = c; bv = S.phi[c]; }
-        }
+    __syncthreads();
+    if (tid == 0) {
+      int nact = 0, nwait = 0;
+      for (int c = 0; c < PT; ++c) {
+        nact += S.state[c] == COL_ACTIVE;
+        nwait += S.state[c] == COL_WAITING;
       }
-      win[tid] = best;
-      const int64_t j = tile.pt0 + tid;
-      const float qnan = __builtin_nanf("");
-      if (!distance) {
-        if (best < 0) {
-          pb.phi[j] = qnan; pb.dphidt[j] = qnan;
-          if (pb.iters) pb.iters[j] = -1;
-          if (pb.kstar) pb.kstar[j] = -1;
-        } else {
-          pb.phi[j] = (float)S.phi[best];
-          pb.dphidt[j] = (float)(-S.hp[best]);
-          if (pb.iters) pb.iters[j] = (S.flags[best] & FLAG_CAPPED) ? -2 : S.iters[best];
-          if (pb.kstar) pb.kstar[j] = best - tid * K;
-        }
-      } else {
-        if (best < 0) {
-          pb.dist[j] = qnan;
-          if (pb.kstar) pb.kstar[j] = -1;
-          if (pb.inside) pb.inside[j] = 0;
-          if (pb.newton) pb.newton[j] = -1;
-        } else {
-          pb.dist[j] = inside ? 0.f : (float)S.s[best];
-          if (pb.kstar) pb.kstar[j] = best - tid * K;
-          if (pb.inside) pb.inside[j] = inside ? 1 : 0;
-          if (pb.newton) pb.newton[j] = (S.flags[best] & (FLAG_CAPPED | FLAG_NEWTON_CAP)) ? -2 : S.newton[best];
-        }
+      if (MODE == 1) {
+        const int kn = k_it + 1;
+        if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0))
+          S.ctl[CTL_ANCHOR] = 1;
       }
     }
     __syncthreads();
-    for (int g = tid; g < npt * n; g += kBlock) {
-      const int p = g / n, i = g % n;
-      const int c = win[p];
-      const int64_t j = tile.pt0 + p;
-      float v;
-      if (c < 0) v = __builtin_nanf("");
-      else if (!distance) v = pout[(size_t)c * n_pad + i];
-      else {
-        const float y = pb.x[(size_t)j * n + i];
-        if (S.flags[c] & FLAG_INSIDE) v = y;
-        else v = (float)((double)y - S.s[c] * (double)pout[(size_t)c * n_pad + i] / S.pn[c]);
-      }
-      pb.grad[(size_t)j * n + i] = v;
-    }
-    __syncthreads();
+    ++k_it;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Host launcher
+// Host side
 // ---------------------------------------------------------------------------
 int dense_cols_per_tile(int mode, int n_pad) {
   if (mode == 1) return n_pad <= 1024 ? 64 : 32;
@@ -731,21 +857,33 @@ int dense_cols_per_tile(int mode, int n_pad) {
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_cols_per_tile(mode, n_pad);
-  size_t b;
   if (mode == 1) {
-    size_t b16 = (size_t)pt * (n_pad + 8) * 2;
-    size_t b64 = (size_t)(n_pad <= 1024 ? 16 : 8) * (n_pad + 2) * 8;
-    b = b16 > b64 ? b16 : b64;
-  } else {
-    b = (size_t)pt * (n_pad + 4) * 4;
+    const size_t b16 = (size_t)pt * (n_pad + 8) * 2;
+    const int kc_max = pt == 64 ? 256 : 512;
+    const int kc = n_pad < kc_max ? n_pad : kc_max;
+    const size_t b64 = (size_t)pt * (kc + 2) * 8;
+    return b16 > b64 ? b16 : b64;
   }
-  return b;
+  return (size_t)pt * (n_pad + 4) * 4;
+}
+
+__global__ void reset_call_kernel(int* counter, double* bestv, int32_t* bestk, int64_t npts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *counter = 0;
+  if (i < npts) { bestv[i] = __builtin_inf(); bestk[i] = -1; }
+}
+
+hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npts, hipStream_t stream) {
+  const int64_t m = npts > 0 ? npts : 1;
+  hipLaunchKernelGGL(reset_call_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, counter, bestv,
+                     bestk, npts);
+  return hipGetLastError();
 }
 
 template <int MODE, int CT>
-static hipError_t launch_t(const DenseProb* d_probs, const DenseTile* d_tiles, int ntiles, float* ws,
-                           int64_t ws_per_wg, int grid, size_t lds, int distance, int warmup,
-                           int anchor_every, hipStream_t stream) {
+static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
+                           float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
+                           int distance, int anchor_every, hipStream_t stream) {
   auto kern = dense_kernel<MODE, CT>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -754,24 +892,28 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseTile* d_tiles, i
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, d_probs, d_tiles, ntiles, ws,
-                     ws_per_wg, distance, warmup, anchor_every);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
+                     ws_per_wg, ws64_per_wg, distance, anchor_every);
   return hipGetLastError();
 }
 
-hipError_t launch_dense(int mode, int cols_per_tile, const DenseProb* d_probs, const DenseTile* d_tiles,
-                        int ntiles, float* ws, int64_t ws_per_wg, int grid, size_t lds, int distance,
-                        int warmup, int anchor_every, hipStream_t stream) {
+hipError_t launch_dense(int mode, int cols_per_tile, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                        int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
+                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream) {
   const int ct = cols_per_tile / 16;
+#define HOPF_LAUNCH(M, C) \
+  return launch_t<M, C>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, distance, \
+                        anchor_every, stream)
   if (mode == 1) {
-    if (ct == 4) return launch_t<1, 4>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
-    if (ct == 2) return launch_t<1, 2>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
-    if (ct == 1) return launch_t<1, 1>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
+    if (ct == 4) HOPF_LAUNCH(1, 4);
+    if (ct == 2) HOPF_LAUNCH(1, 2);
+    if (ct == 1) HOPF_LAUNCH(1, 1);
   } else {
-    if (ct == 4) return launch_t<0, 4>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
-    if (ct == 2) return launch_t<0, 2>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
-    if (ct == 1) return launch_t<0, 1>(d_probs, d_tiles, ntiles, ws, ws_per_wg, grid, lds, distance, warmup, anchor_every, stream);
+    if (ct == 4) HOPF_LAUNCH(0, 4);
+    if (ct == 2) HOPF_LAUNCH(0, 2);
+    if (ct == 1) HOPF_LAUNCH(0, 1);
   }
+#undef HOPF_LAUNCH
   return hipErrorInvalidValue;
 }
 
