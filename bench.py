@@ -27,6 +27,26 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (matrix)
 METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % roofline"
 
+# HBM traffic of the dense kernel on the default workload, from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE; profiles/dense_kernel_n1024_65536pts_l2wl1_bf16refined.md), each
+# scaled by what the counter reads for a plain 256 MiB device copy.  Valid only for the kernel
+# source it was measured on (hash of dense.hip + common.hpp); reported as null otherwise.
+TRAFFIC = {"source_sha256": "5a043b9f3e0c3579aca6c54cdb8ba73ed67f8deefbab023af366974074ed3cf9",
+           "read_bytes": 230.737e9, "write_bytes": 36.183e9, "precision": "bf16_refined", "npts": 1 << 16,
+           "tol": 1e-12}
+
+
+def measured_traffic(precision, npts, tol):
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dense.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1605_01799_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (h.hexdigest() != TRAFFIC["source_sha256"] or precision != TRAFFIC["precision"]
+            or npts != TRAFFIC["npts"] or tol != TRAFFIC["tol"]):
+        return None
+    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -36,10 +56,24 @@ def parse():
     ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "f32"])
     ap.add_argument("--npts", type=int, default=1 << 16)
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
+                         "scale of the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def copy_calibrate():
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 5}), flush=True)
 
 
 def main():
@@ -48,6 +82,9 @@ def main():
         print("bench.py: this build measures one GPU only (the workload is one GPU's share; "
               "see the sharding notes in DESIGN.md); --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.copy_calibrate:
+        copy_calibrate()
+        return
     import torch
     from paper_1605_01799_amd import hopf as H
     from paper_1605_01799_amd import workloads as W
@@ -106,7 +143,8 @@ def main():
                    "products": "BF16 MFMA on increments + FP64 MFMA anchors" if a.precision == "bf16_refined"
                    else "FP32 MFMA"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(a.precision, npts, tol), "traffic_unit": "HBM bytes read + written per launch",
                      "kernel": "dense_kernel (one launch per step)",
                      "algorithmic": "sum over points of iterations x 2 n^2 FLOP",
                      "flop_per_launch": flops, "launch_ms": eval_ms},

@@ -35,8 +35,10 @@
  *    status; no state is changed on error.  hopf_last_error() returns a
  *    thread-local description of the last non-OK status.  Per-point problems
  *    are reported in iters[]: >= 1 converged after that many v-updates, -2
- *    the iteration cap was hit (outputs come from the last iterate), -1 a
- *    non-finite input or t <= 0 (outputs are NaN).
+ *    the iteration cap was hit, or (HOPF_F32 only) the step norm stopped
+ *    decreasing for 64 iterations before reaching tol, i.e. the iterate
+ *    stalled at FP32 precision (outputs come from the last iterate), -1 a
+ *    non-finite input, or t <= 0 or not finite (outputs are NaN).
  *  - Calls that share a problem handle may run concurrently on different
  *    streams; calls on one device share the workspace and are serialised by
  *    the library's per-device lock around enqueueing (not around execution:
@@ -130,7 +132,9 @@ hopf_status hopf_eval(hopf_problem_t problem, int64_t npts, const void* x, const
  * ellipsoid), inside (npts, nullable: 1 if y lies in the union, then dist = 0
  * and cp = y), newton (npts, nullable: Newton steps of the nearest ellipsoid,
  * -2 if a cap was hit, -1 for a non-finite y).  s_tol: Newton stops when
- * |s_{l+1} - s_l| <= s_tol * max(1, s). */
+ * |s_{l+1} - s_l| <= s_tol * max(1, s).  Every inner solve has its own
+ * max_iter budget; a solve that hits it (or stalls, HOPF_F32) still gives
+ * the Newton step, and the point is then reported with newton = -2. */
 hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void* y, double s_tol,
                                void* dist, void* cp, int32_t* kstar, int32_t* inside,
                                int32_t* newton, void* stream);

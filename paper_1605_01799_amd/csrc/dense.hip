@@ -197,13 +197,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 struct ColShared {
   double t[kMaxCols], th1[kMaxCols], th2[kMaxCols], gam[kMaxCols], gama[kMaxCols], dgam[kMaxCols];
   double ssa2[kMaxCols], ssq[kMaxCols], prev[kMaxCols], s[kMaxCols], phi[kMaxCols], hp[kMaxCols];
-  double pn[kMaxCols];
-  int col[kMaxCols], j[kMaxCols], k[kMaxCols], state[kMaxCols], phase[kMaxCols], iters[kMaxCols];
+  double pn[kMaxCols], best[kMaxCols];
+  int stall[kMaxCols], col[kMaxCols], j[kMaxCols], k[kMaxCols], state[kMaxCols], phase[kMaxCols], iters[kMaxCols];
   int newton[kMaxCols], flags[kMaxCols], fresh[kMaxCols];
   double red[4][kMaxCols][kNRed];
   int ctl[16];
 };
-enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8 };
+// FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
+// FLAG_CAPPED: some solve of this slot did (reported as -2).
+enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16 };
+// FP32 mode: the split-Bregman step norm is nonincreasing in exact arithmetic (the iteration
+// map is firmly nonexpansive), so a step that has not reached a new minimum for this many
+// iterations is rounding noise: the iterate has stalled at the working precision.
+constexpr int kStallIters = 64;
 enum {
   CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
   CTL_EXIT, CTL_BETTER, CTL_ANY
@@ -480,11 +486,12 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       const int64_t jj = S.j[c];
       const double tv = distance ? 0.0 : (double)pb.t[jj];
       S.t[c] = tv;
-      S.state[c] = (distance || tv > 0.0) ? COL_ACTIVE : COL_INVALID;
+      S.state[c] = (distance || (tv > 0.0 && isfinite(tv))) ? COL_ACTIVE : COL_INVALID;
       S.th1[c] = has_l1 ? tv / lam : 0.0;
       S.th2[c] = (!distance && has_l2) ? tv / lam : 0.0;
       S.gam[c] = 1.0; S.gama[c] = 1.0; S.dgam[c] = 0.0; S.ssa2[c] = 0.0; S.ssq[c] = 0.0;
       S.prev[c] = 1e300; S.s[c] = 0.0; S.phi[c] = 0.0; S.hp[c] = 0.0; S.pn[c] = 0.0;
+      S.best[c] = 1e300; S.stall[c] = 0;
       S.iters[c] = 0; S.newton[c] = 0; S.flags[c] = FLAG_FIRST; S.phase[c] = PH_WARMUP;
     }
     __syncthreads();
@@ -783,13 +790,18 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const double a = sqrt(sm[0]), b = sqrt(S.prev[c]);
         S.prev[c] = sm[0];
         const bool conv = can_stop && (a + b) * (a + b) <= pb.tol;
-        const bool capped = S.iters[c] >= pb.max_iter;
+        bool stalled = false;
+        if (MODE == 0) {
+          if (sm[0] < S.best[c]) { S.best[c] = sm[0]; S.stall[c] = 0; }
+          else stalled = ++S.stall[c] >= kStallIters;
+        }
+        const bool capped = S.iters[c] >= pb.max_iter || stalled;
         if (st == COL_ACTIVE) {
           if (conv) S.state[c] = COL_WAITING;
-          else if (capped) { S.state[c] = COL_WAITING; S.flags[c] |= FLAG_CAPPED; }
+          else if (capped) { S.state[c] = COL_WAITING; S.flags[c] |= FLAG_SOLVE_CAP | FLAG_CAPPED; }
         } else {
-          if (capped && !conv) S.flags[c] |= FLAG_CAPPED;
-          if (conv || (S.flags[c] & FLAG_CAPPED)) evaluate = true;
+          if (capped && !conv) S.flags[c] |= FLAG_SOLVE_CAP | FLAG_CAPPED;
+          if (conv || (S.flags[c] & FLAG_SOLVE_CAP)) evaluate = true;
           else S.state[c] = COL_ACTIVE;
         }
       }
@@ -804,7 +816,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         } else {
           if (S.s[c] == 0.0 && val <= 0.0) {  // psi(y, 0) = L_k(y) <= 0: y lies in ellipsoid k
             S.flags[c] |= FLAG_INSIDE; S.state[c] = COL_DONE;
-          } else if (!(pn > 0.0) || (S.flags[c] & FLAG_CAPPED)) {
+          } else if (!(pn > 0.0)) {
             S.state[c] = COL_DONE;
           } else {
             const double ds = val / pn;  // s_{l+1} = s_l - psi / (d psi / ds), d psi/ds = -|grad psi|
@@ -820,7 +832,10 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               const double nz = sqrt(fmax(S.ssq[c], 0.0));
               const double g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
               S.gam[c] = g; S.dgam[c] = g - S.gama[c];
-              S.prev[c] = 1e300;
+              // a new solve: its own iteration budget and stall watch (a capped solve still
+              // gives a usable psi and gradient, so Newton goes on and the result is flagged)
+              S.prev[c] = 1e300; S.best[c] = 1e300; S.stall[c] = 0; S.iters[c] = 0;
+              S.flags[c] &= ~FLAG_SOLVE_CAP;
               S.state[c] = COL_ACTIVE;
             }
           }

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   const T* xj = (const T*)pb.x + j * n;
   const double t = (double)((const T*)pb.t)[j];
   double x[NMAX];
-  bool ok = t > 0.0;
+  bool ok = t > 0.0 && isfinite(t);
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     x[i] = i < n ? (double)xj[i] : 0.0;
