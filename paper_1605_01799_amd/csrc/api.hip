@@ -409,20 +409,25 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     int64_t o = 0;
     for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
   }
-  // one launch per column-width class (problems whose padded size gives the same slots per tile)
+  // one launch per kernel class: columns per tile and workgroups per CU (key = 4 cols + occupancy)
+  auto class_of = [&](int n_pad) -> int {
+    return 4 * dense_cols_per_tile(mode, n_pad) + dense_occupancy(mode, n_pad);
+  };
   std::vector<int> classes;
   for (auto& c : calls) {
-    int pt = dense_cols_per_tile(mode, c.p->n_pad);
-    if (c.view.npts > 0 && std::find(classes.begin(), classes.end(), pt) == classes.end()) classes.push_back(pt);
+    const int key = class_of(c.p->n_pad);
+    if (c.view.npts > 0 && std::find(classes.begin(), classes.end(), key) == classes.end()) classes.push_back(key);
   }
-  std::sort(classes.begin(), classes.end(), [](int a, int b) { return a > b; });
+  std::sort(classes.begin(), classes.end());
   int cls = 0;
-  for (int pt : classes) {
+  for (int key : classes) {
+    const int pt = key / 4;
+    const int occ = key % 4;
     std::vector<DenseProb> views;
     std::vector<std::pair<double, int>> order;  // (cost, view index)
     int max_npad = 32;
     for (auto& c : calls) {
-      if (dense_cols_per_tile(mode, c.p->n_pad) != pt || c.view.npts == 0) continue;
+      if (class_of(c.p->n_pad) != key || c.view.npts == 0) continue;
       order.push_back({(double)c.p->n_pad * c.p->n_pad * c.p->K * (double)c.view.npts, (int)views.size()});
       views.push_back(c.view);
       max_npad = std::max(max_npad, c.p->n_pad);
@@ -452,7 +457,7 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     std::memcpy(blob.data() + off_c, ch.data(), sizeof(DenseChunk) * nchunks);
     void* dmeta = nullptr;
     if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
-    const int grid = std::min(nchunks, w->ncu);
+    const int grid = std::min(nchunks, occ * w->ncu);
     const int64_t ws_per_wg = 4 * (int64_t)pt * max_npad;
     const int64_t ws64_per_wg = (int64_t)pt * max_npad;
     if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
@@ -465,9 +470,9 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
       hipError_t e = launch_reset(counter, v.bestv, v.bestk, v.npts, stream);
       if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
     }
-    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta, (const DenseChunk*)((unsigned char*)dmeta + off_c),
-                                nchunks, counter, w->state, w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance,
-                                anchor_every, stream);
+    const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
+    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state, w->state64,
+                                ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every, occ, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
     ++cls;
     // the next class reuses the metadata/staging buffers and the workspace: wait for this one

@@ -38,194 +38,21 @@
 // grad L_k(y), each Newton step warm-starting the inner iteration.
 #include "common.hpp"
 #include "dense.hpp"
+#include "dense_shared.hpp"
 
 namespace hopf {
 
-constexpr int kMaxCols = 64;
-constexpr int kNRed = 6;  // step^2, |s|^2 increment, <x',d>, (2d-v).(r-lam v), sum w|d|, |d|^2
-
-// Per-slot state accesses (global address space; the resident slots' state is sized to stay in
-// the last-level cache, so ordinary cached accesses are used).
-__device__ __forceinline__ f32x4 ld_nt4(const float* p) { return *gp((const f32x4*)p); }
-__device__ __forceinline__ void st_nt4(float* p, f32x4 v) { *gp((f32x4*)p) = v; }
-__device__ __forceinline__ float ld_nt(const float* p) { return *gp(p); }
-__device__ __forceinline__ void st_nt(float* p, float v) { *gp(p) = v; }
-__device__ __forceinline__ double ld_nt(const double* p) { return *gp(p); }
-__device__ __forceinline__ void st_nt(double* p, double v) { *gp(p) = v; }
-
-__device__ __forceinline__ float clampf(float z, float lo, float hi) { return fminf(fmaxf(z, lo), hi); }
-// FP32 threshold of coordinate i, used for the per-iteration increments (every use of a slot's
-// threshold goes through this one formula, so all of them agree bit for bit).
-__device__ __forceinline__ float theta_f(float th1f, float wf) { return th1f * wf; }
-// shrink1 of an anchor value in FP64 with the FP64 threshold: the anchor reference d^a must be
-// exact, since every increment of the following iterations is measured from it.
-__device__ __forceinline__ double anchor_shrink(float za, double th1, const double* w, int i) {
-  const double z = (double)za, th = th1 * *gp(w + i);
-  return z - fmin(fmax(z, -th), th);
-}
-
-template <int MODE, int CT>
-struct Dense {
-  static constexpr int PT = 16 * CT;  // columns per tile
-  static constexpr int RG = 4;        // row tiles per wave per pass
-
-  // ---------------------------------------------------------------- GEMM pieces
-  // acc[r][c] += M[16 rt_r .. , :] * B[:, 16 c ..] over the full contraction.
-  // All RG row tiles are always computed (a row-tile index past the end is clamped to tile 0 and
-  // its result discarded by the caller), so the MFMA stream has no branches.
-  static __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pad,
-                                                   const __bf16* B, int ldb, const int* rt, int nrt,
-                                                   f32x4 (&acc)[RG][CT]) {
-    // A fragments (rows of M, L2-resident) stream with three k-steps in flight; B is in LDS.
-    const int l = threadIdx.x & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const HOPF_GLOBAL bf16x8* arow[RG];
-#pragma unroll
-    for (int r = 0; r < RG; ++r)
-      arow[r] = gp((const bf16x8*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 8 * lg));
-    const bf16x8* bcol = (const bf16x8*)(B + lr * ldb + 8 * lg);
-    const int bstride = 16 * ldb / 8;  // in bf16x8 units
-    const int nk = n_pad >> 5;
-    bf16x8 a[4][RG];
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (u < nk) {
-#pragma unroll
-        for (int r = 0; r < RG; ++r) a[u][r] = arow[r][4 * u];
-      }
-    for (int ks = 0; ks < nk; ks += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = ks + u;
-        if (kk < nk) {
-          if (kk + 3 < nk) {
-#pragma unroll
-            for (int r = 0; r < RG; ++r) a[(u + 3) & 3][r] = arow[r][4 * (kk + 3)];
-          }
-          bf16x8 b[CT];
-#pragma unroll
-          for (int c = 0; c < CT; ++c) b[c] = bcol[c * bstride + 4 * kk];
-#pragma unroll
-          for (int r = 0; r < RG; ++r)
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][r], b[c], acc[r][c], 0, 0, 0);
-        }
-      }
-    }
-  }
-
-  static __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad, const float* B,
-                                                  int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
-    const int l = threadIdx.x & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const HOPF_GLOBAL f32x4* arow[RG];
-#pragma unroll
-    for (int r = 0; r < RG; ++r)
-      arow[r] = gp((const f32x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 4 * lg));
-    const float* bcol = B + lr * ldb + 4 * lg;
-    f32x4 an[RG];
-#pragma unroll
-    for (int r = 0; r < RG; ++r) an[r] = arow[r][0];
-    for (int k0 = 0; k0 < n_pad; k0 += 16) {
-      f32x4 a[RG], b[CT];
-#pragma unroll
-      for (int r = 0; r < RG; ++r) a[r] = an[r];
-      if (k0 + 16 < n_pad) {
-#pragma unroll
-        for (int r = 0; r < RG; ++r) an[r] = arow[r][(k0 + 16) / 4];
-      }
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + k0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < RG; ++r)
-#pragma unroll
-          for (int c = 0; c < CT; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
-    }
-  }
-
-  // FP64: the RG row tiles times a K-chunk [k0, k0 + kc) of the right-hand-side block held in
-  // LDS (B[c * ldb + kk], chunk-local kk).  A rows are loaded in the order 4(rho%4) + rho/4 so
-  // that the output lands in the lane layout of the FP32/BF16 16x16 products:
-  // lane l, register i -> row 4(l/16) + i, column l%16.
-  static __device__ __forceinline__ void gemm_f64_chunk(const double* __restrict__ M, int n_pad, int k0, int kc,
-                                                        const double* B, int ldb, const int* rt, int nrt,
-                                                        f64x4 (&acc)[RG][CT]) {
-    const int l = threadIdx.x & 63;
-    const int lr = l & 15, lg = l >> 4;
-    const int arow_perm = 4 * (lr & 3) + (lr >> 2);
-    const HOPF_GLOBAL f64x4* arow[RG];
-#pragma unroll
-    for (int r = 0; r < RG; ++r)
-      arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
-    const double* bcol = B + lr * ldb + 4 * lg;
-    f64x4 an[RG];
-#pragma unroll
-    for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r]);
-    for (int kk = 0; kk < kc; kk += 16) {
-      f64x4 a[RG], b[CT];
-#pragma unroll
-      for (int r = 0; r < RG; ++r) a[r] = an[r];
-      if (kk + 16 < kc) {
-#pragma unroll
-        for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r] + (kk + 16) / 4);
-      }
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < RG; ++r)
-#pragma unroll
-          for (int c = 0; c < CT; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
-    }
-  }
-};
-
-// Wave-level sum of a double across the 64 lanes (result in every lane).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-// Per-column (slot) scalars and the workgroup's control words, in LDS.
-struct ColShared {
-  double t[kMaxCols], th1[kMaxCols], th2[kMaxCols], gam[kMaxCols], gama[kMaxCols], dgam[kMaxCols];
-  double ssa2[kMaxCols], ssq[kMaxCols], prev[kMaxCols], s[kMaxCols], phi[kMaxCols], hp[kMaxCols];
-  double pn[kMaxCols], best[kMaxCols];
-  int stall[kMaxCols], col[kMaxCols], j[kMaxCols], k[kMaxCols], state[kMaxCols], phase[kMaxCols], iters[kMaxCols];
-  int newton[kMaxCols], flags[kMaxCols], fresh[kMaxCols];
-  double red[4][kMaxCols][kNRed];
-  int ctl[16];
-};
-// FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
-// FLAG_CAPPED: some solve of this slot did (reported as -2).
-enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16 };
-// FP32 mode: the split-Bregman step norm is nonincreasing in exact arithmetic (the iteration
-// map is firmly nonexpansive), so a step that has not reached a new minimum for this many
-// iterations is rounding noise: the iterate has stalled at the working precision.
-constexpr int kStallIters = 64;
-enum {
-  CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
-  CTL_EXIT, CTL_BETTER, CTL_ANY
-};
-enum { PH_WARMUP = 0, PH_DELTA = 1 };
-
-template <int MODE, int CT>
-__global__ void __launch_bounds__(kBlock, 1)
+// MODE 0: FP32 products; MODE 1: BF16 increments + FP64 anchors.  CT column tiles of 16, RG row
+// tiles per wave and product pass, OCC workgroups per CU (2: each workgroup keeps at most 256
+// registers per lane and 80 KiB of LDS, so two tiles interleave their products and epilogues).
+template <int MODE, int CT, int RG, int OCC>
+__global__ void __launch_bounds__(kBlock, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
              int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every) {
-  using D = Dense<MODE, CT>;
-  constexpr int PT = D::PT;
-  constexpr int RG = D::RG;
+  constexpr int PT = 16 * CT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  __shared__ ColShared S;
+  __shared__ ColShared<PT> S;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, l = tid & 63;
@@ -304,7 +131,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       // v^a = M r^a (FP64 MFMA), K-chunked through LDS; ea = v^a - d^a
       {
         double* B64 = (double*)lds_raw;
-        const int KC = n_pad < (PT == 64 ? 256 : 512) ? n_pad : (PT == 64 ? 256 : 512);
+        constexpr int KCM = dense_anchor_chunk(PT, OCC);
+        const int KC = n_pad < KCM ? n_pad : KCM;
         const int ldb = KC + 2;
         for (int rt0 = 0; rt0 < RT; rt0 += 4 * RG) {
           int rt[RG]; int nrt = 0;
@@ -333,7 +161,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               B64[c * ldb + kk] = r;
             }
             __syncthreads();
-            D::gemm_f64_chunk(pb.Md, n_pad, k0, kc, B64, ldb, rt, nrt, acc);
+            gemm_f64_chunk<RG, CT>(pb.Md, n_pad, k0, kc, B64, ldb, rt, nrt, acc);
           }
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
@@ -627,8 +455,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       for (int r = 0; r < RG; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (MODE == 1) D::gemm_bf16(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
-      else D::gemm_f32(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
+      if (MODE == 1) gemm_bf16<RG, CT>(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
+      else gemm_f32<RG, CT>(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
 
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -864,17 +692,25 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 // Host side
 // ---------------------------------------------------------------------------
 int dense_cols_per_tile(int mode, int n_pad) {
-  if (mode == 1) return n_pad <= 1024 ? 64 : 32;
+  if (mode == 1) return (n_pad <= 1024 && dense_occupancy(mode, n_pad) == 1) ? 64 : 32;
   if (n_pad <= 512) return 64;
   if (n_pad <= 1024) return 32;
   return 16;
+}
+
+int dense_occupancy(int mode, int n_pad) {
+  static const int occ2 = [] {
+    const char* v = getenv("HOPF_OCC2");
+    return v ? atoi(v) : 1;
+  }();
+  return (mode == 1 && n_pad <= 1024 && occ2) ? 2 : 1;
 }
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_cols_per_tile(mode, n_pad);
   if (mode == 1) {
     const size_t b16 = (size_t)pt * (n_pad + 8) * 2;
-    const int kc_max = pt == 64 ? 256 : 512;
+    const int kc_max = dense_anchor_chunk(pt, dense_occupancy(mode, n_pad));
     const int kc = n_pad < kc_max ? n_pad : kc_max;
     const size_t b64 = (size_t)pt * (kc + 2) * 8;
     return b16 > b64 ? b16 : b64;
@@ -895,11 +731,11 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
   return hipGetLastError();
 }
 
-template <int MODE, int CT>
+template <int MODE, int CT, int RG, int OCC>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
                            int distance, int anchor_every, hipStream_t stream) {
-  auto kern = dense_kernel<MODE, CT>;
+  auto kern = dense_kernel<MODE, CT, RG, OCC>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -914,19 +750,19 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
 
 hipError_t launch_dense(int mode, int cols_per_tile, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream) {
+                        int grid, size_t lds, int distance, int anchor_every, int occ, hipStream_t stream) {
   const int ct = cols_per_tile / 16;
-#define HOPF_LAUNCH(M, C) \
-  return launch_t<M, C>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, distance, \
-                        anchor_every, stream)
+#define HOPF_LAUNCH(M, C, R, O)                                                                                  \
+  return launch_t<M, C, R, O>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
+                              distance, anchor_every, stream)
   if (mode == 1) {
-    if (ct == 4) HOPF_LAUNCH(1, 4);
-    if (ct == 2) HOPF_LAUNCH(1, 2);
-    if (ct == 1) HOPF_LAUNCH(1, 1);
+    if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2);
+    if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1);
+    if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1);
   } else {
-    if (ct == 4) HOPF_LAUNCH(0, 4);
-    if (ct == 2) HOPF_LAUNCH(0, 2);
-    if (ct == 1) HOPF_LAUNCH(0, 1);
+    if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1);
+    if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1);
+    if (ct == 1) HOPF_LAUNCH(0, 1, 4, 1);
   }
 #undef HOPF_LAUNCH
   return hipErrorInvalidValue;

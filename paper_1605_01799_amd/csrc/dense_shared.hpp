@@ -1,0 +1,207 @@
+// Pieces of the dense solver: helpers, the per-wave MFMA products, and the per-column control
+// block kept in LDS.
+#pragma once
+#include "common.hpp"
+
+namespace hopf {
+
+constexpr int kMaxCols = 64;
+constexpr int kNRed = 6;  // step^2, |s|^2 increment, <x',d>, (2d-v).(r-lam v), sum w|d|, |d|^2
+
+// Per-slot state accesses (global address space; the resident slots' state is sized to stay in
+// the last-level cache, so ordinary cached accesses are used).
+__device__ __forceinline__ f32x4 ld_nt4(const float* p) { return *gp((const f32x4*)p); }
+__device__ __forceinline__ void st_nt4(float* p, f32x4 v) { *gp((f32x4*)p) = v; }
+__device__ __forceinline__ float ld_nt(const float* p) { return *gp(p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { *gp(p) = v; }
+__device__ __forceinline__ double ld_nt(const double* p) { return *gp(p); }
+__device__ __forceinline__ void st_nt(double* p, double v) { *gp(p) = v; }
+
+__device__ __forceinline__ float clampf(float z, float lo, float hi) { return fminf(fmaxf(z, lo), hi); }
+// FP32 threshold of coordinate i, used for the per-iteration increments (every use of a slot's
+// threshold goes through this one formula, so all of them agree bit for bit).
+__device__ __forceinline__ float theta_f(float th1f, float wf) { return th1f * wf; }
+// shrink1 of an anchor value in FP64 with the FP64 threshold: the anchor reference d^a must be
+// exact, since every increment of the following iterations is measured from it.
+__device__ __forceinline__ double anchor_shrink(float za, double th1, const double* w, int i) {
+  const double z = (double)za, th = th1 * *gp(w + i);
+  return z - fmin(fmax(z, -th), th);
+}
+
+// ---------------------------------------------------------------- GEMM pieces (one wave)
+// acc[r][c] += M[16 rt_r .. , :] * B[:, 16 c ..] over the full contraction.
+// All RG row tiles are always computed (a row-tile index past the end is clamped to tile 0 and
+// its result discarded by the caller), so the MFMA stream has no branches.
+template <int RG, int CT, int PF = 3>
+__device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pad,
+                                                 const __bf16* B, int ldb, const int* rt, int nrt,
+                                                 f32x4 (&acc)[RG][CT]) {
+  // A fragments (rows of M, L2-resident) stream with PF k-steps in flight; B is in LDS.
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const HOPF_GLOBAL bf16x8* arow[RG];
+#pragma unroll
+  for (int r = 0; r < RG; ++r)
+    arow[r] = gp((const bf16x8*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 8 * lg));
+  const bf16x8* bcol = (const bf16x8*)(B + lr * ldb + 8 * lg);
+  const int bstride = 16 * ldb / 8;  // in bf16x8 units
+  const int nk = n_pad >> 5;
+  constexpr int NB = PF + 1;  // register buffers of A fragments
+  bf16x8 a[NB][RG];
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    if (u < nk) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) a[u][r] = arow[r][4 * u];
+    }
+  for (int ks = 0; ks < nk; ks += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int kk = ks + u;
+      if (kk < nk) {
+        if (kk + PF < nk) {
+#pragma unroll
+          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][4 * (kk + PF)];
+        }
+        bf16x8 b[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = bcol[c * bstride + 4 * kk];
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][r], b[c], acc[r][c], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int RG, int CT>
+__device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad, const float* B,
+                                                int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const HOPF_GLOBAL f32x4* arow[RG];
+#pragma unroll
+  for (int r = 0; r < RG; ++r)
+    arow[r] = gp((const f32x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 4 * lg));
+  const float* bcol = B + lr * ldb + 4 * lg;
+  f32x4 an[RG];
+#pragma unroll
+  for (int r = 0; r < RG; ++r) an[r] = arow[r][0];
+  for (int k0 = 0; k0 < n_pad; k0 += 16) {
+    f32x4 a[RG], b[CT];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) a[r] = an[r];
+    if (k0 + 16 < n_pad) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) an[r] = arow[r][(k0 + 16) / 4];
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + k0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
+  }
+}
+
+// FP64: the RG row tiles times a K-chunk [k0, k0 + kc) of the right-hand-side block held in
+// LDS (B[c * ldb + kk], chunk-local kk).  A rows are loaded in the order 4(rho%4) + rho/4 so
+// that the output lands in the lane layout of the FP32/BF16 16x16 products:
+// lane l, register i -> row 4(l/16) + i, column l%16.
+template <int RG, int CT>
+__device__ __forceinline__ void gemm_f64_chunk(const double* __restrict__ M, int n_pad, int k0, int kc,
+                                                      const double* B, int ldb, const int* rt, int nrt,
+                                                      f64x4 (&acc)[RG][CT]) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const int arow_perm = 4 * (lr & 3) + (lr >> 2);
+  const HOPF_GLOBAL f64x4* arow[RG];
+#pragma unroll
+  for (int r = 0; r < RG; ++r)
+    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
+  const double* bcol = B + lr * ldb + 4 * lg;
+  f64x4 an[RG];
+#pragma unroll
+  for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r]);
+  for (int kk = 0; kk < kc; kk += 16) {
+    f64x4 a[RG], b[CT];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) a[r] = an[r];
+    if (kk + 16 < kc) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r] + (kk + 16) / 4);
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
+  }
+}
+
+// FP64: one row tile (rows 16 rt ..) times a K-chunk [k0, k0 + kc) of the right-hand-side block
+// in LDS, accumulated into acc[c]; same row permutation and output layout as gemm_f64_chunk.
+template <int CT>
+__device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ M, int n_pad, int rt, int k0, int kc,
+                                              const double* B, int ldb, f64x4 (&acc)[CT]) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const int arow_perm = 4 * (lr & 3) + (lr >> 2);
+  const HOPF_GLOBAL f64x4* arow = gp((const f64x4*)(M + (size_t)(16 * rt + arow_perm) * n_pad + k0 + 4 * lg));
+  const double* bcol = B + lr * ldb + 4 * lg;
+  f64x4 an = __builtin_nontemporal_load(arow);
+  for (int kk = 0; kk < kc; kk += 16) {
+    const f64x4 a = an;
+    if (kk + 16 < kc) an = __builtin_nontemporal_load(arow + (kk + 16) / 4);
+    f64x4 b[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[c][q], acc[c], 0, 0, 0);
+  }
+}
+
+// Wave-level sum of a double across the 64 lanes (result in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Per-column (slot) scalars and the workgroup's control words, in LDS (P columns).
+template <int P>
+struct ColShared {
+  double t[P], th1[P], th2[P], gam[P], gama[P], dgam[P];
+  double ssa2[P], ssq[P], prev[P], s[P], phi[P], hp[P];
+  double pn[P], best[P];
+  int stall[P], col[P], j[P], k[P], state[P], phase[P], iters[P];
+  int newton[P], flags[P], fresh[P];
+  double red[4][P][kNRed];
+  int ctl[16];
+};
+// FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
+// FLAG_CAPPED: some solve of this slot did (reported as -2).
+enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16 };
+// FP32 mode: the split-Bregman step norm is nonincreasing in exact arithmetic (the iteration
+// map is firmly nonexpansive), so a step that has not reached a new minimum for this many
+// iterations is rounding noise: the iterate has stalled at the working precision.
+constexpr int kStallIters = 64;
+enum {
+  CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
+  CTL_EXIT, CTL_BETTER, CTL_ANY
+};
+enum { PH_WARMUP = 0, PH_DELTA = 1 };
+
+
+}  // namespace hopf
