@@ -35,6 +35,21 @@ enum ColState : int {
   COL_INVALID = 5   // non-finite input or t <= 0
 };
 
+// Operand layouts of the rounded copies of M (n_pad x n_pad, rows padded with zeros): stored in
+// the order the MFMA A fragments are read, so that a wave's fragment load is contiguous.
+//  BF16 (16x16x32 products): fragment (row tile rt, k-step kk of 32): lane l = r + 16 g holds
+//    M[16 rt + r][32 kk + 8 g .. + 7]; fragments in (rt, kk) order, 64 lanes x 8 values each.
+//  FP32 (16x16x4 products, 16 columns per step): fragment (rt, ks of 16): lane l = r + 16 g holds
+//    M[16 rt + r][16 ks + 4 g .. + 3].
+__host__ __device__ inline size_t mb_index(int i, int j, int n_pad) {
+  const int nk = n_pad >> 5;
+  return (((size_t)(i >> 4) * nk + (j >> 5)) * 64 + (i & 15) + 16 * ((j >> 3) & 3)) * 8 + (j & 7);
+}
+__host__ __device__ inline size_t mf_index(int i, int j, int n_pad) {
+  const int nks = n_pad >> 4;
+  return (((size_t)(i >> 4) * nks + (j >> 4)) * 64 + (i & 15) + 16 * ((j >> 2) & 3)) * 4 + (j & 3);
+}
+
 // Hamiltonian kinds (same numbering as the public header).
 enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2 };
 __host__ __device__ inline bool hk_has_l1(int hk) { return hk == HK_WL1 || hk == HK_L2_WL1; }

@@ -93,38 +93,64 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 
     // ================================================================ anchor (REFINED mode)
     if (MODE == 1 && S.ctl[CTL_ANCHOR]) {
-      // pass A (one wave per slot): renormalise z = za + dz, exact anchor reference s_a, norms
-      for (int c = wave; c < PT; c += 4) {
-        const int st = S.state[c];
-        if (st != COL_ACTIVE && st != COL_WAITING) continue;
-        const double th1 = S.th1[c];
-        double pss = 0.0, pinc = 0.0;
-        for (int i = l; i < n_pad; i += 64) {
-          const size_t e = (size_t)c * n_pad + i;
-          const double z = (double)ld_nt(za + e) + (double)ld_nt(dz + e);
-          const float zan = (float)z;
-          const float dzn = (float)(z - (double)zan);
-          st_nt(za + e, zan); st_nt(dz + e, dzn);
-          const float th = theta_f((float)th1, *gp(pb.wf + i));
-          const float ca = clampf(zan, -th, th), sa = zan - ca;
-          const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
-          const double sa64 = anchor_shrink(zan, th1, pb.w, i);
-          pss += sa64 * sa64;
-          pinc += (double)ds * (2.0 * (double)sa + (double)ds);
-        }
-        pss = wave_sum(pss); pinc = wave_sum(pinc);
-        if (l == 0) {
-          S.ssa2[c] = pss;
-          const double ssq = pss + pinc;
-          S.ssq[c] = ssq;
-          double ga = 1.0, g = 1.0;
-          if (has_l2) {
-            const double na = sqrt(pss), nz = sqrt(fmax(ssq, 0.0)), th2 = S.th2[c];
-            ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
-            g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
+      // pass A (block order, as the epilogue): renormalise z = za + dz (za the nearest float, dz
+      // the remainder), the exact anchor reference s_a in FP64, and the norms of the shrink2 factors
+      {
+        double pss[CT], pinc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          pss[ct] = 0.0; pinc[ct] = 0.0;
+          const int c = 16 * ct + (l & 15);
+          const int st = S.state[c];
+          if (st != COL_ACTIVE && st != COL_WAITING) continue;
+          const double th1 = S.th1[c];
+          for (int rt = wave; rt < RT; rt += 4) {
+            const int row0 = 16 * rt + 4 * (l >> 4);
+            const size_t et = st_block(rt, ct, RT) + 4 * l;
+            f32x4 zv = ld_nt4(za + et), dv = ld_nt4(dz + et);
+            const f32x4 wv = *gp((const f32x4*)(pb.wf + row0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double z = (double)zv[q] + (double)dv[q];
+              const float zan = (float)z;
+              const float dzn = (float)(z - (double)zan);
+              zv[q] = zan; dv[q] = dzn;
+              const float th = theta_f((float)th1, wv[q]);
+              const float ca = clampf(zan, -th, th), sa = zan - ca;
+              const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
+              const double sa64 = anchor_shrink(zan, th1, pb.w, row0 + q);
+              pss[ct] += sa64 * sa64;
+              pinc[ct] += (double)ds * (2.0 * (double)sa + (double)ds);
+            }
+            st_nt4(za + et, zv); st_nt4(dz + et, dv);
           }
-          S.gama[c] = ga; S.gam[c] = g; S.dgam[c] = g - ga;
-          S.phase[c] = PH_DELTA;
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          double a = pss[ct], b = pinc[ct];
+          a += __shfl_xor(a, 16); a += __shfl_xor(a, 32);
+          b += __shfl_xor(b, 16); b += __shfl_xor(b, 32);
+          if (l < 16) { S.red[wave][16 * ct + l][0] = a; S.red[wave][16 * ct + l][1] = b; }
+        }
+        __syncthreads();
+        if (tid < PT) {
+          const int c = tid;
+          const int st = S.state[c];
+          if (st == COL_ACTIVE || st == COL_WAITING) {
+            const double pssc = S.red[0][c][0] + S.red[1][c][0] + S.red[2][c][0] + S.red[3][c][0];
+            const double pincc = S.red[0][c][1] + S.red[1][c][1] + S.red[2][c][1] + S.red[3][c][1];
+            S.ssa2[c] = pssc;
+            const double ssq = pssc + pincc;
+            S.ssq[c] = ssq;
+            double ga = 1.0, g = 1.0;
+            if (has_l2) {
+              const double na = sqrt(pssc), nz = sqrt(fmax(ssq, 0.0)), th2 = S.th2[c];
+              ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
+              g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
+            }
+            S.gama[c] = ga; S.gam[c] = g; S.dgam[c] = g - ga;
+            S.phase[c] = PH_DELTA;
+          }
         }
       }
       __syncthreads();
@@ -146,19 +172,33 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           for (int k0 = 0; k0 < n_pad; k0 += KC) {
             const int kc = (n_pad - k0) < KC ? (n_pad - k0) : KC;  // multiple of 32: n_pad and KC are
             __syncthreads();
-            // r^a = x' + lambda (2 d^a - z^a) in FP64 for the anchored slots (0 for the others)
-            for (int g = tid; g < PT * kc; g += kBlock) {
-              const int c = g / kc, kk = g % kc, i = k0 + kk;
+            // r^a = x' + lambda (2 d^a - z^a) in FP64 for the anchored slots (0 for the others), in
+            // block order: the chunk's (row tile, column tile) blocks are shared among the waves
+            const int nrb = kc >> 4;
+            for (int b = wave; b < nrb * CT; b += 4) {
+              const int ct = b / nrb, rtc = (k0 >> 4) + b % nrb;
+              const int c = 16 * ct + (l & 15);
               const int st = S.state[c];
-              double r = 0.0;
-              if ((st == COL_ACTIVE || st == COL_WAITING) && i < n) {
-                const float zan = ld_nt(za + (size_t)c * n_pad + i);
-                const double sa64 = anchor_shrink(zan, S.th1[c], pb.w, i);
-                const double xp = (double)*gp(pb.x + (size_t)S.j[c] * n + i) -
-                                  (pb.centres ? *gp(pb.centres + (size_t)S.k[c] * n_pad + i) : 0.0);
-                r = xp + lam * (2.0 * S.gama[c] * sa64 - (double)zan);
+              const int row0 = 16 * rtc + 4 * (l >> 4);
+              double rv[4] = {0.0, 0.0, 0.0, 0.0};
+              if (st == COL_ACTIVE || st == COL_WAITING) {
+                const f32x4 zv = ld_nt4(za + st_block(rtc, ct, RT) + 4 * l);
+                const double th1 = S.th1[c], ga = S.gama[c];
+                const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
+                const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int row = row0 + q;
+                  if (row < n) {
+                    const double sa64 = anchor_shrink(zv[q], th1, pb.w, row);
+                    const double xp = (double)xj[row] - (cen ? cen[row] : 0.0);
+                    rv[q] = xp + lam * (2.0 * ga * sa64 - (double)zv[q]);
+                  }
+                }
               }
-              B64[c * ldb + kk] = r;
+              double* dst = B64 + c * ldb + (row0 - k0);
+              *(double2*)dst = double2{rv[0], rv[1]};
+              *(double2*)(dst + 2) = double2{rv[2], rv[3]};
             }
             __syncthreads();
             gemm_f64_chunk<RG, CT>(pb.Md, n_pad, k0, kc, B64, ldb, rt, nrt, acc);
@@ -174,14 +214,15 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               if (r >= nrt) continue;
               const int row0 = 16 * rt[r] + 4 * (l >> 4);
               f32x4 ev;
-              const f32x4 zv = ld_nt4(za + (size_t)c * n_pad + row0);
+              const size_t et = st_block(rt[r], ct, RT) + 4 * l;
+              const f32x4 zv = ld_nt4(za + et);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 const int row = row0 + i;
                 const double sa64 = anchor_shrink(zv[i], S.th1[c], pb.w, row);
                 ev[i] = (row < n) ? (float)(acc[r][ct][i] - ga * sa64) : 0.f;
               }
-              st_nt4(ea + (size_t)c * n_pad + row0, ev);
+              st_nt4(ea + et, ev);
             }
           }
         }
@@ -337,10 +378,12 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           if (!isfinite(xv)) bad = true;
           v = (float)((double)xv - (cen ? cen[i] : 0.0));
         }
-        const size_t e = (size_t)c * n_pad + i;
-        st_nt(za + e, (st == COL_ACTIVE) ? v : 0.f);
+        // until the first anchor, ea holds x' (the right-hand side of the plain iterations)
+        const size_t e = st_index(c, i, RT);
+        const float v0 = (st == COL_ACTIVE) ? v : 0.f;
+        st_nt(za + e, v0);
         st_nt(dz + e, 0.f);
-        st_nt(ea + e, 0.f);
+        st_nt(ea + e, v0);
       }
       const bool anybad = __any(bad);
       if (l == 0 && anybad && st == COL_ACTIVE) S.state[c] = COL_INVALID;
@@ -366,28 +409,28 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     }
 
     // ================================================================ prologue: right-hand sides
-    // One wave per slot: the slot's scalars are wave-uniform; lane l handles 4 consecutive
-    // coordinates per step.
+    // Block order: wave w takes the row tiles w, w+4, ... of every column tile; lane l works on
+    // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
     {
       const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;
-      for (int c = wave; c < PT; c += 4) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = 16 * ct + (l & 15);
         const int st = S.state[c];
         const bool on = st == COL_ACTIVE || st == COL_PHI;
         const bool deltac = MODE == 1 && S.phase[c] == PH_DELTA;
         const bool first = S.flags[c] & FLAG_FIRST;
         const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c], gf = (float)S.gam[c];
         const float th1f = (float)S.th1[c];
-        const HOPF_GLOBAL float* xj = on ? gp(pb.x + (size_t)S.j[c] * n) : nullptr;
-        const HOPF_GLOBAL double* cen = (on && pb.centres) ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
-        const float* zac = za + (size_t)c * n_pad;
-        const float* dzc = dz + (size_t)c * n_pad;
-        for (int i0 = 4 * l; i0 < n_pad; i0 += 256) {
+        for (int rt = wave; rt < RT; rt += 4) {
+          const int row0 = 16 * rt + 4 * (l >> 4);
+          const size_t et = st_block(rt, ct, RT) + 4 * l;
           f32x4 rv = {0.f, 0.f, 0.f, 0.f};
           if (on) {
-            const f32x4 zv = ld_nt4(zac + i0);
-            const f32x4 wv = *gp((const f32x4*)(pb.wf + i0));
+            const f32x4 zv = ld_nt4(za + et);
+            const f32x4 wv = *gp((const f32x4*)(pb.wf + row0));
             if (deltac) {
-              const f32x4 dv = ld_nt4(dzc + i0);
+              const f32x4 dv = ld_nt4(dz + et);
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const float th = theta_f(th1f, wv[q]);
@@ -397,16 +440,13 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 rv[q] = flam * (2.f * dd - dv[q]);
               }
             } else {
+              const f32x4 xpv = ld_nt4(ea + et);  // x' (0 beyond n)
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
-                const int i = i0 + q;
-                const int ic = i < n ? i : n - 1;  // in-bounds address; value masked below
-                const float xv = xj[ic];
-                const float xp = (i < n) ? (float)((double)xv - (cen ? cen[i] : 0.0)) : 0.f;
                 const float z = zv[q];
                 const float th = theta_f(th1f, wv[q]);
                 const float d = first ? z : gf * (z - clampf(z, -th, th));
-                rv[q] = (i < n) ? xp + flam * (2.f * d - z) : 0.f;
+                rv[q] = xpv[q] + flam * (2.f * d - z);
               }
             }
           }
@@ -415,9 +455,9 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
             bf16x4 o;
 #pragma unroll
             for (int q = 0; q < 4; ++q) o[q] = to_bf16(rv[q]);
-            *(bf16x4*)((__bf16*)lds_raw + c * ldb + i0) = o;
+            *(bf16x4*)((__bf16*)lds_raw + c * ldb + row0) = o;
           } else {
-            *(f32x4*)((float*)lds_raw + c * ldb + i0) = rv;
+            *(f32x4*)((float*)lds_raw + c * ldb + row0) = rv;
           }
         }
       }
@@ -471,16 +511,17 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         for (int r = 0; r < RG; ++r) {
           if (r >= nrt) continue;
           const int row0 = 16 * rt[r] + 4 * (l >> 4);
-          const size_t e = (size_t)c * n_pad + row0;
-          zst[r] = ld_nt4(za + e);
+          const size_t et = st_block(rt[r], ct, RT) + 4 * l;
+          zst[r] = ld_nt4(za + et);
           wst[r] = *gp((const f32x4*)(pb.wf + row0));
-          if (delta) { dst[r] = ld_nt4(dz + e); est[r] = ld_nt4(ea + e); }
+          if (delta) { dst[r] = ld_nt4(dz + et); est[r] = ld_nt4(ea + et); }
         }
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
           if (r >= nrt) continue;
           const int row0 = 16 * rt[r] + 4 * (l >> 4);
-          const size_t e = (size_t)c * n_pad + row0;
+          const size_t e = (size_t)c * n_pad + row0;      // value staging: column-major
+          const size_t et = st_block(rt[r], ct, RT) + 4 * l;  // state: block layout
           const f32x4 v = acc[r][ct];
           f32x4 zav = zst[r];
           if (delta) {
@@ -531,7 +572,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               }
               st_nt4(pout + e, pv);
             }
-            st_nt4(dz + e, dzv);
+            st_nt4(dz + et, dzv);
           } else {
             // plain iteration (F32 mode, or the BF16 warm-up): z^{k+1} = z - d + v
             const float gf = gf_[ct];
@@ -552,7 +593,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               }
               part[ct][0] += (double)s0;
               part[ct][1] += (double)s1;
-              st_nt4(za + e, zav);
+              st_nt4(za + et, zav);
             } else if (MODE == 0) {  // COL_PHI in F32 mode: r is in LDS
               const float* B32 = (const float*)lds_raw;
               const int ldb = n_pad + 4;

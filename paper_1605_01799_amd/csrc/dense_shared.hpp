@@ -17,6 +17,16 @@ __device__ __forceinline__ void st_nt(float* p, float v) { *gp(p) = v; }
 __device__ __forceinline__ double ld_nt(const double* p) { return *gp(p); }
 __device__ __forceinline__ void st_nt(double* p, double v) { *gp(p) = v; }
 
+// Slot-state layout (z^a, dz, e^a of a tile's PT columns, n_pad rows each): 16 x 16 blocks,
+// block (row tile rt, column tile ct) at (ct RT + rt) * 256 floats (RT = n_pad / 16); inside a
+// block the MFMA output lane order, lane l = column % 16 + 16 * ((row % 16) / 4) holding rows
+// 4 (l / 16) .. + 3 of column l % 16 as 4 consecutive floats.  A wave's f32x4 access of a block
+// is one contiguous KiB.
+__device__ __forceinline__ size_t st_block(int rt, int ct, int RT) { return ((size_t)ct * RT + rt) * 256; }
+__device__ __forceinline__ size_t st_index(int c, int i, int RT) {
+  return st_block(i >> 4, c >> 4, RT) + 4 * ((c & 15) + 16 * ((i & 15) >> 2)) + (i & 3);
+}
+
 __device__ __forceinline__ float clampf(float z, float lo, float hi) { return fminf(fmaxf(z, lo), hi); }
 // FP32 threshold of coordinate i, used for the per-iteration increments (every use of a slot's
 // threshold goes through this one formula, so all of them agree bit for bit).
@@ -39,20 +49,21 @@ __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pa
   // A fragments (rows of M, L2-resident) stream with PF k-steps in flight; B is in LDS.
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
+  // M is stored in fragment order (mb_index): row tile rt, k-step kk at (rt nk + kk) 64 + l
+  const int nk = n_pad >> 5;
   const HOPF_GLOBAL bf16x8* arow[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const bf16x8*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 8 * lg));
+    arow[r] = gp((const bf16x8*)M + (size_t)(r < nrt ? rt[r] : 0) * nk * 64 + l);
   const bf16x8* bcol = (const bf16x8*)(B + lr * ldb + 8 * lg);
   const int bstride = 16 * ldb / 8;  // in bf16x8 units
-  const int nk = n_pad >> 5;
   constexpr int NB = PF + 1;  // register buffers of A fragments
   bf16x8 a[NB][RG];
 #pragma unroll
   for (int u = 0; u < PF; ++u)
     if (u < nk) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r) a[u][r] = arow[r][4 * u];
+      for (int r = 0; r < RG; ++r) a[u][r] = arow[r][64 * u];
     }
   for (int ks = 0; ks < nk; ks += NB) {
 #pragma unroll
@@ -61,7 +72,7 @@ __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pa
       if (kk < nk) {
         if (kk + PF < nk) {
 #pragma unroll
-          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][4 * (kk + PF)];
+          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][64 * (kk + PF)];
         }
         bf16x8 b[CT];
 #pragma unroll
@@ -81,10 +92,12 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
                                                 int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
+  // M is stored in fragment order (mf_index): row tile rt, k-step ks at (rt nks + ks) 64 + l
+  const int nks = n_pad >> 4;
   const HOPF_GLOBAL f32x4* arow[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const f32x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + lr) * n_pad + 4 * lg));
+    arow[r] = gp((const f32x4*)M + (size_t)(r < nrt ? rt[r] : 0) * nks * 64 + l);
   const float* bcol = B + lr * ldb + 4 * lg;
   f32x4 an[RG];
 #pragma unroll
@@ -95,7 +108,7 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
     for (int r = 0; r < RG; ++r) a[r] = an[r];
     if (k0 + 16 < n_pad) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r) an[r] = arow[r][(k0 + 16) / 4];
+      for (int r = 0; r < RG; ++r) an[r] = arow[r][64 * ((k0 + 16) >> 4)];
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + k0);

@@ -160,8 +160,8 @@ __global__ void finalize_copies_kernel(const double* S, int n, int n_pad, double
   double v = 0.0;
   if (i < n && j < n) v = 0.5 * (S[(size_t)i * n_pad + j] + S[(size_t)j * n_pad + i]);
   if (Md) Md[e] = v;
-  if (Mf) Mf[e] = (float)v;
-  if (Mb) Mb[e] = to_bf16((float)v);
+  if (Mf) Mf[mf_index(i, j, n_pad)] = (float)v;
+  if (Mb) Mb[mb_index(i, j, n_pad)] = to_bf16((float)v);
 }
 
 // Diagonal A: M = diag(1 / (a_i + lambda)).
@@ -172,8 +172,8 @@ __global__ void diag_inverse_kernel(const double* a, int n, int n_pad, double la
   int i = (int)(e / n_pad), j = (int)(e % n_pad);
   double v = (i == j && i < n) ? 1.0 / (a[i] + lambda) : 0.0;
   if (Md) Md[e] = v;
-  if (Mf) Mf[e] = (float)v;
-  if (Mb) Mb[e] = to_bf16((float)v);
+  if (Mf) Mf[mf_index(i, j, n_pad)] = (float)v;
+  if (Mb) Mb[mb_index(i, j, n_pad)] = to_bf16((float)v);
   if (minv_diag && i == j && i < n) minv_diag[i] = v;
 }
 
