@@ -57,7 +57,6 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
   const int tid = threadIdx.x;
   const int wave = tid >> 6, l = tid & 63;
   float* const wsb = ws + (int64_t)blockIdx.x * ws_per_wg;
-  (void)ws64; (void)ws64_per_wg;
 
   if (tid < PT) { S.state[tid] = COL_EMPTY; S.fresh[tid] = 0; }
   if (tid == 0) {
@@ -104,25 +103,37 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const int st = S.state[c];
           if (st != COL_ACTIVE && st != COL_WAITING) continue;
           const double th1 = S.th1[c];
-          for (int rt = wave; rt < RT; rt += 4) {
-            const int row0 = 16 * rt + 4 * (l >> 4);
-            const size_t et = st_block(rt, ct, RT) + 4 * l;
-            f32x4 zv = ld_nt4(za + et), dv = ld_nt4(dz + et);
-            const f32x4 wv = *gp((const f32x4*)(pb.wf + row0));
+          constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
+          for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+            f32x4 zv[PB], dv[PB], wv[PB];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const double z = (double)zv[q] + (double)dv[q];
-              const float zan = (float)z;
-              const float dzn = (float)(z - (double)zan);
-              zv[q] = zan; dv[q] = dzn;
-              const float th = theta_f((float)th1, wv[q]);
-              const float ca = clampf(zan, -th, th), sa = zan - ca;
-              const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
-              const double sa64 = anchor_shrink(zan, th1, pb.w, row0 + q);
-              pss[ct] += sa64 * sa64;
-              pinc[ct] += (double)ds * (2.0 * (double)sa + (double)ds);
+            for (int u = 0; u < PB; ++u) {
+              const int rtc = (rtb + 4 * u) < RT ? rtb + 4 * u : 0;
+              const size_t et = st_block(rtc, ct, RT) + 4 * l;
+              zv[u] = ld_nt4(za + et); dv[u] = ld_nt4(dz + et);
+              wv[u] = *gp((const f32x4*)(pb.wf + 16 * rtc + 4 * (l >> 4)));
             }
-            st_nt4(za + et, zv); st_nt4(dz + et, dv);
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+              const int rt = rtb + 4 * u;
+              if (rt >= RT) continue;  // wave-uniform
+              const int row0 = 16 * rt + 4 * (l >> 4);
+              const size_t et = st_block(rt, ct, RT) + 4 * l;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const double z = (double)zv[u][q] + (double)dv[u][q];
+                const float zan = (float)z;
+                const float dzn = (float)(z - (double)zan);
+                zv[u][q] = zan; dv[u][q] = dzn;
+                const float th = theta_f((float)th1, wv[u][q]);
+                const float ca = clampf(zan, -th, th), sa = zan - ca;
+                const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
+                const double sa64 = anchor_shrink(zan, th1, pb.w, row0 + q);
+                pss[ct] += sa64 * sa64;
+                pinc[ct] += (double)ds * (2.0 * (double)sa + (double)ds);
+              }
+              st_nt4(za + et, zv[u]); st_nt4(dz + et, dv[u]);
+            }
           }
         }
 #pragma unroll
@@ -154,55 +165,63 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         }
       }
       __syncthreads();
-      // v^a = M r^a (FP64 MFMA), K-chunked through LDS; ea = v^a - d^a
+      // v^a = M r^a (FP64 MFMA); ea = v^a - d^a.  r^a = x' + lambda (2 d^a - z^a) is formed once
+      // per anchor into the workgroup's FP64 staging (column-major, n_pad per column), which the
+      // products then stream as their right-hand sides.
       {
-        double* B64 = (double*)lds_raw;
-        constexpr int KCM = dense_anchor_chunk(PT, OCC);
-        const int KC = n_pad < KCM ? n_pad : KCM;
-        const int ldb = KC + 2;
-        for (int rt0 = 0; rt0 < RT; rt0 += 4 * RG) {
-          int rt[RG]; int nrt = 0;
+        double* const ra = ws64 + (int64_t)blockIdx.x * ws64_per_wg;
 #pragma unroll
-          for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
-          f64x4 acc[RG][CT];
+        for (int ct = 0; ct < CT; ++ct) {
+          const int c = 16 * ct + (l & 15);
+          const int st = S.state[c];
+          const bool on = st == COL_ACTIVE || st == COL_WAITING;
+          const double th1 = S.th1[c], ga = S.gama[c];
+          const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
+          const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
+          constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
+          for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+            f32x4 zv[PB];
 #pragma unroll
-          for (int r = 0; r < RG; ++r)
+            for (int u = 0; u < PB; ++u) {
+              const int rtc = (rtb + 4 * u) < RT ? rtb + 4 * u : 0;
+              zv[u] = on ? ld_nt4(za + st_block(rtc, ct, RT) + 4 * l) : f32x4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-          for (int k0 = 0; k0 < n_pad; k0 += KC) {
-            const int kc = (n_pad - k0) < KC ? (n_pad - k0) : KC;  // multiple of 32: n_pad and KC are
-            __syncthreads();
-            // r^a = x' + lambda (2 d^a - z^a) in FP64 for the anchored slots (0 for the others), in
-            // block order: the chunk's (row tile, column tile) blocks are shared among the waves
-            const int nrb = kc >> 4;
-            for (int b = wave; b < nrb * CT; b += 4) {
-              const int ct = b / nrb, rtc = (k0 >> 4) + b % nrb;
-              const int c = 16 * ct + (l & 15);
-              const int st = S.state[c];
-              const int row0 = 16 * rtc + 4 * (l >> 4);
+            for (int u = 0; u < PB; ++u) {
+              const int rt = rtb + 4 * u;
+              if (rt >= RT) continue;  // wave-uniform
+              const int row0 = 16 * rt + 4 * (l >> 4);
               double rv[4] = {0.0, 0.0, 0.0, 0.0};
-              if (st == COL_ACTIVE || st == COL_WAITING) {
-                const f32x4 zv = ld_nt4(za + st_block(rtc, ct, RT) + 4 * l);
-                const double th1 = S.th1[c], ga = S.gama[c];
-                const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
-                const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
+              if (on) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                   const int row = row0 + q;
                   if (row < n) {
-                    const double sa64 = anchor_shrink(zv[q], th1, pb.w, row);
+                    const double sa64 = anchor_shrink(zv[u][q], th1, pb.w, row);
                     const double xp = (double)xj[row] - (cen ? cen[row] : 0.0);
-                    rv[q] = xp + lam * (2.0 * ga * sa64 - (double)zv[q]);
+                    rv[q] = xp + lam * (2.0 * ga * sa64 - (double)zv[u][q]);
                   }
                 }
               }
-              double* dst = B64 + c * ldb + (row0 - k0);
-              *(double2*)dst = double2{rv[0], rv[1]};
-              *(double2*)(dst + 2) = double2{rv[2], rv[3]};
+              HOPF_GLOBAL double* dst = gp(ra + (size_t)c * n_pad + row0);
+              *(HOPF_GLOBAL f64x2*)dst = f64x2{rv[0], rv[1]};
+              *(HOPF_GLOBAL f64x2*)(dst + 2) = f64x2{rv[2], rv[3]};
             }
-            __syncthreads();
-            gemm_f64_chunk<RG, CT>(pb.Md, n_pad, k0, kc, B64, ldb, rt, nrt, acc);
           }
+        }
+        __syncthreads();  // the staging is complete (written and read by this workgroup only)
+        constexpr int RGA = (CT >= 4 && RG > 2) ? 2 : RG;  // row tiles per FP64 product pass
+        for (int rt0 = 0; rt0 < RT; rt0 += 4 * RGA) {
+          int rt[RGA]; int nrt = 0;
+#pragma unroll
+          for (int r = 0; r < RGA; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
+          if (nrt == 0) continue;  // wave-uniform
+          f64x4 acc[RGA][CT];
+#pragma unroll
+          for (int r = 0; r < RGA; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+          gemm_f64<RGA, CT>(pb.Md, n_pad, ra, rt, nrt, acc);
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const int c = 16 * ct + (l & 15);
@@ -210,7 +229,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
             if (st != COL_ACTIVE && st != COL_WAITING) continue;
             const double ga = S.gama[c];
 #pragma unroll
-            for (int r = 0; r < RG; ++r) {
+            for (int r = 0; r < RGA; ++r) {
               if (r >= nrt) continue;
               const int row0 = 16 * rt[r] + 4 * (l >> 4);
               f32x4 ev;
@@ -413,6 +432,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
     {
       const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;
+      constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + (l & 15);
@@ -422,42 +442,58 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const bool first = S.flags[c] & FLAG_FIRST;
         const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c], gf = (float)S.gam[c];
         const float th1f = (float)S.th1[c];
-        for (int rt = wave; rt < RT; rt += 4) {
-          const int row0 = 16 * rt + 4 * (l >> 4);
-          const size_t et = st_block(rt, ct, RT) + 4 * l;
-          f32x4 rv = {0.f, 0.f, 0.f, 0.f};
-          if (on) {
-            const f32x4 zv = ld_nt4(za + et);
-            const f32x4 wv = *gp((const f32x4*)(pb.wf + row0));
-            if (deltac) {
-              const f32x4 dv = ld_nt4(dz + et);
+        // batches of PB row tiles: all their state loads are in flight before any is used
+        const float* sv_src = deltac ? dz : ea;  // increment (delta phase) or x' (plain)
+        for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+          f32x4 zv[PB], sv[PB], wv[PB];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const float th = theta_f(th1f, wv[q]);
-                const float ca = clampf(zv[q], -th, th), sa = zv[q] - ca;
-                const float ds = dv[q] - clampf(dv[q] + sa, -th - ca, th - ca);
-                const float dd = gaf * ds + dgf * (sa + ds);
-                rv[q] = flam * (2.f * dd - dv[q]);
-              }
+          for (int u = 0; u < PB; ++u) {
+            const int rt = rtb + 4 * u;
+            const int rtc = rt < RT ? rt : 0;  // in-bounds address; result not stored
+            const size_t et = st_block(rtc, ct, RT) + 4 * l;
+            if (on) {
+              zv[u] = ld_nt4(za + et);
+              sv[u] = ld_nt4(sv_src + et);
+              wv[u] = *gp((const f32x4*)(pb.wf + 16 * rtc + 4 * (l >> 4)));
             } else {
-              const f32x4 xpv = ld_nt4(ea + et);  // x' (0 beyond n)
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const float z = zv[q];
-                const float th = theta_f(th1f, wv[q]);
-                const float d = first ? z : gf * (z - clampf(z, -th, th));
-                rv[q] = xpv[q] + flam * (2.f * d - z);
-              }
+              zv[u] = f32x4{0.f, 0.f, 0.f, 0.f}; sv[u] = zv[u]; wv[u] = zv[u];
             }
           }
-          if (MODE == 1) {
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            bf16x4 o;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = to_bf16(rv[q]);
-            *(bf16x4*)((__bf16*)lds_raw + c * ldb + row0) = o;
-          } else {
-            *(f32x4*)((float*)lds_raw + c * ldb + row0) = rv;
+          for (int u = 0; u < PB; ++u) {
+            const int rt = rtb + 4 * u;
+            if (rt >= RT) continue;  // wave-uniform
+            const int row0 = 16 * rt + 4 * (l >> 4);
+            f32x4 rv = {0.f, 0.f, 0.f, 0.f};
+            if (on) {
+              if (deltac) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const float th = theta_f(th1f, wv[u][q]);
+                  const float ca = clampf(zv[u][q], -th, th), sa = zv[u][q] - ca;
+                  const float ds = sv[u][q] - clampf(sv[u][q] + sa, -th - ca, th - ca);
+                  const float dd = gaf * ds + dgf * (sa + ds);
+                  rv[q] = flam * (2.f * dd - sv[u][q]);
+                }
+              } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const float z = zv[u][q];
+                  const float th = theta_f(th1f, wv[u][q]);
+                  const float d = first ? z : gf * (z - clampf(z, -th, th));
+                  rv[q] = sv[u][q] + flam * (2.f * d - z);
+                }
+              }
+            }
+            if (MODE == 1) {
+              typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+              bf16x4 o;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) o[q] = to_bf16(rv[q]);
+              *(bf16x4*)((__bf16*)lds_raw + c * ldb + row0) = o;
+            } else {
+              *(f32x4*)((float*)lds_raw + c * ldb + row0) = rv;
+            }
           }
         }
       }
@@ -749,13 +785,7 @@ int dense_occupancy(int mode, int n_pad) {
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_cols_per_tile(mode, n_pad);
-  if (mode == 1) {
-    const size_t b16 = (size_t)pt * (n_pad + 8) * 2;
-    const int kc_max = dense_anchor_chunk(pt, dense_occupancy(mode, n_pad));
-    const int kc = n_pad < kc_max ? n_pad : kc_max;
-    const size_t b64 = (size_t)pt * (kc + 2) * 8;
-    return b16 > b64 ? b16 : b64;
-  }
+  if (mode == 1) return (size_t)pt * (n_pad + 8) * 2;
   return (size_t)pt * (n_pad + 4) * 4;
 }
 

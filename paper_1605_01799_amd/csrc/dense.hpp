@@ -7,8 +7,6 @@ namespace hopf {
 int dense_cols_per_tile(int mode, int n_pad);
 // Workgroups per CU of the launch for this mode and padded size (1 or 2).
 int dense_occupancy(int mode, int n_pad);
-// Rows of the FP64 anchor chunk held in LDS for a tile of pt columns.
-__host__ __device__ constexpr int dense_anchor_chunk(int pt, int occ) { return (occ == 2 || pt == 64) ? 256 : 512; }
 size_t dense_lds_bytes(int mode, int n_pad);
 // Resets the chunk counter and the per-point best arrays before a launch.
 hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npts, hipStream_t stream);

@@ -122,35 +122,40 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
   }
 }
 
-// FP64: the RG row tiles times a K-chunk [k0, k0 + kc) of the right-hand-side block held in
-// LDS (B[c * ldb + kk], chunk-local kk).  A rows are loaded in the order 4(rho%4) + rho/4 so
-// that the output lands in the lane layout of the FP32/BF16 16x16 products:
-// lane l, register i -> row 4(l/16) + i, column l%16.
+// FP64: acc[r][c] += M[16 rt_r .., :] * B[:, 16 c ..] with the right-hand sides B in global
+// memory, column-major (column c at B + c n_pad).  A rows are loaded in the order
+// 4(rho%4) + rho/4 so that the output lands in the lane layout of the FP32/BF16 16x16 products:
+// lane l, register i -> row 4(l/16) + i, column l%16.  Operands stream one k-step ahead.
 template <int RG, int CT>
-__device__ __forceinline__ void gemm_f64_chunk(const double* __restrict__ M, int n_pad, int k0, int kc,
-                                                      const double* B, int ldb, const int* rt, int nrt,
-                                                      f64x4 (&acc)[RG][CT]) {
+__device__ __forceinline__ void gemm_f64(const double* __restrict__ M, int n_pad, const double* B,
+                                         const int* rt, int nrt, f64x4 (&acc)[RG][CT]) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   const int arow_perm = 4 * (lr & 3) + (lr >> 2);
   const HOPF_GLOBAL f64x4* arow[RG];
+  const HOPF_GLOBAL f64x4* bcol[CT];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
-  const double* bcol = B + lr * ldb + 4 * lg;
-  f64x4 an[RG];
+    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + 4 * lg));
+#pragma unroll
+  for (int c = 0; c < CT; ++c) bcol[c] = gp((const f64x4*)(B + (size_t)(16 * c + lr) * n_pad + 4 * lg));
+  f64x4 an[RG], bn[CT];
 #pragma unroll
   for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r]);
-  for (int kk = 0; kk < kc; kk += 16) {
+#pragma unroll
+  for (int c = 0; c < CT; ++c) bn[c] = bcol[c][0];
+  for (int kk = 0; kk < n_pad; kk += 16) {
     f64x4 a[RG], b[CT];
 #pragma unroll
     for (int r = 0; r < RG; ++r) a[r] = an[r];
-    if (kk + 16 < kc) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = bn[c];
+    if (kk + 16 < n_pad) {
 #pragma unroll
       for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r] + (kk + 16) / 4);
-    }
 #pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
+      for (int c = 0; c < CT; ++c) bn[c] = bcol[c][(kk + 16) / 4];
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -158,30 +163,6 @@ __device__ __forceinline__ void gemm_f64_chunk(const double* __restrict__ M, int
 #pragma unroll
         for (int c = 0; c < CT; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
-  }
-}
-
-// FP64: one row tile (rows 16 rt ..) times a K-chunk [k0, k0 + kc) of the right-hand-side block
-// in LDS, accumulated into acc[c]; same row permutation and output layout as gemm_f64_chunk.
-template <int CT>
-__device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ M, int n_pad, int rt, int k0, int kc,
-                                              const double* B, int ldb, f64x4 (&acc)[CT]) {
-  const int l = threadIdx.x & 63;
-  const int lr = l & 15, lg = l >> 4;
-  const int arow_perm = 4 * (lr & 3) + (lr >> 2);
-  const HOPF_GLOBAL f64x4* arow = gp((const f64x4*)(M + (size_t)(16 * rt + arow_perm) * n_pad + k0 + 4 * lg));
-  const double* bcol = B + lr * ldb + 4 * lg;
-  f64x4 an = __builtin_nontemporal_load(arow);
-  for (int kk = 0; kk < kc; kk += 16) {
-    const f64x4 a = an;
-    if (kk + 16 < kc) an = __builtin_nontemporal_load(arow + (kk + 16) / 4);
-    f64x4 b[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = *(const f64x4*)(bcol + 16 * c * ldb + kk);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[c][q], acc[c], 0, 0, 0);
   }
 }
 
