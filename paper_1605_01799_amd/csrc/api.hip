@@ -409,9 +409,10 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     int64_t o = 0;
     for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
   }
-  // one launch per kernel class: columns per tile and workgroups per CU (key = 4 cols + occupancy)
+  // one launch per kernel class: the launch shape of the padded size
   auto class_of = [&](int n_pad) -> int {
-    return 4 * dense_cols_per_tile(mode, n_pad) + dense_occupancy(mode, n_pad);
+    const DenseVariant v = dense_variant(mode, n_pad);
+    return 100 * v.pt + 10 * v.occ + v.nw;
   };
   std::vector<int> classes;
   for (auto& c : calls) {
@@ -421,8 +422,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   std::sort(classes.begin(), classes.end());
   int cls = 0;
   for (int key : classes) {
-    const int pt = key / 4;
-    const int occ = key % 4;
+    const DenseVariant var{key / 100, (key / 10) % 10, key % 10};
+    const int pt = var.pt, occ = var.occ;
     std::vector<DenseProb> views;
     std::vector<std::pair<double, int>> order;  // (cost, view index)
     int max_npad = 32;
@@ -471,8 +472,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
       if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
     }
     const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
-    hipError_t e = launch_dense(mode, pt, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state, w->state64,
-                                ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every, occ, stream);
+    hipError_t e = launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state, w->state64,
+                                ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
     ++cls;
     // the next class reuses the metadata/staging buffers and the workspace: wait for this one

@@ -43,16 +43,17 @@
 namespace hopf {
 
 // MODE 0: FP32 products; MODE 1: BF16 increments + FP64 anchors.  CT column tiles of 16, RG row
-// tiles per wave and product pass, OCC workgroups per CU (2: each workgroup keeps at most 256
-// registers per lane and 80 KiB of LDS, so two tiles interleave their products and epilogues).
-template <int MODE, int CT, int RG, int OCC>
-__global__ void __launch_bounds__(kBlock, OCC)
+// tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
+// OCC workgroups per CU.  With two waves per SIMD (NW = 8, or OCC = 2) each wave keeps at most
+// 256 registers per lane, and one wave's products overlap another's epilogue.
+template <int MODE, int CT, int RG, int OCC, int NW>
+__global__ void __launch_bounds__(NW * 64, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
              int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every) {
   constexpr int PT = 16 * CT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  __shared__ ColShared<PT> S;
+  __shared__ ColShared<PT, NW> S;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, l = tid & 63;
@@ -103,19 +104,19 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const int st = S.state[c];
           if (st != COL_ACTIVE && st != COL_WAITING) continue;
           const double th1 = S.th1[c];
-          constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
-          for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+          constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
+          for (int rtb = wave; rtb < RT; rtb += NW * PB) {
             f32x4 zv[PB], dv[PB], wv[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-              const int rtc = (rtb + 4 * u) < RT ? rtb + 4 * u : 0;
+              const int rtc = (rtb + NW * u) < RT ? rtb + NW * u : 0;
               const size_t et = st_block(rtc, ct, RT) + 4 * l;
               zv[u] = ld_nt4(za + et); dv[u] = ld_nt4(dz + et);
               wv[u] = *gp((const f32x4*)(pb.wf + 16 * rtc + 4 * (l >> 4)));
             }
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-              const int rt = rtb + 4 * u;
+              const int rt = rtb + NW * u;
               if (rt >= RT) continue;  // wave-uniform
               const int row0 = 16 * rt + 4 * (l >> 4);
               const size_t et = st_block(rt, ct, RT) + 4 * l;
@@ -148,8 +149,9 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const int c = tid;
           const int st = S.state[c];
           if (st == COL_ACTIVE || st == COL_WAITING) {
-            const double pssc = S.red[0][c][0] + S.red[1][c][0] + S.red[2][c][0] + S.red[3][c][0];
-            const double pincc = S.red[0][c][1] + S.red[1][c][1] + S.red[2][c][1] + S.red[3][c][1];
+            double pssc = 0.0, pincc = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { pssc += S.red[w][c][0]; pincc += S.red[w][c][1]; }
             S.ssa2[c] = pssc;
             const double ssq = pssc + pincc;
             S.ssq[c] = ssq;
@@ -178,17 +180,17 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const double th1 = S.th1[c], ga = S.gama[c];
           const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
           const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
-          constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
-          for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+          constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
+          for (int rtb = wave; rtb < RT; rtb += NW * PB) {
             f32x4 zv[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-              const int rtc = (rtb + 4 * u) < RT ? rtb + 4 * u : 0;
+              const int rtc = (rtb + NW * u) < RT ? rtb + NW * u : 0;
               zv[u] = on ? ld_nt4(za + st_block(rtc, ct, RT) + 4 * l) : f32x4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
-              const int rt = rtb + 4 * u;
+              const int rt = rtb + NW * u;
               if (rt >= RT) continue;  // wave-uniform
               const int row0 = 16 * rt + 4 * (l >> 4);
               double rv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -210,11 +212,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           }
         }
         __syncthreads();  // the staging is complete (written and read by this workgroup only)
-        constexpr int RGA = (CT >= 4 && RG > 2) ? 2 : RG;  // row tiles per FP64 product pass
-        for (int rt0 = 0; rt0 < RT; rt0 += 4 * RGA) {
+        constexpr int RGA = CT >= 4 ? (NW == 8 ? 1 : 2) : RG;  // row tiles per FP64 product pass
+        for (int rt0 = 0; rt0 < RT; rt0 += NW * RGA) {
           int rt[RGA]; int nrt = 0;
 #pragma unroll
-          for (int r = 0; r < RGA; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
+          for (int r = 0; r < RGA; ++r) { rt[r] = rt0 + wave + NW * r; if (rt[r] < RT) nrt = r + 1; }
           if (nrt == 0) continue;  // wave-uniform
           f64x4 acc[RGA][CT];
 #pragma unroll
@@ -305,7 +307,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       __syncthreads();
       const int better = S.ctl[CTL_BETTER];
       if (better) {
-        for (int i = tid; i < n; i += kBlock) {
+        for (int i = tid; i < n; i += NW * 64) {
           float v;
           if (better == 2) v = __builtin_nanf("");
           else if (!distance) v = ld_nt(pout + (size_t)c * n_pad + i);
@@ -384,7 +386,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     }
     __syncthreads();
     // ... and state (one wave per slot; also the finiteness check)
-    for (int c = wave; c < PT; c += 4) {
+    for (int c = wave; c < PT; c += NW) {
       if (!S.fresh[c]) continue;
       const int st = S.state[c];
       bool bad = false;
@@ -427,12 +429,16 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       }
     }
 
+    if (tid < PT) {  // value sums of this pass (ordered before their atomic updates by the barrier below)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S.redv[tid][q] = 0.0;
+    }
     // ================================================================ prologue: right-hand sides
     // Block order: wave w takes the row tiles w, w+4, ... of every column tile; lane l works on
     // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
     {
       const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;
-      constexpr int PB = OCC == 2 ? 2 : 4;  // row tiles whose loads are in flight together
+      constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + (l & 15);
@@ -444,11 +450,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const float th1f = (float)S.th1[c];
         // batches of PB row tiles: all their state loads are in flight before any is used
         const float* sv_src = deltac ? dz : ea;  // increment (delta phase) or x' (plain)
-        for (int rtb = wave; rtb < RT; rtb += 4 * PB) {
+        for (int rtb = wave; rtb < RT; rtb += NW * PB) {
           f32x4 zv[PB], sv[PB], wv[PB];
 #pragma unroll
           for (int u = 0; u < PB; ++u) {
-            const int rt = rtb + 4 * u;
+            const int rt = rtb + NW * u;
             const int rtc = rt < RT ? rt : 0;  // in-bounds address; result not stored
             const size_t et = st_block(rtc, ct, RT) + 4 * l;
             if (on) {
@@ -461,7 +467,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           }
 #pragma unroll
           for (int u = 0; u < PB; ++u) {
-            const int rt = rtb + 4 * u;
+            const int rt = rtb + NW * u;
             if (rt >= RT) continue;  // wave-uniform
             const int row0 = 16 * rt + 4 * (l >> 4);
             f32x4 rv = {0.f, 0.f, 0.f, 0.f};
@@ -501,31 +507,16 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     __syncthreads();
 
     // ================================================================ GEMM + epilogue
-    double part[CT][kNRed];
+    float part[CT][2];  // this lane's step^2 and |s|^2 (increment) partials; value sums go to S.redv
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-#pragma unroll
-      for (int q = 0; q < kNRed; ++q) part[c][q] = 0.0;
-    // this lane's CT slots (columns 16 ct + l % 16): scalars hoisted out of the row loop
-    int st_[CT];
-    bool first_[CT], delta_[CT];
-    float th1f_[CT], gaf_[CT], dgf_[CT], gf_[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int c = 16 * ct + (l & 15);
-      st_[ct] = S.state[c];
-      first_[ct] = S.flags[c] & FLAG_FIRST;
-      delta_[ct] = MODE == 1 && S.phase[c] == PH_DELTA;
-      th1f_[ct] = (float)S.th1[c];
-      gaf_[ct] = (float)S.gama[c];
-      dgf_[ct] = (float)S.dgam[c];
-      gf_[ct] = (float)S.gam[c];
-    }
+    for (int c = 0; c < CT; ++c) { part[c][0] = 0.f; part[c][1] = 0.f; }
+    // the column scalars of this lane's slots (columns 16 ct + l % 16) are read from LDS where
+    // they are used: registers are kept for the products
 
-    for (int rt0 = 0; rt0 < RT; rt0 += 4 * RG) {
+    for (int rt0 = 0; rt0 < RT; rt0 += NW * RG) {
       int rt[RG]; int nrt = 0;
 #pragma unroll
-      for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + 4 * r; if (rt[r] < RT) nrt = r + 1; }
+      for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + NW * r; if (rt[r] < RT) nrt = r + 1; }
       f32x4 acc[RG][CT];
 #pragma unroll
       for (int r = 0; r < RG; ++r)
@@ -537,10 +528,10 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + (l & 15);
-        const int st = st_[ct];
+        const int st = S.state[c];
         if (st != COL_ACTIVE && st != COL_PHI) continue;
-        const bool delta = delta_[ct];
-        const float th1f = th1f_[ct];
+        const bool delta = MODE == 1 && S.phase[c] == PH_DELTA;
+        const float th1f = (float)S.th1[c];
         // the state of all RG row tiles of this column is requested before any of it is used
         f32x4 zst[RG], dst[RG], est[RG], wst[RG];
 #pragma unroll
@@ -565,7 +556,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
             // exact product (a column that converged to a stale anchor's fixed point continues).
             f32x4 dzv = dst[r];
             const f32x4 eav = est[r];
-            const float gaf = gaf_[ct], dgf = dgf_[ct];
+            const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
             float s0 = 0.f, s1 = 0.f;
             f32x4 ddv;
 #pragma unroll
@@ -583,14 +574,15 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               ddv[q] = dd;
               dzv[q] = dzn;
             }
-            part[ct][0] += (double)s0;
-            part[ct][1] += (double)s1;
+            part[ct][0] += s0;
+            part[ct][1] += s1;
             if (st == COL_PHI) {  // value from the exact-product identity at the current iterate
               const double ga = S.gama[c], th1 = S.th1[c];
               const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
               const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
               const f32x4 dz0 = dst[r];
               f32x4 pv;
+              double v2 = 0.0, v3 = 0.0, v4 = 0.0, v5 = 0.0;
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = row0 + q;
@@ -600,19 +592,20 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
                 const double rr = xp + lam * (2.0 * da - (double)zav[q]) + lam * (2.0 * (double)ddv[q] - (double)dz0[q]);
                 if (i >= n) d = 0.0;
-                part[ct][2] += xp * d;
-                part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
-                part[ct][4] += (double)wst[r][q] * fabs(d);
-                part[ct][5] += d * d;
+                v2 += xp * d;
+                v3 += (2.0 * d - vv) * (rr - lam * vv);
+                v4 += (double)wst[r][q] * fabs(d);
+                v5 += d * d;
                 pv[q] = (float)d;
               }
+              value_sums(S.redv[c], v2, v3, v4, v5);
               st_nt4(pout + e, pv);
             }
             st_nt4(dz + et, dzv);
           } else {
             // plain iteration (F32 mode, or the BF16 warm-up): z^{k+1} = z - d + v
-            const float gf = gf_[ct];
-            const bool first = first_[ct];
+            const float gf = (float)S.gam[c];
+            const bool first = S.flags[c] & FLAG_FIRST;
             if (st == COL_ACTIVE) {
               float s0 = 0.f, s1 = 0.f;
 #pragma unroll
@@ -627,8 +620,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 s1 += sn * sn;
                 zav[q] = zn;
               }
-              part[ct][0] += (double)s0;
-              part[ct][1] += (double)s1;
+              part[ct][0] += s0;
+              part[ct][1] += s1;
               st_nt4(za + et, zav);
             } else if (MODE == 0) {  // COL_PHI in F32 mode: r is in LDS
               const float* B32 = (const float*)lds_raw;
@@ -636,6 +629,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
               const double* cen = pb.centres ? pb.centres + (size_t)S.k[c] * n_pad : nullptr;
               f32x4 pv;
+              double v2 = 0.0, v3 = 0.0, v4 = 0.0, v5 = 0.0;
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = row0 + q;
@@ -645,24 +639,25 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 const double vv = (double)v[q];
                 const double rr = (double)B32[c * ldb + i];
                 const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
-                part[ct][2] += xp * d;
-                part[ct][3] += (2.0 * d - vv) * (rr - lam * vv);
-                part[ct][4] += (double)wst[r][q] * fabs(d);
-                part[ct][5] += d * d;
+                v2 += xp * d;
+                v3 += (2.0 * d - vv) * (rr - lam * vv);
+                v4 += (double)wst[r][q] * fabs(d);
+                v5 += d * d;
                 pv[q] = (float)d;
               }
+              value_sums(S.redv[c], v2, v3, v4, v5);
               st_nt4(pout + e, pv);
             }
           }
         }
       }
     }
-    // reduce partials: over the 4 lane groups, then across waves through LDS
+    // reduce the step partials: over the 4 lane groups, then across waves through LDS
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-      for (int q = 0; q < kNRed; ++q) {
-        double v = part[ct][q];
+      for (int q = 0; q < 2; ++q) {
+        double v = (double)part[ct][q];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         if (l < 16) S.red[wave][16 * ct + l][q] = v;
@@ -674,8 +669,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       const int c = tid;
       const int st = S.state[c];
       double sm[kNRed];
+      sm[0] = 0.0; sm[1] = 0.0;
 #pragma unroll
-      for (int q = 0; q < kNRed; ++q) sm[q] = S.red[0][c][q] + S.red[1][c][q] + S.red[2][c][q] + S.red[3][c][q];
+      for (int w = 0; w < NW; ++w) { sm[0] += S.red[w][c][0]; sm[1] += S.red[w][c][1]; }
+#pragma unroll
+      for (int q = 2; q < kNRed; ++q) sm[q] = S.redv[c][q - 2];
       const bool delta = MODE == 1 && S.phase[c] == PH_DELTA;
       const bool stepped = st == COL_ACTIVE || (MODE == 1 && st == COL_PHI);
       bool evaluate = (MODE == 0 && st == COL_PHI);
@@ -768,23 +766,26 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-int dense_cols_per_tile(int mode, int n_pad) {
-  if (mode == 1) return (n_pad <= 1024 && dense_occupancy(mode, n_pad) == 1) ? 64 : 32;
-  if (n_pad <= 512) return 64;
-  if (n_pad <= 1024) return 32;
-  return 16;
-}
-
-int dense_occupancy(int mode, int n_pad) {
-  static const int occ2 = [] {
-    const char* v = getenv("HOPF_OCC2");
-    return v ? atoi(v) : 1;
+DenseVariant dense_variant(int mode, int n_pad) {
+  // refined mode up to n_pad = 1024: two 32-column workgroups of 4 waves per CU (default), or
+  // one 64-column workgroup of 8 waves (HOPF_DENSE=1) or of 4 waves (HOPF_DENSE=2)
+  static const int pick = [] {
+    const char* v = getenv("HOPF_DENSE");
+    return v ? atoi(v) : 0;
   }();
-  return (mode == 1 && n_pad <= 1024 && occ2) ? 2 : 1;
+  if (mode == 1) {
+    if (n_pad > 1024) return DenseVariant{32, 1, 4};
+    if (pick == 1) return DenseVariant{64, 1, 8};
+    if (pick == 2) return DenseVariant{64, 1, 4};
+    return DenseVariant{32, 2, 4};
+  }
+  if (n_pad <= 512) return DenseVariant{64, 1, 4};
+  if (n_pad <= 1024) return DenseVariant{32, 1, 4};
+  return DenseVariant{16, 1, 4};
 }
 
 size_t dense_lds_bytes(int mode, int n_pad) {
-  const int pt = dense_cols_per_tile(mode, n_pad);
+  const int pt = dense_variant(mode, n_pad).pt;
   if (mode == 1) return (size_t)pt * (n_pad + 8) * 2;
   return (size_t)pt * (n_pad + 4) * 4;
 }
@@ -802,11 +803,11 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
   return hipGetLastError();
 }
 
-template <int MODE, int CT, int RG, int OCC>
+template <int MODE, int CT, int RG, int OCC, int NW>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
                            int distance, int anchor_every, hipStream_t stream) {
-  auto kern = dense_kernel<MODE, CT, RG, OCC>;
+  auto kern = dense_kernel<MODE, CT, RG, OCC, NW>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -814,26 +815,27 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
                      ws_per_wg, ws64_per_wg, distance, anchor_every);
   return hipGetLastError();
 }
 
-hipError_t launch_dense(int mode, int cols_per_tile, const DenseProb* d_probs, const DenseChunk* d_chunks,
+hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, int occ, hipStream_t stream) {
-  const int ct = cols_per_tile / 16;
-#define HOPF_LAUNCH(M, C, R, O)                                                                                  \
-  return launch_t<M, C, R, O>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
-                              distance, anchor_every, stream)
+                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream) {
+  const int ct = var.pt / 16, occ = var.occ, nw = var.nw;
+#define HOPF_LAUNCH(M, C, R, O, W)                                                                                  \
+  return launch_t<M, C, R, O, W>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
+                                 distance, anchor_every, stream)
   if (mode == 1) {
-    if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2);
-    if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1);
-    if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1);
+    if (nw == 8 && ct == 4) HOPF_LAUNCH(1, 4, 2, 1, 8);
+    if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4);
+    if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1, 4);
+    if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1, 4);
   } else {
-    if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1);
-    if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1);
-    if (ct == 1) HOPF_LAUNCH(0, 1, 4, 1);
+    if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1, 4);
+    if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1, 4);
+    if (ct == 1) HOPF_LAUNCH(0, 1, 4, 1, 4);
   }
 #undef HOPF_LAUNCH
   return hipErrorInvalidValue;

@@ -4,14 +4,17 @@
 namespace hopf {
 
 // mode 0: FP32 products; mode 1: BF16 increments refined by FP64 anchor products.
-int dense_cols_per_tile(int mode, int n_pad);
-// Workgroups per CU of the launch for this mode and padded size (1 or 2).
-int dense_occupancy(int mode, int n_pad);
+// The launch shape for a mode and padded size: columns per tile, workgroups per CU, waves per
+// workgroup.
+struct DenseVariant {
+  int pt, occ, nw;
+};
+DenseVariant dense_variant(int mode, int n_pad);
 size_t dense_lds_bytes(int mode, int n_pad);
 // Resets the chunk counter and the per-point best arrays before a launch.
 hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npts, hipStream_t stream);
-hipError_t launch_dense(int mode, int cols_per_tile, const DenseProb* d_probs, const DenseChunk* d_chunks,
+hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, int occ, hipStream_t stream);
+                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream);
 
 }  // namespace hopf

@@ -166,6 +166,15 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ M, int n_pad
   }
 }
 
+// Value sums of a value iteration, added by every lane that holds rows of the column (rare:
+// one iteration per solve), straight into the column's LDS slots.
+__device__ __forceinline__ void value_sums(double* slot, double v2, double v3, double v4, double v5) {
+  atomicAdd(slot + 0, v2);
+  atomicAdd(slot + 1, v3);
+  atomicAdd(slot + 2, v4);
+  atomicAdd(slot + 3, v5);
+}
+
 // Wave-level sum of a double across the 64 lanes (result in every lane).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -174,14 +183,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Per-column (slot) scalars and the workgroup's control words, in LDS (P columns).
-template <int P>
+template <int P, int NW>
 struct ColShared {
   double t[P], th1[P], th2[P], gam[P], gama[P], dgam[P];
   double ssa2[P], ssq[P], prev[P], s[P], phi[P], hp[P];
   double pn[P], best[P];
   int stall[P], col[P], j[P], k[P], state[P], phase[P], iters[P];
   int newton[P], flags[P], fresh[P];
-  double red[4][P][kNRed];
+  double red[NW][P][2];  // per-wave partials of step^2 and |s|^2
+  double redv[P][4];     // value sums of a value iteration (LDS atomics)
   int ctl[16];
 };
 // FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
