@@ -30,16 +30,17 @@ METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % rooflin
 # HBM traffic of the dense kernel on the default workload, from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE; profiles/dense_kernel_n1024_65536pts_l2wl1_bf16refined.md), each
 # scaled by what the counter reads for a plain 256 MiB device copy.  Valid only for the kernel
-# source it was measured on (hash of dense.hip + common.hpp); reported as null otherwise.
-TRAFFIC = {"source_sha256": "5a043b9f3e0c3579aca6c54cdb8ba73ed67f8deefbab023af366974074ed3cf9",
-           "read_bytes": 230.737e9, "write_bytes": 36.183e9, "precision": "bf16_refined", "npts": 1 << 16,
+# source it was measured on (hash of dense.hip + dense_shared.hpp + common.hpp); reported as null
+# otherwise.
+TRAFFIC = {"source_sha256": "86192f94e8afb9d3a75ab0036620b649f9708f823a2b93495e34ac9e442b0a19",
+           "read_bytes": 378.053e9, "write_bytes": 47.503e9, "precision": "bf16_refined", "npts": 1 << 16,
            "tol": 1e-12}
 
 
 def measured_traffic(precision, npts, tol):
     import hashlib
     h = hashlib.sha256()
-    for f in ("dense.hip", "common.hpp"):
+    for f in ("dense.hip", "dense_shared.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_1605_01799_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if (h.hexdigest() != TRAFFIC["source_sha256"] or precision != TRAFFIC["precision"]

@@ -259,12 +259,19 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     }
 
     // ================================================================ flush finished slots
-    for (int c = 0; c < PT; ++c) {
-      const int st = S.state[c];
-      if (st != COL_DONE && st != COL_INVALID) continue;
-      const int64_t j = S.j[c];
-      const int kk = S.k[c];
-      if (tid == 0) {
+    // Thread 0 settles the outputs of every finished slot in slot order (the best copy of a
+    // point so far, lowest copy index on ties), marking the slot whose p is to be written; then
+    // all threads copy those vectors.  Copies of one point live in one workgroup, so the best
+    // value of a point is only ever compared here, by this thread.
+    if (tid == 0) {
+      int any = 0;
+      for (int c = 0; c < PT; ++c) {
+        S.better[c] = 0;
+        const int st = S.state[c];
+        if (st != COL_DONE && st != COL_INVALID) continue;
+        any = 1;
+        const int64_t j = S.j[c];
+        const int kk = S.k[c];
         int better;
         if (st == COL_INVALID) {
           better = 2;
@@ -275,7 +282,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           better = (bk < 0 || key < bv || (key == bv && kk < bk)) ? 1 : 0;
           if (better) { pb.bestv[j] = key; pb.bestk[j] = kk; }
         }
-        S.ctl[CTL_BETTER] = better;
+        if (better) {  // an earlier slot of this pass that wrote the same point is superseded
+          for (int c2 = 0; c2 < c; ++c2)
+            if (S.better[c2] && S.j[c2] == S.j[c]) S.better[c2] = 0;
+        }
+        S.better[c] = better;
         const float qnan = __builtin_nanf("");
         if (better == 2) {
           pb.bestk[j] = -2;
@@ -304,23 +315,29 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           }
         }
       }
-      __syncthreads();
-      const int better = S.ctl[CTL_BETTER];
-      if (better) {
-        for (int i = tid; i < n; i += NW * 64) {
+      S.ctl[CTL_BETTER] = any;
+    }
+    __syncthreads();
+    if (S.ctl[CTL_BETTER]) {
+      for (int c = wave; c < PT; c += NW) {  // one wave per slot, lanes over coordinates
+        const int better = S.better[c];
+        if (!better) continue;
+        const int64_t j = S.j[c];
+        const bool ins = S.flags[c] & FLAG_INSIDE;
+        const double sc = distance ? S.s[c] / S.pn[c] : 0.0;
+        for (int i = l; i < n; i += 64) {
           float v;
           if (better == 2) v = __builtin_nanf("");
           else if (!distance) v = ld_nt(pout + (size_t)c * n_pad + i);
           else {
             const float y = pb.x[(size_t)j * n + i];
-            if (S.flags[c] & FLAG_INSIDE) v = y;
-            else v = (float)((double)y - S.s[c] * (double)ld_nt(pout + (size_t)c * n_pad + i) / S.pn[c]);
+            v = ins ? y : (float)((double)y - sc * (double)ld_nt(pout + (size_t)c * n_pad + i));
           }
           pb.grad[(size_t)j * n + i] = v;
         }
       }
       __syncthreads();
-      if (tid == 0) S.state[c] = COL_EMPTY;
+      if (tid < PT && (S.state[tid] == COL_DONE || S.state[tid] == COL_INVALID)) S.state[tid] = COL_EMPTY;
       __syncthreads();
     }
 

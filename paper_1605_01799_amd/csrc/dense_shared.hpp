@@ -189,7 +189,7 @@ struct ColShared {
   double ssa2[P], ssq[P], prev[P], s[P], phi[P], hp[P];
   double pn[P], best[P];
   int stall[P], col[P], j[P], k[P], state[P], phase[P], iters[P];
-  int newton[P], flags[P], fresh[P];
+  int newton[P], flags[P], fresh[P], better[P];
   double red[NW][P][2];  // per-wave partials of step^2 and |s|^2
   double redv[P][4];     // value sums of a value iteration (LDS atomics)
   int ctl[16];
