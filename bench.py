@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1s", "c2", "c5"],
+                    help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
+                         "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
+                         "FP32 dense at 2^20 points, c5 = n=256 union of 4 ellipsoids, forward + backward")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
                          "scale of the FETCH_SIZE / WRITE_SIZE counters")
@@ -85,6 +89,9 @@ def main():
         sys.exit(2)
     if a.copy_calibrate:
         copy_calibrate()
+        return
+    if a.workload != "c3":
+        bench_other(a)
         return
     import torch
     from paper_1605_01799_amd import hopf as H
@@ -185,6 +192,177 @@ def main():
                                              % (m, tol, threads)}
     except Exception as e:  # the oracle is test infrastructure; its absence only drops these fields
         rec["accuracy_error"] = str(e)
+    print(json.dumps(rec), flush=True)
+
+
+def timed_steps(step, steps, warmup):
+    """Runs warmup + steps calls of step(ev); returns (ms per step by the host clock, mean ms
+    between the events each step records around its dominant launch)."""
+    import torch
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+
+def bench_other(a):
+    import torch
+    from paper_1605_01799_amd import hopf as H
+    from paper_1605_01799_amd import workloads as W
+    import oracle
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    threads = min(16, os.cpu_count() or 1)
+    rec = {"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "unit": "point-evals/s"}
+
+    if a.workload == "c1s":
+        npts = a.npts if a.npts != 1 << 16 else 1 << 24
+        p = W.workload_scaled_n8(npts)
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        prob = H.Problem(np.ones(p.n), diagonal=True, hkind="wl1", precision="f64", tol=1e-24, max_iter=500)
+        out = dict(phi=torch.empty(npts, dtype=torch.float64, device=dev),
+                   grad=torch.empty(npts, p.n, dtype=torch.float64, device=dev),
+                   dphidt=torch.empty(npts, dtype=torch.float64, device=dev),
+                   iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        per_point = 8 * p.n + 8 + 8 * p.n + 8 + 8 + 4 + 4   # x, t in; p, phi, dphidt, iters, kstar out
+        achieved = npts * per_point / (kms / 1e3) / 1e9
+        # the closed form of this workload (A = I, H = l1): p = sign(x) max(|x| - t, 0)
+        g = out["grad"].cpu().numpy()
+        pcf = np.sign(p.x) * np.maximum(np.abs(p.x) - p.t[:, None], 0)
+        m = min(npts, 1 << 20)
+        c0 = time.perf_counter()
+        oracle.oracle_eval(np.eye(p.n), p.x[:m], p.t[:m], "wl1", tol=1e-24, max_iter=500, nthreads=threads)
+        c1 = time.perf_counter()
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=8 FP64 diagonal path; % HBM roofline",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f64",
+                   config={"workload": "n=8, A=I, H=l1, %d points x~N(0,1), t~U(0.1,2), FP64, tol 1e-24, "
+                                       "cap 500" % npts, "npts": npts},
+                   roofline={"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                             "frac": achieved / 8000.0, "traffic": None, "kernel": "diag_kernel<double, 8>",
+                             "algorithmic": "%d B per point (in and out)" % per_point, "launch_ms": kms},
+                   accuracy={"max_abs_err_grad_vs_closed_form": float(np.abs(g - pcf).max()), "points": npts},
+                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+    elif a.workload == "c2":
+        npts = a.npts if a.npts != 1 << 16 else 1 << 20
+        p = W.round_inputs(W.workload2(npts))
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        tol = a.tol if a.tol is not None else 1e-10
+        kw = dict(hkind="wl1", w=p.w, tol=tol, max_iter=20000, precision="f32")
+        out = dict(phi=torch.empty(npts, device=dev), grad=torch.empty(npts, p.n, device=dev),
+                   dphidt=torch.empty(npts, device=dev), iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            prob = H.Problem(p.A, **kw)
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+            del prob
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        it = out["iters"].cpu().numpy()
+        flops = float(np.sum(np.abs(it)).astype(np.float64) * 2.0 * p.n * p.n)
+        achieved = flops / (kms / 1e3) / 1e12
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample * 4, npts), replace=False))
+        ref = oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64), "wl1", w=p.w,
+                                 tol=1e-28, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        m = min(npts, 1 << 14)
+        c0 = time.perf_counter()
+        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), "wl1", w=p.w, tol=tol,
+                           nthreads=threads)
+        c1 = time.perf_counter()
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=64 dense FP32; % FP32 MFMA roofline",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
+                   config={"workload": "n=64 dense SPD A, H=weighted l1, %d points x~N(0,4I), t~U(0.05,3), FP32, "
+                                       "tol %g; step = set-up + evaluation" % (npts, tol), "npts": npts},
+                   roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<0, 4, 4, 1, 4>",
+                             "algorithmic": "sum over points of iterations x 2 n^2 FLOP", "launch_ms": kms},
+                   iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": 5e-5},
+                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+    else:  # c5: forward over the union of 4 ellipsoids, then the envelope backward
+        npts = a.npts if a.npts != 1 << 16 else 1 << 18
+        p = W.round_inputs(W.workload5(npts))
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        g = torch.from_numpy(np.random.default_rng(5).normal(size=npts).astype(np.float32)).to(dev)
+        tol = a.tol if a.tol is not None else 1e-10
+        prob = H.Problem(p.A, centres=p.centres, level_set=True, hkind="wl1", w=p.w, precision="f32", tol=tol,
+                         max_iter=20000)
+        bw_ms = []
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            out = prob.eval(x, t)
+            if ev is not None:
+                ev[1].record(stream)
+                e2 = torch.cuda.Event(enable_timing=True)
+                e2.record(stream)
+            b = prob.backward(g, out["grad"], out["dphidt"], out["kstar"])
+            if ev is not None:
+                e3 = torch.cuda.Event(enable_timing=True)
+                e3.record(stream)
+                bw_ms.append((e2, e3))
+            step.out, step.b = out, b
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        bms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in bw_ms]))
+        it = step.out["iters"].cpu().numpy()
+        flops = float(p.K * np.sum(np.abs(it)).astype(np.float64) * 2.0 * p.n * p.n)
+        achieved = flops / (kms / 1e3) / 1e12
+        bw_bytes = npts * (4 * (2 * p.n + 2) + 4 * (p.n + 1) + 4)
+        rng = np.random.default_rng(8)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample, npts), replace=False))
+        ref = oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64), "wl1", w=p.w,
+                                 centres=p.centres, level_set=True, tol=1e-28, nthreads=threads)
+        ef = np.abs(step.out["phi"].cpu().numpy()[idx] - ref["phi"]) / np.maximum(np.abs(ref["phi"]), 1)
+        m = min(npts, 512)
+        c0 = time.perf_counter()
+        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), "wl1", w=p.w,
+                           centres=p.centres, level_set=True, tol=tol, nthreads=threads)
+        c1 = time.perf_counter()
+        rec.update(metric="Hopf point-evals/sec (φ forward + envelope backward), n=256, union of 4 ellipsoids, FP32",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
+                   config={"workload": "n=256, J = min over 4 ellipsoid level sets, H=weighted l1, %d points, FP32, "
+                                       "tol %g; step = forward + backward (x, t, A, centres)" % (npts, tol),
+                           "npts": npts},
+                   roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<0, 4, 4, 1, 4>",
+                             "algorithmic": "K x iterations of the attaining copy x 2 n^2 FLOP per point "
+                                            "(the other copies' counts are not returned)", "launch_ms": kms},
+                   backward={"ms": bms, "hbm_GBps": bw_bytes / (bms / 1e3) / 1e9,
+                             "hbm_frac": bw_bytes / (bms / 1e3) / 1e9 / 8000.0,
+                             "algorithmic_bytes": bw_bytes},
+                   iterations={"mean_attaining_copy": float(np.abs(it).mean())},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_phi": float(ef.max()), "bound": 5e-5},
+                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+                                 "sample": "first %d points (forward only), same tol, FP64 oracle, %d threads"
+                                           % (m, threads)})
     print(json.dumps(rec), flush=True)
 
 
