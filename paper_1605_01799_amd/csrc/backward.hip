@@ -68,6 +68,9 @@ __global__ void bw_reduce_kernel(int64_t m, int nsplit, const double* part, doub
 }
 
 // gc partial: per split s, per (k, i): sum over points j of the split with kstar_j == k of g_j p_ji.
+// One pass over the points of the split: for K <= KMAX the K sums of coordinate i stay in
+// registers (each point adds to the sum of its own attaining copy); larger K loop over k.
+template <int KMAX>
 __global__ void bw_gc_partial_kernel(int64_t npts, int n, int K, int64_t chunk, const float* g,
                                      const float* grad, const int32_t* kstar, double* part) {
   const int split = blockIdx.y;
@@ -75,6 +78,21 @@ __global__ void bw_gc_partial_kernel(int64_t npts, int n, int K, int64_t chunk, 
   if (i >= n) return;
   const int64_t p0 = (int64_t)split * chunk;
   const int64_t p1 = p0 + chunk < npts ? p0 + chunk : npts;
+  if (K <= KMAX) {
+    double s[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) s[k] = 0.0;
+    for (int64_t j = p0; j < p1; ++j) {
+      const int kk = kstar ? kstar[j] : 0;
+      const double v = (double)g[j] * (double)grad[j * n + i];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) s[k] += (kk == k) ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < K) part[((int64_t)split * K + k) * n + i] = s[k];
+    return;
+  }
   for (int k = 0; k < K; ++k) {
     double s = 0.0;
     for (int64_t j = p0; j < p1; ++j) {
@@ -110,7 +128,7 @@ hipError_t launch_backward(const BackwardArgs& a, double* scratch, hipStream_t s
   }
   if (a.gc) {
     double* sc = scratch + (a.gA ? (size_t)nsplit * n * n : 0);
-    hipLaunchKernelGGL(bw_gc_partial_kernel, dim3((n + 255) / 256, nsplit), dim3(256), 0, stream, npts, n,
+    hipLaunchKernelGGL(bw_gc_partial_kernel<8>, dim3((n + 255) / 256, nsplit), dim3(256), 0, stream, npts, n,
                        a.K, chunk, a.g, a.grad, a.kstar, sc);
     const int64_t m = (int64_t)a.K * n;
     hipLaunchKernelGGL(bw_reduce_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, m, nsplit,
