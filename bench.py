@@ -299,7 +299,7 @@ def bench_other(a):
                    config={"workload": "n=64 dense SPD A, H=weighted l1, %d points x~N(0,4I), t~U(0.05,3), FP32, "
                                        "tol %g; step = set-up + evaluation" % (npts, tol), "npts": npts},
                    roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<0, 4, 4, 1, 4>",
+                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_small_kernel<4, 1, 2> (n_pad <= 64)",
                              "algorithmic": "sum over points of iterations x 2 n^2 FLOP", "launch_ms": kms},
                    iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
                    accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": 5e-5},

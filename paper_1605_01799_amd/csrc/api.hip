@@ -409,8 +409,12 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     int64_t o = 0;
     for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
   }
-  // one launch per kernel class: the launch shape of the padded size
+  // one launch per kernel class: the launch shape of the padded size (kSmallClass: the
+  // one-wave-per-tile kernel of small FP32 problems)
+  constexpr int kSmallClass = 1 << 20;
+  const bool use_small = env_int("HOPF_SMALL", 1) != 0;
   auto class_of = [&](int n_pad) -> int {
+    if (use_small && dense_small_fits(mode, n_pad, distance)) return kSmallClass;
     const DenseVariant v = dense_variant(mode, n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;
   };
@@ -422,7 +426,9 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   std::sort(classes.begin(), classes.end());
   int cls = 0;
   for (int key : classes) {
-    const DenseVariant var{key / 100, (key / 10) % 10, key % 10};
+    const bool small = key == kSmallClass;
+    const DenseVariant var = small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4}
+                                   : DenseVariant{key / 100, (key / 10) % 10, key % 10};
     const int pt = var.pt, occ = var.occ;
     std::vector<DenseProb> views;
     std::vector<std::pair<double, int>> order;  // (cost, view index)
@@ -458,13 +464,15 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     std::memcpy(blob.data() + off_c, ch.data(), sizeof(DenseChunk) * nchunks);
     void* dmeta = nullptr;
     if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
-    const int grid = std::min(nchunks, occ * w->ncu);
-    const int64_t ws_per_wg = 4 * (int64_t)pt * max_npad;
+    // the small kernel: four independent waves per workgroup, each taking chunks
+    const int grid = small ? std::min((nchunks + 3) / 4, occ * w->ncu) : std::min(nchunks, occ * w->ncu);
+    const int64_t ws_per_wg = small ? 0 : 4 * (int64_t)pt * max_npad;
     const int64_t ws64_per_wg = (int64_t)pt * max_npad;
     if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
     if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * ws64_per_wg * grid))) return st;
     size_t lds = 0;
-    for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
+    if (!small)
+      for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
     int* counter = w->counter + cls;
     // reset the counter, and the best arrays of this class's problems
     for (auto& v : views) {
@@ -472,8 +480,11 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
       if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
     }
     const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
-    hipError_t e = launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state, w->state64,
-                                ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every, stream);
+    hipError_t e = small ? launch_dense_small(max_npad, (const DenseProb*)dmeta, dchunks, nchunks, counter, grid,
+                                              stream)
+                         : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
+                                        w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
+                                        stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
     ++cls;
     // the next class reuses the metadata/staging buffers and the workspace: wait for this one

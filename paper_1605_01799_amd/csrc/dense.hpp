@@ -17,4 +17,12 @@ hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, co
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
                         int grid, size_t lds, int distance, int anchor_every, hipStream_t stream);
 
+// Small problems (dense_small.hip): FP32 evaluation of n_pad <= 64, one wave per 64-column tile
+// with the iteration in registers.
+bool dense_small_fits(int mode, int n_pad, int distance);
+int dense_small_cols();       // columns per wave
+int dense_small_occupancy();  // workgroups per CU
+hipError_t launch_dense_small(int n_pad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
+                              int* counter, int grid, hipStream_t stream);
+
 }  // namespace hopf

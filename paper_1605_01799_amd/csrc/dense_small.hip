@@ -1,0 +1,367 @@
+// Small dense problems (n_pad <= 64), FP32 products: one wave per tile of 16 CT columns, with
+// the whole iteration in registers and no workgroup barrier.
+//
+// Same method and arithmetic as the FP32 mode of the tile solver in dense.hip (split Bregman,
+// eqs. (3.4a)-(3.4c), in Douglas-Rachford form on z = v + b; see that file).  What differs is
+// where things live.  With n_pad = 16 RTM rows (RTM <= 4) a lane holds, for each of its CT
+// columns 16 ct + l%16 (ct < CT), the rows 16 rt + 4 (l/16) + q (q = 0..3) of every row tile
+// rt: the MFMA output layout.  The B operand of the 16x16x4 FP32 product for k-step kt (k = 16 kt + 4 (l/16)
+// + q) is then exactly the lane's own right-hand side of row tile kt, and the A operand
+// (M[16 rt + l%16][16 kt + 4 (l/16) + q]) is held for the whole problem in RTM x RTM registers
+// of four floats (M is stored in that fragment order).  The product v = M r, the prox, the step
+// norms (two lane shuffles per column) and the stopping decisions never leave the wave.
+//
+// Columns are (point, copy) pairs; a wave takes chunks of whole points from the launch's queue,
+// so the copies of a point are settled by one wave, in column order.
+#include "common.hpp"
+#include "dense.hpp"
+#include "dense_shared.hpp"
+
+#ifndef SMALL_CT
+#define SMALL_CT 1   // column tiles per wave
+#define SMALL_OCC 2  // workgroups per CU
+#endif
+
+namespace hopf {
+
+namespace {
+
+// Sum over the four lanes of a column (l, l ^ 16, l ^ 32, l ^ 48), in FP64.
+__device__ __forceinline__ double col_sum(float f) {
+  double v = (double)f;
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+}  // namespace
+
+// RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU.
+template <int RTM, int CT, int OCC>
+__global__ void __launch_bounds__(kBlock, OCC)
+dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
+                   int* __restrict__ chunk_counter) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+
+  // queue position of this wave (wave-uniform values, held by every lane)
+  int prob = -1, nextcol = 0, cend = 0, pending = -1, nomore = 0;
+  {
+    int c0 = 0;
+    if (l == 0) c0 = atomicAdd(chunk_counter, 1);
+    c0 = __shfl(c0, 0);
+    if (c0 >= nchunks) return;
+    prob = chunks[c0].prob; nextcol = chunks[c0].col0; cend = nextcol + chunks[c0].ncols;
+  }
+
+  // per-problem registers
+  DenseProb pb = probs[prob];
+  f32x4 Mf[RTM][RTM];
+  f32x4 wv[RTM];
+  auto load_problem = [&]() {
+    pb = probs[prob];
+    const int nks = pb.n_pad >> 4;
+#pragma unroll
+    for (int rt = 0; rt < RTM; ++rt) {
+      const int rtc = rt < nks ? rt : 0;
+#pragma unroll
+      for (int kt = 0; kt < RTM; ++kt) {
+        const int ktc = kt < nks ? kt : 0;
+        Mf[rt][kt] = (rt < nks && kt < nks) ? *gp((const f32x4*)pb.Mf + ((size_t)rtc * nks + ktc) * 64 + l)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      wv[rt] = rt < nks ? *gp((const f32x4*)(pb.wf + 16 * rtc + 4 * lg)) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  load_problem();
+
+  // per-column registers (column 16 ct + lr; replicated in the four lanes of the column)
+  f32x4 z[RTM][CT], xp[RTM][CT];
+  int st[CT], flags[CT], iters[CT], stall[CT], jj[CT], kk[CT];
+  float thr[CT], gam[CT];  // t / lambda, the shrink2 factor
+  float prev[CT], bst[CT];
+  double phi[CT], hp[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    st[ct] = COL_EMPTY; flags[ct] = 0; iters[ct] = 0; stall[ct] = 0; jj[ct] = 0; kk[ct] = 0;
+    thr[ct] = 0.f; gam[ct] = 1.f;
+    prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < RTM; ++rt) { z[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f}; xp[rt][ct] = z[rt][ct]; }
+  }
+
+  while (true) {
+    const int n = pb.n, n_pad = pb.n_pad, K = pb.K;
+    const int nrt = n_pad >> 4;
+    const float flam = (float)pb.lambda;
+    const bool has_l1 = hk_has_l1(pb.hkind), has_l2 = hk_has_l2(pb.hkind);
+
+    // ============================================================ settle finished columns
+    int any_fin = 0, any_empty = 0;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      any_fin |= (st[ct] == COL_DONE || st[ct] == COL_INVALID) ? 1 : 0;
+      any_empty |= st[ct] == COL_EMPTY ? 1 : 0;
+    }
+    any_fin = __any(any_fin);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      if (!any_fin) break;  // wave-uniform: most passes finish no column
+      for (int c0 = 0; c0 < 16; ++c0) {  // wave-uniform loop over the columns, in column order
+        const int s = __shfl(st[ct], c0);
+        if (s != COL_DONE && s != COL_INVALID) continue;
+        // the column's scalars, broadcast by every lane (no lane may be inactive in a shuffle)
+        const int j = __shfl(jj[ct], c0), k = __shfl(kk[ct], c0);
+        const double key = __shfl(phi[ct], c0), hpk = __shfl(hp[ct], c0);
+        const int fl = __shfl(flags[ct], c0), itk = __shfl(iters[ct], c0);
+        int better = 0;
+        if (l == 0) {
+          if (s == COL_INVALID) {
+            better = 2;
+            pb.bestk[j] = -2;
+            pb.phi[j] = __builtin_nanf(""); pb.dphidt[j] = __builtin_nanf("");
+            if (pb.iters) pb.iters[j] = -1;
+            if (pb.kstar) pb.kstar[j] = -1;
+          } else {
+            const int bk = pb.bestk[j];
+            const double bv = pb.bestv[j];
+            better = (bk < 0 || key < bv || (key == bv && k < bk)) ? 1 : 0;
+            if (better) {
+              pb.bestv[j] = key; pb.bestk[j] = k;
+              pb.phi[j] = (float)key;
+              pb.dphidt[j] = (float)(-hpk);
+              if (pb.iters) pb.iters[j] = (fl & FLAG_CAPPED) ? -2 : itk;
+              if (pb.kstar) pb.kstar[j] = k;
+            }
+          }
+        }
+        better = __shfl(better, 0);
+        if (better && lr == c0) {  // the column's four lanes write p (kept in z) or NaN
+          HOPF_GLOBAL float* g = gp(pb.grad + (size_t)j * n);
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * rt + 4 * lg + q;
+              if (rt < nrt && row < n) g[row] = better == 2 ? __builtin_nanf("") : z[rt][ct][q];
+            }
+          }
+        }
+        if (lr == c0) st[ct] = COL_EMPTY;
+      }
+    }
+
+    // ============================================================ refill empty columns
+    int live = 0;
+    any_empty = __any(any_empty | any_fin);  // settled columns are empty now
+    if (!any_empty) live = 1;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      if (!any_empty) break;  // wave-uniform
+      for (int c0 = 0; c0 < 16; ++c0) {
+        const int s = __shfl(st[ct], c0);
+        if (s != COL_EMPTY) { live = 1; continue; }
+        while (nextcol >= cend && pending < 0 && !nomore) {
+          int nc = 0;
+          if (l == 0) nc = atomicAdd(chunk_counter, 1);
+          nc = __shfl(nc, 0);
+          if (nc >= nchunks) { nomore = 1; break; }
+          if (chunks[nc].prob == prob) { nextcol = chunks[nc].col0; cend = nextcol + chunks[nc].ncols; }
+          else pending = nc;
+        }
+        if (nextcol >= cend) continue;
+        const int col = nextcol++;
+        live = 1;
+        if (lr == c0) {  // the column's four lanes take the new (point, copy)
+          const int j = col / K, k = col % K;
+          jj[ct] = j; kk[ct] = k;
+          const float tv = pb.t[j];
+          const bool tok = tv > 0.f && isfinite(tv);
+          thr[ct] = (float)((double)tv / pb.lambda);
+          gam[ct] = 1.f; iters[ct] = 0; stall[ct] = 0; flags[ct] = FLAG_FIRST;
+          prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
+          const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
+          const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
+          bool nf = false;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * rt + 4 * lg + q;
+              float v = 0.f;
+              if (rt < nrt && row < n) {
+                const float xv = xj[row];
+                if (!isfinite(xv)) nf = true;
+                v = (float)((double)xv - (cen ? cen[row] : 0.0));
+              }
+              xp[rt][ct][q] = v;
+              z[rt][ct][q] = v;
+            }
+          }
+          st[ct] = tok ? COL_ACTIVE : COL_INVALID;
+          if (nf) st[ct] = COL_INVALID;  // combined over the column's lanes below
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {  // a non-finite coordinate in any lane of a column invalidates it
+      int inv = st[ct] == COL_INVALID ? 1 : 0;
+      inv |= __shfl_xor(inv, 16);
+      inv |= __shfl_xor(inv, 32);
+      if (inv && st[ct] == COL_ACTIVE) st[ct] = COL_INVALID;
+    }
+    if (!live) {
+      if (pending >= 0) {  // drained: switch to the pending problem
+        prob = chunks[pending].prob; nextcol = chunks[pending].col0; cend = nextcol + chunks[pending].ncols;
+        pending = -1;
+        load_problem();
+        continue;
+      }
+      break;
+    }
+    // only invalid columns left: settle them before iterating
+    {
+      int any_on = 0, any_inv = 0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        any_on |= (st[ct] == COL_ACTIVE || st[ct] == COL_WAITING || st[ct] == COL_PHI) ? 1 : 0;
+        any_inv |= st[ct] == COL_INVALID ? 1 : 0;
+      }
+      if (!__any(any_on)) {
+        if (__any(any_inv)) continue;
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      if (st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass evaluates the value
+
+    // ============================================================ right-hand sides
+    f32x4 r[RTM][CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const bool on = st[ct] == COL_ACTIVE || st[ct] == COL_PHI;
+      const bool first = flags[ct] & FLAG_FIRST;
+#pragma unroll
+      for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float zz = z[rt][ct][q];
+          const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
+          const float d = first ? zz : gam[ct] * (zz - clampf(zz, -th, th));
+          r[rt][ct][q] = on ? xp[rt][ct][q] + flam * (2.f * d - zz) : 0.f;
+        }
+      }
+    }
+
+    // ============================================================ products + epilogue
+    // per-lane partial sums (at most 4 RTM terms each; the column sums are taken in FP64)
+    float s0[CT], s1[CT], v2[CT], v3[CT], v4[CT], v5[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) { s0[ct] = 0.f; s1[ct] = 0.f; v2[ct] = 0.f; v3[ct] = 0.f; v4[ct] = 0.f; v5[ct] = 0.f; }
+#pragma unroll
+    for (int rt = 0; rt < RTM; ++rt) {
+      if (rt >= nrt) continue;  // wave-uniform
+      f32x4 acc[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < RTM; ++kt) {
+        if (kt >= nrt) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[rt][kt][q], r[kt][ct][q], acc[ct], 0, 0, 0);
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int s = st[ct];
+        const bool first = flags[ct] & FLAG_FIRST;
+        if (s == COL_ACTIVE) {
+          float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float zz = z[rt][ct][q];
+            const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
+            const float d = first ? zz : gam[ct] * (zz - clampf(zz, -th, th));
+            const float zn = zz - d + acc[ct][q];
+            const float step = zn - zz;
+            const float sn = zn - clampf(zn, -th, th);
+            a0 += step * step;
+            a1 += sn * sn;
+            z[rt][ct][q] = zn;
+          }
+          s0[ct] += a0;
+          s1[ct] += a1;
+        } else if (s == COL_PHI) {  // value sums at the converged iterate; p replaces z
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = 16 * rt + 4 * lg + q;
+            const float zz = z[rt][ct][q];
+            const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
+            const float d = (row < n) ? (first ? zz : gam[ct] * (zz - clampf(zz, -th, th))) : 0.f;
+            const float vv = acc[ct][q];
+            v2[ct] += xp[rt][ct][q] * d;
+            v3[ct] += (2.f * d - vv) * (r[rt][ct][q] - flam * vv);
+            v4[ct] += wv[rt][q] * fabsf(d);
+            v5[ct] += d * d;
+            z[rt][ct][q] = d;
+          }
+        }
+      }
+    }
+
+    // ============================================================ per-column update
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const double sm0 = col_sum(s0[ct]), sm1 = col_sum(s1[ct]);
+      const double sm2 = col_sum(v2[ct]), sm3 = col_sum(v3[ct]), sm4 = col_sum(v4[ct]), sm5 = col_sum(v5[ct]);
+      if (st[ct] == COL_ACTIVE) {
+        iters[ct] += 1;
+        float g = 1.f;
+        if (has_l2) {
+          const double nz = sqrt(fmax(sm1, 0.0));
+          g = nz > 0.0 ? (float)(fmax(nz - (double)thr[ct], 0.0) / nz) : 0.f;
+        }
+        gam[ct] = g;
+        flags[ct] &= ~FLAG_FIRST;
+        const double a = sqrt(sm0), b = sqrt((double)prev[ct]);
+        prev[ct] = (float)sm0;
+        const bool conv = (a + b) * (a + b) <= pb.tol;
+        bool stalled = false;
+        if (sm0 < (double)bst[ct]) { bst[ct] = (float)sm0; stall[ct] = 0; }
+        else stalled = ++stall[ct] >= kStallIters;
+        const bool capped = iters[ct] >= pb.max_iter || stalled;
+        if (conv) st[ct] = COL_WAITING;
+        else if (capped) { st[ct] = COL_WAITING; flags[ct] |= FLAG_SOLVE_CAP | FLAG_CAPPED; }
+      } else if (st[ct] == COL_PHI) {
+        const double pn = sqrt(sm5);
+        const double H = (has_l1 ? sm4 : 0.0) + (has_l2 ? pn : 0.0);
+        const double tv = (double)pb.t[jj[ct]];
+        phi[ct] = sm2 - 0.5 * sm3 - tv * H - (pb.level_set ? 0.5 : 0.0);
+        hp[ct] = H;
+        st[ct] = COL_DONE;
+      }
+    }
+  }
+}
+
+bool dense_small_fits(int mode, int n_pad, int distance) { return mode == 0 && !distance && n_pad <= 64; }
+
+int dense_small_cols() { return 16 * SMALL_CT; }
+int dense_small_occupancy() { return SMALL_OCC; }
+
+hipError_t launch_dense_small(int n_pad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
+                              int* counter, int grid, hipStream_t stream) {
+  if (n_pad <= 32)
+    hipLaunchKernelGGL((dense_small_kernel<2, SMALL_CT, SMALL_OCC>), dim3(grid), dim3(kBlock), 0, stream, d_probs,
+                       d_chunks, nchunks, counter);
+  else if (n_pad <= 64)
+    hipLaunchKernelGGL((dense_small_kernel<4, SMALL_CT, SMALL_OCC>), dim3(grid), dim3(kBlock), 0, stream, d_probs,
+                       d_chunks, nchunks, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace hopf
