@@ -13,6 +13,8 @@
 //
 // Columns are (point, copy) pairs; a wave takes chunks of whole points from the launch's queue,
 // so the copies of a point are settled by one wave, in column order.
+#include <type_traits>
+
 #include "common.hpp"
 #include "dense.hpp"
 #include "dense_shared.hpp"
@@ -34,6 +36,17 @@ __device__ __forceinline__ double col_sum(float f) {
   return v;
 }
 
+// The same in FP32 (the step norms, which only decide when to stop); the four lanes add in the
+// same pairs and agree bit for bit.
+__device__ __forceinline__ float col_sumf(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// clamp(z, lo, hi) for lo <= hi, one instruction
+__device__ __forceinline__ float med3f(float z, float lo, float hi) { return __builtin_amdgcn_fmed3f(z, lo, hi); }
+
 }  // namespace
 
 // RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU.
@@ -43,24 +56,28 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
                    int* __restrict__ chunk_counter) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
+  // wave-uniform values go through readfirstlane so that the queue state, the problem's scalars
+  // and every branch on them live in scalar registers
+  auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
 
-  // queue position of this wave (wave-uniform values, held by every lane)
+  // queue position of this wave
   int prob = -1, nextcol = 0, cend = 0, pending = -1, nomore = 0;
   {
     int c0 = 0;
     if (l == 0) c0 = atomicAdd(chunk_counter, 1);
-    c0 = __shfl(c0, 0);
+    c0 = uni(__shfl(c0, 0));
     if (c0 >= nchunks) return;
-    prob = chunks[c0].prob; nextcol = chunks[c0].col0; cend = nextcol + chunks[c0].ncols;
+    prob = uni(chunks[c0].prob); nextcol = uni(chunks[c0].col0); cend = nextcol + uni(chunks[c0].ncols);
   }
 
-  // per-problem registers
+  // per-problem registers; rows and columns beyond n_pad (n_pad < 16 RTM) are zero in M, w and x',
+  // so their coordinates stay zero and the products need no bounds
   DenseProb pb = probs[prob];
   f32x4 Mf[RTM][RTM];
   f32x4 wv[RTM];
   auto load_problem = [&]() {
     pb = probs[prob];
-    const int nks = pb.n_pad >> 4;
+    const int nks = uni(pb.n_pad) >> 4;
 #pragma unroll
     for (int rt = 0; rt < RTM; ++rt) {
       const int rtc = rt < nks ? rt : 0;
@@ -91,10 +108,10 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
   }
 
   while (true) {
-    const int n = pb.n, n_pad = pb.n_pad, K = pb.K;
+    const int n = uni(pb.n), n_pad = uni(pb.n_pad), K = uni(pb.K), hkind = uni(pb.hkind);
     const int nrt = n_pad >> 4;
     const float flam = (float)pb.lambda;
-    const bool has_l1 = hk_has_l1(pb.hkind), has_l2 = hk_has_l2(pb.hkind);
+    const bool has_l1 = hk_has_l1(hkind), has_l2 = hk_has_l2(hkind);
 
     // ============================================================ settle finished columns
     int any_fin = 0, any_empty = 0;
@@ -106,9 +123,9 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     any_fin = __any(any_fin);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      if (!any_fin) break;  // wave-uniform: most passes finish no column
-      for (int c0 = 0; c0 < 16; ++c0) {  // wave-uniform loop over the columns, in column order
-        const int s = __shfl(st[ct], c0);
+      if (!any_fin) break;  // most passes finish no column
+      for (int c0 = 0; c0 < 16; ++c0) {  // the columns in column order
+        const int s = uni(__shfl(st[ct], c0));
         if (s != COL_DONE && s != COL_INVALID) continue;
         // the column's scalars, broadcast by every lane (no lane may be inactive in a shuffle)
         const int j = __shfl(jj[ct], c0), k = __shfl(kk[ct], c0);
@@ -135,7 +152,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             }
           }
         }
-        better = __shfl(better, 0);
+        better = uni(__shfl(better, 0));
         if (better && lr == c0) {  // the column's four lanes write p (kept in z) or NaN
           HOPF_GLOBAL float* g = gp(pb.grad + (size_t)j * n);
 #pragma unroll
@@ -157,16 +174,16 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     if (!any_empty) live = 1;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      if (!any_empty) break;  // wave-uniform
+      if (!any_empty) break;
       for (int c0 = 0; c0 < 16; ++c0) {
-        const int s = __shfl(st[ct], c0);
+        const int s = uni(__shfl(st[ct], c0));
         if (s != COL_EMPTY) { live = 1; continue; }
         while (nextcol >= cend && pending < 0 && !nomore) {
           int nc = 0;
           if (l == 0) nc = atomicAdd(chunk_counter, 1);
-          nc = __shfl(nc, 0);
+          nc = uni(__shfl(nc, 0));
           if (nc >= nchunks) { nomore = 1; break; }
-          if (chunks[nc].prob == prob) { nextcol = chunks[nc].col0; cend = nextcol + chunks[nc].ncols; }
+          if (uni(chunks[nc].prob) == prob) { nextcol = uni(chunks[nc].col0); cend = nextcol + uni(chunks[nc].ncols); }
           else pending = nc;
         }
         if (nextcol >= cend) continue;
@@ -212,7 +229,8 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     }
     if (!live) {
       if (pending >= 0) {  // drained: switch to the pending problem
-        prob = chunks[pending].prob; nextcol = chunks[pending].col0; cend = nextcol + chunks[pending].ncols;
+        prob = uni(chunks[pending].prob); nextcol = uni(chunks[pending].col0);
+        cend = nextcol + uni(chunks[pending].ncols);
         pending = -1;
         load_problem();
         continue;
@@ -231,118 +249,157 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         if (__any(any_inv)) continue;
       }
     }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-      if (st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass evaluates the value
-
-    // ============================================================ right-hand sides
-    f32x4 r[RTM][CT];
+    int phi_lane = 0;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const bool on = st[ct] == COL_ACTIVE || st[ct] == COL_PHI;
-      const bool first = flags[ct] & FLAG_FIRST;
-#pragma unroll
-      for (int rt = 0; rt < RTM; ++rt) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float zz = z[rt][ct][q];
-          const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
-          const float d = first ? zz : gam[ct] * (zz - clampf(zz, -th, th));
-          r[rt][ct][q] = on ? xp[rt][ct][q] + flam * (2.f * d - zz) : 0.f;
-        }
-      }
+      if (st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass evaluates the value
+      phi_lane |= st[ct] == COL_PHI ? 1 : 0;
     }
+    const bool any_phi = __any(phi_lane);
 
-    // ============================================================ products + epilogue
-    // per-lane partial sums (at most 4 RTM terms each; the column sums are taken in FP64)
-    float s0[CT], s1[CT], v2[CT], v3[CT], v4[CT], v5[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) { s0[ct] = 0.f; s1[ct] = 0.f; v2[ct] = 0.f; v3[ct] = 0.f; v4[ct] = 0.f; v5[ct] = 0.f; }
-#pragma unroll
-    for (int rt = 0; rt < RTM; ++rt) {
-      if (rt >= nrt) continue;  // wave-uniform
-      f32x4 acc[CT];
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kt = 0; kt < RTM; ++kt) {
-        if (kt >= nrt) continue;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[rt][kt][q], r[kt][ct][q], acc[ct], 0, 0, 0);
-      }
+    // one pass of every column: the Hamiltonian's kind fixed at compile time, so that the pass is
+    // straight-line code the scheduler can interleave (products of one row tile with the update
+    // of the previous one)
+    auto pass = [&](auto l2tag) {
+      constexpr bool HL2 = decltype(l2tag)::value;
+      // ---------------------------------------------------------- right-hand sides
+      // d = prox of the current z (eq. (3.4b)); the first pass of a solve has d = z, which is the
+      // same formula with threshold 0 and factor 1.  u = z - d is the C operand of the products,
+      // so that they return the next z = z - d + M r directly (eq. (3.4a) in Douglas-Rachford
+      // form); r = x' + lambda (2 d - z).  Columns that are not iterating compute garbage that is
+      // never read (the product keeps columns apart).
+      float thd[CT], gd[CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        const int s = st[ct];
         const bool first = flags[ct] & FLAG_FIRST;
-        if (s == COL_ACTIVE) {
-          float a0 = 0.f, a1 = 0.f;
+        thd[ct] = (first || !has_l1) ? 0.f : thr[ct];
+        gd[ct] = (first || !HL2) ? 1.f : gam[ct];
+      }
+      f32x4 r[RTM][CT], u[RTM][CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+        for (int rt = 0; rt < RTM; ++rt) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float zz = z[rt][ct][q];
-            const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
-            const float d = first ? zz : gam[ct] * (zz - clampf(zz, -th, th));
-            const float zn = zz - d + acc[ct][q];
-            const float step = zn - zz;
-            const float sn = zn - clampf(zn, -th, th);
-            a0 += step * step;
-            a1 += sn * sn;
-            z[rt][ct][q] = zn;
-          }
-          s0[ct] += a0;
-          s1[ct] += a1;
-        } else if (s == COL_PHI) {  // value sums at the converged iterate; p replaces z
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int row = 16 * rt + 4 * lg + q;
-            const float zz = z[rt][ct][q];
-            const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
-            const float d = (row < n) ? (first ? zz : gam[ct] * (zz - clampf(zz, -th, th))) : 0.f;
-            const float vv = acc[ct][q];
-            v2[ct] += xp[rt][ct][q] * d;
-            v3[ct] += (2.f * d - vv) * (r[rt][ct][q] - flam * vv);
-            v4[ct] += wv[rt][q] * fabsf(d);
-            v5[ct] += d * d;
-            z[rt][ct][q] = d;
+            const float th = theta_f(thd[ct], wv[rt][q]);
+            const float sh = zz - med3f(zz, -th, th);
+            const float d = HL2 ? gd[ct] * sh : sh;
+            u[rt][ct][q] = zz - d;
+            r[rt][ct][q] = xp[rt][ct][q] + flam * (2.f * d - zz);
           }
         }
       }
-    }
-
-    // ============================================================ per-column update
+      if (any_phi) {  // the value pass needs the plain product M r
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const double sm0 = col_sum(s0[ct]), sm1 = col_sum(s1[ct]);
-      const double sm2 = col_sum(v2[ct]), sm3 = col_sum(v3[ct]), sm4 = col_sum(v4[ct]), sm5 = col_sum(v5[ct]);
-      if (st[ct] == COL_ACTIVE) {
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u[rt][ct][q] = st[ct] == COL_PHI ? 0.f : u[rt][ct][q];
+      }
+
+      // ---------------------------------------------------------- products, then the step sums
+      // (u becomes z - d + M r, or M r in a value pass)
+#pragma unroll
+      for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+        for (int kt = 0; kt < RTM; ++kt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              u[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[rt][kt][q], r[kt][ct][q], u[rt][ct], 0, 0, 0);
+
+      float s0[CT], s1[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const bool act = st[ct] == COL_ACTIVE;
+        float a0 = 0.f, a1 = 0.f;
+        const float thn = has_l1 ? thr[ct] : 0.f;
+#pragma unroll
+        for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float zn = u[rt][ct][q];
+            const float step = zn - z[rt][ct][q];
+            a0 += step * step;
+            if (HL2) {  // |shrink1(z)|, for the shrink2 factor of the next pass
+              const float th = theta_f(thn, wv[rt][q]);
+              const float sn = zn - med3f(zn, -th, th);
+              a1 += sn * sn;
+            }
+            z[rt][ct][q] = act ? zn : z[rt][ct][q];
+          }
+        }
+        s0[ct] = col_sumf(a0);
+        s1[ct] = HL2 ? col_sumf(a1) : 0.f;
+      }
+
+      // ---------------------------------------------------------- per-column update
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        if (st[ct] != COL_ACTIVE) continue;
+        const double sm0 = (double)s0[ct];
         iters[ct] += 1;
         float g = 1.f;
-        if (has_l2) {
-          const double nz = sqrt(fmax(sm1, 0.0));
+        if (HL2) {
+          const double nz = sqrt(fmax((double)s1[ct], 0.0));
           g = nz > 0.0 ? (float)(fmax(nz - (double)thr[ct], 0.0) / nz) : 0.f;
         }
         gam[ct] = g;
         flags[ct] &= ~FLAG_FIRST;
-        const double a = sqrt(sm0), b = sqrt((double)prev[ct]);
+        // (|dz_k| + |dz_{k-1}|)^2 <= tol
+        const double pv = (double)prev[ct];
         prev[ct] = (float)sm0;
-        const bool conv = (a + b) * (a + b) <= pb.tol;
+        const bool conv = sm0 + pv + 2.0 * sqrt(sm0 * pv) <= pb.tol;
         bool stalled = false;
         if (sm0 < (double)bst[ct]) { bst[ct] = (float)sm0; stall[ct] = 0; }
         else stalled = ++stall[ct] >= kStallIters;
         const bool capped = iters[ct] >= pb.max_iter || stalled;
         if (conv) st[ct] = COL_WAITING;
         else if (capped) { st[ct] = COL_WAITING; flags[ct] |= FLAG_SOLVE_CAP | FLAG_CAPPED; }
-      } else if (st[ct] == COL_PHI) {
-        const double pn = sqrt(sm5);
-        const double H = (has_l1 ? sm4 : 0.0) + (has_l2 ? pn : 0.0);
-        const double tv = (double)pb.t[jj[ct]];
-        phi[ct] = sm2 - 0.5 * sm3 - tv * H - (pb.level_set ? 0.5 : 0.0);
-        hp[ct] = H;
-        st[ct] = COL_DONE;
       }
-    }
+
+      // ---------------------------------------------------------- value pass (eq. (3.5))
+      if (any_phi) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const bool isphi = st[ct] == COL_PHI;
+          float v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * rt + 4 * lg + q;
+              const float zz = z[rt][ct][q];
+              const float th = theta_f(thd[ct], wv[rt][q]);
+              const float sh = zz - med3f(zz, -th, th);
+              const float d = (row < n) ? (HL2 ? gd[ct] * sh : sh) : 0.f;
+              const float vv = u[rt][ct][q];
+              const float rr = xp[rt][ct][q] + flam * (2.f * d - zz);
+              v2 += xp[rt][ct][q] * d;
+              v3 += (2.f * d - vv) * (rr - flam * vv);
+              v4 += wv[rt][q] * fabsf(d);
+              v5 += d * d;
+              z[rt][ct][q] = isphi ? d : zz;  // p replaces z
+            }
+          }
+          const double sm2 = col_sum(v2), sm3 = col_sum(v3), sm4 = col_sum(v4), sm5 = col_sum(v5);
+          if (isphi) {
+            const double pn = sqrt(sm5);
+            const double H = (has_l1 ? sm4 : 0.0) + (HL2 ? pn : 0.0);
+            const double tv = (double)pb.t[jj[ct]];
+            phi[ct] = sm2 - 0.5 * sm3 - tv * H - (pb.level_set ? 0.5 : 0.0);
+            hp[ct] = H;
+            st[ct] = COL_DONE;
+          }
+        }
+      }
+    };
+    if (has_l2) pass(std::true_type{});
+    else pass(std::false_type{});
   }
 }
 
