@@ -95,8 +95,14 @@ static double shrink1(double z, double a) {
   return z >= 0.0 ? m : -m;
 }
 
-/* H(p) for the supported family (support functions of a box, a ball, and their Minkowski sum). */
+/* H(p) for the supported family (support functions of a box, a ball, their Minkowski sum, and
+ * of the ellipsoid sum y_i^2 / w_i <= 1: the norm sqrt(<p, D p>) with D = diag(w), section 4.4). */
 static double ham(int n, int hkind, const double* w, const double* p) {
+  if (hkind == OH_WL2) {
+    ksum k = {0, 0};
+    for (int i = 0; i < n; ++i) ks_add(&k, wgt(w, i) * p[i] * p[i]);
+    return sqrt(ks_val(&k));
+  }
   double h = 0.0;
   if (hkind == OH_WL1 || hkind == OH_L2_WL1) {
     ksum k = {0, 0};
@@ -113,7 +119,46 @@ static double ham(int n, int hkind, const double* w, const double* p) {
  * L2 + WL1: shrink2(shrink1(z, theta*w), theta), the composition of the two maps
  * (the prox of a sum of a group norm and a separable norm that both act on
  * the same single group). */
+/* prox of theta * sqrt(<., D .>), D = diag(w) > 0 (section 4.4).  By eq. (prox-projection) it is
+ * z - pi_C(z), C the Wulff shape of theta H: the ellipsoid sum y_i^2 / s_i <= 1 with squared
+ * semi-axes s_i = theta^2 w_i.  For z in C the prox is 0.  Otherwise the projection is
+ * s_i z_i / (s_i + mu), with mu > 0 the Lagrange multiplier solving sum s_i z_i^2 / (s_i + mu)^2 = 1,
+ * i.e. the minimiser of mu -> sum s_i z_i^2 / (s_i + mu) + mu, found as the paper does by Newton's
+ * method from mu = 0 (here run until the step is at rounding level, not the paper's 1e-8).
+ * Then d_i = z_i - s_i z_i / (s_i + mu) = mu z_i / (s_i + mu). */
+static void prox_wl2(int n, const double* w, double theta, const double* z, double* d) {
+  ksum q = {0, 0};
+  for (int i = 0; i < n; ++i) ks_add(&q, z[i] * z[i] / (theta * theta * wgt(w, i)));
+  if (ks_val(&q) <= 1.0) {
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    return;
+  }
+  double mu = 0.0;
+  for (int it = 0; it < 1000; ++it) {
+    ksum g = {0, 0}, gp = {0, 0};  /* derivative and second derivative of the minimised function */
+    ks_add(&g, 1.0);
+    for (int i = 0; i < n; ++i) {
+      const double s = theta * theta * wgt(w, i), den = s + mu;
+      const double e = s * z[i] * z[i] / (den * den);
+      ks_add(&g, -e);
+      ks_add(&gp, 2.0 * e / den);
+    }
+    const double dmu = -ks_val(&g) / ks_val(&gp);
+    if (!(dmu > 0.0)) break; /* increasing from the left until rounding stops it */
+    mu += dmu;
+    if (dmu <= 1e-16 * (mu > 1.0 ? mu : 1.0)) break;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double s = theta * theta * wgt(w, i);
+    d[i] = mu * z[i] / (s + mu);
+  }
+}
+
 static void prox_h(int n, int hkind, const double* w, double theta, const double* z, double* d) {
+  if (hkind == OH_WL2) {
+    prox_wl2(n, w, theta, z, d);
+    return;
+  }
   if (hkind == OH_WL1 || hkind == OH_L2_WL1) {
     for (int i = 0; i < n; ++i) d[i] = shrink1(z[i], theta * wgt(w, i));
   } else {
@@ -249,10 +294,10 @@ static void* eval_worker(void* arg) {
 
 static int check_problem(const oh_problem* pb) {
   if (!pb || pb->n < 1 || !pb->A || pb->K < 1 || !(pb->lambda > 0) || pb->max_iter < 1) return -1;
-  if (pb->hkind < OH_WL1 || pb->hkind > OH_L2_WL1) return -1;
+  if (pb->hkind < OH_WL1 || pb->hkind > OH_WL2) return -1;
   if (pb->w)
     for (int i = 0; i < pb->n; ++i)
-      if (!(pb->w[i] >= 0)) return -1;
+      if (!(pb->w[i] >= 0) || (pb->hkind == OH_WL2 && !(pb->w[i] > 0))) return -1;
   return 0;
 }
 

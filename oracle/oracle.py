@@ -29,8 +29,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hopf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_hopf.so")
 
-OH_WL1, OH_L2, OH_L2_WL1 = 0, 1, 2
-_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1}
+OH_WL1, OH_L2, OH_L2_WL1, OH_WL2 = 0, 1, 2, 3
+_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1, "wl2": OH_WL2}
 
 
 def build(force: bool = True) -> str:

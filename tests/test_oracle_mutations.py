@@ -28,6 +28,9 @@ MUTANTS = {
     "newton_step_sign": ("sv += ds;", "sv -= ds;"),
     "dphidt_sign": ("J->dphidt[j] = -ham(", "J->dphidt[j] = ham("),
     "centre_sign": ("xp[i] = x[i] - (pb->centres", "xp[i] = x[i] + (pb->centres"),
+    "wl2_multiplier_equation_rhs": ("ks_add(&g, 1.0);", "ks_add(&g, 0.5);"),
+    "wl2_prox_wrong_factor": ("d[i] = mu * z[i] / (s + mu);", "d[i] = s * z[i] / (s + mu);"),
+    "wl2_hamiltonian_unweighted": ("ks_add(&k, wgt(w, i) * p[i] * p[i]);", "ks_add(&k, p[i] * p[i]);"),
     "secular_projection_index": ("us[a] = sigma[a] * u[a] / (sigma[a] + mu);", "us[a] = sigma[a] * u[a] / (sigma[a] + mu * mu);"),
 }
 
@@ -73,12 +76,19 @@ def battery(lib):
         def kkt():
             from tests.test_oracle_pins import kkt_residual
             ok = True
-            for hk in ("wl1", "l2", "l2_wl1"):
+            for hk in ("wl1", "l2", "l2_wl1", "wl2"):
                 for lam in (1.0, 0.4):
                     r = O.oracle_eval(A, x, t, hk, w=w, lam=lam, tol=1e-26, max_iter=20000)
                     ok &= all(kkt_residual(A, x[j], t[j], r["grad"][j], hk, w) < 1e-7 for j in range(8))
             return ok
         check("kkt", kkt)
+
+        def wl2_scaled_l2():
+            r = O.oracle_eval(A, x, t, "wl2", w=np.full(n, 2.0), tol=1e-26, max_iter=20000)
+            r2 = O.oracle_eval(A, x, np.sqrt(2.0) * t, "l2", tol=1e-26, max_iter=20000)
+            ok = np.allclose(r["phi"], r2["phi"], atol=1e-9) and np.allclose(r["grad"], r2["grad"], atol=1e-9)
+            return ok and np.allclose(r["dphidt"], -np.sqrt(2.0) * np.linalg.norm(r["grad"], axis=1), atol=1e-9)
+        check("wl2_scaled_l2", wl2_scaled_l2)
 
         def union_translation():
             C = rng.normal(0, 2, (2, n))

@@ -103,8 +103,59 @@ def test_fig4_union_closed_form(oracle_lib):
     assert np.all(r["kstar"][clear] == kexp[clear])
 
 
+def test_wl2_constant_weights_is_scaled_l2(oracle_lib):
+    """H = sqrt(<p, D p>) with D = c I is sqrt(c) |p|: the problem at time t equals the l2 one
+    at time sqrt(c) t (same phi and p), and dphi/dt = -sqrt(c) |p|."""
+    rng = np.random.default_rng(31)
+    n = 9
+    A = rand_spd(n, rng, 0.2, 6)
+    x = rng.normal(0, 2, (40, n))
+    t = rng.uniform(0.05, 3, 40)
+    for c in (0.3, 1.0, 4.0):
+        r = oracle_lib.oracle_eval(A, x, t, "wl2", w=np.full(n, c), tol=TOL)
+        r2 = oracle_lib.oracle_eval(A, x, np.sqrt(c) * t, "l2", tol=TOL)
+        np.testing.assert_allclose(r["phi"], r2["phi"], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(r["grad"], r2["grad"], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(r["dphidt"], -np.sqrt(c) * np.linalg.norm(r["grad"], axis=1),
+                                   rtol=1e-11, atol=1e-11)
+
+
+def ellipsoid_projection_bisection(z, s):
+    """Projection of z onto {y : sum y_i^2 / s_i <= 1} by bisection on the Lagrange multiplier
+    (a different root finder from the oracle's Newton)."""
+    if np.sum(z * z / s) <= 1:
+        return z.copy()
+    f = lambda mu: np.sum(s * z * z / (s + mu) ** 2) - 1
+    lo, hi = 0.0, 1.0
+    while f(hi) > 0:
+        hi *= 2
+    for _ in range(300):
+        m = 0.5 * (lo + hi)
+        lo, hi = (m, hi) if f(m) > 0 else (lo, m)
+    return s * z / (s + 0.5 * (lo + hi))
+
+
+def test_wl2_identity_is_ellipsoid_projection(oracle_lib):
+    """A = I: p* = prox_{tH}(x) = x - pi_{tC}(x) (eq. (prox-projection)), with C the Wulff
+    shape sum y_i^2 / w_i <= 1 of H = sqrt(<., D .>); phi = <x,p> - |p|^2/2 - t H(p).
+    Includes points inside tC (p = 0, phi = 0)."""
+    rng = np.random.default_rng(32)
+    n = 7
+    w = rng.uniform(0.5, 2, n)
+    x = rng.normal(0, 2, (60, n))
+    t = rng.uniform(0.05, 3, 60)
+    x[:6] *= 0.05  # inside t C
+    r = oracle_lib.oracle_eval(np.eye(n), x, t, "wl2", w=w, tol=TOL)
+    for j in range(60):
+        p = x[j] - ellipsoid_projection_bisection(x[j], t[j] ** 2 * w)
+        H = np.sqrt(np.sum(w * p * p))
+        np.testing.assert_allclose(r["grad"][j], p, rtol=1e-11, atol=1e-12)
+        assert abs(r["phi"][j] - (x[j] @ p - 0.5 * p @ p - t[j] * H)) <= 1e-11 * max(1, abs(r["phi"][j]))
+    assert np.all(r["grad"][:6] == 0) and np.all(r["phi"][:6] == 0)
+
+
 # ---------------------------------------------------------------- brute force
-@pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1"])
+@pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1", "wl2"])
 def test_brute_force_n2(oracle_lib, hkind):
     """n = 2, dense SPD A: minimise F(p) = 1/2 p^T A p + t H(p) - <x,p> by a grid search
     refined with Nelder-Mead; phi and p must agree with the oracle."""
@@ -113,6 +164,8 @@ def test_brute_force_n2(oracle_lib, hkind):
     w = rng.uniform(0.5, 2, 2)
 
     def H(p):
+        if hkind == "wl2":
+            return np.sqrt(np.sum(w * p * p))
         h = 0.0
         if hkind in ("wl1", "l2_wl1"):
             h += np.sum(w * np.abs(p))
@@ -133,6 +186,8 @@ def test_brute_force_n2(oracle_lib, hkind):
             hv = hv + w[0] * np.abs(P1) + w[1] * np.abs(P2)
         if hkind in ("l2", "l2_wl1"):
             hv = hv + np.sqrt(P1 ** 2 + P2 ** 2)
+        if hkind == "wl2":
+            hv = np.sqrt(w[0] * P1 ** 2 + w[1] * P2 ** 2)
         vals = vals + t * hv
         i = np.unravel_index(np.argmin(vals), vals.shape)
         best = minimize(F, np.array([g[i[0]], g[i[1]]]), method="Nelder-Mead",
@@ -152,6 +207,9 @@ def kkt_residual(A, x, t, p, hkind, w):
     s = (x - A @ p) / t
     viol = 0.0
     nz = np.abs(p) > 0
+    if hkind == "wl2":  # dH(p) = D p / H(p) for p != 0; for p = 0, s in the ellipsoid sum s_i^2 / w_i <= 1
+        hp = np.sqrt(np.sum(w * p * p))
+        return np.linalg.norm(s - w * p / hp) if hp > 0 else max(0.0, np.sum(s * s / w) - 1)
     if hkind == "wl1":
         viol = max(viol, np.max(np.abs(s[nz] - w[nz] * np.sign(p[nz])), initial=0))
         viol = max(viol, np.max(np.abs(s[~nz]) - w[~nz], initial=0))
@@ -169,7 +227,7 @@ def kkt_residual(A, x, t, p, hkind, w):
     return viol
 
 
-@pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1"])
+@pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1", "wl2"])
 def test_kkt_dense(oracle_lib, hkind):
     rng = np.random.default_rng(11)
     n = 24
@@ -193,6 +251,11 @@ def test_kkt_paper_matrices(oracle_lib):
             r = oracle_lib.oracle_eval(M, x, t, hk, tol=TOL)
             for j in range(20):
                 assert kkt_residual(M, x[j], t[j], r["grad"][j], hk, np.ones(n)) < 1e-8
+        # H = sqrt(<., D .>) (the tables' ||.||_D column) with J* = 1/2 <., D .> and with A
+        for M in (D, A):
+            r = oracle_lib.oracle_eval(M, x, t, "wl2", w=np.diag(D).copy(), tol=TOL)
+            for j in range(20):
+                assert kkt_residual(M, x[j], t[j], r["grad"][j], "wl2", np.diag(D)) < 1e-8
 
 
 def test_duality_gap_certificate(oracle_lib):
@@ -204,7 +267,7 @@ def test_duality_gap_certificate(oracle_lib):
     w = rng.uniform(0.5, 2, n)
     x = rng.normal(0, 2, (50, n))
     t = rng.uniform(0.05, 3, 50)
-    for hk in ("wl1", "l2", "l2_wl1"):
+    for hk in ("wl1", "l2", "l2_wl1", "wl2"):
         r = oracle_lib.oracle_eval(A, x, t, hk, w=w, tol=TOL, with_gap=True)
         assert np.all(r["gap"] >= -1e-10)
         assert np.all(r["gap"] <= 1e-10 * np.maximum(1, np.abs(r["phi"])))
@@ -221,7 +284,7 @@ def test_invariants(oracle_lib):
     w = rng.uniform(0.5, 2, n)
     x = rng.normal(0, 2, (30, n))
     t = rng.uniform(0.05, 3, 30)
-    for hk in ("wl1", "l2", "l2_wl1"):
+    for hk in ("wl1", "l2", "l2_wl1", "wl2"):
         r = oracle_lib.oracle_eval(A, x, t, hk, w=w, tol=TOL)
         # homogeneity: phi(a x, a t) = a^2 phi(x, t), p(a x, a t) = a p(x, t)
         r3 = oracle_lib.oracle_eval(A, 3 * x, 3 * t, hk, w=w, tol=TOL)
@@ -253,7 +316,7 @@ def test_pde_finite_differences(oracle_lib):
     x = rng.normal(0, 2, (10, n))
     t = rng.uniform(0.2, 2, 10)
     h = 1e-5
-    for hk in ("wl1", "l2", "l2_wl1"):
+    for hk in ("wl1", "l2", "l2_wl1", "wl2"):
         r = oracle_lib.oracle_eval(A, x, t, hk, w=w, tol=TOL)
         rp = oracle_lib.oracle_eval(A, x, t + h, hk, w=w, tol=TOL)
         rm = oracle_lib.oracle_eval(A, x, t - h, hk, w=w, tol=TOL)
