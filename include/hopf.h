@@ -64,7 +64,15 @@ typedef enum {
 typedef enum {
   HOPF_H_WL1 = 0,     /* H(p) = sum_i w_i |p_i|            (support function of a box)  */
   HOPF_H_L2 = 1,      /* H(p) = ||p||_2                    (support function of a ball) */
-  HOPF_H_L2_WL1 = 2   /* H(p) = ||p||_2 + sum_i w_i |p_i|  (their Minkowski sum)        */
+  HOPF_H_L2_WL1 = 2,  /* H(p) = ||p||_2 + sum_i w_i |p_i|  (their Minkowski sum)        */
+  HOPF_H_WL2 = 3      /* H(p) = sqrt(sum_i w_i p_i^2), w_i > 0: the norm sqrt(<p, D p>),
+                         D = diag(w), of section 4.4 (support function of the ellipsoid
+                         sum_i y_i^2 / w_i <= 1).  Its prox is z minus the projection onto
+                         that ellipsoid (eq. (prox-projection)), one Newton solve for the
+                         Lagrange multiplier per iteration.  Supported where a point's
+                         state stays in one wave or one thread: diagonal A with n <= 32
+                         (any precision), or HOPF_F32 with n <= 64; other problems are
+                         rejected with HOPF_EINVAL at create time. */
 } hopf_hkind;
 
 typedef enum {
@@ -83,7 +91,8 @@ typedef struct {
   const double* centres;     /* host, K*n, or NULL (all centres 0) */
   int32_t level_set;         /* 1: J_k(y) = 1/2((y-c_k)^T A^{-1} (y-c_k) - 1), ellipsoid k */
   hopf_hkind hkind;
-  const double* w;           /* host, n weights >= 0, or NULL (all 1); ignored for HOPF_H_L2 */
+  const double* w;           /* host, n weights >= 0 (> 0 for HOPF_H_WL2), or NULL (all 1);
+                                ignored for HOPF_H_L2 */
   double lambda;             /* split-Bregman penalty > 0 (the paper uses 1) */
   double tol;                /* stopping tolerance on squared norms (see hopf_eval) */
   int32_t max_iter;          /* iteration cap >= 1 */

@@ -11,7 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhopf.so")
 
 HOPF_OK, HOPF_EINVAL, HOPF_ENOTSPD, HOPF_ENOMEM, HOPF_EDEVICE = 0, -1, -2, -3, -4
-HKIND = {"wl1": 0, "l2": 1, "l2_wl1": 2}
+HKIND = {"wl1": 0, "l2": 1, "l2_wl1": 2, "wl2": 3}
 PRECISION = {"f64": 0, "f32": 1, "bf16_refined": 2}
 
 # every symbol include/hopf.h declares

@@ -145,13 +145,15 @@ static hopf_status validate(const hopf_problem_desc* d) {
   if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) return fail(HOPF_EINVAL, "lambda must be finite and > 0");
   if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return fail(HOPF_EINVAL, "tol must be finite and >= 0");
   if (d->max_iter < 1) return fail(HOPF_EINVAL, "max_iter must be >= 1");
-  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_L2_WL1) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
+  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_WL2) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
   if (d->precision < HOPF_F64 || d->precision > HOPF_BF16_REFINED)
     return fail(HOPF_EINVAL, "unknown precision %d", (int)d->precision);
   const int n = d->n;
   if (d->w)
     for (int i = 0; i < n; ++i)
       if (!(d->w[i] >= 0.0) || !std::isfinite(d->w[i])) return fail(HOPF_EINVAL, "w[%d] must be finite and >= 0", i);
+      else if (d->hkind == HOPF_H_WL2 && !(d->w[i] > 0.0))
+        return fail(HOPF_EINVAL, "w[%d] must be > 0 for HOPF_H_WL2 (D = diag(w) positive definite)", i);
   if (d->centres)
     for (int64_t i = 0; i < (int64_t)d->K * n; ++i)
       if (!std::isfinite(d->centres[i])) return fail(HOPF_EINVAL, "centres[%lld] is not finite", (long long)i);
@@ -174,6 +176,10 @@ static hopf_status validate(const hopf_problem_desc* d) {
   }
   if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
     return fail(HOPF_EINVAL, "HOPF_F64 supports diagonal A with n <= %d; use HOPF_F32 or HOPF_BF16_REFINED", kDiagMaxN);
+  // the ellipsoid projection needs whole-column reductions inside its Newton loop: supported by
+  // the per-thread diagonal kernel and the wave-local small dense kernel
+  if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= 64)))
+    return fail(HOPF_EINVAL, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= 64", kDiagMaxN);
   return HOPF_OK;
 }
 
@@ -413,14 +419,16 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   // one-wave-per-tile kernel of small FP32 problems)
   constexpr int kSmallClass = 1 << 20;
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
-  auto class_of = [&](int n_pad) -> int {
-    if (use_small && dense_small_fits(mode, n_pad, distance)) return kSmallClass;
-    const DenseVariant v = dense_variant(mode, n_pad);
+  auto class_of = [&](const hopf_problem* p) -> int {
+    // sqrt(<p, D p>) runs only in the small kernel (distance problems use l2 whatever the kind)
+    const bool need_small = p->hkind == HOPF_H_WL2 && !distance;
+    if ((use_small || need_small) && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
+    const DenseVariant v = dense_variant(mode, p->n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;
   };
   std::vector<int> classes;
   for (auto& c : calls) {
-    const int key = class_of(c.p->n_pad);
+    const int key = class_of(c.p);
     if (c.view.npts > 0 && std::find(classes.begin(), classes.end(), key) == classes.end()) classes.push_back(key);
   }
   std::sort(classes.begin(), classes.end());
@@ -434,7 +442,7 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     std::vector<std::pair<double, int>> order;  // (cost, view index)
     int max_npad = 32;
     for (auto& c : calls) {
-      if (class_of(c.p->n_pad) != key || c.view.npts == 0) continue;
+      if (class_of(c.p) != key || c.view.npts == 0) continue;
       order.push_back({(double)c.p->n_pad * c.p->n_pad * c.p->K * (double)c.view.npts, (int)views.size()});
       views.push_back(c.view);
       max_npad = std::max(max_npad, c.p->n_pad);

@@ -52,7 +52,7 @@ __host__ __device__ inline size_t mf_index(int i, int j, int n_pad) {
 }
 
 // Hamiltonian kinds (same numbering as the public header).
-enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2 };
+enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2, HK_WL2 = 3 };  // HK_WL2: sqrt(<p, diag(w) p>)
 __host__ __device__ inline bool hk_has_l1(int hk) { return hk == HK_WL1 || hk == HK_L2_WL1; }
 __host__ __device__ inline bool hk_has_l2(int hk) { return hk == HK_L2 || hk == HK_L2_WL1; }
 

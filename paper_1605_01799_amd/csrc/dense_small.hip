@@ -47,6 +47,14 @@ __device__ __forceinline__ float col_sumf(float v) {
 // clamp(z, lo, hi) for lo <= hi, one instruction
 __device__ __forceinline__ float med3f(float z, float lo, float hi) { return __builtin_amdgcn_fmed3f(z, lo, hi); }
 
+// prox of theta sqrt(<., D .>) at coordinate z with s = theta^2 w (see the pass below); the first
+// pass of a solve has d = z
+__device__ __forceinline__ float wl2_prox(float z, float s, float mu, bool first, bool inside) {
+  return first ? z : ((inside || !(s > 0.f)) ? 0.f : mu * z * __builtin_amdgcn_rcpf(s + mu));
+}
+constexpr int kWl2Newton = 40;           // cap on the multiplier's Newton steps per pass
+constexpr float kWl2Rel = 2.5e-7f;       // a step below this fraction of mu ends them
+
 }  // namespace
 
 // RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU.
@@ -260,8 +268,11 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     // one pass of every column: the Hamiltonian's kind fixed at compile time, so that the pass is
     // straight-line code the scheduler can interleave (products of one row tile with the update
     // of the previous one)
-    auto pass = [&](auto l2tag) {
-      constexpr bool HL2 = decltype(l2tag)::value;
+    auto pass = [&](auto kindtag) {
+      // KIND 0: weighted l1 (shrink1 only); 1: l2 or l2 + weighted l1 (shrink2 factor);
+      // 2: sqrt(<p, D p>) (projection onto the Wulff ellipsoid)
+      constexpr int KIND = decltype(kindtag)::value;
+      constexpr bool HL2 = KIND == 1, WL2 = KIND == 2;
       // ---------------------------------------------------------- right-hand sides
       // d = prox of the current z (eq. (3.4b)); the first pass of a solve has d = z, which is the
       // same formula with threshold 0 and factor 1.  u = z - d is the C operand of the products,
@@ -275,6 +286,60 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         thd[ct] = (first || !has_l1) ? 0.f : thr[ct];
         gd[ct] = (first || !HL2) ? 1.f : gam[ct];
       }
+      // sqrt(<p, D p>): prox_{theta H}(z) = z - pi(z), pi the projection onto the ellipsoid
+      // sum y_i^2 / s_i <= 1 with s_i = theta^2 w_i (section 4.4, eq. (prox-projection)):
+      // 0 for z inside, else d_i = mu z_i / (s_i + mu) with mu > 0 solving
+      // phi(mu) = sum s_i z_i^2 / (s_i + mu)^2 = 1.  Newton runs on 1 / sqrt(phi) - 1 (concave and
+      // increasing in mu, so from mu = 0 the steps increase monotonically to the root, exactly in
+      // one step when all s_i are equal); every column of the wave iterates until its step is at
+      // FP32 rounding level.
+      float mu[CT], th2[CT];
+      bool dz0[CT];  // d = 0 (z inside the ellipsoid)
+      if (WL2) {
+        bool go[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const bool first = flags[ct] & FLAG_FIRST;
+          const bool on = st[ct] == COL_ACTIVE || st[ct] == COL_PHI;
+          th2[ct] = thr[ct] * thr[ct];
+          float qa = 0.f;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float zz = z[rt][ct][q], sv = th2[ct] * wv[rt][q];
+              qa += sv > 0.f ? zz * zz * __builtin_amdgcn_rcpf(sv) : 0.f;
+            }
+          const float qs = col_sumf(qa);
+          dz0[ct] = !first && !(qs > 1.f);
+          go[ct] = on && !first && !dz0[ct];
+          mu[ct] = 0.f;
+        }
+        for (int it = 0; it < kWl2Newton; ++it) {
+          int any = 0;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            float pa = 0.f, pb3 = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                // sv = 0 on padding rows: they contribute nothing (and rcp(0) must not reach a sum)
+                const float zz = z[rt][ct][q], sv = th2[ct] * wv[rt][q];
+                const float inv = sv > 0.f ? __builtin_amdgcn_rcpf(sv + mu[ct]) : 0.f;
+                const float e = sv * zz * zz * inv * inv;
+                pa += e;
+                pb3 += e * inv;
+              }
+            const float ph = col_sumf(pa), ps = col_sumf(pb3);
+            const float step = ph * (__builtin_sqrtf(ph) - 1.f) / ps;
+            go[ct] = go[ct] && step > kWl2Rel * mu[ct];
+            if (go[ct]) mu[ct] += step;
+            any |= go[ct] ? 1 : 0;
+          }
+          if (!__any(any)) break;
+        }
+      }
       f32x4 r[RTM][CT], u[RTM][CT];
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -283,9 +348,13 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float zz = z[rt][ct][q];
-            const float th = theta_f(thd[ct], wv[rt][q]);
-            const float sh = zz - med3f(zz, -th, th);
-            const float d = HL2 ? gd[ct] * sh : sh;
+            float d;
+            if (WL2) {
+              d = wl2_prox(zz, th2[ct] * wv[rt][q], mu[ct], flags[ct] & FLAG_FIRST, dz0[ct]);
+            } else {
+              const float th = theta_f(thd[ct], wv[rt][q]);
+              d = (HL2 ? gd[ct] : 1.f) * (zz - med3f(zz, -th, th));
+            }
             u[rt][ct][q] = zz - d;
             r[rt][ct][q] = xp[rt][ct][q] + flam * (2.f * d - zz);
           }
@@ -374,14 +443,19 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             for (int q = 0; q < 4; ++q) {
               const int row = 16 * rt + 4 * lg + q;
               const float zz = z[rt][ct][q];
-              const float th = theta_f(thd[ct], wv[rt][q]);
-              const float sh = zz - med3f(zz, -th, th);
-              const float d = (row < n) ? (HL2 ? gd[ct] * sh : sh) : 0.f;
+              float d;
+              if (WL2) {
+                d = wl2_prox(zz, th2[ct] * wv[rt][q], mu[ct], flags[ct] & FLAG_FIRST, dz0[ct]);
+              } else {
+                const float th = theta_f(thd[ct], wv[rt][q]);
+                d = (HL2 ? gd[ct] : 1.f) * (zz - med3f(zz, -th, th));
+              }
+              if (row >= n) d = 0.f;
               const float vv = u[rt][ct][q];
               const float rr = xp[rt][ct][q] + flam * (2.f * d - zz);
               v2 += xp[rt][ct][q] * d;
               v3 += (2.f * d - vv) * (rr - flam * vv);
-              v4 += wv[rt][q] * fabsf(d);
+              v4 += WL2 ? wv[rt][q] * d * d : wv[rt][q] * fabsf(d);
               v5 += d * d;
               z[rt][ct][q] = isphi ? d : zz;  // p replaces z
             }
@@ -389,7 +463,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
           const double sm2 = col_sum(v2), sm3 = col_sum(v3), sm4 = col_sum(v4), sm5 = col_sum(v5);
           if (isphi) {
             const double pn = sqrt(sm5);
-            const double H = (has_l1 ? sm4 : 0.0) + (HL2 ? pn : 0.0);
+            const double H = WL2 ? sqrt(sm4) : (has_l1 ? sm4 : 0.0) + (HL2 ? pn : 0.0);
             const double tv = (double)pb.t[jj[ct]];
             phi[ct] = sm2 - 0.5 * sm3 - tv * H - (pb.level_set ? 0.5 : 0.0);
             hp[ct] = H;
@@ -398,8 +472,9 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         }
       }
     };
-    if (has_l2) pass(std::true_type{});
-    else pass(std::false_type{});
+    if (hkind == HK_WL2) pass(std::integral_constant<int, 2>{});
+    else if (has_l2) pass(std::integral_constant<int, 1>{});
+    else pass(std::integral_constant<int, 0>{});
   }
 }
 

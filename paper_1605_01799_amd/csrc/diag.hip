@@ -5,11 +5,48 @@
 // its stopping test (section 4.5: the three squared norms
 // |v^k - v^{k-1}|^2, |d^k - d^{k-1}|^2, |d^k - v^k|^2 all <= tol), then takes
 // the min over the K translated copies (section 2).  The path is bound by HBM
-// traffic: it reads x and t once and writes phi, grad, dphidt once.
+// traffic: it reads x and t once and writes phi, grad, dphidt once (for sqrt(<p, D p>) the prox
+// runs a Newton loop per iteration and the path is bound by FP64 arithmetic instead).
 #include "common.hpp"
 #include "diag.hpp"
 
 namespace hopf {
+
+// In place: z <- prox of theta sqrt(<., D .>), D = diag(w) (section 4.4): z minus its projection
+// onto the Wulff ellipsoid sum y_i^2 / s_i <= 1, s_i = theta^2 w_i (eq. (prox-projection)).  Zero
+// inside; otherwise z_i mu / (s_i + mu) with mu > 0 the root of phi(mu) = sum s_i z_i^2 /
+// (s_i + mu)^2 = 1, by Newton on 1 / sqrt(phi) - 1 (concave and increasing: monotone from mu = 0,
+// exact in one step when all s_i are equal) until the step is at FP64 rounding level.
+template <int NMAX>
+__device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, double* z) {
+  double q = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n) q += z[i] * z[i] / (theta * theta * (w ? w[i] : 1.0));
+  if (!(q > 1.0)) {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) z[i] = 0.0;
+    return;
+  }
+  double mu = 0.0;
+  for (int it = 0; it < 100; ++it) {
+    double ph = 0.0, ps = 0.0;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      if (i >= n) continue;
+      const double s = theta * theta * (w ? w[i] : 1.0), inv = 1.0 / (s + mu);
+      const double e = s * z[i] * z[i] * inv * inv;
+      ph += e;
+      ps += e * inv;
+    }
+    const double step = ph * (sqrt(ph) - 1.0) / ps;
+    if (!(step > 1e-15 * mu)) break;
+    mu += step;
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n) z[i] = mu * z[i] / (theta * theta * (w ? w[i] : 1.0) + mu);
+}
 
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
@@ -35,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
     if (pb.kstar) pb.kstar[j] = -1;
     return;
   }
-  const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind);
+  const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
   const double th = t / lam;
   double best = 0.0, bh = 0.0;
   int kbest = -1, itbest = 0;
@@ -73,6 +110,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) dn[i] *= f;
       }
+      if (wl2) wl2_prox<NMAX>(n, pb.w, th, dn);                  // (3.4b), z - projection
       double r1 = 0.0, r2 = 0.0, r3 = 0.0;
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) {
@@ -92,10 +130,11 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
       if (i >= n) continue;
       xd += xp[i] * d[i];
       q += pb.adiag[i] * d[i] * d[i];
-      h1 += (pb.w ? pb.w[i] : 1.0) * fabs(d[i]);
+      const double wi = pb.w ? pb.w[i] : 1.0;
+      h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
       h2 += d[i] * d[i];
     }
-    const double H = (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
+    const double H = wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
     const double val = xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
     if (kbest < 0 || val < best) {
       best = val; bh = H; kbest = k; itbest = conv ? it : -2;

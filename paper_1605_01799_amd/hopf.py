@@ -50,7 +50,7 @@ def _device_array(a: torch.Tensor, dtype, name, shape):
 
 class Problem:
     """One problem: J(y) = 1/2 y^T A^{-1} y (or the min over K translated copies / ellipsoid
-    level sets c_k + {u^T A^{-1} u <= 1}), H in {"wl1", "l2", "l2_wl1"} with weights w."""
+    level sets c_k + {u^T A^{-1} u <= 1}), H in {"wl1", "l2", "l2_wl1", "wl2"} with weights w ("wl2": sqrt(<p, diag(w) p>))."""
 
     def __init__(self, A=None, *, n: Optional[int] = None, diagonal: bool = False, centres=None,
                  level_set: bool = False, hkind: str = "wl1", w=None, lam: float = 1.0,

@@ -52,7 +52,7 @@ class Problem:
     ellipsoid level-set functions), H = hkind with weights w, and its points."""
     n: int
     A: np.ndarray                 # n x n float64 SPD
-    hkind: str                    # "wl1" | "l2" | "l2_wl1"
+    hkind: str                    # "wl1" | "l2" | "l2_wl1" | "wl2"
     w: Optional[np.ndarray]       # n float64 (None: all ones)
     x: np.ndarray                 # npts x n
     t: np.ndarray                 # npts
@@ -130,6 +130,24 @@ def _dense_problem(index: int, n: int, npts_full: int, npts: int, hkind: str) ->
 
 def workload2(npts: int = 1 << 20) -> Problem:
     return _dense_problem(2, 64, 1 << 20, npts, "wl1")
+
+
+def workload2_wl2(npts: int = 1 << 20) -> Problem:
+    """The n = 64 dense workload with H = sqrt(<p, diag(w) p>) instead of the weighted l1."""
+    return _dense_problem(2, 64, 1 << 20, npts, "wl2")
+
+
+def workload_paper_d(n: int = 16, npts: int = 1 << 20, j_is_d: bool = True) -> Problem:
+    """The setting of the paper's timing tables (section 4.5) for the ||.||_D column:
+    D_ii = 1 + (i-1)/(n-1), H = sqrt(<p, D p>), J = 1/2 <y, D^{-1} y> (A = D, diagonal) or
+    J = 1/2 |y|^2 (A = I); (x, t) uniform in [-10, 10]^n x (0, 10]."""
+    rng = rng_for(7, n)
+    D = 1.0 + np.arange(n) / (n - 1)
+    x = rng.uniform(-10.0, 10.0, (npts, n))
+    t = 10.0 - rng.uniform(0.0, 10.0, npts)   # in (0, 10]
+    A = D.copy() if j_is_d else np.ones(n)
+    return Problem(n=n, A=np.diag(A), hkind="wl2", w=D.copy(), x=x, t=t, A_is_diagonal=True,
+                   spectrum=A.copy())
 
 
 def workload3(npts: int = 1 << 16) -> Problem:
