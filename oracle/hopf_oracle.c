@@ -97,7 +97,10 @@ static double shrink1(double z, double a) {
 
 /* H(p) for the supported family (support functions of a box, a ball, their Minkowski sum, and
  * of the ellipsoid sum y_i^2 / w_i <= 1: the norm sqrt(<p, D p>) with D = diag(w), section 4.4). */
-static double ham(int n, int hkind, const double* w, const double* p) {
+static double ham(const oh_problem* pb, int hkind, const double* p) {
+  const int n = pb->n;
+  const double* w = pb->w;
+  if (hkind == OH_AL2) return sqrt(quad(n, pb->HA, p)); /* sqrt(<p, HA p>) */
   if (hkind == OH_WL2) {
     ksum k = {0, 0};
     for (int i = 0; i < n; ++i) ks_add(&k, wgt(w, i) * p[i] * p[i]);
@@ -151,6 +154,26 @@ static void prox_wl2(int n, const double* w, double theta, const double* z, doub
   for (int i = 0; i < n; ++i) {
     const double s = theta * theta * wgt(w, i);
     d[i] = mu * z[i] / (s + mu);
+  }
+}
+
+/* prox of theta * sqrt(<., HA .>) for a full SPD HA = Q diag(sig) Q^T (section 4.4, the case
+ * ||.||_A): the Wulff shape is the ellipsoid y^T HA^{-1} y <= 1 and, as the paper states, the
+ * projection onto it is Q pi_D(Q^T w) with pi_D the projection onto the axis-aligned ellipsoid of
+ * the eigenvalues; so d = z - Q pi_D(Q^T z) = Q (u - pi_D(u)), u = Q^T z, the diagonal prox in
+ * the eigenbasis rotated back. */
+static void prox_al2(int n, const double* Q, const double* sig, double theta, const double* z,
+                     double* d, double* u, double* du) {
+  for (int a = 0; a < n; ++a) {
+    ksum k = {0, 0};
+    for (int i = 0; i < n; ++i) ks_add(&k, Q[(size_t)i * n + a] * z[i]);
+    u[a] = ks_val(&k);
+  }
+  prox_wl2(n, sig, theta, u, du);
+  for (int i = 0; i < n; ++i) {
+    ksum k = {0, 0};
+    for (int a = 0; a < n; ++a) ks_add(&k, Q[(size_t)i * n + a] * du[a]);
+    d[i] = ks_val(&k);
   }
 }
 
@@ -215,7 +238,9 @@ static double hopf_solve(const oh_problem* pb, int hkind, const double* LS, cons
     chol_solve(n, LS, s->rhs, s->tmp, s->vn);
     /* (3.4b): d = prox_{(t/lambda) H}(v + b) */
     for (int i = 0; i < n; ++i) s->z[i] = s->vn[i] + s->b[i];
-    prox_h(n, hkind, pb->w, t / lam, s->z, s->dn);
+    const double theta = t / lam;
+    if (hkind == OH_AL2) prox_al2(n, pb->HQ, pb->Hsig, theta, s->z, s->dn, s->tmp, s->y);
+    else prox_h(n, hkind, pb->w, theta, s->z, s->dn);
     /* (3.4c): b = b + v - d */
     for (int i = 0; i < n; ++i) s->b[i] = s->b[i] + s->vn[i] - s->dn[i];
     double r1 = sqdist(n, s->vn, s->v);
@@ -230,7 +255,7 @@ static double hopf_solve(const oh_problem* pb, int hkind, const double* LS, cons
   memcpy(out_p, p, sizeof(double) * (size_t)n);
   ksum F = {0, 0};
   ks_add(&F, 0.5 * quad(n, pb->A, p));
-  ks_add(&F, t * ham(n, hkind, pb->w, p));
+  ks_add(&F, t * ham(pb, hkind, p));
   ks_add(&F, -dot(n, xp, p));
   double Fv = ks_val(&F);
   if (gap) {
@@ -285,7 +310,7 @@ static void* eval_worker(void* arg) {
     J->phi[j] = best;
     J->kstar[j] = kb;
     /* dphi/dt = -H(grad phi), from (1.1a) */
-    J->dphidt[j] = -ham(n, pb->hkind, pb->w, J->grad + (size_t)j * n);
+    J->dphidt[j] = -ham(pb, pb->hkind, J->grad + (size_t)j * n);
   }
   free(xp);
   scratch_free(&s);
@@ -294,7 +319,12 @@ static void* eval_worker(void* arg) {
 
 static int check_problem(const oh_problem* pb) {
   if (!pb || pb->n < 1 || !pb->A || pb->K < 1 || !(pb->lambda > 0) || pb->max_iter < 1) return -1;
-  if (pb->hkind < OH_WL1 || pb->hkind > OH_WL2) return -1;
+  if (pb->hkind < OH_WL1 || pb->hkind > OH_AL2) return -1;
+  if (pb->hkind == OH_AL2) {
+    if (!pb->HA || !pb->HQ || !pb->Hsig) return -1;
+    for (int i = 0; i < pb->n; ++i)
+      if (!(pb->Hsig[i] > 0)) return -1;
+  }
   if (pb->w)
     for (int i = 0; i < pb->n; ++i)
       if (!(pb->w[i] >= 0) || (pb->hkind == OH_WL2 && !(pb->w[i] > 0))) return -1;

@@ -19,7 +19,7 @@
 extern "C" {
 #endif
 
-enum { OH_WL1 = 0, OH_L2 = 1, OH_L2_WL1 = 2, OH_WL2 = 3 };
+enum { OH_WL1 = 0, OH_L2 = 1, OH_L2_WL1 = 2, OH_WL2 = 3, OH_AL2 = 4 };
 
 typedef struct {
   int32_t n;
@@ -27,11 +27,16 @@ typedef struct {
   int32_t K;              /* number of ellipsoids / translated copies of J (>= 1) */
   const double* centres;  /* K*n, or NULL (all centres 0) */
   int32_t level_set;      /* 1: J_k(y) = 1/2((y-c_k)^T A^{-1} (y-c_k) - 1) */
-  int32_t hkind;          /* OH_WL1, OH_L2, OH_L2_WL1, OH_WL2 */
+  int32_t hkind;          /* OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2 */
   const double* w;        /* n weights >= 0 (> 0 for OH_WL2), or NULL (all 1) */
   double lambda;          /* split-Bregman penalty (paper: 1) */
   double tol;             /* stop when max of the three squared norms <= tol */
   int32_t max_iter;
+  /* OH_AL2 only: H(p) = sqrt(p^T HA p) with HA (n*n row-major SPD) = HQ diag(Hsig) HQ^T
+   * (HQ row-major, columns = eigenvectors); NULL otherwise */
+  const double* HA;
+  const double* HQ;
+  const double* Hsig;
 } oh_problem;
 
 /* Returns 0 on success, -1 on bad arguments, -2 if A + lambda I (or A) is not SPD.

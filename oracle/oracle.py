@@ -29,8 +29,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hopf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_hopf.so")
 
-OH_WL1, OH_L2, OH_L2_WL1, OH_WL2 = 0, 1, 2, 3
-_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1, "wl2": OH_WL2}
+OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2 = 0, 1, 2, 3, 4
+_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1, "wl2": OH_WL2, "al2": OH_AL2}
 
 
 def build(force: bool = True) -> str:
@@ -52,7 +52,8 @@ class _Problem(ctypes.Structure):
         ("n", ctypes.c_int32), ("A", ctypes.c_void_p), ("K", ctypes.c_int32),
         ("centres", ctypes.c_void_p), ("level_set", ctypes.c_int32), ("hkind", ctypes.c_int32),
         ("w", ctypes.c_void_p), ("lam", ctypes.c_double), ("tol", ctypes.c_double),
-        ("max_iter", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32), ("HA", ctypes.c_void_p), ("HQ", ctypes.c_void_p),
+        ("Hsig", ctypes.c_void_p),
     ]
 
 
@@ -89,7 +90,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter):
+def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA=None):
     A = _f64(A)
     n = A.shape[0]
     if A.shape != (n, n):
@@ -98,9 +99,15 @@ def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter):
     centres = None if centres is None else _f64(centres).reshape(-1, n)
     K = 1 if centres is None else centres.shape[0]
     hk = _HKIND[hkind] if isinstance(hkind, str) else int(hkind)
+    HQ = Hsig = None
+    if HA is not None:
+        # H(p) = sqrt(p^T HA p): its eigendecomposition is a library primitive (numpy.linalg.eigh)
+        HA = _f64(HA)
+        Hsig, HQ = np.linalg.eigh(0.5 * (HA + HA.T))
+        HQ, Hsig = np.ascontiguousarray(HQ), np.ascontiguousarray(Hsig)
     pb = _Problem(n, _ptr(A), K, _ptr(centres), int(bool(level_set)), hk, _ptr(w),
-                  float(lam), float(tol), int(max_iter))
-    return pb, (A, w, centres), n, K
+                  float(lam), float(tol), int(max_iter), _ptr(HA), _ptr(HQ), _ptr(Hsig))
+    return pb, (A, w, centres, HA, HQ, Hsig), n, K
 
 
 def _threads(nthreads):
@@ -110,10 +117,11 @@ def _threads(nthreads):
 
 
 def oracle_eval(A, x, t, hkind="wl1", w=None, centres=None, level_set=False, lam=1.0,
-                tol=1e-28, max_iter=100000, nthreads=None, with_gap=False):
-    """Hopf evaluation of every point of x (npts x n) at times t (npts)."""
+                tol=1e-28, max_iter=100000, nthreads=None, with_gap=False, HA=None):
+    """Hopf evaluation of every point of x (npts x n) at times t (npts).  hkind "al2" takes the
+    SPD matrix HA of H(p) = sqrt(p^T HA p)."""
     lib = _load()
-    pb, keep, n, K = _problem(A, hkind, w, centres, level_set, lam, tol, max_iter)
+    pb, keep, n, K = _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA)
     x = _f64(x).reshape(-1, n)
     t = _f64(t).reshape(-1)
     m = x.shape[0]

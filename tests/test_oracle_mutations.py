@@ -16,12 +16,12 @@ MUTANTS = {
     "bregman_update_sign": ("s->b[i] + s->vn[i] - s->dn[i]", "s->b[i] - s->vn[i] + s->dn[i]"),
     "rhs_drops_lambda": ("xp[i] + lam * (s->d[i] - s->b[i])", "xp[i] + (s->d[i] - s->b[i])"),
     "rhs_sign_b": ("lam * (s->d[i] - s->b[i])", "lam * (s->d[i] + s->b[i])"),
-    "threshold_times_lambda": ("t / lam, s->z, s->dn", "t * lam, s->z, s->dn"),
+    "threshold_times_lambda": ("const double theta = t / lam;", "const double theta = t * lam;"),
     "shrink2_sign": ("(nr - theta > 0.0 ? nr - theta : 0.0) / nr", "(nr + theta > 0.0 ? nr + theta : 0.0) / nr"),
     "shrink1_ignores_weights": ("d[i] = shrink1(z[i], theta * wgt(w, i));", "d[i] = shrink1(z[i], theta);"),
     "backsolve_transposed": ("ks_add(&k, -L[(size_t)m * n + i] * out[m]);", "ks_add(&k, -L[(size_t)i * n + m] * out[m]);"),
     "cholesky_sign": ("ks_add(&k, -L[(size_t)j * n + m] * L[(size_t)j * n + m]);", "ks_add(&k, L[(size_t)j * n + m] * L[(size_t)j * n + m]);"),
-    "value_drops_H": ("ks_add(&F, t * ham(n, hkind, pb->w, p));", "ks_add(&F, 0.0);"),
+    "value_drops_H": ("ks_add(&F, t * ham(pb, hkind, p));", "ks_add(&F, 0.0);"),
     "value_half_missing": ("ks_add(&F, 0.5 * quad(n, pb->A, p));", "ks_add(&F, quad(n, pb->A, p));"),
     "union_max_not_min": ("if (val < best || kb < 0)", "if (val > best || kb < 0)"),
     "level_set_offset_sign": ("if (pb->level_set) val -= 0.5;", "if (pb->level_set) val += 0.5;"),
@@ -31,6 +31,8 @@ MUTANTS = {
     "wl2_multiplier_equation_rhs": ("ks_add(&g, 1.0);", "ks_add(&g, 0.5);"),
     "wl2_prox_wrong_factor": ("d[i] = mu * z[i] / (s + mu);", "d[i] = s * z[i] / (s + mu);"),
     "wl2_hamiltonian_unweighted": ("ks_add(&k, wgt(w, i) * p[i] * p[i]);", "ks_add(&k, p[i] * p[i]);"),
+    "al2_rotation_transposed": ("ks_add(&k, Q[(size_t)i * n + a] * z[i]);", "ks_add(&k, Q[(size_t)a * n + i] * z[i]);"),
+    "al2_back_rotation_dropped": ("ks_add(&k, Q[(size_t)i * n + a] * du[a]);", "ks_add(&k, (i == a) * du[a]);"),
     "secular_projection_index": ("us[a] = sigma[a] * u[a] / (sigma[a] + mu);", "us[a] = sigma[a] * u[a] / (sigma[a] + mu * mu);"),
 }
 
@@ -89,6 +91,15 @@ def battery(lib):
             ok = np.allclose(r["phi"], r2["phi"], atol=1e-9) and np.allclose(r["grad"], r2["grad"], atol=1e-9)
             return ok and np.allclose(r["dphidt"], -np.sqrt(2.0) * np.linalg.norm(r["grad"], axis=1), atol=1e-9)
         check("wl2_scaled_l2", wl2_scaled_l2)
+
+        def al2_kkt():
+            from tests.test_oracle_pins import al2_kkt_residual
+            HA = (Q * rng.uniform(0.5, 3, n)) @ Q.T
+            HA = 0.5 * (HA + HA.T)
+            A2 = np.diag(rng.uniform(0.5, 2, n))
+            r = O.oracle_eval(A2, x, t, "al2", HA=HA, tol=1e-26, max_iter=20000)
+            return all(al2_kkt_residual(A2, HA, x[j], t[j], r["grad"][j]) < 1e-7 for j in range(8))
+        check("al2_kkt", al2_kkt)
 
         def union_translation():
             C = rng.normal(0, 2, (2, n))

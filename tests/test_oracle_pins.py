@@ -154,6 +154,81 @@ def test_wl2_identity_is_ellipsoid_projection(oracle_lib):
     assert np.all(r["grad"][:6] == 0) and np.all(r["phi"][:6] == 0)
 
 
+def al2_kkt_residual(A, HA, x, t, p):
+    """Optimality for H(p) = sqrt(p^T HA p): (x - A p)/t = HA p / H(p) for p != 0, and
+    (x/t)^T HA^{-1} (x/t) <= 1 (x/t in the Wulff ellipsoid) for p = 0."""
+    s = (x - A @ p) / t
+    h = np.sqrt(p @ HA @ p)
+    if h > 0:
+        return np.linalg.norm(s - HA @ p / h)
+    return max(0.0, s @ np.linalg.solve(HA, s) - 1)
+
+
+def test_al2_pins(oracle_lib):
+    """H = sqrt(<p, HA p>) with a full SPD HA (section 4.4, ||.||_A): KKT at convergence (also
+    for points inside t C), the duality-gap bracket, HA = c I against l2 at time sqrt(c) t, and
+    covariance under a rotation R of the whole problem (A -> R A R^T, HA -> R HA R^T, x -> R x:
+    phi unchanged, p -> R p), which exercises the rotation into HA's eigenbasis."""
+    rng = np.random.default_rng(41)
+    n = 10
+    A = rand_spd(n, rng, 0.2, 6)
+    HA = rand_spd(n, rng, 0.5, 3)
+    x = rng.normal(0, 2, (40, n))
+    t = rng.uniform(0.05, 3, 40)
+    x[:4] *= 0.01
+    t[:4] = 2.0
+    r = oracle_lib.oracle_eval(A, x, t, "al2", HA=HA, tol=TOL, with_gap=True)
+    for j in range(40):
+        assert al2_kkt_residual(A, HA, x[j], t[j], r["grad"][j]) < 1e-8
+    assert np.all(r["grad"][:4] == 0)
+    assert np.all(r["gap"] >= -1e-10) and np.all(r["gap"] <= 1e-10 * np.maximum(1, np.abs(r["phi"])))
+    np.testing.assert_allclose(r["dphidt"], -np.sqrt(np.einsum("ij,jk,ik->i", r["grad"], HA, r["grad"])),
+                               rtol=1e-12, atol=1e-12)
+    for c in (0.5, 3.0):
+        rc = oracle_lib.oracle_eval(A, x, t, "al2", HA=c * np.eye(n), tol=TOL)
+        r2 = oracle_lib.oracle_eval(A, x, np.sqrt(c) * t, "l2", tol=TOL)
+        np.testing.assert_allclose(rc["phi"], r2["phi"], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(rc["grad"], r2["grad"], rtol=1e-10, atol=1e-10)
+    R = W.haar_orthogonal(n, rng)
+    rr = oracle_lib.oracle_eval(R @ A @ R.T, x @ R.T, t, "al2", HA=R @ HA @ R.T, tol=TOL)
+    np.testing.assert_allclose(rr["phi"], r["phi"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(rr["grad"], r["grad"] @ R.T, rtol=1e-9, atol=1e-9)
+
+
+def test_al2_paper_matrices(oracle_lib):
+    """The tables' ||.||_A column: HA = I + 1 1^T with J = 1/2 |.|^2 and J = 1/2 <., D^{-1} .>."""
+    for n in (4, 8, 16):
+        HA = np.eye(n) + np.ones((n, n))
+        D = np.diag(1 + np.arange(n) / (n - 1))
+        x = RNG.uniform(-10, 10, (15, n))
+        t = RNG.uniform(0.01, 10, 15)
+        for M in (np.eye(n), D):
+            r = oracle_lib.oracle_eval(M, x, t, "al2", HA=HA, tol=TOL)
+            for j in range(15):
+                assert al2_kkt_residual(M, HA, x[j], t[j], r["grad"][j]) < 1e-8
+
+
+def test_al2_brute_force_n2(oracle_lib):
+    rng = np.random.default_rng(42)
+    A = rand_spd(2, rng)
+    HA = rand_spd(2, rng, 0.5, 2)
+    for _ in range(5):
+        x = rng.normal(0, 3, 2)
+        t = rng.uniform(0.05, 2)
+        g = np.linspace(-8, 8, 401)
+        P1, P2 = np.meshgrid(g, g, indexing="ij")
+        quad = lambda M: M[0, 0] * P1 ** 2 + 2 * M[0, 1] * P1 * P2 + M[1, 1] * P2 ** 2
+        vals = 0.5 * quad(A) - x[0] * P1 - x[1] * P2 + t * np.sqrt(quad(HA))
+        i = np.unravel_index(np.argmin(vals), vals.shape)
+        F = lambda p: 0.5 * p @ A @ p + t * np.sqrt(p @ HA @ p) - x @ p
+        best = minimize(F, np.array([g[i[0]], g[i[1]]]), method="Nelder-Mead",
+                        options=dict(xatol=1e-12, fatol=1e-15, maxiter=20000))
+        fb = min(best.fun, vals[i])
+        r = oracle_lib.oracle_eval(A, x[None], [t], "al2", HA=HA, tol=TOL)
+        assert abs(-r["phi"][0] - fb) <= 1e-9 * max(1, abs(fb))
+        assert -r["phi"][0] <= fb + 1e-12
+
+
 # ---------------------------------------------------------------- brute force
 @pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1", "wl2"])
 def test_brute_force_n2(oracle_lib, hkind):
