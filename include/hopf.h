@@ -65,7 +65,7 @@ typedef enum {
   HOPF_H_WL1 = 0,     /* H(p) = sum_i w_i |p_i|            (support function of a box)  */
   HOPF_H_L2 = 1,      /* H(p) = ||p||_2                    (support function of a ball) */
   HOPF_H_L2_WL1 = 2,  /* H(p) = ||p||_2 + sum_i w_i |p_i|  (their Minkowski sum)        */
-  HOPF_H_WL2 = 3      /* H(p) = sqrt(sum_i w_i p_i^2), w_i > 0: the norm sqrt(<p, D p>),
+  HOPF_H_WL2 = 3,     /* H(p) = sqrt(sum_i w_i p_i^2), w_i > 0: the norm sqrt(<p, D p>),
                          D = diag(w), of section 4.4 (support function of the ellipsoid
                          sum_i y_i^2 / w_i <= 1).  Its prox is z minus the projection onto
                          that ellipsoid (eq. (prox-projection)), one Newton solve for the
@@ -73,6 +73,12 @@ typedef enum {
                          state stays in one wave or one thread: diagonal A with n <= 32
                          (any precision), or HOPF_F32 with n <= 64; other problems are
                          rejected with HOPF_EINVAL at create time. */
+  HOPF_H_AL2 = 4      /* H(p) = sqrt(<p, HA p>) for a full SPD matrix HA (the norm ||.||_A of
+                         section 4.4; HA in the descriptor).  The library diagonalises HA on the
+                         device (HA = P diag(s) P^T, FP64 Jacobi) and holds the problem in that
+                         basis, where H is HOPF_H_WL2 with weights s, A becomes P^T A P and the
+                         centres P^T c; points are rotated in before the solve and gradients /
+                         closest points rotated back after it.  HOPF_F32 with n <= 64. */
 } hopf_hkind;
 
 typedef enum {
@@ -97,6 +103,9 @@ typedef struct {
   double tol;                /* stopping tolerance on squared norms (see hopf_eval) */
   int32_t max_iter;          /* iteration cap >= 1 */
   hopf_precision precision;
+  const double* HA;          /* host, n*n row-major SPD matrix of H for HOPF_H_AL2; otherwise
+                                ignored (may be NULL).  HOPF_ENOTSPD if it is not positive
+                                definite. */
 } hopf_problem_desc;
 
 typedef struct hopf_problem* hopf_problem_t;
@@ -173,7 +182,8 @@ hopf_status hopf_backward(hopf_problem_t problem, int64_t npts, const void* gphi
                           void* stream);
 
 /* Device-side factor of the problem, for inspection and tests: copies
- * M = (A + lambda I)^{-1} (n*n, row-major, FP64) to the host array out. */
+ * M = (A + lambda I)^{-1} (n*n, row-major, FP64) to the host array out.  For a HOPF_H_AL2
+ * problem this is the factor of the problem in HA's eigenbasis, (P^T A P + lambda I)^{-1}. */
 hopf_status hopf_problem_get_inverse(hopf_problem_t problem, double* out);
 
 /* Problem dimension, padded dimension, K, precision; any pointer may be NULL. */

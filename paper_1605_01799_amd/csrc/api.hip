@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "dense.hpp"
 #include "diag.hpp"
+#include "rotate.hpp"
 #include "setup.hpp"
 
 using namespace hopf;
@@ -61,6 +62,9 @@ struct hopf_problem {
   __bf16* d_Mb = nullptr;       // n_pad^2 (BF16_REFINED precision)
   double* d_adiag = nullptr;    // n (diagonal A)
   double* d_minv = nullptr;     // n (diagonal A)
+  // HOPF_H_AL2: eigenvectors P of HA (n x n, FP64); the problem is held in HA's eigenbasis
+  // (A' = P^T A P, weights = eigenvalues, centres P^T c) and points are rotated in and out
+  double* d_HP = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -74,6 +78,7 @@ struct Workspace {
   int* counter = nullptr;
   unsigned char* meta = nullptr; size_t meta_bytes = 0;
   double* scratch = nullptr; size_t scratch_bytes = 0;
+  float* rot = nullptr; size_t rot_bytes = 0;              // rotated points of HOPF_H_AL2 problems
   unsigned char* pinned = nullptr; size_t pinned_bytes = 0;
   hipEvent_t ev = nullptr;
   bool ev_pending = false;
@@ -145,7 +150,7 @@ static hopf_status validate(const hopf_problem_desc* d) {
   if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) return fail(HOPF_EINVAL, "lambda must be finite and > 0");
   if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return fail(HOPF_EINVAL, "tol must be finite and >= 0");
   if (d->max_iter < 1) return fail(HOPF_EINVAL, "max_iter must be >= 1");
-  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_WL2) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
+  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_AL2) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
   if (d->precision < HOPF_F64 || d->precision > HOPF_BF16_REFINED)
     return fail(HOPF_EINVAL, "unknown precision %d", (int)d->precision);
   const int n = d->n;
@@ -180,13 +185,67 @@ static hopf_status validate(const hopf_problem_desc* d) {
   // the per-thread diagonal kernel and the wave-local small dense kernel
   if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= 64)))
     return fail(HOPF_EINVAL, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= 64", kDiagMaxN);
+  if (d->hkind == HOPF_H_AL2) {
+    // solved in HA's eigenbasis, where A becomes dense: the wave-local FP32 kernel
+    if (d->precision != HOPF_F32 || n > kRotMaxN)
+      return fail(HOPF_EINVAL, "HOPF_H_AL2 supports HOPF_F32 with n <= %d", kRotMaxN);
+    if (!d->HA) return fail(HOPF_EINVAL, "HOPF_H_AL2 needs the matrix HA");
+    for (int64_t i = 0; i < (int64_t)n * n; ++i)
+      if (!std::isfinite(d->HA[i])) return fail(HOPF_EINVAL, "HA[%lld] is not finite", (long long)i);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j) {
+        double a = d->HA[(size_t)i * n + j], b = d->HA[(size_t)j * n + i];
+        if (std::fabs(a - b) > 1e-12 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))))
+          return fail(HOPF_EINVAL, "HA is not symmetric at (%d, %d)", i, j);
+      }
+  }
   return HOPF_OK;
 }
 
 static void free_problem(hopf_problem* p) {
   hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
-  hipFree(p->d_adiag); hipFree(p->d_minv);
+  hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP);
   delete p;
+}
+
+// HOPF_H_AL2: HA = P diag(sig) P^T on the device (Jacobi, FP64); the problem is moved into that
+// basis in place: A (device, n x n) <- P^T A P, weights <- sig, centres <- P^T c.  Synchronises
+// to check that HA is positive definite.
+static hopf_status rotate_problem(hopf_problem* p, const hopf_problem_desc* d, double* dA, hipStream_t stream) {
+  const int n = p->n;
+  double *dHA = nullptr, *sig = nullptr, *T = nullptr, *A2 = nullptr, *C2 = nullptr;
+  int* sweeps = nullptr;
+  auto cleanup = [&]() { hipFree(dHA); hipFree(sig); hipFree(T); hipFree(A2); hipFree(C2); hipFree(sweeps); };
+  const size_t nn = (size_t)n * n;
+  if (hipMalloc(&p->d_HP, sizeof(double) * nn) || hipMalloc(&dHA, sizeof(double) * nn) ||
+      hipMalloc(&sig, sizeof(double) * n) || hipMalloc(&T, sizeof(double) * nn) ||
+      hipMalloc(&A2, sizeof(double) * nn) || hipMalloc(&sweeps, sizeof(int))) {
+    cleanup();
+    return fail(HOPF_ENOMEM, "hipMalloc HA eigenbasis");
+  }
+  hipError_t e = hipMemcpy(dHA, d->HA, sizeof(double) * nn, hipMemcpyHostToDevice);
+  if (!e) e = launch_jacobi_eig(dHA, n, p->d_HP, sig, sweeps, stream);
+  if (!e) e = launch_congruence(dA, p->d_HP, n, T, A2, stream);
+  if (!e) e = hipMemcpyAsync(dA, A2, sizeof(double) * nn, hipMemcpyDeviceToDevice, stream);
+  if (!e) e = launch_set_weights(sig, n, p->n_pad, p->d_w, p->d_wf, stream);
+  if (!e && p->d_centres) {
+    const size_t cb = sizeof(double) * (size_t)p->K * p->n_pad;
+    if (hipMalloc(&C2, cb)) { cleanup(); return fail(HOPF_ENOMEM, "hipMalloc centres"); }
+    e = hipMemsetAsync(C2, 0, cb, stream);
+    if (!e) e = launch_rotate_centres(p->d_centres, C2, p->n_pad, p->d_HP, n, p->K, stream);
+    if (!e) e = hipMemcpyAsync(p->d_centres, C2, cb, hipMemcpyDeviceToDevice, stream);
+  }
+  std::vector<double> hs(n);
+  int hsw = 0;
+  if (!e) e = hipStreamSynchronize(stream);
+  if (!e) e = hipMemcpy(hs.data(), sig, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (!e) e = hipMemcpy(&hsw, sweeps, sizeof(int), hipMemcpyDeviceToHost);
+  cleanup();
+  if (e) return fail(HOPF_EDEVICE, "HA eigenbasis: %s", hipGetErrorString(e));
+  for (int i = 0; i < n; ++i)
+    if (!(hs[i] > 0.0)) return fail(HOPF_ENOTSPD, "HA is not positive definite (eigenvalue %g)", hs[i]);
+  (void)hsw;
+  return HOPF_OK;
 }
 
 static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, hopf_problem** out,
@@ -201,7 +260,8 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   p->device = dev;
   p->n = d->n; p->K = d->K; p->level_set = d->level_set ? 1 : 0; p->hkind = d->hkind;
   p->precision = d->precision; p->lambda = d->lambda; p->tol = d->tol; p->max_iter = d->max_iter;
-  p->diagonal = (d->A == nullptr || d->A_is_diagonal) ? 1 : 0;
+  const bool al2 = d->hkind == HOPF_H_AL2;
+  p->diagonal = (!al2 && (d->A == nullptr || d->A_is_diagonal)) ? 1 : 0;
   const int n = d->n;
   const int n_pad = (n + 31) / 32 * 32;
   p->n_pad = n_pad;
@@ -250,9 +310,20 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
       hipFree(dA);
       return bail(fail(HOPF_ENOMEM, "hipMalloc setup"));
     }
-    if (hipMemcpy(dA, d->A, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice)) {
+    std::vector<double> hA;
+    const double* srcA = d->A;
+    if (al2 && (d->A == nullptr || d->A_is_diagonal)) {  // the rotated problem is dense
+      hA.assign((size_t)n * n, 0.0);
+      for (int i = 0; i < n; ++i) hA[(size_t)i * n + i] = d->A ? d->A[i] : 1.0;
+      srcA = hA.data();
+    }
+    if (hipMemcpy(dA, srcA, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice)) {
       hipFree(dA); hipFree(S);
       return bail(fail(HOPF_EDEVICE, "copy A"));
+    }
+    if (al2) {
+      hopf_status rs = rotate_problem(p, d, dA, stream);
+      if (rs) { hipFree(dA); hipFree(S); return bail(rs); }
     }
     e = launch_build_shifted(dA, n, n_pad, d->lambda, S, stream);
     hipStreamSynchronize(stream);
@@ -421,7 +492,7 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
   auto class_of = [&](const hopf_problem* p) -> int {
     // sqrt(<p, D p>) runs only in the small kernel (distance problems use l2 whatever the kind)
-    const bool need_small = p->hkind == HOPF_H_WL2 && !distance;
+    const bool need_small = (p->hkind == HOPF_H_WL2 || p->hkind == HOPF_H_AL2) && !distance;
     if ((use_small || need_small) && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;
@@ -504,7 +575,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
 static DenseProb make_view(hopf_problem* p) {
   DenseProb v;
   std::memset(&v, 0, sizeof v);
-  v.n = p->n; v.n_pad = p->n_pad; v.K = p->K; v.level_set = p->level_set; v.hkind = p->hkind;
+  v.n = p->n; v.n_pad = p->n_pad; v.K = p->K; v.level_set = p->level_set;
+  v.hkind = p->hkind == HOPF_H_AL2 ? HK_WL2 : p->hkind;  // in HA's eigenbasis
   v.max_iter = p->max_iter; v.lambda = p->lambda; v.tol = p->tol;
   v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.w = p->d_w; v.wf = p->d_wf; v.centres = p->d_centres;
   v.max_newton = 50;
@@ -512,6 +584,55 @@ static DenseProb make_view(hopf_problem* p) {
 }
 
 static int mode_of(hopf_problem* p) { return p->precision == HOPF_BF16_REFINED ? 1 : 0; }
+
+// Points of HOPF_H_AL2 problems are solved in HA's eigenbasis: their x (or y) is rotated into a
+// workspace buffer before the solve, and the solver's gradient (or closest point) is rotated back
+// into the caller's buffer after it.
+struct RotBack {
+  const float* q; float* dst; const double* P; int n; int64_t npts;
+};
+static hopf_status rotate_calls_in(std::vector<DenseCall>& calls, hipStream_t stream, std::vector<RotBack>* back) {
+  size_t need = 0;
+  for (auto& c : calls)
+    if (c.p->hkind == HOPF_H_AL2) need += 2 * (size_t)c.view.npts * c.p->n;
+  if (need == 0) return HOPF_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace* w;
+  hopf_status st = ws_get(dev, &w);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> lk(w->mu);
+    if ((st = ws_grow((void**)&w->rot, &w->rot_bytes, sizeof(float) * need))) return st;
+  }
+  float* q = w->rot;
+  for (auto& c : calls) {
+    if (c.p->hkind != HOPF_H_AL2 || c.view.npts == 0) continue;
+    const int n = c.p->n;
+    float* xr = q; q += (size_t)c.view.npts * n;
+    float* qr = q; q += (size_t)c.view.npts * n;
+    hipError_t e = launch_rotate_points_in(c.view.x, xr, c.p->d_HP, n, c.view.npts, stream);
+    if (e) return fail(HOPF_EDEVICE, "rotate points: %s", hipGetErrorString(e));
+    back->push_back(RotBack{qr, c.view.grad, c.p->d_HP, n, c.view.npts});
+    c.view.x = xr;
+    c.view.grad = qr;
+  }
+  return HOPF_OK;
+}
+static hopf_status rotate_calls_out(const std::vector<RotBack>& back, hipStream_t stream) {
+  for (const RotBack& b : back) {
+    hipError_t e = launch_rotate_points_out(b.q, b.dst, b.P, b.n, b.npts, stream);
+    if (e) return fail(HOPF_EDEVICE, "rotate points back: %s", hipGetErrorString(e));
+  }
+  return HOPF_OK;
+}
+static hopf_status run_dense_rotated(std::vector<DenseCall>& calls, int mode, int distance, hipStream_t stream) {
+  std::vector<RotBack> back;
+  hopf_status st = rotate_calls_in(calls, stream, &back);
+  if (!st) st = run_dense(calls, mode, distance, stream);
+  if (!st) st = rotate_calls_out(back, stream);
+  return st;
+}
 
 extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, const void* t, void* phi,
                                  void* grad, void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
@@ -538,7 +659,7 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
   v = make_view(p);
   v.x = (const float*)x; v.t = (const float*)t; v.npts = npts;
   v.phi = (float*)phi; v.grad = (float*)grad; v.dphidt = (float*)dphidt; v.iters = iters; v.kstar = kstar;
-  return run_dense(calls, mode_of(p), 0, s);
+  return run_dense_rotated(calls, mode_of(p), 0, s);
 }
 
 extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const void* y, double s_tol,
@@ -557,7 +678,7 @@ extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const 
   v = make_view(p);
   v.x = (const float*)y; v.npts = npts; v.grad = (float*)cp; v.kstar = kstar;
   v.dist = (float*)dist; v.inside = inside; v.newton = newton; v.s_tol = s_tol;
-  return run_dense(calls, mode_of(p), 1, (hipStream_t)stream);
+  return run_dense_rotated(calls, mode_of(p), 1, (hipStream_t)stream);
 }
 
 extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
@@ -592,7 +713,7 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
     xoff += np * p->n;
     calls.push_back(c);
   }
-  return run_dense(calls, prec == HOPF_BF16_REFINED ? 1 : 0, 0, (hipStream_t)stream);
+  return run_dense_rotated(calls, prec == HOPF_BF16_REFINED ? 1 : 0, 0, (hipStream_t)stream);
 }
 
 extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void* gphi, const void* grad_saved,
