@@ -60,12 +60,13 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1s", "c2", "c5", "c2wl2", "pd16"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1s", "c2", "c5", "c2wl2", "pd16", "pa16"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
                          "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
                          "FP32 dense at 2^20 points, c5 = n=256 union of 4 ellipsoids, forward + backward; "
                          "c2wl2 = c2 with H = sqrt(<p, diag(w) p>); pd16 = the paper's timing-table setting "
-                         "for that H at n=16 (J = 1/2 <y, D^-1 y>, FP64, tol 1e-8)")
+                         "for that H at n=16 (J = 1/2 <y, D^-1 y>, FP64, tol 1e-8); pa16 = the same for "
+                         "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis)")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
                          "scale of the FETCH_SIZE / WRITE_SIZE counters")
@@ -317,6 +318,60 @@ def bench_other(a):
                                      "(squared norms <= 1e-8) itself leaves errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "one core of an i5-5300U (Table 4)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
+                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+    elif a.workload == "pa16":
+        npts = a.npts if a.npts != 1 << 16 else 1 << 22
+        p = W.round_inputs(W.workload_paper_a(16, npts))
+        HA = p.HA
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        tol = a.tol if a.tol is not None else 1e-8
+        prob = H.Problem(np.diag(p.A).copy(), diagonal=True, hkind="al2", HA=HA, precision="f32", tol=tol,
+                         max_iter=20000)
+        out = dict(phi=torch.empty(npts, device=dev), grad=torch.empty(npts, p.n, device=dev),
+                   dphidt=torch.empty(npts, device=dev), iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        it = out["iters"].cpu().numpy()
+        n_pad = 32
+        flops = float(np.sum(np.abs(it)).astype(np.float64) * 2.0 * n_pad * n_pad)
+        achieved = flops / (kms / 1e3) / 1e12
+        rng = np.random.default_rng(9)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample * 4, npts), replace=False))
+        ref = oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64), "al2", HA=HA,
+                                 tol=1e-28, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        m = min(npts, 1 << 16)
+        c0 = time.perf_counter()
+        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), "al2", HA=HA, tol=tol,
+                           max_iter=20000, nthreads=threads)
+        c1 = time.perf_counter()
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16, H=sqrt(<p,HA p>) in HA's eigenbasis, FP32; "
+                          "% FP32 MFMA roofline",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
+                   config={"workload": "paper timing-table setting: n=16, D_ii = 1+(i-1)/15, J = 1/2 <y, D^-1 y>, "
+                                       "H = sqrt(<p, HA p>), HA = I + 1 1^T, %d points x~U[-10,10]^16, t~U(0,10], "
+                                       "FP32, tol %g; step = rotations in and out + evaluation" % (npts, tol),
+                           "npts": npts},
+                   roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_small_kernel<2, 1, 2>",
+                             "algorithmic": "sum over points of iterations x 2 n_pad^2 FLOP (n_pad = 32: the "
+                                            "products the kernel issues; 2 n^2 is a quarter of it)", "launch_ms": kms},
+                   iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": None,
+                             "note": "against the converged oracle (tol 1e-28); the paper's stop rule leaves "
+                                     "errors of this size"},
+                   paper={"seconds_per_eval": 1.04e-05, "hardware": "one core of an i5-5300U (Table 4, FP64)",
+                          "note": "context only: another machine, one core, FP64"},
                    cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
                                  "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
     elif a.workload in ("c2", "c2wl2"):

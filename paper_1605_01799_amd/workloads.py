@@ -52,7 +52,7 @@ class Problem:
     ellipsoid level-set functions), H = hkind with weights w, and its points."""
     n: int
     A: np.ndarray                 # n x n float64 SPD
-    hkind: str                    # "wl1" | "l2" | "l2_wl1" | "wl2"
+    hkind: str                    # "wl1" | "l2" | "l2_wl1" | "wl2" | "al2"
     w: Optional[np.ndarray]       # n float64 (None: all ones)
     x: np.ndarray                 # npts x n
     t: np.ndarray                 # npts
@@ -60,6 +60,7 @@ class Problem:
     level_set: bool = False
     A_is_diagonal: bool = False
     spectrum: Optional[np.ndarray] = None  # eigenvalues of A (for reference only)
+    HA: Optional[np.ndarray] = None        # n x n SPD matrix of H for hkind "al2"
 
     @property
     def npts(self) -> int:
@@ -148,6 +149,19 @@ def workload_paper_d(n: int = 16, npts: int = 1 << 20, j_is_d: bool = True) -> P
     A = D.copy() if j_is_d else np.ones(n)
     return Problem(n=n, A=np.diag(A), hkind="wl2", w=D.copy(), x=x, t=t, A_is_diagonal=True,
                    spectrum=A.copy())
+
+
+def workload_paper_a(n: int = 16, npts: int = 1 << 20) -> Problem:
+    """The paper's timing-table setting (section 4.5) for the ||.||_A column with
+    J = 1/2 <y, D^{-1} y>: D_ii = 1 + (i-1)/(n-1), H = sqrt(<p, HA p>) with HA = I + 1 1^T,
+    (x, t) uniform in [-10, 10]^n x (0, 10]."""
+    rng = rng_for(8, n)
+    D = 1.0 + np.arange(n) / (n - 1)
+    x = rng.uniform(-10.0, 10.0, (npts, n))
+    t = 10.0 - rng.uniform(0.0, 10.0, npts)
+    HA = np.eye(n) + np.ones((n, n))
+    return Problem(n=n, A=np.diag(D), hkind="al2", w=None, x=x, t=t, A_is_diagonal=True,
+                   spectrum=D.copy(), HA=HA)
 
 
 def workload3(npts: int = 1 << 16) -> Problem:
