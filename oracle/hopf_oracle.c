@@ -101,6 +101,11 @@ static double ham(const oh_problem* pb, int hkind, const double* p) {
   const int n = pb->n;
   const double* w = pb->w;
   if (hkind == OH_AL2) return sqrt(quad(n, pb->HA, p)); /* sqrt(<p, HA p>) */
+  if (hkind == OH_LINF) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = fabs(p[i]) > m ? fabs(p[i]) : m;
+    return m;
+  }
   if (hkind == OH_WL2) {
     ksum k = {0, 0};
     for (int i = 0; i < n; ++i) ks_add(&k, wgt(w, i) * p[i] * p[i]);
@@ -177,6 +182,66 @@ static void prox_al2(int n, const double* Q, const double* sig, double theta, co
   }
 }
 
+/* The breakpoint method of sections 4.2 and 4.4 for a root of a decreasing, piecewise-affine
+ * function f(mu) = a |shrink1(z, mu)|_1 - b mu - c on [0, max |z_i|], whose breakpoints are 0 and
+ * the |z_i|: sort the breakpoints increasingly, find the two consecutive ones l_j, l_{j+1} with
+ * f(l_j) >= 0 > f(l_{j+1}), and interpolate (f is affine between them).  The caller guarantees
+ * f(0) >= 0 > f(max |z_i|).  `bp` holds n + 1 doubles. */
+static double shrink1_norm(int n, const double* z, double mu) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i) ks_add(&k, fabs(shrink1(z[i], mu)));
+  return ks_val(&k);
+}
+static int cmp_double(const void* a, const void* b) {
+  const double x = *(const double*)a, y = *(const double*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+static double breakpoint_root(int n, const double* z, double a, double b, double c, double* bp) {
+  bp[0] = 0.0;
+  for (int i = 0; i < n; ++i) bp[i + 1] = fabs(z[i]);
+  qsort(bp, (size_t)n + 1, sizeof(double), cmp_double);
+  double lo = bp[0], flo = a * shrink1_norm(n, z, lo) - b * lo - c;
+  for (int j = 1; j <= n; ++j) {
+    if (bp[j] == lo) continue;
+    const double hi = bp[j], fhi = a * shrink1_norm(n, z, hi) - b * hi - c;
+    if (fhi < 0.0) return lo + flo * (hi - lo) / (flo - fhi);
+    lo = hi; flo = fhi;
+  }
+  return lo;
+}
+
+/* prox of theta |.|_inf (section 4.2): z - pi(z), pi the projection onto the l1 ball of radius
+ * theta (the Wulff shape); 0 when |z|_1 <= theta, else z - shrink1(z, mu) with mu the root of
+ * |shrink1(z, mu)|_1 = theta (eqs. projection_mu_linfty, condition_mu_linfty). */
+static void prox_linf(int n, double theta, const double* z, double* d, double* bp) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i) ks_add(&k, fabs(z[i]));
+  if (ks_val(&k) <= theta) {
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    return;
+  }
+  const double mu = breakpoint_root(n, z, 1.0, 0.0, theta, bp);
+  for (int i = 0; i < n; ++i) d[i] = z[i] - shrink1(z[i], mu);
+}
+
+/* prox of (alpha / 2) |.|_1^2 (section 4.4): shrink1(z, beta) with beta = alpha |shrink1(z, beta)|_1
+ * (eqs. optimality_beta_l1_2, prox_l1_2_with_beta), beta the root of the breakpoint function
+ * alpha |shrink1(z, beta)|_1 - beta. */
+static void prox_l1sq(int n, double alpha, const double* z, double* out, double* bp) {
+  int nz = 0;
+  for (int i = 0; i < n; ++i) nz |= z[i] != 0.0;
+  const double beta = nz ? breakpoint_root(n, z, alpha, 1.0, 0.0, bp) : 0.0;
+  for (int i = 0; i < n; ++i) out[i] = shrink1(z[i], beta);
+}
+
+/* prox of (alpha / 2) |.|_inf^2 by Moreau's identity with its conjugate (1 / (2 alpha)) |.|_1^2
+ * (section 4.4; the printed form with alpha / 2 in both terms holds for alpha = 1 only):
+ * z - prox_{(1 / (2 alpha)) |.|_1^2}(z). */
+static void prox_linfsq(int n, double alpha, const double* z, double* out, double* bp, double* tmp) {
+  prox_l1sq(n, 1.0 / alpha, z, tmp, bp);
+  for (int i = 0; i < n; ++i) out[i] = z[i] - tmp[i];
+}
+
 static void prox_h(int n, int hkind, const double* w, double theta, const double* z, double* d) {
   if (hkind == OH_WL2) {
     prox_wl2(n, w, theta, z, d);
@@ -205,16 +270,28 @@ static void prox_h(int n, int hkind, const double* w, double theta, const double
 /* ------------------------------------------------------------------------- */
 typedef struct {
   int n;
-  double *v, *d, *b, *rhs, *vn, *dn, *z, *tmp, *y;
+  double *v, *d, *b, *rhs, *vn, *dn, *z, *tmp, *y, *t2, *bp;
 } scratch;
 
 static int scratch_alloc(scratch* s, int n) {
   s->n = n;
-  double* buf = (double*)calloc((size_t)9 * n, sizeof(double));
+  double* buf = (double*)calloc((size_t)11 * n + 1, sizeof(double));
   if (!buf) return -1;
   s->v = buf; s->d = buf + n; s->b = buf + 2 * n; s->rhs = buf + 3 * n; s->vn = buf + 4 * n;
   s->dn = buf + 5 * n; s->z = buf + 6 * n; s->tmp = buf + 7 * n; s->y = buf + 8 * n;
+  s->t2 = buf + 9 * n; s->bp = buf + 10 * n; /* bp: n + 1 breakpoints */
   return 0;
+}
+
+static double norm1(int n, const double* p) {
+  ksum k = {0, 0};
+  for (int i = 0; i < n; ++i) ks_add(&k, fabs(p[i]));
+  return ks_val(&k);
+}
+static double norminf(int n, const double* p) {
+  double m = 0.0;
+  for (int i = 0; i < n; ++i) m = fabs(p[i]) > m ? fabs(p[i]) : m;
+  return m;
 }
 static void scratch_free(scratch* s) { free(s->v); }
 
@@ -234,12 +311,20 @@ static double hopf_solve(const oh_problem* pb, int hkind, const double* LS, cons
   while (k < pb->max_iter) {
     ++k;
     /* (3.4a): v = argmin J*(v) - <x,v> + lambda/2 ||d - v - b||^2  <=>  (A + lambda I) v = x + lambda (d - b) */
-    for (int i = 0; i < n; ++i) s->rhs[i] = xp[i] + lam * (s->d[i] - s->b[i]);
-    chol_solve(n, LS, s->rhs, s->tmp, s->vn);
+    if (pb->jkind == OJ_QUAD) {
+      for (int i = 0; i < n; ++i) s->rhs[i] = xp[i] + lam * (s->d[i] - s->b[i]);
+      chol_solve(n, LS, s->rhs, s->tmp, s->vn);
+    } else {
+      /* the same minimisation for a squared-norm J* is the prox of (1 / lambda) J* at d - b + x / lambda */
+      for (int i = 0; i < n; ++i) s->rhs[i] = s->d[i] - s->b[i] + xp[i] / lam;
+      if (pb->jkind == OJ_L1SQ) prox_linfsq(n, 1.0 / lam, s->rhs, s->vn, s->bp, s->t2); /* J* = 1/2 |.|_inf^2 */
+      else prox_l1sq(n, 1.0 / lam, s->rhs, s->vn, s->bp);                              /* J* = 1/2 |.|_1^2 */
+    }
     /* (3.4b): d = prox_{(t/lambda) H}(v + b) */
     for (int i = 0; i < n; ++i) s->z[i] = s->vn[i] + s->b[i];
     const double theta = t / lam;
     if (hkind == OH_AL2) prox_al2(n, pb->HQ, pb->Hsig, theta, s->z, s->dn, s->tmp, s->y);
+    else if (hkind == OH_LINF) prox_linf(n, theta, s->z, s->dn, s->bp);
     else prox_h(n, hkind, pb->w, theta, s->z, s->dn);
     /* (3.4c): b = b + v - d */
     for (int i = 0; i < n; ++i) s->b[i] = s->b[i] + s->vn[i] - s->dn[i];
@@ -254,15 +339,26 @@ static double hopf_solve(const oh_problem* pb, int hkind, const double* LS, cons
   const double* p = s->d;
   memcpy(out_p, p, sizeof(double) * (size_t)n);
   ksum F = {0, 0};
-  ks_add(&F, 0.5 * quad(n, pb->A, p));
+  if (pb->jkind == OJ_QUAD) ks_add(&F, 0.5 * quad(n, pb->A, p));
+  else {
+    const double q = pb->jkind == OJ_L1SQ ? norminf(n, p) : norm1(n, p); /* J* = 1/2 (dual norm)^2 */
+    ks_add(&F, 0.5 * q * q);
+  }
   ks_add(&F, t * ham(pb, hkind, p));
   ks_add(&F, -dot(n, xp, p));
   double Fv = ks_val(&F);
   if (gap) {
     /* Hopf-Lax feasible point y = x' - lambda b: lambda b / t lies in t^{-1} * t dH(d) within the Wulff shape. */
     for (int i = 0; i < n; ++i) s->y[i] = xp[i] - lam * s->b[i];
-    chol_solve(n, LA, s->y, s->tmp, s->z); /* z = A^{-1} y */
-    *gap = 0.5 * dot(n, s->y, s->z) + Fv;
+    double Jy;
+    if (pb->jkind == OJ_QUAD) {
+      chol_solve(n, LA, s->y, s->tmp, s->z); /* z = A^{-1} y */
+      Jy = 0.5 * dot(n, s->y, s->z);
+    } else {
+      const double q = pb->jkind == OJ_L1SQ ? norm1(n, s->y) : norminf(n, s->y);
+      Jy = 0.5 * q * q;
+    }
+    *gap = Jy + Fv;
   }
   return -Fv;
 }
@@ -319,7 +415,8 @@ static void* eval_worker(void* arg) {
 
 static int check_problem(const oh_problem* pb) {
   if (!pb || pb->n < 1 || !pb->A || pb->K < 1 || !(pb->lambda > 0) || pb->max_iter < 1) return -1;
-  if (pb->hkind < OH_WL1 || pb->hkind > OH_AL2) return -1;
+  if (pb->hkind < OH_WL1 || pb->hkind > OH_LINF) return -1;
+  if (pb->jkind < OJ_QUAD || pb->jkind > OJ_LINFSQ) return -1;
   if (pb->hkind == OH_AL2) {
     if (!pb->HA || !pb->HQ || !pb->Hsig) return -1;
     for (int i = 0; i < pb->n; ++i)

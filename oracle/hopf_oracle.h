@@ -19,7 +19,9 @@
 extern "C" {
 #endif
 
-enum { OH_WL1 = 0, OH_L2 = 1, OH_L2_WL1 = 2, OH_WL2 = 3, OH_AL2 = 4 };
+enum { OH_WL1 = 0, OH_L2 = 1, OH_L2_WL1 = 2, OH_WL2 = 3, OH_AL2 = 4, OH_LINF = 5 };
+/* initial data: quadratic 1/2 y^T A^{-1} y, or the squared norms of section 4.4 */
+enum { OJ_QUAD = 0, OJ_L1SQ = 1, OJ_LINFSQ = 2 };
 
 typedef struct {
   int32_t n;
@@ -27,7 +29,7 @@ typedef struct {
   int32_t K;              /* number of ellipsoids / translated copies of J (>= 1) */
   const double* centres;  /* K*n, or NULL (all centres 0) */
   int32_t level_set;      /* 1: J_k(y) = 1/2((y-c_k)^T A^{-1} (y-c_k) - 1) */
-  int32_t hkind;          /* OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2 */
+  int32_t hkind;          /* OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2, OH_LINF (||p||_inf) */
   const double* w;        /* n weights >= 0 (> 0 for OH_WL2), or NULL (all 1) */
   double lambda;          /* split-Bregman penalty (paper: 1) */
   double tol;             /* stop when max of the three squared norms <= tol */
@@ -37,6 +39,9 @@ typedef struct {
   const double* HA;
   const double* HQ;
   const double* Hsig;
+  /* OJ_QUAD: J(y) = 1/2 y^T A^{-1} y; OJ_L1SQ: J(y) = 1/2 |y|_1^2 (J*(p) = 1/2 |p|_inf^2);
+   * OJ_LINFSQ: J(y) = 1/2 |y|_inf^2 (J*(p) = 1/2 |p|_1^2).  For the last two A is not used. */
+  int32_t jkind;
 } oh_problem;
 
 /* Returns 0 on success, -1 on bad arguments, -2 if A + lambda I (or A) is not SPD.

@@ -29,8 +29,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hopf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_hopf.so")
 
-OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2 = 0, 1, 2, 3, 4
-_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1, "wl2": OH_WL2, "al2": OH_AL2}
+OH_WL1, OH_L2, OH_L2_WL1, OH_WL2, OH_AL2, OH_LINF = 0, 1, 2, 3, 4, 5
+_HKIND = {"wl1": OH_WL1, "l2": OH_L2, "l2_wl1": OH_L2_WL1, "wl2": OH_WL2, "al2": OH_AL2,
+          "linf": OH_LINF}
+_JKIND = {"quad": 0, "l1sq": 1, "linfsq": 2}
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +55,7 @@ class _Problem(ctypes.Structure):
         ("centres", ctypes.c_void_p), ("level_set", ctypes.c_int32), ("hkind", ctypes.c_int32),
         ("w", ctypes.c_void_p), ("lam", ctypes.c_double), ("tol", ctypes.c_double),
         ("max_iter", ctypes.c_int32), ("HA", ctypes.c_void_p), ("HQ", ctypes.c_void_p),
-        ("Hsig", ctypes.c_void_p),
+        ("Hsig", ctypes.c_void_p), ("jkind", ctypes.c_int32),
     ]
 
 
@@ -90,7 +92,7 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA=None):
+def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA=None, jkind="quad"):
     A = _f64(A)
     n = A.shape[0]
     if A.shape != (n, n):
@@ -106,7 +108,7 @@ def _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA=None):
         Hsig, HQ = np.linalg.eigh(0.5 * (HA + HA.T))
         HQ, Hsig = np.ascontiguousarray(HQ), np.ascontiguousarray(Hsig)
     pb = _Problem(n, _ptr(A), K, _ptr(centres), int(bool(level_set)), hk, _ptr(w),
-                  float(lam), float(tol), int(max_iter), _ptr(HA), _ptr(HQ), _ptr(Hsig))
+                  float(lam), float(tol), int(max_iter), _ptr(HA), _ptr(HQ), _ptr(Hsig), _JKIND[jkind])
     return pb, (A, w, centres, HA, HQ, Hsig), n, K
 
 
@@ -117,11 +119,13 @@ def _threads(nthreads):
 
 
 def oracle_eval(A, x, t, hkind="wl1", w=None, centres=None, level_set=False, lam=1.0,
-                tol=1e-28, max_iter=100000, nthreads=None, with_gap=False, HA=None):
+                tol=1e-28, max_iter=100000, nthreads=None, with_gap=False, HA=None, jkind="quad"):
     """Hopf evaluation of every point of x (npts x n) at times t (npts).  hkind "al2" takes the
-    SPD matrix HA of H(p) = sqrt(p^T HA p)."""
+    SPD matrix HA of H(p) = sqrt(p^T HA p); "linf" is H = |p|_inf.  jkind "quad" is
+    J(y) = 1/2 y^T A^{-1} y; "l1sq" J = 1/2 |y|_1^2 and "linfsq" J = 1/2 |y|_inf^2 (A is then
+    only used for its size: pass the identity)."""
     lib = _load()
-    pb, keep, n, K = _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA)
+    pb, keep, n, K = _problem(A, hkind, w, centres, level_set, lam, tol, max_iter, HA, jkind)
     x = _f64(x).reshape(-1, n)
     t = _f64(t).reshape(-1)
     m = x.shape[0]

@@ -33,6 +33,11 @@ MUTANTS = {
     "wl2_hamiltonian_unweighted": ("ks_add(&k, wgt(w, i) * p[i] * p[i]);", "ks_add(&k, p[i] * p[i]);"),
     "al2_rotation_transposed": ("ks_add(&k, Q[(size_t)i * n + a] * z[i]);", "ks_add(&k, Q[(size_t)a * n + i] * z[i]);"),
     "al2_back_rotation_dropped": ("ks_add(&k, Q[(size_t)i * n + a] * du[a]);", "ks_add(&k, (i == a) * du[a]);"),
+    "linf_ball_radius": ("const double mu = breakpoint_root(n, z, 1.0, 0.0, theta, bp);",
+                         "const double mu = breakpoint_root(n, z, 1.0, 0.0, 0.5 * theta, bp);"),
+    "l1sq_threshold_equation": ("breakpoint_root(n, z, alpha, 1.0, 0.0, bp)", "breakpoint_root(n, z, 1.0, alpha, 0.0, bp)"),
+    "linfsq_conjugate_scale": ("prox_l1sq(n, 1.0 / alpha, z, tmp, bp);", "prox_l1sq(n, alpha, z, tmp, bp);"),
+    "breakpoint_interpolation": ("return lo + flo * (hi - lo) / (flo - fhi);", "return lo + fhi * (hi - lo) / (flo - fhi);"),
     "secular_projection_index": ("us[a] = sigma[a] * u[a] / (sigma[a] + mu);", "us[a] = sigma[a] * u[a] / (sigma[a] + mu * mu);"),
 }
 
@@ -100,6 +105,18 @@ def battery(lib):
             r = O.oracle_eval(A2, x, t, "al2", HA=HA, tol=1e-26, max_iter=20000)
             return all(al2_kkt_residual(A2, HA, x[j], t[j], r["grad"][j]) < 1e-7 for j in range(8))
         check("al2_kkt", al2_kkt)
+
+        def norm_family():
+            ok = True
+            y = rng.uniform(-10, 10, (8, n))
+            for jk in ("l1sq", "linfsq"):
+                for hk, lam in (("linf", 1.0), ("linf", 0.5), ("l2", 1.0)):
+                    r = O.oracle_eval(np.eye(n), y, 3 * t, hk, jkind=jk, lam=lam, tol=1e-26, max_iter=20000,
+                                      with_gap=True)
+                    ok &= bool(np.all(np.abs(r["gap"]) <= 1e-9 * np.maximum(1, np.abs(r["phi"]))))
+            r = O.oracle_eval(np.eye(n), y, 3 * t, "linf", tol=1e-26, max_iter=20000, with_gap=True)
+            return ok and bool(np.all(np.abs(r["gap"]) <= 1e-9 * np.maximum(1, np.abs(r["phi"]))))
+        check("norm_family", norm_family)
 
         def union_translation():
             C = rng.normal(0, 2, (2, n))

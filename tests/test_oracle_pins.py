@@ -229,6 +229,99 @@ def test_al2_brute_force_n2(oracle_lib):
         assert -r["phi"][0] <= fb + 1e-12
 
 
+# ---------------------------------------------------------------- H = |.|_inf, J = squared norms
+NORM_J = {"l1sq": lambda y: 0.5 * np.sum(np.abs(y)) ** 2, "linfsq": lambda y: 0.5 * np.max(np.abs(y)) ** 2}
+NORM_JSTAR = {"l1sq": lambda p: 0.5 * np.max(np.abs(p)) ** 2, "linfsq": lambda p: 0.5 * np.sum(np.abs(p)) ** 2}
+
+
+@pytest.mark.parametrize("jk", ["quad", "l1sq", "linfsq"])
+@pytest.mark.parametrize("hk", ["linf", "l2", "wl1", "wl2"])
+def test_norm_family_n1_closed_form(oracle_lib, jk, hk):
+    """n = 1: every norm is |.|, so J = y^2 / 2 and H = |p| (w = 1): phi = (|x| - t)_+^2 / 2, p = shrink1(x, t)."""
+    rng = np.random.default_rng(51)
+    x = rng.normal(0, 3, (40, 1))
+    t = rng.uniform(0.05, 3, 40)
+    r = oracle_lib.oracle_eval(np.eye(1), x, t, hk, jkind=jk, tol=TOL)
+    np.testing.assert_allclose(r["phi"], 0.5 * np.maximum(np.abs(x[:, 0]) - t, 0) ** 2, atol=1e-13)
+    np.testing.assert_allclose(r["grad"][:, 0], shrink(x[:, 0], t), atol=1e-13)
+
+
+def l1_ball_projection_bisection(z, r):
+    if np.sum(np.abs(z)) <= r:
+        return z.copy()
+    lo, hi = 0.0, np.max(np.abs(z))
+    for _ in range(300):
+        m = 0.5 * (lo + hi)
+        lo, hi = (m, hi) if np.sum(np.maximum(np.abs(z) - m, 0)) > r else (lo, m)
+    return shrink(z, 0.5 * (lo + hi))
+
+
+def test_linf_identity_is_l1_ball_projection(oracle_lib):
+    """J = |y|^2 / 2, H = |.|_inf: p* = x - pi_{tB1}(x) (section 4.2; the Wulff shape of |.|_inf is
+    the l1 ball), the projection here found by bisection on the multiplier instead of the breakpoint
+    search."""
+    rng = np.random.default_rng(52)
+    n = 9
+    x = rng.uniform(-10, 10, (60, n))
+    t = rng.uniform(0.01, 10, 60)
+    t[:5] = 200.0  # x inside t B1: p = 0
+    r = oracle_lib.oracle_eval(np.eye(n), x, t, "linf", tol=TOL)
+    for j in range(60):
+        p = x[j] - l1_ball_projection_bisection(x[j], t[j])
+        np.testing.assert_allclose(r["grad"][j], p, atol=1e-11)
+        assert abs(r["phi"][j] - (x[j] @ p - 0.5 * p @ p - t[j] * np.max(np.abs(p)))) <= 1e-10 * max(1, abs(r["phi"][j]))
+    assert np.all(r["grad"][:5] == 0)
+
+
+@pytest.mark.parametrize("jk", ["l1sq", "linfsq"])
+@pytest.mark.parametrize("hk", ["linf", "l2", "wl1"])
+def test_norm_family_brute_force_n2(oracle_lib, jk, hk):
+    """n = 2: min over p of J*(p) + t H(p) - <x, p> by a grid plus Nelder-Mead, for the squared-norm
+    initial data (J* the squared dual norm)."""
+    rng = np.random.default_rng(53)
+    w = rng.uniform(0.5, 2, 2)
+    Hf = {"linf": lambda p: np.max(np.abs(p)), "l2": np.linalg.norm, "wl1": lambda p: np.sum(w * np.abs(p))}[hk]
+    for _ in range(4):
+        x = rng.normal(0, 3, 2)
+        t = rng.uniform(0.05, 2)
+        F = lambda p: NORM_JSTAR[jk](p) + t * Hf(p) - x @ p
+        # nested grids (these F have kinks, so a zooming grid rather than a local descent)
+        c, rad = np.zeros(2), 8.0
+        for _ in range(14):
+            g = np.linspace(-rad, rad, 81)
+            vals = np.array([[F(c + np.array([a, b])) for b in g] for a in g])
+            i = np.unravel_index(np.argmin(vals), vals.shape)
+            c = c + np.array([g[i[0]], g[i[1]]])
+            rad /= 4.0
+        fb = F(c)
+        r = oracle_lib.oracle_eval(np.eye(2), x[None], [t], hk, w=w, jkind=jk, tol=TOL)
+        assert abs(F(r["grad"][0]) + r["phi"][0]) <= 1e-12 * max(1, abs(fb))   # phi = -F(p)
+        assert abs(-r["phi"][0] - fb) <= 1e-9 * max(1, abs(fb))
+        assert -r["phi"][0] <= fb + 1e-12
+
+
+@pytest.mark.parametrize("jk", ["l1sq", "linfsq"])
+def test_norm_family_certificates(oracle_lib, jk):
+    """The paper's timing-table setting (n = 4, 8, 16; x in [-10, 10]^n, t in (0, 10]): the duality
+    gap J(x - lambda b) + F(d) closes, invariance under permuting coordinates (all these norms are
+    symmetric), homogeneity phi(a x, a t) = a^2 phi(x, t), and phi <= J(x)."""
+    rng = np.random.default_rng(54)
+    for n in (4, 8, 16):
+        x = rng.uniform(-10, 10, (25, n))
+        t = rng.uniform(0.01, 10, 25)
+        for hk in ("linf", "l2", "wl1"):
+            r = oracle_lib.oracle_eval(np.eye(n), x, t, hk, jkind=jk, tol=TOL, with_gap=True)
+            sc = np.maximum(1, np.abs(r["phi"]))
+            assert np.all(np.abs(r["gap"]) <= 1e-12 * sc)
+            perm = rng.permutation(n)
+            rp = oracle_lib.oracle_eval(np.eye(n), x[:, perm], t, hk, jkind=jk, tol=TOL)
+            np.testing.assert_allclose(rp["phi"], r["phi"], rtol=1e-11, atol=1e-11)
+            np.testing.assert_allclose(rp["grad"], r["grad"][:, perm], rtol=1e-9, atol=1e-9)
+            r2 = oracle_lib.oracle_eval(np.eye(n), 2 * x, 2 * t, hk, jkind=jk, tol=TOL)
+            np.testing.assert_allclose(r2["phi"], 4 * r["phi"], rtol=1e-10, atol=1e-10)
+            assert np.all(r["phi"] <= np.array([NORM_J[jk](xx) for xx in x]) + 1e-10)
+
+
 # ---------------------------------------------------------------- brute force
 @pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1", "wl2"])
 def test_brute_force_n2(oracle_lib, hkind):
