@@ -60,13 +60,15 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1s", "c2", "c5", "c2wl2", "pd16", "pa16"],
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c1s", "c2", "c5", "c2wl2", "pd16", "pa16", "t5n16"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
                          "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
                          "FP32 dense at 2^20 points, c5 = n=256 union of 4 ellipsoids, forward + backward; "
                          "c2wl2 = c2 with H = sqrt(<p, diag(w) p>); pd16 = the paper's timing-table setting "
                          "for that H at n=16 (J = 1/2 <y, D^-1 y>, FP64, tol 1e-8); pa16 = the same for "
-                         "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis)")
+                         "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis); "
+                         "t5n16 = the paper's Table 5 workload, J = 1/2 |y|_1^2, H = |p|_inf, n=16, FP64, tol 1e-8")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
                          "scale of the FETCH_SIZE / WRITE_SIZE counters")
@@ -317,6 +319,61 @@ def bench_other(a):
                              "note": "against the converged oracle (tol 1e-28); the paper's stop rule "
                                      "(squared norms <= 1e-8) itself leaves errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "one core of an i5-5300U (Table 4)",
+                          "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
+                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+    elif a.workload == "t5n16":
+        npts = a.npts if a.npts != 1 << 16 else 1 << 22
+        p = W.workload_paper_norms(16, npts, "linf")
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        tol = a.tol if a.tol is not None else 1e-8
+        prob = H.Problem(n=p.n, diagonal=True, hkind="linf", jkind="l1sq", precision="f64", tol=tol, max_iter=20000)
+        out = dict(phi=torch.empty(npts, dtype=torch.float64, device=dev),
+                   grad=torch.empty(npts, p.n, dtype=torch.float64, device=dev),
+                   dphidt=torch.empty(npts, dtype=torch.float64, device=dev),
+                   iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        it = out["iters"].cpu().numpy()
+        # per point-iteration: two breakpoint searches of n^2 + O(n) FP64 operations each (the
+        # v-update's and the prox's), plus 15 n for the updates and norms
+        flops = float(np.sum(np.abs(it)).astype(np.float64) * (2.0 * 2 * p.n * p.n + 15.0 * p.n))
+        achieved = flops / (kms / 1e3) / 1e12
+        rng = np.random.default_rng(10)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample * 4, npts), replace=False))
+        ref = oracle.oracle_eval(np.eye(p.n), p.x[idx], p.t[idx], "linf", jkind="l1sq", tol=1e-28, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        m = min(npts, 1 << 16)
+        c0 = time.perf_counter()
+        oracle.oracle_eval(np.eye(p.n), p.x[:m], p.t[:m], "linf", jkind="l1sq", tol=tol, max_iter=20000,
+                           nthreads=threads)
+        c1 = time.perf_counter()
+        value = npts / (ms / 1e3)
+        paper_s = 2.22e-05   # Table 5, n = 16, 16 cores: seconds per evaluation
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16, J=1/2|y|_1^2, H=|p|_inf, FP64; % FP64 vector roofline",
+                   value=value, steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f64",
+                   vs_baseline=value * paper_s,
+                   config={"workload": "the paper's Table 5 setting: n=16, J = 1/2 |y|_1^2, H = |p|_inf, %d points "
+                                       "x~U[-10,10]^16, t~U(0,10], FP64, tol %g" % (npts, tol), "npts": npts},
+                   roofline={"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": achieved / 78.6, "traffic": None, "kernel": "diag_kernel<double, 16>",
+                             "algorithmic": "sum over points of iterations x (4 n^2 + 15 n) FP64 operations (two "
+                                            "breakpoint searches by testing every breakpoint, the updates)",
+                             "launch_ms": kms},
+                   iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": None,
+                             "note": "against the converged oracle (tol 1e-28); the paper's stop rule leaves "
+                                     "errors of this size"},
+                   paper={"seconds_per_eval": paper_s, "hardware": "16 cores of 2x Xeon E5-2690 (Table 5)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
                    cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
                                  "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})

@@ -73,13 +73,25 @@ typedef enum {
                          state stays in one wave or one thread: diagonal A with n <= 32
                          (any precision), or HOPF_F32 with n <= 64; other problems are
                          rejected with HOPF_EINVAL at create time. */
-  HOPF_H_AL2 = 4      /* H(p) = sqrt(<p, HA p>) for a full SPD matrix HA (the norm ||.||_A of
+  HOPF_H_AL2 = 4,     /* H(p) = sqrt(<p, HA p>) for a full SPD matrix HA (the norm ||.||_A of
                          section 4.4; HA in the descriptor).  The library diagonalises HA on the
                          device (HA = P diag(s) P^T, FP64 Jacobi) and holds the problem in that
                          basis, where H is HOPF_H_WL2 with weights s, A becomes P^T A P and the
                          centres P^T c; points are rotated in before the solve and gradients /
                          closest points rotated back after it.  HOPF_F32 with n <= 64. */
+  HOPF_H_LINF = 5     /* H(p) = ||p||_inf (section 4.2): its prox is z minus the projection onto
+                         the l1 ball (the Wulff shape), found by a breakpoint search.  On the
+                         per-thread path only: diagonal A or a squared-norm J, n <= 32. */
 } hopf_hkind;
+
+/* Initial data J (section 4.4).  HOPF_J_QUADRATIC uses the descriptor's A; the squared norms
+ * ignore A (it may be NULL), run on the per-thread path (n <= 32, HOPF_F64 or HOPF_F32) and take
+ * update (3.4a) as the prox of J* (the squared dual norm) by a breakpoint search. */
+typedef enum {
+  HOPF_J_QUADRATIC = 0,  /* J(y) = 1/2 y^T A^{-1} y            (J*(p) = 1/2 p^T A p)      */
+  HOPF_J_L1SQ = 1,       /* J(y) = 1/2 ||y||_1^2                (J*(p) = 1/2 ||p||_inf^2)  */
+  HOPF_J_LINFSQ = 2      /* J(y) = 1/2 ||y||_inf^2              (J*(p) = 1/2 ||p||_1^2)    */
+} hopf_jkind;
 
 typedef enum {
   HOPF_F64 = 0,          /* double I/O and arithmetic (diagonal A only) */
@@ -106,6 +118,8 @@ typedef struct {
   const double* HA;          /* host, n*n row-major SPD matrix of H for HOPF_H_AL2; otherwise
                                 ignored (may be NULL).  HOPF_ENOTSPD if it is not positive
                                 definite. */
+  int32_t jkind;             /* hopf_jkind; 0 (HOPF_J_QUADRATIC) keeps the A above.  Translated
+                                copies (K, centres) apply to every kind: J_k = J(. - c_k). */
 } hopf_problem_desc;
 
 typedef struct hopf_problem* hopf_problem_t;

@@ -53,6 +53,7 @@ extern "C" const char* hopf_version(void) { return "hopf-mi355x 0.1 (gfx950)"; }
 struct hopf_problem {
   int device = 0;
   int n = 0, n_pad = 0, K = 1, level_set = 0, hkind = 0, precision = 0, diagonal = 0, max_iter = 1;
+  int jkind = 0;  // hopf_jkind
   double lambda = 1.0, tol = 0.0;
   double* d_w = nullptr;        // n_pad
   float* d_wf = nullptr;        // n_pad, FP32 copy
@@ -150,7 +151,8 @@ static hopf_status validate(const hopf_problem_desc* d) {
   if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) return fail(HOPF_EINVAL, "lambda must be finite and > 0");
   if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return fail(HOPF_EINVAL, "tol must be finite and >= 0");
   if (d->max_iter < 1) return fail(HOPF_EINVAL, "max_iter must be >= 1");
-  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_AL2) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
+  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_LINF) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
+  if (d->jkind < HOPF_J_QUADRATIC || d->jkind > HOPF_J_LINFSQ) return fail(HOPF_EINVAL, "unknown jkind %d", (int)d->jkind);
   if (d->precision < HOPF_F64 || d->precision > HOPF_BF16_REFINED)
     return fail(HOPF_EINVAL, "unknown precision %d", (int)d->precision);
   const int n = d->n;
@@ -162,8 +164,9 @@ static hopf_status validate(const hopf_problem_desc* d) {
   if (d->centres)
     for (int64_t i = 0; i < (int64_t)d->K * n; ++i)
       if (!std::isfinite(d->centres[i])) return fail(HOPF_EINVAL, "centres[%lld] is not finite", (long long)i);
-  const bool diag = d->A == nullptr || d->A_is_diagonal;
-  if (d->A) {
+  const bool normsq = d->jkind != HOPF_J_QUADRATIC;
+  const bool diag = normsq || d->A == nullptr || d->A_is_diagonal;
+  if (d->A && !normsq) {
     const int64_t m = d->A_is_diagonal ? n : (int64_t)n * n;
     for (int64_t i = 0; i < m; ++i)
       if (!std::isfinite(d->A[i])) return fail(HOPF_EINVAL, "A[%lld] is not finite", (long long)i);
@@ -185,6 +188,13 @@ static hopf_status validate(const hopf_problem_desc* d) {
   // the per-thread diagonal kernel and the wave-local small dense kernel
   if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= 64)))
     return fail(HOPF_EINVAL, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= 64", kDiagMaxN);
+  // the breakpoint searches run in the per-thread kernel
+  if (normsq && (n > kDiagMaxN || d->precision == HOPF_BF16_REFINED))
+    return fail(HOPF_EINVAL, "squared-norm J supports n <= %d with HOPF_F64 or HOPF_F32", kDiagMaxN);
+  if (d->hkind == HOPF_H_LINF && !(diag && n <= kDiagMaxN && d->precision != HOPF_BF16_REFINED))
+    return fail(HOPF_EINVAL, "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32",
+                kDiagMaxN);
+  if (normsq && d->hkind == HOPF_H_AL2) return fail(HOPF_EINVAL, "HOPF_H_AL2 needs the quadratic J");
   if (d->hkind == HOPF_H_AL2) {
     // solved in HA's eigenbasis, where A becomes dense: the wave-local FP32 kernel
     if (d->precision != HOPF_F32 || n > kRotMaxN)
@@ -261,7 +271,8 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   p->n = d->n; p->K = d->K; p->level_set = d->level_set ? 1 : 0; p->hkind = d->hkind;
   p->precision = d->precision; p->lambda = d->lambda; p->tol = d->tol; p->max_iter = d->max_iter;
   const bool al2 = d->hkind == HOPF_H_AL2;
-  p->diagonal = (!al2 && (d->A == nullptr || d->A_is_diagonal)) ? 1 : 0;
+  p->jkind = d->jkind;
+  p->diagonal = (!al2 && (p->jkind != HOPF_J_QUADRATIC || d->A == nullptr || d->A_is_diagonal)) ? 1 : 0;
   const int n = d->n;
   const int n_pad = (n + 31) / 32 * 32;
   p->n_pad = n_pad;
@@ -294,8 +305,8 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
   if (p->diagonal) {
-    std::vector<double> a(n, 1.0);
-    if (d->A) for (int i = 0; i < n; ++i) a[i] = d->A[i];
+    std::vector<double> a(n, 1.0);  // unused by the squared-norm initial data
+    if (d->A && p->jkind == HOPF_J_QUADRATIC) for (int i = 0; i < n; ++i) a[i] = d->A[i];
     if (hipMalloc(&p->d_adiag, sizeof(double) * n) || hipMalloc(&p->d_minv, sizeof(double) * n))
       return bail(fail(HOPF_ENOMEM, "hipMalloc diagonal"));
     if (hipMemcpy(p->d_adiag, a.data(), sizeof(double) * n, hipMemcpyHostToDevice))
@@ -645,11 +656,22 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
   if (p->diagonal && p->n <= kDiagMaxN) {
     DiagProb dp;
     dp.n = p->n; dp.ld = p->n_pad; dp.K = p->K; dp.level_set = p->level_set; dp.hkind = p->hkind;
+    dp.jkind = p->jkind;
     dp.max_iter = p->max_iter; dp.lambda = p->lambda; dp.tol = p->tol;
     dp.minv = p->d_minv; dp.adiag = p->d_adiag; dp.w = p->d_w; dp.centres = p->d_centres;
     dp.x = x; dp.t = t; dp.npts = npts; dp.phi = phi; dp.grad = grad; dp.dphidt = dphidt;
     dp.iters = iters; dp.kstar = kstar;
-    hipError_t e = launch_diag(dp, p->precision == HOPF_F64, s);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    Workspace* w;
+    hopf_status st = ws_get(dev, &w);
+    if (st) return st;
+    {
+      std::lock_guard<std::mutex> lk(w->mu);
+      if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
+    }
+    // the last counter slot is the per-thread kernel's point queue (the tile kernels use the first)
+    hipError_t e = launch_diag(dp, p->precision == HOPF_F64, w->counter + 15, w->ncu, s);
     if (e) return fail(HOPF_EDEVICE, "diag launch: %s", hipGetErrorString(e));
     return HOPF_OK;
   }
@@ -667,6 +689,7 @@ extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const 
                                           int32_t* newton, void* stream) {
   if (!p) return fail(HOPF_EINVAL, "problem is NULL");
   if (!p->level_set) return fail(HOPF_EINVAL, "closest point needs an ellipsoid level-set problem (level_set = 1)");
+  if (p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "closest point needs the quadratic J (ellipsoids)");
   if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "closest point needs HOPF_F32 or HOPF_BF16_REFINED");
   if (!(s_tol > 0.0) || !std::isfinite(s_tol)) return fail(HOPF_EINVAL, "s_tol must be finite and > 0");
   if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
@@ -696,6 +719,8 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
     if (!p) return fail(HOPF_EINVAL, "problem %d is NULL", q);
     if (p->precision != prec) return fail(HOPF_EINVAL, "problems of a ragged batch must share one precision");
     if (prec == HOPF_F64) return fail(HOPF_EINVAL, "ragged batches need HOPF_F32 or HOPF_BF16_REFINED");
+    if (p->jkind != HOPF_J_QUADRATIC || p->hkind == HOPF_H_LINF)
+      return fail(HOPF_EINVAL, "problem %d: squared-norm J and HOPF_H_LINF run per point (hopf_eval), not in ragged batches", q);
     const int64_t np = pt_offset[q + 1] - pt_offset[q];
     if (np < 0) return fail(HOPF_EINVAL, "pt_offset must be nondecreasing");
     DenseCall c;
@@ -725,6 +750,7 @@ extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void*
   if (npts > 0 && (!gphi || !grad_saved)) return fail(HOPF_EINVAL, "gphi and grad_saved are required");
   if (gt && !dphidt_saved) return fail(HOPF_EINVAL, "gt needs dphidt_saved");
   if (gc && p->K > 1 && !kstar_saved) return fail(HOPF_EINVAL, "gc needs kstar_saved when K > 1");
+  if (gA && p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "gA needs the quadratic J");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   Workspace* w;

@@ -1,5 +1,7 @@
-// Diagonal-A Hopf solver: J(y) = 1/2 sum y_i^2 / a_i, so update (3.4a) is
-// elementwise, v_i = (x'_i + lambda (d_i - b_i)) / (a_i + lambda).  One thread
+// Per-thread Hopf solver for diagonal A: J(y) = 1/2 sum y_i^2 / a_i, so update (3.4a) is
+// elementwise, v_i = (x'_i + lambda (d_i - b_i)) / (a_i + lambda); also for the squared-norm
+// initial data 1/2 |y|_1^2 and 1/2 |y|_inf^2 (section 4.4), whose update (3.4a) is the prox of the
+// squared dual norm, and for H = |p|_inf (section 4.2), both by a breakpoint search.  One thread
 // per query point runs the split-Bregman updates (3.4a)-(3.4c) literally, in
 // FP64 registers, with the paper's initial values (v0 = d0 = x', b0 = 0) and
 // its stopping test (section 4.5: the three squared norms
@@ -7,6 +9,9 @@
 // the min over the K translated copies (section 2).  The path is bound by HBM
 // traffic: it reads x and t once and writes phi, grad, dphidt once (for sqrt(<p, D p>) the prox
 // runs a Newton loop per iteration and the path is bound by FP64 arithmetic instead).
+#include <algorithm>
+#include <cstdint>
+
 #include "common.hpp"
 #include "diag.hpp"
 
@@ -48,6 +53,193 @@ __device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, d
     if (i < n) z[i] = mu * z[i] / (theta * theta * (w ? w[i] : 1.0) + mu);
 }
 
+// The breakpoint problems of sections 4.2 and 4.4: the root mu of the decreasing, piecewise-affine
+// f(mu) = a S(mu) - b mu - c, S(mu) = sum_i (u_i - mu)_+ (u_i = |z_i| >= 0), given f(0) > 0 >
+// f(max u).  The paper sorts the breakpoints {0, u_i} and searches them; a thread instead tests
+// every breakpoint (O(n^2), all indices static so nothing leaves registers): with L the largest
+// breakpoint where f >= 0, the root lies in the affine piece after L, whose active set is
+// {i : u_i > L}, so a (sum_act u_i - m mu) - b mu - c = 0 gives mu directly.
+template <int NMAX>
+__device__ __forceinline__ double breakpoint_root(const double* u, int n, double a, double b, double c) {
+  double L = 0.0;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    if (k >= n) continue;
+    double S = 0.0;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+      if (i < n) S += fmax(u[i] - u[k], 0.0);
+    if (a * S - b * u[k] - c >= 0.0 && u[k] > L) L = u[k];
+  }
+  double sa = 0.0, m = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n && u[i] > L) { sa += u[i]; m += 1.0; }
+  return (a * sa - c) / (a * m + b);
+}
+
+// prox of theta |.|_inf (section 4.2): z - pi(z), pi the projection onto the l1 ball of radius
+// theta; 0 inside it, else clamp(z, -mu, mu) with |shrink1(z, mu)|_1 = theta.  In place.
+template <int NMAX>
+__device__ __forceinline__ void linf_prox(int n, double theta, double* z) {
+  double u[NMAX], s1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) { u[i] = i < n ? fabs(z[i]) : 0.0; s1 += u[i]; }
+  if (!(s1 > theta)) {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) z[i] = 0.0;
+    return;
+  }
+  const double mu = breakpoint_root<NMAX>(u, n, 1.0, 0.0, theta);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) z[i] = fmin(fmax(z[i], -mu), mu);
+}
+
+// Update (3.4a) for a squared-norm J: v = prox of J* / lambda at w = d - b + x / lambda (in place).
+// J* = 1/2 |.|_1^2 (J = 1/2 |.|_inf^2): shrink1(w, beta), beta = |shrink1(w, beta)|_1 / lambda
+// (section 4.4).  J* = 1/2 |.|_inf^2 (J = 1/2 |.|_1^2): by Moreau's identity with the conjugate
+// (lambda / 2) |.|_1^2, w - shrink1(w, beta) = clamp(w, -beta, beta), beta = lambda |shrink1(w, beta)|_1.
+template <int NMAX>
+__device__ __forceinline__ void normsq_vupdate(int n, int jkind, double lam, double* w) {
+  double u[NMAX], s1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) { u[i] = i < n ? fabs(w[i]) : 0.0; s1 += u[i]; }
+  if (!(s1 > 0.0)) return;  // w = 0: the prox is 0
+  const double a = jkind == JK_LINFSQ ? 1.0 / lam : lam;
+  const double beta = breakpoint_root<NMAX>(u, n, a, 1.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    const double c = fmin(fmax(w[i], -beta), beta);
+    w[i] = jkind == JK_LINFSQ ? w[i] - c : c;
+  }
+}
+
+// For the persistent kernel below: one split-Bregman iteration (3.4a)-(3.4c) of one point and
+// copy, in place, for every kind of J and H of the per-thread path; returns the paper's stopping
+// test (section 4.5).
+template <int NMAX>
+__device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const double* xp, double* v, double* d,
+                                        double* b) {
+  const int n = pb.n;
+  const double lam = pb.lambda;
+  const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
+  double vn[NMAX], dn[NMAX];
+  double ss = 0.0;
+  if (pb.jkind == JK_QUAD) {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+      vn[i] = i < n ? pb.minv[i] * (xp[i] + lam * (d[i] - b[i])) : 0.0;  // (3.4a)
+  } else {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) vn[i] = i < n ? d[i] - b[i] + xp[i] / lam : 0.0;
+    normsq_vupdate<NMAX>(n, pb.jkind, lam, vn);                         // (3.4a), squared norm
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i >= n) { dn[i] = 0.0; continue; }
+    double z = vn[i] + b[i];
+    double s = z;
+    if (l1) {                                                 // (3.4b), shrink1
+      double a = th * (pb.w ? pb.w[i] : 1.0);
+      double m = fabs(z) - a;
+      s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
+    }
+    dn[i] = s;
+    ss += s * s;
+  }
+  if (l2) {                                                   // (3.4b), shrink2
+    double nr = sqrt(ss);
+    double f = nr > 0.0 ? fmax(nr - th, 0.0) / nr : 0.0;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) dn[i] *= f;
+  }
+  if (wl2) wl2_prox<NMAX>(n, pb.w, th, dn);                  // (3.4b), z - projection
+  if (pb.hkind == HK_LINF) linf_prox<NMAX>(n, th, dn);       // (3.4b), z - l1-ball projection
+  double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i >= n) continue;
+    b[i] = b[i] + vn[i] - dn[i];                              // (3.4c)
+    r1 += (vn[i] - v[i]) * (vn[i] - v[i]);
+    r2 += (dn[i] - d[i]) * (dn[i] - d[i]);
+    r3 += (dn[i] - vn[i]) * (dn[i] - vn[i]);
+    v[i] = vn[i]; d[i] = dn[i];
+  }
+  return r1 <= pb.tol && r2 <= pb.tol && r3 <= pb.tol;
+}
+
+// phi_k = <x', d> - J*(d) - t H(d)  (- 1/2 for an ellipsoid level set); J*(d) = 1/2 sum a_i d_i^2,
+// or the squared dual norm for the squared-norm initial data.  *H receives H(d).
+template <int NMAX>
+__device__ __forceinline__ double copy_value(const DiagProb& pb, double t, const double* xp, const double* d,
+                                             double* Hout) {
+  const int n = pb.n;
+  const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
+  const bool quad = pb.jkind == JK_QUAD;
+  double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0, dmax = 0.0, dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i >= n) continue;
+    xd += xp[i] * d[i];
+    if (quad) q += pb.adiag[i] * d[i] * d[i];
+    const double wi = pb.w ? pb.w[i] : 1.0;
+    h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
+    h2 += d[i] * d[i];
+    dmax = fmax(dmax, fabs(d[i]));
+    dsum += fabs(d[i]);
+  }
+  if (!quad) q = pb.jkind == JK_L1SQ ? dmax * dmax : dsum * dsum;
+  const double H = pb.hkind == HK_LINF ? dmax : wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
+  *Hout = H;
+  return xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
+}
+
+template <int NMAX>
+__device__ __forceinline__ void init_copy(const DiagProb& pb, const double* x, int k, double* xp, double* v,
+                                          double* d, double* b) {
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    xp[i] = (i < pb.n) ? x[i] - (pb.centres ? pb.centres[(size_t)k * pb.ld + i] : 0.0) : 0.0;
+    v[i] = xp[i]; d[i] = xp[i]; b[i] = 0.0;
+  }
+}
+
+// loads point j; false (and NaN outputs, iters = kstar = -1) for t <= 0 or non-finite input
+template <typename T, int NMAX>
+__device__ __forceinline__ bool load_point(const DiagProb& pb, int64_t j, double* x, double* t) {
+  const int n = pb.n;
+  const T* xj = (const T*)pb.x + j * n;
+  *t = (double)((const T*)pb.t)[j];
+  bool ok = *t > 0.0 && isfinite(*t);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    x[i] = i < n ? (double)xj[i] : 0.0;
+    if (i < n && !isfinite(x[i])) ok = false;
+  }
+  if (!ok) {
+    const T qn = (T)__builtin_nan("");
+    T* gj = (T*)pb.grad + j * n;
+    ((T*)pb.phi)[j] = qn; ((T*)pb.dphidt)[j] = qn;
+    for (int i = 0; i < n; ++i) gj[i] = qn;
+    if (pb.iters) pb.iters[j] = -1;
+    if (pb.kstar) pb.kstar[j] = -1;
+  }
+  return ok;
+}
+
+template <typename T, int NMAX>
+__device__ __forceinline__ void store_point(const DiagProb& pb, int64_t j, double best, double bh, int kbest,
+                                            int itbest, const double* pbest) {
+  T* gj = (T*)pb.grad + j * pb.n;
+  ((T*)pb.phi)[j] = (T)best;
+  ((T*)pb.dphidt)[j] = (T)(-bh);
+  for (int i = 0; i < pb.n; ++i) gj[i] = (T)pbest[i];
+  if (pb.iters) pb.iters[j] = itbest;
+  if (pb.kstar) pb.kstar[j] = kbest;
+}
+
+// One thread per point (the iteration counts of this family are short and uniform): the quadratic
+// diagonal J with the weighted l1 / l2 / ellipsoidal norms.
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,19 +341,82 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   if (pb.kstar) pb.kstar[j] = kbest;
 }
 
-template <typename T>
-static hipError_t launch_t(const DiagProb& pb, hipStream_t stream) {
-  const unsigned grid = (unsigned)((pb.npts + kBlock - 1) / kBlock);
-  if (pb.n <= 8) hipLaunchKernelGGL((diag_kernel<T, 8>), dim3(grid), dim3(kBlock), 0, stream, pb);
-  else if (pb.n <= 16) hipLaunchKernelGGL((diag_kernel<T, 16>), dim3(grid), dim3(kBlock), 0, stream, pb);
-  else if (pb.n <= 32) hipLaunchKernelGGL((diag_kernel<T, 32>), dim3(grid), dim3(kBlock), 0, stream, pb);
-  else return hipErrorInvalidValue;
+// The squared-norm initial data and H = |.|_inf: iteration counts vary over orders of magnitude
+// between points (the paper's ADMM is slow for these nonsmooth pairs), so one point per thread
+// would keep a whole wave waiting for its slowest lane.  Here every lane runs its own state
+// machine: each pass is one iteration of the lane's current (point, copy); a lane that finishes
+// a copy evaluates it, moves to the next copy or writes the point and takes the next one from a
+// global counter, without waiting for the rest of its wave.  The grid is persistent.
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(kBlock) diag_ext_kernel(DiagProb pb, int* __restrict__ counter) {
+  double x[NMAX], xp[NMAX], v[NMAX], d[NMAX], b[NMAX], pbest[NMAX];
+  double t = 0.0, th = 0.0, best = 0.0, bh = 0.0;
+  int64_t j = -1;
+  int k = 0, it = 0, kbest = -1, itbest = 0;
+  bool have = false;
+  auto fetch = [&]() {  // next valid point, or have = false
+    while (true) {
+      j = (int64_t)atomicAdd((unsigned int*)counter, 1u);  // unsigned: the overshoot past npts cannot wrap
+      if (j >= pb.npts) { have = false; return; }
+      if (load_point<T, NMAX>(pb, j, x, &t)) break;
+    }
+    have = true;
+    th = t / pb.lambda;
+    k = 0; it = 0; kbest = -1; itbest = 0; best = 0.0; bh = 0.0;
+    init_copy<NMAX>(pb, x, 0, xp, v, d, b);
+  };
+  fetch();
+  while (have) {
+    ++it;
+    const bool conv = sb_step<NMAX>(pb, th, xp, v, d, b);
+    if (conv || it >= pb.max_iter) {
+      double H;
+      const double val = copy_value<NMAX>(pb, t, xp, d, &H);
+      if (kbest < 0 || val < best) {
+        best = val; bh = H; kbest = k; itbest = conv ? it : -2;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
+      }
+      if (++k < pb.K) {
+        it = 0;
+        init_copy<NMAX>(pb, x, k, xp, v, d, b);
+      } else {
+        store_point<T, NMAX>(pb, j, best, bh, kbest, itbest, pbest);
+        fetch();
+      }
+    }
+  }
+}
+
+template <typename T, int NMAX>
+static hipError_t launch_n(const DiagProb& pb, bool ext, int* counter, int ncu, hipStream_t stream) {
+  if (!ext) {
+    const unsigned grid = (unsigned)((pb.npts + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((diag_kernel<T, NMAX>), dim3(grid), dim3(kBlock), 0, stream, pb);
+  } else {
+    // persistent: enough workgroups for the resident waves (at most 8 workgroups per CU)
+    const int64_t need = (pb.npts + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)std::min<int64_t>(need, (int64_t)8 * ncu);
+    hipError_t e = hipMemsetAsync(counter, 0, sizeof(int), stream);
+    if (e) return e;
+    hipLaunchKernelGGL((diag_ext_kernel<T, NMAX>), dim3(grid), dim3(kBlock), 0, stream, pb, counter);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DiagProb& pb, bool f64, hipStream_t stream) {
+template <typename T>
+static hipError_t launch_t(const DiagProb& pb, bool ext, int* counter, int ncu, hipStream_t stream) {
+  if (pb.n <= 8) return launch_n<T, 8>(pb, ext, counter, ncu, stream);
+  if (pb.n <= 16) return launch_n<T, 16>(pb, ext, counter, ncu, stream);
+  if (pb.n <= 32) return launch_n<T, 32>(pb, ext, counter, ncu, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_diag(const DiagProb& pb, bool f64, int* counter, int ncu, hipStream_t stream) {
   if (pb.npts == 0) return hipSuccess;
-  return f64 ? launch_t<double>(pb, stream) : launch_t<float>(pb, stream);
+  const bool ext = pb.jkind != JK_QUAD || pb.hkind == HK_LINF;
+  if (ext && (!counter || pb.npts > INT32_MAX)) return hipErrorInvalidValue;
+  return f64 ? launch_t<double>(pb, ext, counter, ncu, stream) : launch_t<float>(pb, ext, counter, ncu, stream);
 }
 
 }  // namespace hopf

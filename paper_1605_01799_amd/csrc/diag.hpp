@@ -7,6 +7,7 @@ constexpr int kDiagMaxN = 32;
 
 struct DiagProb {
   int n, ld, K, level_set, hkind, max_iter;  // ld: stride of the centre rows
+  int jkind;              // JK_QUAD: J = 1/2 sum y_i^2 / a_i; JK_L1SQ, JK_LINFSQ: squared norms
   double lambda, tol;
   const double* minv;     // n: 1 / (a_i + lambda)
   const double* adiag;    // n: a_i
@@ -17,6 +18,8 @@ struct DiagProb {
   void* phi; void* grad; void* dphidt; int32_t* iters; int32_t* kstar;
 };
 
-hipError_t launch_diag(const DiagProb& pb, bool f64, hipStream_t stream);
+// counter: one device int of scratch (the persistent kernel's point queue; reset here on the
+// stream), ncu: compute units of the device.
+hipError_t launch_diag(const DiagProb& pb, bool f64, int* counter, int ncu, hipStream_t stream);
 
 }  // namespace hopf

@@ -164,6 +164,16 @@ def workload_paper_a(n: int = 16, npts: int = 1 << 20) -> Problem:
                    spectrum=D.copy(), HA=HA)
 
 
+def workload_paper_norms(n: int = 16, npts: int = 1 << 20, hkind: str = "linf") -> Problem:
+    """The paper's timing tables for the squared-norm initial data (section 4.5; Table 5 is
+    J = 1/2 |y|_1^2 with H = |p|_inf): (x, t) uniform in [-10, 10]^n x (0, 10].  J is not part of
+    the record (the caller picks the squared norm); A is the identity placeholder."""
+    rng = rng_for(9, n)
+    x = rng.uniform(-10.0, 10.0, (npts, n))
+    t = 10.0 - rng.uniform(0.0, 10.0, npts)
+    return Problem(n=n, A=np.eye(n), hkind=hkind, w=None, x=x, t=t, A_is_diagonal=True, spectrum=np.ones(n))
+
+
 def workload3(npts: int = 1 << 16) -> Problem:
     return _dense_problem(3, 1024, 1 << 16, npts, "l2_wl1")
 
