@@ -146,8 +146,10 @@ template <typename TI, typename TO, bool TRANS>
 __global__ void __launch_bounds__(kBlock) rotate_rows_kernel(const TI* __restrict__ in, int64_t ld_in,
                                                              TO* __restrict__ out, int64_t ld_out,
                                                              const double* __restrict__ P, int n, int64_t rows) {
+  // P staged so that the threads of one point (consecutive output coordinates c) read
+  // consecutive LDS words: as is for P^T (column c), transposed for P (row c)
   __shared__ double sP[kRotMaxN * kRotMaxN];
-  for (int e = threadIdx.x; e < n * n; e += kBlock) sP[e] = P[e];
+  for (int e = threadIdx.x; e < n * n; e += kBlock) sP[e] = TRANS ? P[e] : P[(e % n) * n + e / n];
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= rows * n) return;
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(kBlock) rotate_rows_kernel(const TI* __restric
   if (TRANS) {
     for (int i = 0; i < n; ++i) s += sP[i * n + c] * (double)x[i];
   } else {
-    for (int a = 0; a < n; ++a) s += sP[c * n + a] * (double)x[a];
+    for (int a = 0; a < n; ++a) s += sP[a * n + c] * (double)x[a];
   }
   out[j * ld_out + c] = (TO)s;
 }
