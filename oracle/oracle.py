@@ -204,3 +204,36 @@ def oracle_backward(grad, kstar, t_h, gphi, K=1):
         sel = np.asarray(kstar) == k
         gc[k] = -(gphi[sel, None] * grad[sel]).sum(0)
     return dict(gx=gx, gt=gt, gA=gA, gc=gc)
+
+
+def oracle_control(A, x, t, grad, kstar=None, centres=None):
+    """Optimal-control read-out of section 2 (optimal control and HJ-PDE): the terminal value
+    x(T) = ybar, the Hopf-Lax minimiser, for which grad phi = p* lies in dJ(ybar) -- for the
+    quadratic J_k(y) = 1/2 (y - c_k)^T A^{-1} (y - c_k) that is ybar = c_k + A p* -- and the
+    control beta = (x - x(T)) / t, which is grad H(p*) wherever H is differentiable at p* (the
+    paper's beta = grad H(grad phi) and x(T) = x - t grad H(grad phi)), and otherwise the element of
+    dH(p*) that the optimality of p* selects (x' - A p* = t beta).  Definition written out."""
+    A = _f64(A)
+    x = _f64(x)
+    p = _f64(grad)
+    t = _f64(t).reshape(-1)
+    c = np.zeros_like(x)
+    if centres is not None:
+        C = _f64(centres).reshape(-1, x.shape[1])
+        c = C[np.zeros(x.shape[0], np.int64) if kstar is None else np.asarray(kstar)]
+    xT = c + p @ A.T
+    beta = (x - xT) / t[:, None]
+    return dict(beta=beta, xT=xT)
+
+
+def oracle_max_over_hamiltonians(A, x, t, hkinds, ws=None, **kw):
+    """The min-of-Hamiltonians fact of section 2 (extensions): phi for H = min_i H_i with one
+    convex J is max_i phi_i, each phi_i the Hopf value for H_i; grad phi and dphi/dt are those of
+    the attaining i (the lowest index on ties).  Definition written out over oracle_eval."""
+    ws = ws if ws is not None else [None] * len(hkinds)
+    rs = [oracle_eval(A, x, t, hk, w=w, **kw) for hk, w in zip(hkinds, ws)]
+    phis = np.stack([r["phi"] for r in rs])
+    istar = np.argmax(phis, axis=0)
+    j = np.arange(phis.shape[1])
+    return dict(phi=phis[istar, j], grad=np.stack([r["grad"] for r in rs])[istar, j],
+                dphidt=np.stack([r["dphidt"] for r in rs])[istar, j], istar=istar.astype(np.int32))

@@ -170,3 +170,38 @@ def test_mutant_is_caught(oracle_lib, name):
     with tempfile.TemporaryDirectory() as d:
         lib = _compile(src.replace(old, new), d, "m_" + name)
         assert battery(lib), "planted mistake %s not caught" % name
+
+
+def test_control_mistakes_are_caught(oracle_lib):
+    """Planted mistakes in the control read-out (written in Python): a flipped sign of A p*, a
+    transposed A, a dropped centre, the control's sign: each breaks a pin of the read-out."""
+    from tests.test_oracle_pins import in_wulff
+    rng = np.random.default_rng(71)
+    n, K = 6, 2
+    Q = np.linalg.qr(rng.normal(size=(n, n)))[0]
+    A = (Q * rng.uniform(0.2, 5, n)) @ Q.T
+    A = 0.5 * (A + A.T)
+    N = rng.normal(size=(n, n))          # a non-symmetric perturbation for the transposed variant
+    w = rng.uniform(0.5, 2, n)
+    C = rng.normal(0, 2, (K, n))
+    x = rng.normal(0, 3, (20, n))
+    t = rng.uniform(0.1, 2, 20)
+    r = O.oracle_eval(A, x, t, "wl1", w=w, centres=C, level_set=True, tol=1e-26, max_iter=20000)
+    Ainv = np.linalg.inv(A)
+
+    def pins(xT, beta):
+        ok = True
+        for j in range(20):
+            u = xT[j] - C[r["kstar"][j]]
+            ok &= abs(0.5 * (u @ Ainv @ u - 1) - r["phi"][j]) <= 1e-8 * max(1, abs(r["phi"][j]))
+            ok &= bool(in_wulff(beta[j], "wl1", w))
+            ok &= abs(beta[j] @ r["grad"][j] + r["dphidt"][j]) <= 1e-8 * max(1, abs(r["dphidt"][j]))
+        return ok
+
+    good = O.oracle_control(A, x, t, r["grad"], r["kstar"], C)
+    assert pins(good["xT"], good["beta"])
+    c = C[r["kstar"]]
+    p = r["grad"]
+    for xT in (c - p @ A.T, p @ A.T, c + p @ (A + 0.1 * N)):
+        assert not pins(xT, (x - xT) / t[:, None])
+    assert not pins(good["xT"], -good["beta"])

@@ -322,6 +322,68 @@ def test_norm_family_certificates(oracle_lib, jk):
             assert np.all(r["phi"] <= np.array([NORM_J[jk](xx) for xx in x]) + 1e-10)
 
 
+# ---------------------------------------------------------------- control read-out, min of H
+def in_wulff(beta, hk, w, tol=1e-9):
+    """beta in C, the Wulff shape of H (H* = indicator of C)."""
+    if hk == "wl1":
+        return np.all(np.abs(beta) <= w + tol)
+    if hk == "l2":
+        return np.linalg.norm(beta) <= 1 + tol
+    if hk == "l2_wl1":   # Minkowski sum of the box |b_i| <= w_i and the unit ball
+        return np.linalg.norm(beta - np.clip(beta, -w, w)) <= 1 + tol
+    if hk == "wl2":
+        return np.sum(beta * beta / w) <= 1 + tol
+    raise ValueError(hk)
+
+
+@pytest.mark.parametrize("hk", ["wl1", "l2", "l2_wl1", "wl2"])
+def test_control_readout(oracle_lib, hk):
+    """Section 2 (optimal control): with beta the control and x(T) the terminal value, the Hopf-Lax
+    formula with H* the indicator of C gives phi(x, t) = J_k*(x(T)) with beta in C and
+    <beta, p*> = H(p*) (beta in dH(p*)); on a union of level sets, x(T) is measured from c_k*."""
+    rng = np.random.default_rng(61)
+    n, K = 8, 2
+    A = rand_spd(n, rng, 0.2, 5)
+    w = rng.uniform(0.5, 2, n)
+    C = rng.normal(0, 2, (K, n))
+    x = rng.normal(0, 3, (40, n))
+    t = rng.uniform(0.05, 3, 40)
+    r = oracle_lib.oracle_eval(A, x, t, hk, w=w, centres=C, level_set=True, tol=TOL)
+    c = oracle_lib.oracle_control(A, x, t, r["grad"], r["kstar"], C)
+    Ainv = np.linalg.inv(A)
+    for j in range(40):
+        u = c["xT"][j] - C[r["kstar"][j]]
+        assert abs(0.5 * (u @ Ainv @ u - 1) - r["phi"][j]) <= 1e-10 * max(1, abs(r["phi"][j]))
+        assert in_wulff(c["beta"][j], hk, w)
+        assert abs(c["beta"][j] @ r["grad"][j] + r["dphidt"][j]) <= 1e-9 * max(1, abs(r["dphidt"][j]))
+
+
+def test_max_over_hamiltonians(oracle_lib):
+    """Section 2 (extensions): for H = min_i H_i, phi = max_i phi_i.  Brute force at n = 2 of the
+    non-convex min over u of J*(u) + t min_i H_i(u) - <u, x>, and the PDE at the attaining i:
+    H_i*(grad phi) = min_i H_i(grad phi)."""
+    rng = np.random.default_rng(62)
+    A = rand_spd(2, rng)
+    w1, w2 = np.array([0.3, 1.8]), np.array([1.7, 0.4])
+    Hs = [lambda p: np.sum(w1 * np.abs(p)), lambda p: np.sum(w2 * np.abs(p))]
+    x = rng.normal(0, 3, (12, 2))
+    t = rng.uniform(0.1, 2, 12)
+    m = oracle_lib.oracle_max_over_hamiltonians(A, x, t, ["wl1", "wl1"], ws=[w1, w2], tol=TOL)
+    assert len(set(m["istar"].tolist())) == 2   # both Hamiltonians attain somewhere
+    for j in range(12):
+        F = lambda p: 0.5 * p @ A @ p + t[j] * min(H(p) for H in Hs) - x[j] @ p
+        c, rad = np.zeros(2), 8.0
+        for _ in range(14):
+            g = np.linspace(-rad, rad, 81)
+            vals = np.array([[F(c + np.array([a, b])) for b in g] for a in g])
+            i = np.unravel_index(np.argmin(vals), vals.shape)
+            c = c + np.array([g[i[0]], g[i[1]]])
+            rad /= 4.0
+        assert abs(-m["phi"][j] - F(c)) <= 1e-8 * max(1, abs(F(c)))
+        p = m["grad"][j]
+        assert Hs[m["istar"][j]](p) <= min(H(p) for H in Hs) + 1e-9
+
+
 # ---------------------------------------------------------------- brute force
 @pytest.mark.parametrize("hkind", ["wl1", "l2", "l2_wl1", "wl2"])
 def test_brute_force_n2(oracle_lib, hkind):
