@@ -195,6 +195,25 @@ hopf_status hopf_backward(hopf_problem_t problem, int64_t npts, const void* gphi
                           const int32_t* kstar_saved, void* gx, void* gt, void* gA, void* gc,
                           void* stream);
 
+/* Optimal-control read-out (section 2, optimal control): from the points x (npts*n), times t
+ * (npts) and an evaluation's grad (npts*n, p*) and kstar (npts; nullable when K = 1), writes the
+ * terminal value xT = c_k* + A p* (the Hopf-Lax minimiser, where p* is a subgradient of J_k*) and
+ * the control beta = (x - xT) / t, which equals grad H(p*) wherever H is differentiable at p*
+ * (otherwise it is the subgradient of H at p* that the optimality of p* selects).  Needs the
+ * quadratic J; I/O in the problem's precision (double for HOPF_F64).  Points with kstar < 0
+ * (invalid inputs) get NaN.  A dense A is held in FP32 for this read-out. */
+hopf_status hopf_control(hopf_problem_t problem, int64_t npts, const void* x, const void* t, const void* grad,
+                         const int32_t* kstar, void* beta, void* xT, void* stream);
+
+/* The minimum of Hamiltonians (section 2, extensions): for one J and Hamiltonians H_1..H_k
+ * (k <= 16), phi for H = min_i H_i is max_i phi_i.  Given the k evaluations of the same npts
+ * points (host arrays of k device pointers: phi_i (npts), grad_i (npts*n), dphidt_i (npts)),
+ * writes phi = max_i phi_i and the grad and dphidt of the attaining i (lowest index on ties), and
+ * istar (npts, nullable).  f64 != 0: double arrays, else float. */
+hopf_status hopf_max_over_hamiltonians(int32_t k, int64_t npts, int32_t n, int32_t f64, const void* const* phis,
+                                       const void* const* grads, const void* const* dphidts, void* phi,
+                                       void* grad, void* dphidt, int32_t* istar, void* stream);
+
 /* Device-side factor of the problem, for inspection and tests: copies
  * M = (A + lambda I)^{-1} (n*n, row-major, FP64) to the host array out.  For a HOPF_H_AL2
  * problem this is the factor of the problem in HA's eigenbasis, (P^T A P + lambda I)^{-1}. */

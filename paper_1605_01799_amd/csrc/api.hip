@@ -16,6 +16,7 @@
 #include "backward.hpp"
 #include "common.hpp"
 #include "dense.hpp"
+#include "control.hpp"
 #include "diag.hpp"
 #include "rotate.hpp"
 #include "setup.hpp"
@@ -66,6 +67,8 @@ struct hopf_problem {
   // HOPF_H_AL2: eigenvectors P of HA (n x n, FP64); the problem is held in HA's eigenbasis
   // (A' = P^T A P, weights = eigenvalues, centres P^T c) and points are rotated in and out
   double* d_HP = nullptr;
+  float* d_Af = nullptr;          // dense A (n x n, FP32, original basis) for the control read-out
+  double* d_centres0 = nullptr;   // HOPF_H_AL2: the centres in the original basis (K x n_pad)
 };
 
 // ---------------------------------------------------------------------------
@@ -214,7 +217,7 @@ static hopf_status validate(const hopf_problem_desc* d) {
 
 static void free_problem(hopf_problem* p) {
   hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
-  hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP);
+  hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP); hipFree(p->d_Af); hipFree(p->d_centres0);
   delete p;
 }
 
@@ -331,6 +334,22 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     if (hipMemcpy(dA, srcA, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice)) {
       hipFree(dA); hipFree(S);
       return bail(fail(HOPF_EDEVICE, "copy A"));
+    }
+    {  // FP32 copy of A in the caller's basis, for the control read-out
+      std::vector<float> af((size_t)n * n);
+      for (size_t i = 0; i < af.size(); ++i) af[i] = (float)srcA[i];
+      if (hipMalloc(&p->d_Af, sizeof(float) * af.size()) ||
+          hipMemcpy(p->d_Af, af.data(), sizeof(float) * af.size(), hipMemcpyHostToDevice)) {
+        hipFree(dA); hipFree(S);
+        return bail(fail(HOPF_ENOMEM, "FP32 copy of A"));
+      }
+    }
+    if (al2 && p->d_centres) {
+      const size_t cb = sizeof(double) * (size_t)p->K * n_pad;
+      if (hipMalloc(&p->d_centres0, cb) || hipMemcpy(p->d_centres0, p->d_centres, cb, hipMemcpyDeviceToDevice)) {
+        hipFree(dA); hipFree(S);
+        return bail(fail(HOPF_ENOMEM, "copy of the centres"));
+      }
     }
     if (al2) {
       hopf_status rs = rotate_problem(p, d, dA, stream);
@@ -682,6 +701,44 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
   v.x = (const float*)x; v.t = (const float*)t; v.npts = npts;
   v.phi = (float*)phi; v.grad = (float*)grad; v.dphidt = (float*)dphidt; v.iters = iters; v.kstar = kstar;
   return run_dense_rotated(calls, mode_of(p), 0, s);
+}
+
+extern "C" hopf_status hopf_control(hopf_problem_t p, int64_t npts, const void* x, const void* t, const void* grad,
+                                    const int32_t* kstar, void* beta, void* xT, void* stream) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "the control read-out needs the quadratic J");
+  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (npts == 0) return HOPF_OK;
+  if (!x || !t || !grad || !beta || !xT) return fail(HOPF_EINVAL, "NULL array argument");
+  if (p->K > 1 && !kstar) return fail(HOPF_EINVAL, "kstar is required when K > 1");
+  ControlArgs a;
+  a.n = p->n; a.npts = npts; a.kstar = kstar;
+  a.Af = p->diagonal ? nullptr : p->d_Af;
+  a.adiag = p->d_adiag;
+  a.centres = p->d_centres0 ? p->d_centres0 : p->d_centres;
+  a.ldc = p->n_pad;
+  hipError_t e = launch_control(a, p->precision == HOPF_F64, x, t, grad, beta, xT, (hipStream_t)stream);
+  if (e) return fail(HOPF_EDEVICE, "control launch: %s", hipGetErrorString(e));
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_max_over_hamiltonians(int32_t k, int64_t npts, int32_t n, int32_t f64,
+                                                  const void* const* phis, const void* const* grads,
+                                                  const void* const* dphidts, void* phi, void* grad, void* dphidt,
+                                                  int32_t* istar, void* stream) {
+  if (k < 1 || k > kMaxHamiltonians) return fail(HOPF_EINVAL, "k = %d outside [1, %d]", k, kMaxHamiltonians);
+  if (npts < 0 || n < 1) return fail(HOPF_EINVAL, "bad sizes");
+  if (npts == 0) return HOPF_OK;
+  if (!phis || !grads || !dphidts || !phi || !grad || !dphidt) return fail(HOPF_EINVAL, "NULL array argument");
+  MaxHArgs a;
+  a.k = k; a.n = n; a.npts = npts;
+  for (int i = 0; i < k; ++i) {
+    if (!phis[i] || !grads[i] || !dphidts[i]) return fail(HOPF_EINVAL, "NULL input %d", i);
+    a.phi[i] = phis[i]; a.grad[i] = grads[i]; a.dphidt[i] = dphidts[i];
+  }
+  hipError_t e = launch_max_h(a, f64 != 0, phi, grad, dphidt, istar, (hipStream_t)stream);
+  if (e) return fail(HOPF_EDEVICE, "max launch: %s", hipGetErrorString(e));
+  return HOPF_OK;
 }
 
 extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const void* y, double s_tol,

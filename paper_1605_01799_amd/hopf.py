@@ -179,6 +179,19 @@ class Problem:
                                       _ptr(out.get("gc")), _stream_ptr(stream)))
         return out
 
+    def control(self, x, t, grad, kstar=None, stream=None):
+        """Optimal control beta and terminal value xT of each point from an evaluation's grad and
+        kstar (C ABI hopf_control)."""
+        npts = x.shape[0]
+        x = _device_array(x, self.io_dtype, "x", (npts, self.n))
+        t = _device_array(t, self.io_dtype, "t", (npts,))
+        grad = _device_array(grad, self.io_dtype, "grad", (npts, self.n))
+        out = dict(beta=torch.empty(npts, self.n, dtype=self.io_dtype, device=x.device),
+                   xT=torch.empty(npts, self.n, dtype=self.io_dtype, device=x.device))
+        check(self._lib.hopf_control(self._handle, npts, _ptr(x), _ptr(t), _ptr(grad), _ptr(kstar),
+                                     _ptr(out["beta"]), _ptr(out["xT"]), _stream_ptr(stream)))
+        return out
+
     def inverse(self) -> np.ndarray:
         out = np.empty((self.n, self.n))
         check(self._lib.hopf_problem_get_inverse(self._handle, out.ctypes.data))
@@ -216,6 +229,27 @@ def eval_ragged(problems: Sequence[Problem], xs: Sequence[torch.Tensor], ts: Seq
         grads.append(grad[o:o + c * p.n].view(c, p.n))
         o += c * p.n
     return dict(phi=phi, grad=grads, dphidt=dphidt, iters=iters, kstar=kstar, offsets=off)
+
+
+def max_over_hamiltonians(outs: Sequence[dict], stream=None):
+    """phi for H = min_i H_i from the evaluations outs[i] (same points, same J, Hamiltonian H_i):
+    max_i phi_i with the grad and dphidt of the attaining i (C ABI hopf_max_over_hamiltonians)."""
+    lib = _lib.load()
+    k = len(outs)
+    npts, n = outs[0]["grad"].shape
+    dt = outs[0]["phi"].dtype
+    for o in outs:
+        for key in ("phi", "grad", "dphidt"):
+            if o[key].dtype != dt or not o[key].is_contiguous():
+                raise ValueError("the evaluations must share one dtype and be contiguous")
+    arr = lambda key: (ctypes.c_void_p * k)(*[o[key].data_ptr() for o in outs])
+    dev = outs[0]["phi"].device
+    res = dict(phi=torch.empty(npts, dtype=dt, device=dev), grad=torch.empty(npts, n, dtype=dt, device=dev),
+               dphidt=torch.empty(npts, dtype=dt, device=dev), istar=torch.empty(npts, dtype=torch.int32, device=dev))
+    check(lib.hopf_max_over_hamiltonians(k, npts, n, int(dt == torch.float64), arr("phi"), arr("grad"), arr("dphidt"),
+                                         _ptr(res["phi"]), _ptr(res["grad"]), _ptr(res["dphidt"]), _ptr(res["istar"]),
+                                         _stream_ptr(stream)))
+    return res
 
 
 class HopfValue(torch.autograd.Function):
