@@ -13,6 +13,7 @@
 //
 // Columns are (point, copy) pairs; a wave takes chunks of whole points from the launch's queue,
 // so the copies of a point are settled by one wave, in column order.
+#include <cstdint>
 #include <type_traits>
 
 #include "common.hpp"
@@ -122,19 +123,42 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     const bool has_l1 = hk_has_l1(hkind), has_l2 = hk_has_l2(hkind);
 
     // ============================================================ settle finished columns
-    int any_fin = 0, any_empty = 0;
+    // Lanes 0..15 stand for the 16 columns of each tile in the ballots below (lane lr of row
+    // group 0).  With one copy per point the finished columns write their results in parallel;
+    // with several copies they are settled one at a time in column order (the per-point best is
+    // read, compared and written back).
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      any_fin |= (st[ct] == COL_DONE || st[ct] == COL_INVALID) ? 1 : 0;
-      any_empty |= st[ct] == COL_EMPTY ? 1 : 0;
-    }
-    any_fin = __any(any_fin);
+      const bool fin = st[ct] == COL_DONE || st[ct] == COL_INVALID;
+      uint64_t fmask = __ballot(fin && lg == 0) & 0xffffull;
+      if (!fmask) continue;
+      if (K == 1) {
+        if (fin) {  // the column's four lanes: its p rows; row group 0 also the scalars
+          const int j = jj[ct];
+          const bool bad = st[ct] == COL_INVALID;
+          HOPF_GLOBAL float* g = gp(pb.grad + (size_t)j * n);
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      if (!any_fin) break;  // most passes finish no column
-      for (int c0 = 0; c0 < 16; ++c0) {  // the columns in column order
+          for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * rt + 4 * lg + q;
+              if (rt < nrt && row < n) g[row] = bad ? __builtin_nanf("") : z[rt][ct][q];
+            }
+          }
+          if (lg == 0) {
+            pb.phi[j] = bad ? __builtin_nanf("") : (float)phi[ct];
+            pb.dphidt[j] = bad ? __builtin_nanf("") : (float)(-hp[ct]);
+            if (pb.iters) pb.iters[j] = bad ? -1 : ((flags[ct] & FLAG_CAPPED) ? -2 : iters[ct]);
+            if (pb.kstar) pb.kstar[j] = bad ? -1 : 0;
+          }
+          st[ct] = COL_EMPTY;
+        }
+        continue;
+      }
+      while (fmask) {  // in column order
+        const int c0 = __builtin_ctzll(fmask);
+        fmask &= fmask - 1;
         const int s = uni(__shfl(st[ct], c0));
-        if (s != COL_DONE && s != COL_INVALID) continue;
         // the column's scalars, broadcast by every lane (no lane may be inactive in a shuffle)
         const int j = __shfl(jj[ct], c0), k = __shfl(kk[ct], c0);
         const double key = __shfl(phi[ct], c0), hpk = __shfl(hp[ct], c0);
@@ -177,15 +201,17 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     }
 
     // ============================================================ refill empty columns
+    // The queue positions are handed out in column order by a scalar loop; then every refilled
+    // column loads its point at once (one memory latency per refill, whatever the count).
     int live = 0;
-    any_empty = __any(any_empty | any_fin);  // settled columns are empty now
-    if (!any_empty) live = 1;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      if (!any_empty) break;
-      for (int c0 = 0; c0 < 16; ++c0) {
-        const int s = uni(__shfl(st[ct], c0));
-        if (s != COL_EMPTY) { live = 1; continue; }
+      uint64_t emask = __ballot(st[ct] == COL_EMPTY && lg == 0) & 0xffffull;
+      if (emask != 0xffffull) live = 1;
+      int mycol = -1;
+      while (emask) {
+        const int c0 = __builtin_ctzll(emask);
+        emask &= emask - 1;
         while (nextcol >= cend && pending < 0 && !nomore) {
           int nc = 0;
           if (l == 0) nc = atomicAdd(chunk_counter, 1);
@@ -194,38 +220,39 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
           if (uni(chunks[nc].prob) == prob) { nextcol = uni(chunks[nc].col0); cend = nextcol + uni(chunks[nc].ncols); }
           else pending = nc;
         }
-        if (nextcol >= cend) continue;
-        const int col = nextcol++;
+        if (nextcol >= cend) break;  // nothing more for this problem
+        if (lr == c0) mycol = nextcol;
+        ++nextcol;
         live = 1;
-        if (lr == c0) {  // the column's four lanes take the new (point, copy)
-          const int j = col / K, k = col % K;
-          jj[ct] = j; kk[ct] = k;
-          const float tv = pb.t[j];
-          const bool tok = tv > 0.f && isfinite(tv);
-          thr[ct] = (float)((double)tv / pb.lambda);
-          gam[ct] = 1.f; iters[ct] = 0; stall[ct] = 0; flags[ct] = FLAG_FIRST;
-          prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
-          const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
-          const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
-          bool nf = false;
+      }
+      if (mycol >= 0) {  // the column's four lanes take the new (point, copy)
+        const int j = mycol / K, k = mycol % K;
+        jj[ct] = j; kk[ct] = k;
+        const float tv = pb.t[j];
+        const bool tok = tv > 0.f && isfinite(tv);
+        thr[ct] = (float)((double)tv / pb.lambda);
+        gam[ct] = 1.f; iters[ct] = 0; stall[ct] = 0; flags[ct] = FLAG_FIRST;
+        prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
+        const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
+        const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
+        bool nf = false;
 #pragma unroll
-          for (int rt = 0; rt < RTM; ++rt) {
+        for (int rt = 0; rt < RTM; ++rt) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int row = 16 * rt + 4 * lg + q;
-              float v = 0.f;
-              if (rt < nrt && row < n) {
-                const float xv = xj[row];
-                if (!isfinite(xv)) nf = true;
-                v = (float)((double)xv - (cen ? cen[row] : 0.0));
-              }
-              xp[rt][ct][q] = v;
-              z[rt][ct][q] = v;
+          for (int q = 0; q < 4; ++q) {
+            const int row = 16 * rt + 4 * lg + q;
+            float v = 0.f;
+            if (rt < nrt && row < n) {
+              const float xv = xj[row];
+              if (!isfinite(xv)) nf = true;
+              v = (float)((double)xv - (cen ? cen[row] : 0.0));
             }
+            xp[rt][ct][q] = v;
+            z[rt][ct][q] = v;
           }
-          st[ct] = tok ? COL_ACTIVE : COL_INVALID;
-          if (nf) st[ct] = COL_INVALID;  // combined over the column's lanes below
         }
+        st[ct] = tok ? COL_ACTIVE : COL_INVALID;
+        if (nf) st[ct] = COL_INVALID;  // combined over the column's lanes below
       }
     }
 #pragma unroll
