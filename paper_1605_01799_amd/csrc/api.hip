@@ -504,6 +504,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   if (st) return st;
   std::lock_guard<std::mutex> lk(w->mu);
   const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
+  // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
+  const int anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
   if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
   // per-point best arrays for every point of the call
   int64_t tot = 0;
@@ -593,7 +595,7 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
                                               stream)
                          : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
                                         w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
-                                        stream);
+                                        anchor_wait, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
     ++cls;
     // the next class reuses the metadata/staging buffers and the workspace: wait for this one

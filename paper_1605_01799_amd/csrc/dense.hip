@@ -50,7 +50,7 @@ template <int MODE, int CT, int RG, int OCC, int NW>
 __global__ void __launch_bounds__(NW * 64, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
-             int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every) {
+             int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every, int anchor_wait) {
   constexpr int PT = 16 * CT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ ColShared<PT, NW> S;
@@ -213,17 +213,32 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         }
         __syncthreads();  // the staging is complete (written and read by this workgroup only)
         constexpr int RGA = CT >= 4 ? (NW == 8 ? 1 : 2) : RG;  // row tiles per FP64 product pass
+        // the staging streams through LDS in blocks of kb rows of all PT columns (the BF16
+        // right-hand-side buffer is free during an anchor); every wave takes part in every block,
+        // also a wave without row tiles in the last pass
+        const int kbm = anchor_kb(n_pad), ldb64 = kbm + 2;
+        double* const Bl = (double*)lds_raw;
         for (int rt0 = 0; rt0 < RT; rt0 += NW * RGA) {
           int rt[RGA]; int nrt = 0;
 #pragma unroll
           for (int r = 0; r < RGA; ++r) { rt[r] = rt0 + wave + NW * r; if (rt[r] < RT) nrt = r + 1; }
-          if (nrt == 0) continue;  // wave-uniform
           f64x4 acc[RGA][CT];
 #pragma unroll
           for (int r = 0; r < RGA; ++r)
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-          gemm_f64<RGA, CT>(pb.Md, n_pad, ra, rt, nrt, acc);
+          for (int k0 = 0; k0 < n_pad; k0 += kbm) {
+            const int kb = n_pad - k0 < kbm ? n_pad - k0 : kbm;  // a multiple of 16
+            const int hu = kb >> 1;                               // 16-byte units per column
+            __syncthreads();  // the previous block is consumed
+            for (int u = tid; u < PT * hu; u += NW * 64) {
+              const int c = u / hu, off = 2 * (u - c * hu);
+              *(f64x2*)(Bl + c * ldb64 + off) = *gp((const f64x2*)(ra + (size_t)c * n_pad + k0 + off));
+            }
+            __syncthreads();
+            if (nrt > 0) gemm_f64_lds<RGA, CT>(pb.Md, n_pad, k0, kb, Bl, ldb64, rt, nrt, acc);
+          }
+          if (nrt == 0) continue;  // wave-uniform (after the last barrier of the pass)
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const int c = 16 * ct + (l & 15);
@@ -259,11 +274,43 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     }
 
     // ================================================================ flush finished slots
-    // Thread 0 settles the outputs of every finished slot in slot order (the best copy of a
-    // point so far, lowest copy index on ties), marking the slot whose p is to be written; then
-    // all threads copy those vectors.  Copies of one point live in one workgroup, so the best
-    // value of a point is only ever compared here, by this thread.
-    if (tid == 0) {
+    // With one copy per point (and no distance), each finished slot writes its own scalars (its
+    // p was written to the output by its value iteration); only invalid slots are left for the
+    // copy pass below, which writes their NaN rows.
+    // Otherwise thread 0 settles the outputs of every finished slot in slot order (the best copy
+    // of a point so far, lowest copy index on ties), marking the slot whose p is to be written;
+    // then all threads copy those vectors.  Copies of one point live in one workgroup, so the
+    // best value of a point is only ever compared here, by this thread.
+    const bool single = pb.K == 1 && !distance;
+    if (single) {
+      int nan_rows = 0;
+      if (tid < PT) {
+        const int c = tid;
+        const int st = S.state[c];
+        int better = 0;
+        if (st == COL_DONE || st == COL_INVALID) {
+          const int64_t j = S.j[c];
+          const float qnan = __builtin_nanf("");
+          if (st == COL_INVALID) {
+            better = 2;
+            pb.phi[j] = qnan; pb.dphidt[j] = qnan;
+            if (pb.iters) pb.iters[j] = -1;
+            if (pb.kstar) pb.kstar[j] = -1;
+          } else {
+            pb.phi[j] = (float)S.phi[c];
+            pb.dphidt[j] = (float)(-S.hp[c]);
+            if (pb.iters) pb.iters[j] = (S.flags[c] & FLAG_CAPPED) ? -2 : S.iters[c];
+            if (pb.kstar) pb.kstar[j] = 0;
+            S.state[c] = COL_EMPTY;
+          }
+        }
+        S.better[c] = better;
+        nan_rows = better == 2;
+      }
+      if (tid == 0) S.ctl[CTL_BETTER] = 0;
+      __syncthreads();
+      if (nan_rows) S.ctl[CTL_BETTER] = 1;  // benign race: every writer stores 1
+    } else if (tid == 0) {
       int any = 0;
       for (int c = 0; c < PT; ++c) {
         S.better[c] = 0;
@@ -616,7 +663,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 pv[q] = (float)d;
               }
               value_sums(S.redv[c], v2, v3, v4, v5);
-              st_nt4(pout + e, pv);
+              if (single) store_grad(pb.grad + (size_t)S.j[c] * n, row0, n, pv);
+              else st_nt4(pout + e, pv);
             }
             st_nt4(dz + et, dzv);
           } else {
@@ -663,7 +711,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 pv[q] = (float)d;
               }
               value_sums(S.redv[c], v2, v3, v4, v5);
-              st_nt4(pout + e, pv);
+              if (single) store_grad(pb.grad + (size_t)S.j[c] * n, row0, n, pv);
+              else st_nt4(pout + e, pv);
             }
           }
         }
@@ -771,7 +820,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       }
       if (MODE == 1) {
         const int kn = k_it + 1;
-        if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0))
+        if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0) ||
+            (anchor_wait > 0 && nwait >= anchor_wait))
           S.ctl[CTL_ANCHOR] = 1;
       }
     }
@@ -803,7 +853,8 @@ DenseVariant dense_variant(int mode, int n_pad) {
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_variant(mode, n_pad).pt;
-  if (mode == 1) return (size_t)pt * (n_pad + 8) * 2;
+  // refined: the BF16 right-hand sides, or an FP64 block of the anchor products
+  if (mode == 1) return std::max((size_t)pt * (n_pad + 8) * 2, (size_t)pt * (anchor_kb(n_pad) + 2) * 8);
   return (size_t)pt * (n_pad + 4) * 4;
 }
 
@@ -823,7 +874,7 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
 template <int MODE, int CT, int RG, int OCC, int NW>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
-                           int distance, int anchor_every, hipStream_t stream) {
+                           int distance, int anchor_every, int anchor_wait, hipStream_t stream) {
   auto kern = dense_kernel<MODE, CT, RG, OCC, NW>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -833,17 +884,18 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
     attr_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
-                     ws_per_wg, ws64_per_wg, distance, anchor_every);
+                     ws_per_wg, ws64_per_wg, distance, anchor_every, anchor_wait);
   return hipGetLastError();
 }
 
 hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream) {
+                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
+                        hipStream_t stream) {
   const int ct = var.pt / 16, occ = var.occ, nw = var.nw;
 #define HOPF_LAUNCH(M, C, R, O, W)                                                                                  \
   return launch_t<M, C, R, O, W>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
-                                 distance, anchor_every, stream)
+                                 distance, anchor_every, anchor_wait, stream)
   if (mode == 1) {
     if (nw == 8 && ct == 4) HOPF_LAUNCH(1, 4, 2, 1, 8);
     if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4);

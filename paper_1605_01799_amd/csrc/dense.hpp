@@ -15,7 +15,8 @@ size_t dense_lds_bytes(int mode, int n_pad);
 hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npts, hipStream_t stream);
 hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, hipStream_t stream);
+                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
+                        hipStream_t stream);
 
 // Small problems (dense_small.hip): FP32 evaluation of n_pad <= 64, one wave per 64-column tile
 // with the iteration in registers.

@@ -122,48 +122,72 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
   }
 }
 
-// FP64: acc[r][c] += M[16 rt_r .., :] * B[:, 16 c ..] with the right-hand sides B in global
-// memory, column-major (column c at B + c n_pad).  A rows are loaded in the order
-// 4(rho%4) + rho/4 so that the output lands in the lane layout of the FP32/BF16 16x16 products:
-// lane l, register i -> row 4(l/16) + i, column l%16.  Operands stream one k-step ahead.
-template <int RG, int CT>
-__device__ __forceinline__ void gemm_f64(const double* __restrict__ M, int n_pad, const double* B,
-                                         const int* rt, int nrt, f64x4 (&acc)[RG][CT]) {
+// Rows of B per LDS block of the FP64 anchor products (gemm_f64_lds), and the block's leading
+// dimension; the refined kernel's dynamic LDS holds PT (kAnchorKB + 2) doubles.
+constexpr int kAnchorKB = 256;
+__host__ __device__ __forceinline__ int anchor_kb(int n_pad) { return n_pad < kAnchorKB ? n_pad : kAnchorKB; }
+
+// FP64 anchor products with the right-hand sides staged in LDS: acc[r][c] += M[16 rt_r .., k0 ..
+// k0 + kb) * B[k0 .. k0 + kb, 16 c ..], where Bl holds that block column-major (column j at
+// Bl + j ldb, 16-byte aligned).  A rows are loaded in the order 4(rho%4) + rho/4 so that the
+// output lands in the lane layout of the FP32/BF16 16x16 products (lane l, register i -> row
+// 4(l/16) + i, column l%16).  A (8 bytes per entry, not L2-resident) streams PF k-chunks of 16
+// ahead of the products; B comes from LDS.
+template <int RG, int CT, int PF = 3>
+__device__ __forceinline__ void gemm_f64_lds(const double* __restrict__ M, int n_pad, int k0, int kb,
+                                             const double* Bl, int ldb, const int* rt, int nrt,
+                                             f64x4 (&acc)[RG][CT]) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   const int arow_perm = 4 * (lr & 3) + (lr >> 2);
   const HOPF_GLOBAL f64x4* arow[RG];
-  const HOPF_GLOBAL f64x4* bcol[CT];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + 4 * lg));
+    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
+  const double* bcol = Bl + lr * ldb + 4 * lg;
+  const int nk = kb >> 4;
+  constexpr int NB = PF + 1;
+  f64x4 a[NB][RG];
 #pragma unroll
-  for (int c = 0; c < CT; ++c) bcol[c] = gp((const f64x4*)(B + (size_t)(16 * c + lr) * n_pad + 4 * lg));
-  f64x4 an[RG], bn[CT];
+  for (int u = 0; u < PF; ++u)
+    if (u < nk) {
 #pragma unroll
-  for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r]);
-#pragma unroll
-  for (int c = 0; c < CT; ++c) bn[c] = bcol[c][0];
-  for (int kk = 0; kk < n_pad; kk += 16) {
-    f64x4 a[RG], b[CT];
-#pragma unroll
-    for (int r = 0; r < RG; ++r) a[r] = an[r];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = bn[c];
-    if (kk + 16 < n_pad) {
-#pragma unroll
-      for (int r = 0; r < RG; ++r) an[r] = __builtin_nontemporal_load(arow[r] + (kk + 16) / 4);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) bn[c] = bcol[c][(kk + 16) / 4];
+      for (int r = 0; r < RG; ++r) a[u][r] = __builtin_nontemporal_load(arow[r] + 4 * u);
     }
+  for (int ks = 0; ks < nk; ks += NB) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int u = 0; u < NB; ++u) {
+      const int kk = ks + u;
+      if (kk < nk) {
+        if (kk + PF < nk) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r)
+          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = __builtin_nontemporal_load(arow[r] + 4 * (kk + PF));
+        }
+        f64x4 b[CT];
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
+        for (int c = 0; c < CT; ++c) {
+          const f64x2* bp = (const f64x2*)(bcol + 16 * c * ldb + 16 * kk);
+          const f64x2 b0 = bp[0], b1 = bp[1];
+          b[c] = f64x4{b0[0], b0[1], b1[0], b1[1]};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int r = 0; r < RG; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+              acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r][q], b[c][q], acc[r][c], 0, 0, 0);
+      }
+    }
   }
+}
+
+// p of a value iteration written straight to the output row g (rows row0 .. row0 + 3 below n):
+// a later value iteration of the same column, if the stopping test fails there, overwrites it.
+__device__ __forceinline__ void store_grad(float* g, int row0, int n, f32x4 pv) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (row0 + q < n) st_nt(g + row0 + q, pv[q]);
 }
 
 // Value sums of a value iteration, added by every lane that holds rows of the column (rare:
