@@ -62,6 +62,8 @@ struct hopf_problem {
   double* d_Md = nullptr;       // n_pad^2
   float* d_Mf = nullptr;        // n_pad^2 (F32 precision)
   __bf16* d_Mb = nullptr;       // n_pad^2 (BF16_REFINED precision)
+  int8_t* d_Mq = nullptr;       // BF16_REFINED: M in integer slices for the exact anchor products
+  int32_t* d_Mqe = nullptr;     // their row exponents
   double* d_adiag = nullptr;    // n (diagonal A)
   double* d_minv = nullptr;     // n (diagonal A)
   // HOPF_H_AL2: eigenvectors P of HA (n x n, FP64); the problem is held in HA's eigenbasis
@@ -217,6 +219,7 @@ static hopf_status validate(const hopf_problem_desc* d) {
 
 static void free_problem(hopf_problem* p) {
   hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
+  hipFree(p->d_Mq); hipFree(p->d_Mqe);
   hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP); hipFree(p->d_Af); hipFree(p->d_centres0);
   delete p;
 }
@@ -307,6 +310,9 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP32)"));
   if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
+  if (d->precision == HOPF_BF16_REFINED &&
+      (hipMalloc(&p->d_Mq, (size_t)kSlices * n_pad * pad64(n_pad)) || hipMalloc(&p->d_Mqe, sizeof(int32_t) * n_pad)))
+    return bail(fail(HOPF_ENOMEM, "hipMalloc M (slices)"));
   if (p->diagonal) {
     std::vector<double> a(n, 1.0);  // unused by the squared-norm initial data
     if (d->A && p->jkind == HOPF_J_QUADRATIC) for (int i = 0; i < n; ++i) a[i] = d->A[i];
@@ -315,6 +321,7 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     if (hipMemcpy(p->d_adiag, a.data(), sizeof(double) * n, hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy A"));
     e = launch_diag_inverse(p->d_adiag, n, n_pad, d->lambda, p->d_Md, p->d_Mf, p->d_Mb, p->d_minv, stream);
+    if (!e && p->d_Mq) e = launch_slice_rows(p->d_Md, n_pad, p->d_Mq, p->d_Mqe, stream);
     if (e) return bail(fail(HOPF_EDEVICE, "diag inverse: %s", hipGetErrorString(e)));
   } else {
     // A + lambda I in FP64 on the device; the Gauss-Jordan batch is run by the caller
@@ -409,6 +416,7 @@ static hopf_status factor_batch(std::vector<hopf_problem*>& dense, std::vector<d
   for (int r = 0; r < np && !e; ++r) {
     hopf_problem* p = dense[order[r]];
     e = launch_finalize_copies(S[order[r]], p->n, p->n_pad, p->d_Md, p->d_Mf, p->d_Mb, stream);
+    if (!e && p->d_Mq) e = launch_slice_rows(p->d_Md, p->n_pad, p->d_Mq, p->d_Mqe, stream);
   }
   std::vector<int> status(np, 0);
   if (!e) e = hipMemcpyAsync(status.data(), d_status, sizeof(int) * np, hipMemcpyDeviceToHost, stream);
@@ -578,7 +586,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     // the small kernel: four independent waves per workgroup, each taking chunks
     const int grid = small ? std::min((nchunks + 3) / 4, occ * w->ncu) : std::min(nchunks, occ * w->ncu);
     const int64_t ws_per_wg = small ? 0 : 4 * (int64_t)pt * max_npad;
-    const int64_t ws64_per_wg = (int64_t)pt * max_npad;
+    // FP64 anchor staging, then its integer slices (kSlices x pt x pad64 bytes)
+    const int64_t ws64_per_wg = (int64_t)pt * max_npad + (int64_t)kSlices * pt * pad64(max_npad) / 8;
     if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
     if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * ws64_per_wg * grid))) return st;
     size_t lds = 0;
@@ -610,7 +619,7 @@ static DenseProb make_view(hopf_problem* p) {
   v.n = p->n; v.n_pad = p->n_pad; v.K = p->K; v.level_set = p->level_set;
   v.hkind = p->hkind == HOPF_H_AL2 ? HK_WL2 : p->hkind;  // in HA's eigenbasis
   v.max_iter = p->max_iter; v.lambda = p->lambda; v.tol = p->tol;
-  v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.w = p->d_w; v.wf = p->d_wf; v.centres = p->d_centres;
+  v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.Mq = p->d_Mq; v.Mqe = p->d_Mqe; v.w = p->d_w; v.wf = p->d_wf; v.centres = p->d_centres;
   v.max_newton = 50;
   return v;
 }

@@ -9,6 +9,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 
@@ -58,6 +59,23 @@ enum { JK_QUAD = 0, JK_L1SQ = 1, JK_LINFSQ = 2 };
 __host__ __device__ inline bool hk_has_l1(int hk) { return hk == HK_WL1 || hk == HK_L2_WL1; }
 __host__ __device__ inline bool hk_has_l2(int hk) { return hk == HK_L2 || hk == HK_L2_WL1; }
 
+// Exact products of the refined solver's anchors: M and the anchor right-hand sides are split into
+// kSlices signed 7-bit integer slices under a power-of-two scale per row (per column), x =
+// 2^e sum_a m_a 2^{-7a} with |m_a| <= 64, and the slice products run as int8 MFMAs with exact int32
+// accumulation.  slice_exponent(max |x|) is the e of a row or column: max |x| < 2^(e - 1), so the
+// scaled values lie in (-1/2, 1/2) and every rounded slice fits in [-64, 64].
+constexpr int kSlices = 6;
+__host__ __device__ inline int slice_exponent(double maxabs) {
+  if (!(maxabs > 0.0)) return 0;
+  int e = 0;
+  (void)frexp(maxabs, &e);  // maxabs = f 2^e, f in [0.5, 1)
+  return e + 1;
+}
+// Units of 16 bytes of the sliced M in the int8 MFMA operand order: slice a, row tile rt, k-step
+// ks of 64 at ((a RT + rt) nks + ks) 64 + lane, lane = row % 16 + 16 ((k % 64) / 16), holding
+// k % 16 = 0 .. 15 (RT = n_pad / 16, nks = n64 / 64, n64 = n_pad rounded up to 64).
+__host__ __device__ inline int pad64(int n_pad) { return (n_pad + 63) & ~63; }
+
 // Device-side view of one problem for the dense solver (one entry per problem of a launch).
 struct DenseProb {
   int n, n_pad, K, level_set, hkind, max_iter;
@@ -65,6 +83,8 @@ struct DenseProb {
   const __bf16* Mb;      // n_pad*n_pad BF16 copy of M = (A + lambda I)^{-1}
   const float* Mf;       // n_pad*n_pad FP32 copy
   const double* Md;      // n_pad*n_pad FP64
+  const int8_t* Mq;      // kSlices * n_pad * pad64(n_pad) bytes: M in integer slices (refined mode)
+  const int32_t* Mqe;    // n_pad row exponents of the slices
   const double* w;       // n_pad weights (0 beyond n)
   const float* wf;       // the same weights in FP32 (thresholds of the per-iteration increments)
   const double* centres; // K*n_pad (0 beyond n), or null

@@ -167,13 +167,22 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         }
       }
       __syncthreads();
-      // v^a = M r^a (FP64 MFMA); ea = v^a - d^a.  r^a = x' + lambda (2 d^a - z^a) is formed once
-      // per anchor into the workgroup's FP64 staging (column-major, n_pad per column), which the
-      // products then stream as their right-hand sides.
+      // v^a = M r^a; ea = v^a - d^a.  r^a = x' + lambda (2 d^a - z^a) is formed once per anchor in
+      // FP64 (the workgroup's staging, column-major, n_pad per column) and the product is taken in
+      // integer slices (the kSlices definitions): M and r^a are split into kSlices 7-bit slices
+      // under per-row and per-column power-of-two scales, and the slice products with
+      // a + b <= kSlices + 1 (1-based) are accumulated exactly.  The dropped terms and the
+      // truncated slices leave at most ~ n_pad 2^(-7 kSlices) of 2^(e_i + f_c), i.e. about 2^-32
+      // of max_k |M_ik| max_k |r_kc| at n_pad = 1024 in the worst case: far below what the anchor
+      // has to resolve, while the int8 products run many times faster than FP64 ones.
       {
         double* const ra = ws64 + (int64_t)blockIdx.x * ws64_per_wg;
+        const int n64 = pad64(n_pad);
+        int8_t* const rq = (int8_t*)(ra + (size_t)PT * n_pad);  // kSlices x PT x n64 bytes
+        double cmax[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
+          cmax[ct] = 0.0;
           const int c = 16 * ct + (l & 15);
           const int st = S.state[c];
           const bool on = st == COL_ACTIVE || st == COL_WAITING;
@@ -202,6 +211,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                     const double sa64 = anchor_shrink(zv[u][q], th1, pb.w, row);
                     const double xp = (double)xj[row] - (cen ? cen[row] : 0.0);
                     rv[q] = xp + lam * (2.0 * ga * sa64 - (double)zv[u][q]);
+                    cmax[ct] = fmax(cmax[ct], fabs(rv[q]));
                   }
                 }
               }
@@ -211,55 +221,97 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
             }
           }
         }
+        // column scales: the largest |r^a| of each column, over the lane groups, then the waves
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          double m = cmax[ct];
+          m = fmax(m, __shfl_xor(m, 16));
+          m = fmax(m, __shfl_xor(m, 32));
+          if (l < 16) S.red[wave][16 * ct + l][0] = m;
+        }
         __syncthreads();  // the staging is complete (written and read by this workgroup only)
-        constexpr int RGA = CT >= 4 ? (NW == 8 ? 1 : 2) : RG;  // row tiles per FP64 product pass
-        // the staging streams through LDS in blocks of kb rows of all PT columns (the BF16
-        // right-hand-side buffer is free during an anchor); every wave takes part in every block,
-        // also a wave without row tiles in the last pass
-        const int kbm = anchor_kb(n_pad), ldb64 = kbm + 2;
-        double* const Bl = (double*)lds_raw;
-        for (int rt0 = 0; rt0 < RT; rt0 += NW * RGA) {
-          int rt[RGA]; int nrt = 0;
+        if (tid < PT) {
+          double m = 0.0;
 #pragma unroll
-          for (int r = 0; r < RGA; ++r) { rt[r] = rt0 + wave + NW * r; if (rt[r] < RT) nrt = r + 1; }
-          f64x4 acc[RGA][CT];
+          for (int w = 0; w < NW; ++w) m = fmax(m, S.red[w][tid][0]);
+          S.rexp[tid] = slice_exponent(m);
+        }
+        __syncthreads();
+        // the slices of r^a, [slice][column][k] with n64 bytes per column (zero beyond n_pad);
+        // each thread takes 4 consecutive k of one column
+        {
+          const int q4 = n64 >> 2;
+          for (int u = tid; u < PT * q4; u += NW * 64) {
+            const int c = u / q4, k4 = 4 * (u - c * q4);
+            const int fe = S.rexp[c];
+            uint32_t word[kSlices];
 #pragma unroll
-          for (int r = 0; r < RGA; ++r)
+            for (int s = 0; s < kSlices; ++s) word[s] = 0u;
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[r][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-          for (int k0 = 0; k0 < n_pad; k0 += kbm) {
-            const int kb = n_pad - k0 < kbm ? n_pad - k0 : kbm;  // a multiple of 16
-            const int hu = kb >> 1;                               // 16-byte units per column
-            __syncthreads();  // the previous block is consumed
-            for (int u = tid; u < PT * hu; u += NW * 64) {
-              const int c = u / hu, off = 2 * (u - c * hu);
-              *(f64x2*)(Bl + c * ldb64 + off) = *gp((const f64x2*)(ra + (size_t)c * n_pad + k0 + off));
+            for (int e = 0; e < 4; ++e) {
+              const int k = k4 + e;
+              double x = k < n_pad ? ldexp(*gp(ra + (size_t)c * n_pad + k), -fe) : 0.0;
+#pragma unroll
+              for (int s = 0; s < kSlices; ++s) {
+                x *= 128.0;
+                const double r = rint(x);
+                x -= r;
+                word[s] |= (uint32_t)(uint8_t)(int8_t)(int)r << (8 * e);
+              }
+            }
+#pragma unroll
+            for (int s = 0; s < kSlices; ++s) *gp((uint32_t*)(rq + ((size_t)s * PT + c) * n64 + k4)) = word[s];
+          }
+        }
+        // products, one row tile per wave and pass; the slices of r^a stream through LDS in blocks
+        // of kbq rows of all PT columns (the BF16 right-hand-side buffer is free during an
+        // anchor), and every wave takes part in every block, also one without a row tile
+        const int kbq = anchor_kbq(n_pad), ldq = kbq + 16;
+        int8_t* const Bq = (int8_t*)lds_raw;
+        for (int rt0 = 0; rt0 < RT; rt0 += NW) {
+          const int rt = rt0 + wave;
+          const bool has = rt < RT;  // wave-uniform
+          i32x4 acc[kSlices][CT];
+#pragma unroll
+          for (int s = 0; s < kSlices; ++s)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[s][c] = i32x4{0, 0, 0, 0};
+          for (int k0 = 0; k0 < n64; k0 += kbq) {
+            const int kb = n64 - k0 < kbq ? n64 - k0 : kbq;  // a multiple of 64
+            const int hu = kb >> 4;                           // 16-byte units per slice and column
+            __syncthreads();  // the slices are written (first block) or the previous block is consumed
+            for (int u = tid; u < kSlices * PT * hu; u += NW * 64) {
+              const int sc = u / hu, off = 16 * (u - sc * hu);  // sc = slice PT + column
+              *(i32x4*)(Bq + sc * ldq + off) = *gp((const i32x4*)(rq + (size_t)sc * n64 + k0 + off));
             }
             __syncthreads();
-            if (nrt > 0) gemm_f64_lds<RGA, CT>(pb.Md, n_pad, k0, kb, Bl, ldb64, rt, nrt, acc);
+            if (has) gemm_slices<CT>(pb.Mq, RT, n64 >> 6, rt, k0 >> 6, kb >> 6, Bq, ldq, acc);
           }
-          if (nrt == 0) continue;  // wave-uniform (after the last barrier of the pass)
+          if (!has) continue;  // after the last barrier of the pass
+          const int row0 = 16 * rt + 4 * (l >> 4);
+          int rexp_row[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) rexp_row[i] = *gp(pb.Mqe + row0 + i);
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const int c = 16 * ct + (l & 15);
             const int st = S.state[c];
             if (st != COL_ACTIVE && st != COL_WAITING) continue;
             const double ga = S.gama[c];
+            const int fe = S.rexp[c];
+            f32x4 ev;
+            const size_t et = st_block(rt, ct, RT) + 4 * l;
+            const f32x4 zv = ld_nt4(za + et);
 #pragma unroll
-            for (int r = 0; r < RGA; ++r) {
-              if (r >= nrt) continue;
-              const int row0 = 16 * rt[r] + 4 * (l >> 4);
-              f32x4 ev;
-              const size_t et = st_block(rt[r], ct, RT) + 4 * l;
-              const f32x4 zv = ld_nt4(za + et);
+            for (int i = 0; i < 4; ++i) {
+              const int row = row0 + i;
+              double v = 0.0;  // smallest terms first
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int row = row0 + i;
-                const double sa64 = anchor_shrink(zv[i], S.th1[c], pb.w, row);
-                ev[i] = (row < n) ? (float)(acc[r][ct][i] - ga * sa64) : 0.f;
-              }
-              st_nt4(ea + et, ev);
+              for (int s = kSlices - 1; s >= 0; --s) v += ldexp((double)acc[s][ct][i], rexp_row[i] + fe - 7 * (s + 2));
+              const double sa64 = anchor_shrink(zv[i], S.th1[c], pb.w, row);
+              ev[i] = (row < n) ? (float)(v - ga * sa64) : 0.f;
             }
+            st_nt4(ea + et, ev);
           }
         }
       }
@@ -853,8 +905,9 @@ DenseVariant dense_variant(int mode, int n_pad) {
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_variant(mode, n_pad).pt;
-  // refined: the BF16 right-hand sides, or an FP64 block of the anchor products
-  if (mode == 1) return std::max((size_t)pt * (n_pad + 8) * 2, (size_t)pt * (anchor_kb(n_pad) + 2) * 8);
+  // refined: the BF16 right-hand sides, or a block of the anchor right-hand sides' slices
+  if (mode == 1)
+    return std::max((size_t)pt * (n_pad + 8) * 2, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
   return (size_t)pt * (n_pad + 4) * 4;
 }
 

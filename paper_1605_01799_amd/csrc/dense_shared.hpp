@@ -122,61 +122,56 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
   }
 }
 
-// Rows of B per LDS block of the FP64 anchor products (gemm_f64_lds), and the block's leading
-// dimension; the refined kernel's dynamic LDS holds PT (kAnchorKB + 2) doubles.
+// Rows (k) of the anchor right-hand sides per LDS block of the sliced products, and the block's
+// byte stride per (slice, column): the refined kernel's dynamic LDS holds kSlices PT (kbq + 16)
+// bytes.
 constexpr int kAnchorKB = 256;
-__host__ __device__ __forceinline__ int anchor_kb(int n_pad) { return n_pad < kAnchorKB ? n_pad : kAnchorKB; }
+__host__ __device__ __forceinline__ int anchor_kbq(int n_pad) {
+  return pad64(n_pad) < kAnchorKB ? pad64(n_pad) : kAnchorKB;
+}
 
-// FP64 anchor products with the right-hand sides staged in LDS: acc[r][c] += M[16 rt_r .., k0 ..
-// k0 + kb) * B[k0 .. k0 + kb, 16 c ..], where Bl holds that block column-major (column j at
-// Bl + j ldb, 16-byte aligned).  A rows are loaded in the order 4(rho%4) + rho/4 so that the
-// output lands in the lane layout of the FP32/BF16 16x16 products (lane l, register i -> row
-// 4(l/16) + i, column l%16).  A (8 bytes per entry, not L2-resident) streams PF k-chunks of 16
-// ahead of the products; B comes from LDS.
-template <int RG, int CT, int PF = 3>
-__device__ __forceinline__ void gemm_f64_lds(const double* __restrict__ M, int n_pad, int k0, int kb,
-                                             const double* Bl, int ldb, const int* rt, int nrt,
-                                             f64x4 (&acc)[RG][CT]) {
+// Exact anchor products in integer slices: acc[s][c] += sum over the slice pairs a + b = s (0-based)
+// of Mq_a[16 rt .., k] * Bq_b[k, 16 c ..] over the nkb k-steps of 64 from k-step ks0, int8 MFMAs
+// with int32 accumulation (no rounding: |acc| <= kSlices n64 64^2).  Mq in its operand order (the
+// kSlices definitions); Bq the LDS block, slice b of column j at Bq + (b PT + j) ldq, k contiguous.
+// A streams PF k-steps ahead; lane l takes k = 16 (l / 16) .. + 15 of a k-step in both operands.
+template <int CT, int PF = 1>
+__device__ __forceinline__ void gemm_slices(const int8_t* __restrict__ Mq, int RT, int nks, int rt, int ks0,
+                                            int nkb, const int8_t* Bq, int ldq, i32x4 (&acc)[kSlices][CT]) {
+  constexpr int PT = 16 * CT;
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
-  const int arow_perm = 4 * (lr & 3) + (lr >> 2);
-  const HOPF_GLOBAL f64x4* arow[RG];
-#pragma unroll
-  for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const f64x4*)(M + (size_t)(16 * (r < nrt ? rt[r] : 0) + arow_perm) * n_pad + k0 + 4 * lg));
-  const double* bcol = Bl + lr * ldb + 4 * lg;
-  const int nk = kb >> 4;
+  const HOPF_GLOBAL i32x4* abase = gp((const i32x4*)Mq + ((size_t)rt * nks + ks0) * 64 + l);
+  const size_t astride = (size_t)RT * nks * 64;  // units between slices
+  const int8_t* bbase = Bq + lr * ldq + 16 * lg;
   constexpr int NB = PF + 1;
-  f64x4 a[NB][RG];
+  i32x4 a[NB][kSlices];
 #pragma unroll
   for (int u = 0; u < PF; ++u)
-    if (u < nk) {
+    if (u < nkb) {
 #pragma unroll
-      for (int r = 0; r < RG; ++r) a[u][r] = __builtin_nontemporal_load(arow[r] + 4 * u);
+      for (int s = 0; s < kSlices; ++s) a[u][s] = abase[s * astride + 64 * u];
     }
-  for (int ks = 0; ks < nk; ks += NB) {
+  for (int ks = 0; ks < nkb; ks += NB) {
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int kk = ks + u;
-      if (kk < nk) {
-        if (kk + PF < nk) {
+      if (kk < nkb) {
+        if (kk + PF < nkb) {
 #pragma unroll
-          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = __builtin_nontemporal_load(arow[r] + 4 * (kk + PF));
+          for (int s = 0; s < kSlices; ++s) a[(u + PF) % NB][s] = abase[s * astride + 64 * (kk + PF)];
         }
-        f64x4 b[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-          const f64x2* bp = (const f64x2*)(bcol + 16 * c * ldb + 16 * kk);
-          const f64x2 b0 = bp[0], b1 = bp[1];
-          b[c] = f64x4{b0[0], b0[1], b1[0], b1[1]};
+          i32x4 b[kSlices];
+#pragma unroll
+          for (int s = 0; s < kSlices; ++s) b[s] = *(const i32x4*)(bbase + (s * PT + 16 * c) * ldq + 64 * kk);
+#pragma unroll
+          for (int sa = 0; sa < kSlices; ++sa)
+#pragma unroll
+            for (int sb = 0; sa + sb < kSlices; ++sb)
+              acc[sa + sb][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][sa], b[sb], acc[sa + sb][c], 0, 0, 0);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int r = 0; r < RG; ++r)
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-              acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r][q], b[c][q], acc[r][c], 0, 0, 0);
       }
     }
   }
@@ -214,6 +209,7 @@ struct ColShared {
   double pn[P], best[P];
   int stall[P], col[P], j[P], k[P], state[P], phase[P], iters[P];
   int newton[P], flags[P], fresh[P], better[P];
+  int rexp[P];            // column exponents of an anchor's right-hand sides
   double red[NW][P][2];  // per-wave partials of step^2 and |s|^2
   double redv[P][4];     // value sums of a value iteration (LDS atomics)
   int ctl[16];

@@ -164,6 +164,38 @@ __global__ void finalize_copies_kernel(const double* S, int n, int n_pad, double
   if (Mb) Mb[mb_index(i, j, n_pad)] = to_bf16((float)v);
 }
 
+// Integer slices of M for the refined solver's exact anchor products (layout and scale: the
+// kSlices definitions).  One workgroup per row: its largest |M_ik| fixes the row exponent, then
+// every entry is split by repeated scaling by 2^7 and rounding (each step exact in FP64).
+__global__ void __launch_bounds__(kBlock) slice_rows_kernel(const double* Md, int n_pad, int8_t* Mq,
+                                                            int32_t* Mqe) {
+  __shared__ double red[kBlock];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int n64 = pad64(n_pad), nks = n64 >> 6, RT = n_pad >> 4;
+  const double* row = Md + (size_t)i * n_pad;
+  double m = 0.0;
+  for (int k = tid; k < n_pad; k += kBlock) m = fmax(m, fabs(row[k]));
+  red[tid] = m;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const int ex = slice_exponent(red[0]);
+  if (tid == 0) Mqe[i] = ex;
+  const size_t slice_bytes = (size_t)n_pad * n64;
+  for (int k = tid; k < n64; k += kBlock) {
+    double x = k < n_pad ? ldexp(row[k], -ex) : 0.0;
+    const size_t unit = ((size_t)(i >> 4) * nks + (k >> 6)) * 64 + (i & 15) + 16 * ((k & 63) >> 4);
+    for (int a = 0; a < kSlices; ++a) {
+      x *= 128.0;
+      const double r = rint(x);
+      x -= r;
+      Mq[a * slice_bytes + unit * 16 + (k & 15)] = (int8_t)(int)r;
+    }
+  }
+}
+
 // Diagonal A: M = diag(1 / (a_i + lambda)).
 __global__ void diag_inverse_kernel(const double* a, int n, int n_pad, double lambda, double* Md,
                                     float* Mf, __bf16* Mb, double* minv_diag) {
@@ -233,6 +265,11 @@ hipError_t launch_finalize_copies(const double* S, int n, int n_pad, double* Md,
   int64_t tot = (int64_t)n_pad * n_pad;
   hipLaunchKernelGGL(finalize_copies_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream,
                      S, n, n_pad, Md, Mf, Mb);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_rows(const double* Md, int n_pad, int8_t* Mq, int32_t* Mqe, hipStream_t stream) {
+  hipLaunchKernelGGL(slice_rows_kernel, dim3((unsigned)n_pad), dim3(kBlock), 0, stream, Md, n_pad, Mq, Mqe);
   return hipGetLastError();
 }
 

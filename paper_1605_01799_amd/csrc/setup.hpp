@@ -19,6 +19,8 @@ hipError_t launch_build_shifted(const double* A, int n, int n_pad, double lambda
                                 hipStream_t stream);
 hipError_t launch_finalize_copies(const double* S, int n, int n_pad, double* Md, float* Mf, __bf16* Mb,
                                   hipStream_t stream);
+// Integer slices of M (refined mode): kSlices * n_pad * pad64(n_pad) bytes and n_pad exponents.
+hipError_t launch_slice_rows(const double* Md, int n_pad, int8_t* Mq, int32_t* Mqe, hipStream_t stream);
 hipError_t launch_diag_inverse(const double* a, int n, int n_pad, double lambda, double* Md, float* Mf,
                                __bf16* Mb, double* minv_diag, hipStream_t stream);
 
