@@ -106,6 +106,29 @@ def test_padding_residues(oracle_lib, n):
     assert rel_err_phi(out["phi"].cpu().numpy(), ref["phi"]).max() <= REFINED_TOL
 
 
+def test_refined_wide_scales(oracle_lib):
+    """The refined anchors take M and every right-hand side in integer slices under one
+    power-of-two scale per row and per column: coordinates spread over three decades (per
+    coordinate) put small and large entries in the same right-hand side."""
+    rng = np.random.default_rng(4242)
+    n, npts = 96, 64
+    A = rand_problem(n, rng)
+    w = rng.uniform(0.5, 2, n)
+    scale = 10.0 ** rng.uniform(-1.5, 1.5, n)
+    x = (rng.normal(0, 2, (npts, n)) * scale).astype(np.float32)
+    t = rng.uniform(0.05, 3, npts).astype(np.float32)
+    print("case wide scales n=%d npts=%d bf16_refined" % (n, npts), flush=True)
+    # the stopping rule is absolute: scaled with the largest coordinate scale squared
+    prob = H.Problem(A, hkind="l2_wl1", w=w, precision="bf16_refined", tol=1e-16 * n * scale.max() ** 2,
+                     max_iter=20000)
+    out = prob.eval(dev(x), dev(t))
+    torch.cuda.synchronize()
+    assert (out["iters"].cpu().numpy() != -1).all()
+    ref = oracle_lib.oracle_eval(A, x.astype(np.float64), t.astype(np.float64), "l2_wl1", w=w, tol=1e-28)
+    assert rel_err_vec(out["grad"].cpu().numpy(), ref["grad"]).max() <= REFINED_TOL
+    assert rel_err_phi(out["phi"].cpu().numpy(), ref["phi"]).max() <= REFINED_TOL
+
+
 def test_largest_n(oracle_lib):
     rng = np.random.default_rng(2048)
     n, npts = 2048, 40
