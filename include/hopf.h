@@ -96,8 +96,9 @@ typedef enum {
 typedef enum {
   HOPF_F64 = 0,          /* double I/O and arithmetic (diagonal A only) */
   HOPF_F32 = 1,          /* float I/O; FP32 state and FP32 MFMA products */
-  HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined to
-                            FP64-exact anchor products every few iterations */
+  HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined by
+                            anchor products every few iterations that are exact up to
+                            ~2^-32 of the row and column scales (integer slices) */
 } hopf_precision;
 
 typedef struct {

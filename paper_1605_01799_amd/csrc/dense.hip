@@ -21,17 +21,19 @@
 //   F32      z in FP32, FP32 MFMA (16x16x4) products on r.
 //   REFINED  BF16 MFMA (16x16x32) products, FP32 accumulate, applied to the
 //            INCREMENT r^k - r^a since an anchor state; the anchor product
-//            v^a = M r^a is formed exactly with FP64 MFMA (16x16x4) every
-//            `anchor_every` iterations.  The state is kept as an FP32 anchor
-//            za plus an FP32 increment dz (z = za + dz), with ea = v^a - d^a
-//            stored in FP32, so every rounding on the iteration path is
-//            relative to a vanishing increment and the fixed point is the
-//            FP64-exact one.  The first `warmup` iterations run plain BF16
-//            products on the full r (no stopping allowed there).
+//            v^a = M r^a is formed every `anchor_every` iterations from the
+//            FP64 r^a, exactly up to ~2^-32 of its row and column scales, as
+//            int8 MFMA (16x16x64) products of integer slices of M and r^a
+//            with exact int32 accumulation.  The state is kept as an FP32
+//            anchor za plus an FP32 increment dz (z = za + dz), with
+//            ea = v^a - d^a stored in FP32, so every rounding on the iteration
+//            path is relative to a vanishing increment and the fixed point is
+//            that of the exact product.  The first `warmup` iterations run
+//            plain BF16 products on the full r (no stopping allowed there).
 // Values: phi = <x', d> - 1/2 d^T A d - t H(d) (- 1/2 for ellipsoid level
 // sets) with d^T A d = (2 d - v)^T (r - lambda v) + O(|d - v|^2) because
 // (A + lambda I) v = r: evaluated in the iteration after a column converged
-// (after a fresh FP64 anchor in REFINED mode), so no product with A is needed.
+// (after a fresh anchor in REFINED mode), so no product with A is needed.
 // Distances (section 3.2): psi_k(y, s) is the same evaluation with H = |.|_2,
 // t = s and the ellipsoid level set; Newton on s (eq. Newton_zero,
 // d psi / ds = -|grad psi|) starts at s = 0 where psi = L_k(y) and grad psi =
@@ -42,7 +44,7 @@
 
 namespace hopf {
 
-// MODE 0: FP32 products; MODE 1: BF16 increments + FP64 anchors.  CT column tiles of 16, RG row
+// MODE 0: FP32 products; MODE 1: BF16 increments + exact anchors.  CT column tiles of 16, RG row
 // tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
 // OCC workgroups per CU.  With two waves per SIMD (NW = 8, or OCC = 2) each wave keeps at most
 // 256 registers per lane, and one wave's products overlap another's epilogue.

@@ -3,7 +3,7 @@
 
 namespace hopf {
 
-// mode 0: FP32 products; mode 1: BF16 increments refined by FP64 anchor products.
+// mode 0: FP32 products; mode 1: BF16 increments refined by exact (integer-sliced) anchor products.
 // The launch shape for a mode and padded size: columns per tile, workgroups per CU, waves per
 // workgroup.
 struct DenseVariant {

@@ -85,7 +85,7 @@ WORKLOADS = {
     2: "n=64, A=Q diag(s) Q^T (Q Haar, s log-uniform [0.1,10]), H=sum w_i|p_i|, w~U(0.5,2), "
        "2^20 points x~N(0,4I), t~U(0.05,3), FP32 inputs",
     3: "n=1024, A as workload 2, H=||p||_2 + sum w_i|p_i|, w~U(0.5,2), 2^16 points x~N(0,4I), "
-       "t~U(0.05,3), FP32 inputs, BF16 MFMA products refined to FP64-exact anchors",
+       "t~U(0.05,3), FP32 inputs, BF16 MFMA products refined by exact anchor products",
     4: "4096 problems, n=round(logU[4,2048]), A=Q diag(a^2) Q^T (a~U(0.5,3)), w~U(0.5,2), one "
        "t~U(0.05,3) per problem, round(logU[1,4096]) points x~N(0,4I), J=min over K=8 ellipsoid "
        "level sets with centres ~N(0,9I); phi (H=wl1), closest point + distance; FP32",

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element,
 on seeded inputs at sizes the oracle finishes in seconds, spanning several tiles and a
 ragged tail.  Tolerances: 1e-10 relative for the FP64 path; 1e-6 relative for the
-BF16-refined path (FP64-exact anchor products); the plain FP32 path is held to a bound
+BF16-refined path (exact integer-sliced anchor products); the plain FP32 path is held to a bound
 derived from its arithmetic (see FP32_TOL)."""
 import numpy as np
 import pytest
