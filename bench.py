@@ -61,10 +61,12 @@ def parse():
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c3",
-                    choices=["c3", "c1s", "c2", "c5", "c2wl2", "pd16", "pa16", "t5n16"],
+                    choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
                          "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
-                         "FP32 dense at 2^20 points, c5 = n=256 union of 4 ellipsoids, forward + backward; "
+                         "FP32 dense at 2^20 points, c4 = the ragged batch of 4096 problems (n log-uniform "
+                         "in [4, 2048], union of 8 ellipsoids, FP32; generation takes minutes on the host: "
+                         "use --steps 2 --warmup 1), c5 = n=256 union of 4 ellipsoids, forward + backward; "
                          "c2wl2 = c2 with H = sqrt(<p, diag(w) p>); pd16 = the paper's timing-table setting "
                          "for that H at n=16 (J = 1/2 <y, D^-1 y>, FP64, tol 1e-8); pa16 = the same for "
                          "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis); "
@@ -153,7 +155,8 @@ def main():
         "config": {"workload": "n=1024 dense SPD A, H=l2+weighted l1, 2^16 points x~N(0,4I), t~U(0.05,3), "
                                "FP32 inputs, split Bregman lambda=1; step = FP64 set-up + evaluation",
                    "n": n, "npts": npts, "tol": tol, "precision": a.precision,
-                   "products": "BF16 MFMA on increments + FP64 MFMA anchors" if a.precision == "bf16_refined"
+                   "products": "BF16 MFMA on increments + exact anchors (int8 MFMA on integer slices)"
+                   if a.precision == "bf16_refined"
                    else "FP32 MFMA"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
@@ -479,7 +482,7 @@ def bench_other(a):
                    accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": 5e-5},
                    cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
                                  "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
-    else:  # c5: forward over the union of 4 ellipsoids, then the envelope backward
+    elif a.workload == "c5":  # forward over the union of 4 ellipsoids, then the envelope backward
         npts = a.npts if a.npts != 1 << 16 else 1 << 18
         p = W.round_inputs(W.workload5(npts))
         x = torch.from_numpy(p.x).to(dev)
@@ -537,6 +540,113 @@ def bench_other(a):
                    cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
                                  "sample": "first %d points (forward only), same tol, FP64 oracle, %d threads"
                                            % (m, threads)})
+    elif a.workload == "c4":
+        # workload 4: 4096 problems, each its own n (log-uniform in [4, 2048]), A, w, t and point
+        # count (log-uniform in [1, 4096]), J = min over K = 8 ellipsoid level sets, H = weighted
+        # l1, FP32; the whole batch is one call (one launch per kernel class).  The problems are
+        # created (host A copied in, FP64 set-up) once, outside the timed region, and timed
+        # separately; the step is the ragged evaluation.
+        from concurrent.futures import ThreadPoolExecutor
+        nall, pall = W.workload4_sizes()
+        nprob = len(nall)
+        g0 = time.perf_counter()
+        def build_A(G, spec):  # the generator's QR and product on the device (FP64 library calls)
+            g = torch.from_numpy(G).to(dev)
+            q, r = torch.linalg.qr(g)
+            sg = torch.sign(torch.diagonal(r))
+            q = q * torch.where(sg == 0, torch.ones_like(sg), sg)
+            A = (q * torch.from_numpy(spec).to(dev)) @ q.T
+            return (0.5 * (A + A.T)).cpu().numpy()
+        probs = []
+        for i in range(nprob):
+            probs.append(W.round_inputs(W.workload4_problem(i, build_A=build_A)))
+            if (i + 1) % 512 == 0:
+                print("workload 4: %d of %d problems generated (%.0f s)" % (i + 1, nprob, time.perf_counter() - g0),
+                      file=sys.stderr, flush=True)
+
+        def tol4(n):  # the FP32 rounding floor of the squared step, n (u |z|)^2 (|z| ~ 7.2 here)
+            return a.tol if a.tol is not None else max(1e-10, 4 * n * (6e-8 * 7.2) ** 2)
+        specs = [dict(A=p.A, centres=p.centres, level_set=True, hkind="wl1", w=p.w, precision="f32",
+                      tol=tol4(p.n), max_iter=20000) for p in probs]
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        hp = H.Problem.batch(specs)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - s0) * 1e3
+        xs = [torch.from_numpy(p.x).to(dev) for p in probs]
+        ts = [torch.from_numpy(p.t).to(dev) for p in probs]
+        npts = int(pall.sum())
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            step.out = H.eval_ragged(hp, xs, ts)
+            if ev is not None:
+                ev[1].record(stream)
+        print("workload 4: problems created (%.0f ms); evaluating" % setup_ms, file=sys.stderr, flush=True)
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        print("workload 4: %d steps of %.0f ms" % (a.steps, ms), file=sys.stderr, flush=True)
+        out = step.out
+        it = np.abs(out["iters"].cpu().numpy()).astype(np.float64)
+        npt = np.repeat(nall, pall).astype(np.float64)
+        flops_pt = W.W4_K * it * 2.0 * npt * npt  # K copies x iterations of the attaining copy x 2 n^2
+        flops = float(flops_pt.sum())
+        # the survey's mixed roofline: per problem max(FLOP / FP32 MFMA peak, bytes / HBM), summed
+        off = out["offsets"]
+        t_roof = 0.0
+        for q in range(nprob):
+            fq = float(flops_pt[off[q]:off[q + 1]].sum())
+            bq = float(pall[q] * 4 * (3 * nall[q] + 4) + 4 * nall[q] * nall[q])
+            t_roof += max(fq / 157.3e12, bq / 8e12)
+        achieved = flops / (kms / 1e3) / 1e12
+        # accuracy and CPU baseline: one point of each of 48 seeded problems drawn from the whole
+        # batch (so the sample has the batch's mix of n); the accuracy reference is the oracle at
+        # squared-step tolerance 1e-20 (about 1e-10 relative)
+        rng = np.random.default_rng(9)
+        qs = np.sort(rng.choice(nprob, size=48, replace=False))
+        phi_all = out["phi"].cpu().numpy()
+        idxs = {int(q): np.sort(rng.choice(probs[q].npts, size=1, replace=False)) for q in qs}
+
+        def ref_run(q, tol):
+            p = probs[q]
+            return oracle.oracle_eval(p.A, p.x[idxs[q]].astype(np.float64), p.t[idxs[q]].astype(np.float64),
+                                      "wl1", w=p.w, centres=p.centres, level_set=True, tol=tol, nthreads=1)
+        c0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda q: ref_run(int(q), tol4(probs[q].n)), qs))
+        cpu_s = time.perf_counter() - c0
+        cpu_n = sum(len(v) for v in idxs.values())
+        with ThreadPoolExecutor(threads) as ex:
+            refs = list(ex.map(lambda q: ref_run(int(q), 1e-20), qs))
+        errs = []
+        for q, ref in zip(qs, refs):
+            ph = phi_all[off[q]:off[q + 1]][idxs[int(q)]]
+            errs.append(float((np.abs(ph - ref["phi"]) / np.maximum(np.abs(ref["phi"]), 1)).max()))
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), ragged batch of 4096 problems, union of 8 ellipsoids, FP32",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
+                   config={"workload": "4096 problems, n = round(logU[4,2048]), A = Q diag(a^2) Q^T (a~U(0.5,3)), "
+                                       "w~U(0.5,2), one t~U(0.05,3) per problem, round(logU[1,4096]) points "
+                                       "x~N(0,4I), J = min over K=8 ellipsoid level sets (centres ~N(0,9I)), "
+                                       "H = weighted l1, FP32, tol = the FP32 step floor per n; step = the "
+                                       "ragged evaluation (problems created once, timed separately)",
+                           "problems": nprob, "npts": npts, "K": W.W4_K},
+                   roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": achieved / 157.3, "traffic": None,
+                             "mixed_frac": t_roof / (kms / 1e3),
+                             "mixed": "sum over problems of max(FLOP / 157.3 TFLOP/s, bytes / 8 TB/s), "
+                                      "bytes = 4 (3 n + 4) per point + 4 n^2 per problem, over the measured time",
+                             "kernel": "dense_small_kernel and dense_kernel<0, ...> (one launch per class)",
+                             "algorithmic": "K x iterations of the attaining copy x 2 n^2 FLOP per point "
+                                            "(the other copies' counts are not returned)", "launch_ms": kms},
+                   setup={"ms": setup_ms, "what": "host A copied in + batched FP64 Gauss-Jordan of 4096 problems"},
+                   iterations={"mean_attaining_copy": float(it.mean()), "max": int(it.max())},
+                   accuracy={"sample": "1 point of each of %d problems (n %d .. %d)" % (len(qs), nall[qs].min(),
+                                                                                    nall[qs].max()),
+                             "max_rel_err_phi": max(errs), "bound": 5e-5},
+                   cpu_baseline={"value": cpu_n / cpu_s, "unit": "point-evals/s", "cores": threads,
+                                 "kind": "oracle",
+                                 "sample": "the same %d points (one problem per thread), same tol, FP64 "
+                                           "oracle, %d threads" % (cpu_n, threads)})
     print(json.dumps(rec), flush=True)
 
 

@@ -205,13 +205,21 @@ def workload4_sizes() -> tuple:
     return n, P
 
 
-def workload4_problem(i: int) -> Problem:
+def workload4_problem(i: int, build_A=None) -> Problem:
+    """Problem i of workload 4.  build_A(G, spectrum), if given, replaces the host QR and product
+    of haar_orthogonal / spd_from_spectrum (same draws, same definition: A = Q diag(spectrum) Q^T
+    with Q the sign-fixed QR factor of the Gaussian G), e.g. by a device implementation."""
     n_all, P_all = workload4_sizes()
     n, P = int(n_all[i]), int(P_all[i])
     rng = rng_for(4, 10 + i)
-    Q = haar_orthogonal(n, rng)
-    a = rng.uniform(0.5, 3.0, n)
-    A = spd_from_spectrum(Q, a * a)
+    if build_A is None:
+        Q = haar_orthogonal(n, rng)
+        a = rng.uniform(0.5, 3.0, n)
+        A = spd_from_spectrum(Q, a * a)
+    else:
+        G = rng.standard_normal((n, n))
+        a = rng.uniform(0.5, 3.0, n)
+        A = build_A(G, a * a)
     w = rng.uniform(0.5, 2.0, n)
     t = float(rng.uniform(0.05, 3.0))
     centres = rng.normal(0.0, 3.0, (W4_K, n))
