@@ -27,7 +27,7 @@ __device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, d
   double q = 0.0;
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
-    if (i < n) q += z[i] * z[i] / (theta * theta * (w ? w[i] : 1.0));
+    if (i < n) q += z[i] * z[i] / (theta * theta * w[i]);
   if (!(q > 1.0)) {
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) z[i] = 0.0;
@@ -39,7 +39,7 @@ __device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, d
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
       if (i >= n) continue;
-      const double s = theta * theta * (w ? w[i] : 1.0), inv = 1.0 / (s + mu);
+      const double s = theta * theta * w[i], inv = 1.0 / (s + mu);
       const double e = s * z[i] * z[i] * inv * inv;
       ph += e;
       ps += e * inv;
@@ -50,7 +50,7 @@ __device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, d
   }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
-    if (i < n) z[i] = mu * z[i] / (theta * theta * (w ? w[i] : 1.0) + mu);
+    if (i < n) z[i] = mu * z[i] / (theta * theta * w[i] + mu);
 }
 
 // The breakpoint problems of sections 4.2 and 4.4: the root mu of the decreasing, piecewise-affine
@@ -114,12 +114,60 @@ __device__ __forceinline__ void normsq_vupdate(int n, int jkind, double lam, dou
   }
 }
 
+// A coefficient of the problem (the same for every thread), read once into scalar registers.  Read
+// inside the iteration loops, such loads sit under per-coordinate branches and are not hoisted, so
+// every iteration would wait for their latency.
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The diagonal of M = (A + lambda I)^{-1} and the weights (1 without weights), coordinates >= n
+// taking coordinate 0's values (never used).  Up to 16 coordinates they are held in (scalar)
+// registers; beyond, registers are short and they stay in memory (cm, cw then point there).
+constexpr int kCoefRegs = 16;
+__constant__ double kOnes[32] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+template <int NMAX>
+struct DiagCoef {
+  double m[NMAX <= kCoefRegs ? NMAX : 1], w[NMAX <= kCoefRegs ? NMAX : 1];
+  const double* cm;
+  const double* cw;
+  __device__ __forceinline__ explicit DiagCoef(const DiagProb& pb) {
+    if constexpr (NMAX <= kCoefRegs) {
+      // all loads issued before any is used (unconditional, in-bounds indices), then moved to
+      // scalar registers
+      const double* pm = pb.minv ? pb.minv : kOnes;
+      const double* pw = pb.w ? pb.w : kOnes;
+      double tm[NMAX], tw[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        const int ic = i < pb.n ? i : 0;
+        tm[i] = pm[ic];
+        tw[i] = pw[ic];
+      }
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        m[i] = uniform(tm[i]);
+        w[i] = uniform(tw[i]);
+      }
+      cm = m;
+      cw = w;
+    } else {
+      cm = pb.minv;
+      cw = pb.w ? pb.w : kOnes;
+    }
+  }
+};
+
 // For the persistent kernel below: one split-Bregman iteration (3.4a)-(3.4c) of one point and
 // copy, in place, for every kind of J and H of the per-thread path; returns the paper's stopping
 // test (section 4.5).
 template <int NMAX>
-__device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const double* xp, double* v, double* d,
-                                        double* b) {
+__device__ __forceinline__ bool sb_step(const DiagProb& pb, const double* cm, const double* cw, double th,
+                                        const double* xp, double* v, double* d, double* b) {
   const int n = pb.n;
   const double lam = pb.lambda;
   const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
@@ -128,7 +176,7 @@ __device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const dou
   if (pb.jkind == JK_QUAD) {
 #pragma unroll
     for (int i = 0; i < NMAX; ++i)
-      vn[i] = i < n ? pb.minv[i] * (xp[i] + lam * (d[i] - b[i])) : 0.0;  // (3.4a)
+      vn[i] = i < n ? cm[i] * (xp[i] + lam * (d[i] - b[i])) : 0.0;  // (3.4a)
   } else {
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) vn[i] = i < n ? d[i] - b[i] + xp[i] / lam : 0.0;
@@ -140,7 +188,7 @@ __device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const dou
     double z = vn[i] + b[i];
     double s = z;
     if (l1) {                                                 // (3.4b), shrink1
-      double a = th * (pb.w ? pb.w[i] : 1.0);
+      double a = th * cw[i];
       double m = fabs(z) - a;
       s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
     }
@@ -153,7 +201,7 @@ __device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const dou
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) dn[i] *= f;
   }
-  if (wl2) wl2_prox<NMAX>(n, pb.w, th, dn);                  // (3.4b), z - projection
+  if (wl2) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
   if (pb.hkind == HK_LINF) linf_prox<NMAX>(n, th, dn);       // (3.4b), z - l1-ball projection
   double r1 = 0.0, r2 = 0.0, r3 = 0.0;
 #pragma unroll
@@ -171,18 +219,26 @@ __device__ __forceinline__ bool sb_step(const DiagProb& pb, double th, const dou
 // phi_k = <x', d> - J*(d) - t H(d)  (- 1/2 for an ellipsoid level set); J*(d) = 1/2 sum a_i d_i^2,
 // or the squared dual norm for the squared-norm initial data.  *H receives H(d).
 template <int NMAX>
-__device__ __forceinline__ double copy_value(const DiagProb& pb, double t, const double* xp, const double* d,
-                                             double* Hout) {
+__device__ __forceinline__ double copy_value(const DiagProb& pb, const double* cw, double t, const double* xp,
+                                             const double* d, double* Hout) {
   const int n = pb.n;
   const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
   const bool quad = pb.jkind == JK_QUAD;
   double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0, dmax = 0.0, dsum = 0.0;
+  double av[NMAX <= kCoefRegs ? NMAX : 1];  // diagonal of A: all loads in flight together
+  if constexpr (NMAX <= kCoefRegs) {
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) av[i] = quad ? pb.adiag[i < n ? i : 0] : 0.0;
+  }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (i >= n) continue;
     xd += xp[i] * d[i];
-    if (quad) q += pb.adiag[i] * d[i] * d[i];
-    const double wi = pb.w ? pb.w[i] : 1.0;
+    double ai;
+    if constexpr (NMAX <= kCoefRegs) ai = av[i];
+    else ai = quad ? pb.adiag[i] : 0.0;
+    if (quad) q += ai * d[i] * d[i];
+    const double wi = cw[i];
     h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
     h2 += d[i] * d[i];
     dmax = fmax(dmax, fabs(d[i]));
@@ -212,9 +268,11 @@ __device__ __forceinline__ bool load_point(const DiagProb& pb, int64_t j, double
   *t = (double)((const T*)pb.t)[j];
   bool ok = *t > 0.0 && isfinite(*t);
 #pragma unroll
+  for (int i = 0; i < NMAX; ++i) x[i] = (double)xj[i < n ? i : 0];  // all loads in flight together
+#pragma unroll
   for (int i = 0; i < NMAX; ++i) {
-    x[i] = i < n ? (double)xj[i] : 0.0;
     if (i < n && !isfinite(x[i])) ok = false;
+    x[i] = i < n ? x[i] : 0.0;
   }
   if (!ok) {
     const T qn = (T)__builtin_nan("");
@@ -239,8 +297,11 @@ __device__ __forceinline__ void store_point(const DiagProb& pb, int64_t j, doubl
 }
 
 // One thread per point (the iteration counts of this family are short and uniform): the quadratic
-// diagonal J with the weighted l1 / l2 / ellipsoidal norms.
-template <typename T, int NMAX>
+// diagonal J with the weighted l1 / l2 norms, or (WL2) the ellipsoidal norm, whose projection is
+// compiled only into that instance (it would otherwise hold registers, and so occupancy, from the
+// memory-bound norms).  ONE: a single copy without a centre (the plain J), where the point's own
+// x is the iteration's x' and p is written from the final iterate.
+template <typename T, int NMAX, bool WL2, bool ONE>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= pb.npts) return;
@@ -251,9 +312,11 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   double x[NMAX];
   bool ok = t > 0.0 && isfinite(t);
 #pragma unroll
+  for (int i = 0; i < NMAX; ++i) x[i] = (double)xj[i < n ? i : 0];  // all loads in flight together
+#pragma unroll
   for (int i = 0; i < NMAX; ++i) {
-    x[i] = i < n ? (double)xj[i] : 0.0;
     if (i < n && !isfinite(x[i])) ok = false;
+    x[i] = i < n ? x[i] : 0.0;
   }
   T* gj = (T*)pb.grad + j * n;
   if (!ok) {
@@ -264,16 +327,20 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
     if (pb.kstar) pb.kstar[j] = -1;
     return;
   }
-  const bool l1 = hk_has_l1(pb.hkind), l2 = hk_has_l2(pb.hkind), wl2 = pb.hkind == HK_WL2;
+  const bool l1 = !WL2 && hk_has_l1(pb.hkind), l2 = !WL2 && hk_has_l2(pb.hkind);
+  constexpr bool wl2 = WL2;
   const double th = t / lam;
   double best = 0.0, bh = 0.0;
   int kbest = -1, itbest = 0;
   double pbest[NMAX];
-  for (int k = 0; k < pb.K; ++k) {
+  const DiagCoef<NMAX> coef(pb);
+  const double* const cm = coef.cm;
+  const double* const cw = coef.cw;
+  for (int k = 0; k < (ONE ? 1 : pb.K); ++k) {
     double xp[NMAX], v[NMAX], d[NMAX], b[NMAX];
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
-      xp[i] = (i < n) ? x[i] - (pb.centres ? pb.centres[(size_t)k * pb.ld + i] : 0.0) : 0.0;
+      xp[i] = (i < n) ? x[i] - (!ONE && pb.centres ? pb.centres[(size_t)k * pb.ld + i] : 0.0) : 0.0;
       v[i] = xp[i]; d[i] = xp[i]; b[i] = 0.0;
     }
     int it = 0;
@@ -285,11 +352,11 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) {
         if (i >= n) { vn[i] = 0.0; dn[i] = 0.0; continue; }
-        vn[i] = pb.minv[i] * (xp[i] + lam * (d[i] - b[i]));       // (3.4a)
+        vn[i] = cm[i] * (xp[i] + lam * (d[i] - b[i]));        // (3.4a)
         double z = vn[i] + b[i];
         double s = z;
         if (l1) {                                                 // (3.4b), shrink1
-          double a = th * (pb.w ? pb.w[i] : 1.0);
+          double a = th * cw[i];
           double m = fabs(z) - a;
           s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
         }
@@ -302,7 +369,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) dn[i] *= f;
       }
-      if (wl2) wl2_prox<NMAX>(n, pb.w, th, dn);                  // (3.4b), z - projection
+      if constexpr (WL2) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
       double r1 = 0.0, r2 = 0.0, r3 = 0.0;
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) {
@@ -317,12 +384,20 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
     }
     // phi_k = <x', d> - 1/2 sum a_i d_i^2 - t H(d)  (- 1/2 for an ellipsoid level set)
     double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0;
+    double av[NMAX <= kCoefRegs ? NMAX : 1];  // diagonal of A: all loads in flight together
+    if constexpr (NMAX <= kCoefRegs) {
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) av[i] = pb.adiag[i < n ? i : 0];
+    }
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
       if (i >= n) continue;
       xd += xp[i] * d[i];
-      q += pb.adiag[i] * d[i] * d[i];
-      const double wi = pb.w ? pb.w[i] : 1.0;
+      double ai;
+      if constexpr (NMAX <= kCoefRegs) ai = av[i];
+      else ai = pb.adiag[i];
+      q += ai * d[i] * d[i];
+      const double wi = cw[i];
       h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
       h2 += d[i] * d[i];
     }
@@ -330,13 +405,20 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
     const double val = xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
     if (kbest < 0 || val < best) {
       best = val; bh = H; kbest = k; itbest = conv ? it : -2;
+      if constexpr (!ONE) {
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
+        for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
+      }
+    }
+    if constexpr (ONE) {
+      for (int i = 0; i < n; ++i) gj[i] = (T)d[i];
     }
   }
   ((T*)pb.phi)[j] = (T)best;
   ((T*)pb.dphidt)[j] = (T)(-bh);
-  for (int i = 0; i < n; ++i) gj[i] = (T)pbest[i];
+  if constexpr (!ONE) {
+    for (int i = 0; i < n; ++i) gj[i] = (T)pbest[i];
+  }
   if (pb.iters) pb.iters[j] = itbest;
   if (pb.kstar) pb.kstar[j] = kbest;
 }
@@ -350,6 +432,9 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
 template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlock) diag_ext_kernel(DiagProb pb, int* __restrict__ counter) {
   double x[NMAX], xp[NMAX], v[NMAX], d[NMAX], b[NMAX], pbest[NMAX];
+  const DiagCoef<NMAX> coef(pb);
+  const double* const cm = coef.cm;
+  const double* const cw = coef.cw;
   double t = 0.0, th = 0.0, best = 0.0, bh = 0.0;
   int64_t j = -1;
   int k = 0, it = 0, kbest = -1, itbest = 0;
@@ -368,10 +453,10 @@ __global__ void __launch_bounds__(kBlock) diag_ext_kernel(DiagProb pb, int* __re
   fetch();
   while (have) {
     ++it;
-    const bool conv = sb_step<NMAX>(pb, th, xp, v, d, b);
+    const bool conv = sb_step<NMAX>(pb, cm, cw, th, xp, v, d, b);
     if (conv || it >= pb.max_iter) {
       double H;
-      const double val = copy_value<NMAX>(pb, t, xp, d, &H);
+      const double val = copy_value<NMAX>(pb, cw, t, xp, d, &H);
       if (kbest < 0 || val < best) {
         best = val; bh = H; kbest = k; itbest = conv ? it : -2;
 #pragma unroll
@@ -392,7 +477,12 @@ template <typename T, int NMAX>
 static hipError_t launch_n(const DiagProb& pb, bool ext, int* counter, int ncu, hipStream_t stream) {
   if (!ext) {
     const unsigned grid = (unsigned)((pb.npts + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((diag_kernel<T, NMAX>), dim3(grid), dim3(kBlock), 0, stream, pb);
+    if (pb.hkind == HK_WL2)
+      hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false>), dim3(grid), dim3(kBlock), 0, stream, pb);
+    else if (pb.K == 1 && pb.centres == nullptr)
+      hipLaunchKernelGGL((diag_kernel<T, NMAX, false, true>), dim3(grid), dim3(kBlock), 0, stream, pb);
+    else
+      hipLaunchKernelGGL((diag_kernel<T, NMAX, false, false>), dim3(grid), dim3(kBlock), 0, stream, pb);
   } else {
     // persistent: enough workgroups for the resident waves (at most 8 workgroups per CU)
     const int64_t need = (pb.npts + kBlock - 1) / kBlock;
