@@ -17,6 +17,8 @@
 
 namespace hopf {
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 // In place: z <- prox of theta sqrt(<., D .>), D = diag(w) (section 4.4): z minus its projection
 // onto the Wulff ellipsoid sum y_i^2 / s_i <= 1, s_i = theta^2 w_i (eq. (prox-projection)).  Zero
 // inside; otherwise z_i mu / (s_i + mu) with mu > 0 the root of phi(mu) = sum s_i z_i^2 /
@@ -303,124 +305,158 @@ __device__ __forceinline__ void store_point(const DiagProb& pb, int64_t j, doubl
 // x is the iteration's x' and p is written from the final iterate.
 template <typename T, int NMAX, bool WL2, bool ONE>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= pb.npts) return;
+  // grid-stride over the points (loading the next point before solving the current one was
+  // measured slower: the extra registers cost a wave per SIMD)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int n = pb.n;
   const double lam = pb.lambda;
-  const T* xj = (const T*)pb.x + j * n;
-  const double t = (double)((const T*)pb.t)[j];
-  double x[NMAX];
-  bool ok = t > 0.0 && isfinite(t);
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i) x[i] = (double)xj[i < n ? i : 0];  // all loads in flight together
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i) {
-    if (i < n && !isfinite(x[i])) ok = false;
-    x[i] = i < n ? x[i] : 0.0;
-  }
-  T* gj = (T*)pb.grad + j * n;
-  if (!ok) {
-    const T qn = (T)__builtin_nan("");
-    ((T*)pb.phi)[j] = qn; ((T*)pb.dphidt)[j] = qn;
-    for (int i = 0; i < n; ++i) gj[i] = qn;
-    if (pb.iters) pb.iters[j] = -1;
-    if (pb.kstar) pb.kstar[j] = -1;
-    return;
-  }
   const bool l1 = !WL2 && hk_has_l1(pb.hkind), l2 = !WL2 && hk_has_l2(pb.hkind);
   constexpr bool wl2 = WL2;
-  const double th = t / lam;
-  double best = 0.0, bh = 0.0;
-  int kbest = -1, itbest = 0;
-  double pbest[NMAX];
   const DiagCoef<NMAX> coef(pb);
   const double* const cm = coef.cm;
   const double* const cw = coef.cw;
-  for (int k = 0; k < (ONE ? 1 : pb.K); ++k) {
-    double xp[NMAX], v[NMAX], d[NMAX], b[NMAX];
+  T xs[NMAX], ts = (T)0;  // the loaded point (all loads in flight together)
+  // rows of exactly NMAX values, 16-byte aligned: moved as 16-byte vectors (half or a quarter of
+  // the memory instructions of element-wise accesses)
+  constexpr int VW = 16 / (int)sizeof(T);  // values per 16-byte vector
+  constexpr bool VEC = NMAX <= 16 && NMAX % VW == 0;  // (registers are short above 16)
+  const bool vec = VEC && n == NMAX && ((uintptr_t)pb.x % 16) == 0 && ((uintptr_t)pb.grad % 16) == 0;
+  auto issue = [&](int64_t jj) {
+    const T* xj = (const T*)pb.x + jj * n;
+    if (VEC && vec) {
+#pragma unroll
+      for (int q = 0; q < NMAX / VW; ++q) {
+        const u32x4 w = ((const u32x4*)xj)[q];
+        __builtin_memcpy(&xs[q * VW], &w, 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) xs[i] = xj[i < n ? i : 0];
+    }
+    ts = ((const T*)pb.t)[jj];
+  };
+  auto store_row = [&](T* gj, const double* p) {
+    if (VEC && vec) {
+#pragma unroll
+      for (int q = 0; q < NMAX / VW; ++q) {
+        T v[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[e] = (T)p[q * VW + e];
+        u32x4 w;
+        __builtin_memcpy(&w, v, 16);
+        ((u32x4*)gj)[q] = w;
+      }
+    } else {
+      for (int i = 0; i < n; ++i) gj[i] = (T)p[i];
+    }
+  };
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < pb.npts; j += stride) {
+    issue(j);
+    double x[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) x[i] = (double)xs[i];
+    const double t = (double)ts;
+    bool ok = t > 0.0 && isfinite(t);
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
-      xp[i] = (i < n) ? x[i] - (!ONE && pb.centres ? pb.centres[(size_t)k * pb.ld + i] : 0.0) : 0.0;
-      v[i] = xp[i]; d[i] = xp[i]; b[i] = 0.0;
+      if (i < n && !isfinite(x[i])) ok = false;
+      x[i] = i < n ? x[i] : 0.0;
     }
-    int it = 0;
-    bool conv = false;
-    while (it < pb.max_iter) {
-      ++it;
-      double vn[NMAX], dn[NMAX];
-      double ss = 0.0;
+    T* gj = (T*)pb.grad + j * n;
+    if (!ok) {
+      const T qn = (T)__builtin_nan("");
+      ((T*)pb.phi)[j] = qn; ((T*)pb.dphidt)[j] = qn;
+      for (int i = 0; i < n; ++i) gj[i] = qn;
+      if (pb.iters) pb.iters[j] = -1;
+      if (pb.kstar) pb.kstar[j] = -1;
+      continue;
+    }
+    const double th = t / lam;
+    double best = 0.0, bh = 0.0;
+    int kbest = -1, itbest = 0;
+    double pbest[NMAX];
+    for (int k = 0; k < (ONE ? 1 : pb.K); ++k) {
+      double xp[NMAX], v[NMAX], d[NMAX], b[NMAX];
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) {
-        if (i >= n) { vn[i] = 0.0; dn[i] = 0.0; continue; }
-        vn[i] = cm[i] * (xp[i] + lam * (d[i] - b[i]));        // (3.4a)
-        double z = vn[i] + b[i];
-        double s = z;
-        if (l1) {                                                 // (3.4b), shrink1
-          double a = th * cw[i];
-          double m = fabs(z) - a;
-          s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
-        }
-        dn[i] = s;
-        ss += s * s;
+        xp[i] = (i < n) ? x[i] - (!ONE && pb.centres ? pb.centres[(size_t)k * pb.ld + i] : 0.0) : 0.0;
+        v[i] = xp[i]; d[i] = xp[i]; b[i] = 0.0;
       }
-      if (l2) {                                                   // (3.4b), shrink2
-        double nr = sqrt(ss);
-        double f = nr > 0.0 ? fmax(nr - th, 0.0) / nr : 0.0;
+      int it = 0;
+      bool conv = false;
+      while (it < pb.max_iter) {
+        ++it;
+        double vn[NMAX], dn[NMAX];
+        double ss = 0.0;
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) dn[i] *= f;
+        for (int i = 0; i < NMAX; ++i) {
+          if (i >= n) { vn[i] = 0.0; dn[i] = 0.0; continue; }
+          vn[i] = cm[i] * (xp[i] + lam * (d[i] - b[i]));        // (3.4a)
+          double z = vn[i] + b[i];
+          double s = z;
+          if (l1) {                                                 // (3.4b), shrink1
+            double a = th * cw[i];
+            double m = fabs(z) - a;
+            s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
+          }
+          dn[i] = s;
+          ss += s * s;
+        }
+        if (l2) {                                                   // (3.4b), shrink2
+          double nr = sqrt(ss);
+          double f = nr > 0.0 ? fmax(nr - th, 0.0) / nr : 0.0;
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i) dn[i] *= f;
+        }
+        if constexpr (WL2) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
+        double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+          if (i >= n) continue;
+          b[i] = b[i] + vn[i] - dn[i];                              // (3.4c)
+          r1 += (vn[i] - v[i]) * (vn[i] - v[i]);
+          r2 += (dn[i] - d[i]) * (dn[i] - d[i]);
+          r3 += (dn[i] - vn[i]) * (dn[i] - vn[i]);
+          v[i] = vn[i]; d[i] = dn[i];
+        }
+        if (r1 <= pb.tol && r2 <= pb.tol && r3 <= pb.tol) { conv = true; break; }
       }
-      if constexpr (WL2) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
-      double r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      // phi_k = <x', d> - 1/2 sum a_i d_i^2 - t H(d)  (- 1/2 for an ellipsoid level set)
+      double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0;
+      double av[NMAX <= kCoefRegs ? NMAX : 1];  // diagonal of A: all loads in flight together
+      if constexpr (NMAX <= kCoefRegs) {
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) av[i] = pb.adiag[i < n ? i : 0];
+      }
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) {
         if (i >= n) continue;
-        b[i] = b[i] + vn[i] - dn[i];                              // (3.4c)
-        r1 += (vn[i] - v[i]) * (vn[i] - v[i]);
-        r2 += (dn[i] - d[i]) * (dn[i] - d[i]);
-        r3 += (dn[i] - vn[i]) * (dn[i] - vn[i]);
-        v[i] = vn[i]; d[i] = dn[i];
+        xd += xp[i] * d[i];
+        double ai;
+        if constexpr (NMAX <= kCoefRegs) ai = av[i];
+        else ai = pb.adiag[i];
+        q += ai * d[i] * d[i];
+        const double wi = cw[i];
+        h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
+        h2 += d[i] * d[i];
       }
-      if (r1 <= pb.tol && r2 <= pb.tol && r3 <= pb.tol) { conv = true; break; }
-    }
-    // phi_k = <x', d> - 1/2 sum a_i d_i^2 - t H(d)  (- 1/2 for an ellipsoid level set)
-    double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0;
-    double av[NMAX <= kCoefRegs ? NMAX : 1];  // diagonal of A: all loads in flight together
-    if constexpr (NMAX <= kCoefRegs) {
+      const double H = wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
+      const double val = xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
+      if (kbest < 0 || val < best) {
+        best = val; bh = H; kbest = k; itbest = conv ? it : -2;
+        if constexpr (!ONE) {
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) av[i] = pb.adiag[i < n ? i : 0];
-    }
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) {
-      if (i >= n) continue;
-      xd += xp[i] * d[i];
-      double ai;
-      if constexpr (NMAX <= kCoefRegs) ai = av[i];
-      else ai = pb.adiag[i];
-      q += ai * d[i] * d[i];
-      const double wi = cw[i];
-      h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
-      h2 += d[i] * d[i];
-    }
-    const double H = wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
-    const double val = xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
-    if (kbest < 0 || val < best) {
-      best = val; bh = H; kbest = k; itbest = conv ? it : -2;
-      if constexpr (!ONE) {
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
+          for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
+        }
       }
+      if constexpr (ONE) store_row(gj, d);
     }
-    if constexpr (ONE) {
-      for (int i = 0; i < n; ++i) gj[i] = (T)d[i];
-    }
+    ((T*)pb.phi)[j] = (T)best;
+    ((T*)pb.dphidt)[j] = (T)(-bh);
+    if constexpr (!ONE) store_row(gj, pbest);
+    if (pb.iters) pb.iters[j] = itbest;
+    if (pb.kstar) pb.kstar[j] = kbest;
   }
-  ((T*)pb.phi)[j] = (T)best;
-  ((T*)pb.dphidt)[j] = (T)(-bh);
-  if constexpr (!ONE) {
-    for (int i = 0; i < n; ++i) gj[i] = (T)pbest[i];
-  }
-  if (pb.iters) pb.iters[j] = itbest;
-  if (pb.kstar) pb.kstar[j] = kbest;
 }
 
 // The squared-norm initial data and H = |.|_inf: iteration counts vary over orders of magnitude
@@ -476,7 +512,10 @@ __global__ void __launch_bounds__(kBlock) diag_ext_kernel(DiagProb pb, int* __re
 template <typename T, int NMAX>
 static hipError_t launch_n(const DiagProb& pb, bool ext, int* counter, int ncu, hipStream_t stream) {
   if (!ext) {
-    const unsigned grid = (unsigned)((pb.npts + kBlock - 1) / kBlock);
+    // grid-stride: at most 8 workgroups per CU (the kernel's occupancy is lower), each thread then
+    // takes several points
+    const int64_t need = (pb.npts + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)std::min<int64_t>(need, (int64_t)8 * ncu);
     if (pb.hkind == HK_WL2)
       hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false>), dim3(grid), dim3(kBlock), 0, stream, pb);
     else if (pb.K == 1 && pb.centres == nullptr)
