@@ -56,27 +56,41 @@ __device__ __forceinline__ void wl2_prox(int n, const double* w, double theta, d
 }
 
 // The breakpoint problems of sections 4.2 and 4.4: the root mu of the decreasing, piecewise-affine
-// f(mu) = a S(mu) - b mu - c, S(mu) = sum_i (u_i - mu)_+ (u_i = |z_i| >= 0), given f(0) > 0 >
-// f(max u).  The paper sorts the breakpoints {0, u_i} and searches them; a thread instead tests
-// every breakpoint (O(n^2), all indices static so nothing leaves registers): with L the largest
-// breakpoint where f >= 0, the root lies in the affine piece after L, whose active set is
-// {i : u_i > L}, so a (sum_act u_i - m mu) - b mu - c = 0 gives mu directly.
+// f(mu) = a S(mu) - b mu - c, S(mu) = sum_i (u_i - mu)_+ (u_i = |z_i| >= 0, 0 beyond n), given
+// f(0) > 0 > f(max u).  As in the paper, the breakpoints are sorted and searched: u is sorted in
+// place, descending, by a bitonic network (all indices static, so nothing leaves registers); then
+// S at the k-th largest breakpoint is P_k - k u_(k) with P_k the sum of the k larger ones, and
+// since f increases along the descending breakpoints, the first with f >= 0 is the largest such
+// one, L.  The root lies in the affine piece after L, whose active set is {i : u_i > L}, so
+// a (sum_act u_i - m mu) - b mu - c = 0 gives mu directly.
 template <int NMAX>
-__device__ __forceinline__ double breakpoint_root(const double* u, int n, double a, double b, double c) {
-  double L = 0.0;
+__device__ __forceinline__ double breakpoint_root(double* u, double a, double b, double c) {
+  static_assert((NMAX & (NMAX - 1)) == 0, "the sorting network needs a power of two");
+#pragma unroll
+  for (int size = 2; size <= NMAX; size <<= 1)
+#pragma unroll
+    for (int stride = size / 2; stride > 0; stride >>= 1)
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        const int l = i ^ stride;
+        if (l > i) {
+          const double x = u[i], y = u[l];
+          const bool desc = (i & size) == 0 || size == NMAX;
+          u[i] = desc ? fmax(x, y) : fmin(x, y);
+          u[l] = desc ? fmin(x, y) : fmax(x, y);
+        }
+      }
+  double L = 0.0, P = 0.0;
+  bool found = false;
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
-    if (k >= n) continue;
-    double S = 0.0;
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i)
-      if (i < n) S += fmax(u[i] - u[k], 0.0);
-    if (a * S - b * u[k] - c >= 0.0 && u[k] > L) L = u[k];
+    if (!found && u[k] > 0.0 && a * (P - k * u[k]) - b * u[k] - c >= 0.0) { L = u[k]; found = true; }
+    P += u[k];
   }
   double sa = 0.0, m = 0.0;
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
-    if (i < n && u[i] > L) { sa += u[i]; m += 1.0; }
+    if (u[i] > L) { sa += u[i]; m += 1.0; }
   return (a * sa - c) / (a * m + b);
 }
 
@@ -92,7 +106,7 @@ __device__ __forceinline__ void linf_prox(int n, double theta, double* z) {
     for (int i = 0; i < NMAX; ++i) z[i] = 0.0;
     return;
   }
-  const double mu = breakpoint_root<NMAX>(u, n, 1.0, 0.0, theta);
+  const double mu = breakpoint_root<NMAX>(u, 1.0, 0.0, theta);
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) z[i] = fmin(fmax(z[i], -mu), mu);
 }
@@ -108,7 +122,7 @@ __device__ __forceinline__ void normsq_vupdate(int n, int jkind, double lam, dou
   for (int i = 0; i < NMAX; ++i) { u[i] = i < n ? fabs(w[i]) : 0.0; s1 += u[i]; }
   if (!(s1 > 0.0)) return;  // w = 0: the prox is 0
   const double a = jkind == JK_LINFSQ ? 1.0 / lam : lam;
-  const double beta = breakpoint_root<NMAX>(u, n, a, 1.0, 0.0);
+  const double beta = breakpoint_root<NMAX>(u, a, 1.0, 0.0);
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     const double c = fmin(fmax(w[i], -beta), beta);
