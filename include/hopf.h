@@ -98,7 +98,7 @@ typedef enum {
   HOPF_F32 = 1,          /* float I/O; FP32 state and FP32 MFMA products */
   HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined by
                             anchor products every few iterations that are exact up to
-                            ~2^-32 of the row and column scales (integer slices) */
+                            ~2^-31 of the row and column scales (integer slices) */
 } hopf_precision;
 
 typedef struct {

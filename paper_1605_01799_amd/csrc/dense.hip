@@ -22,7 +22,7 @@
 //   REFINED  BF16 MFMA (16x16x32) products, FP32 accumulate, applied to the
 //            INCREMENT r^k - r^a since an anchor state; the anchor product
 //            v^a = M r^a is formed every `anchor_every` iterations from the
-//            FP64 r^a, exactly up to ~2^-32 of its row and column scales, as
+//            FP64 r^a, exactly up to ~2^-31 of its row and column scales, as
 //            int8 MFMA (16x16x64) products of integer slices of M and r^a
 //            with exact int32 accumulation.  The state is kept as an FP32
 //            anchor za plus an FP32 increment dz (z = za + dz), with
@@ -173,10 +173,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       // FP64 (the workgroup's staging, column-major, n_pad per column) and the product is taken in
       // integer slices (the kSlices definitions): M and r^a are split into kSlices 7-bit slices
       // under per-row and per-column power-of-two scales, and the slice products with
-      // a + b <= kSlices + 1 (1-based) are accumulated exactly.  The dropped terms and the
-      // truncated slices leave at most ~ n_pad 2^(-7 kSlices) of 2^(e_i + f_c), i.e. about 2^-32
-      // of max_k |M_ik| max_k |r_kc| at n_pad = 1024 in the worst case: far below what the anchor
-      // has to resolve, while the int8 products run many times faster than FP64 ones.
+      // a + b <= kSlices + 1 (1-based) are accumulated exactly.  The dropped pairs (a + b = 8:
+      // five of them, each term below 2^-44 of 2^(e_i + f_c)) and the truncated slices (below
+      // 2^-43 of the scale per entry) leave at most ~ 7 n_pad 2^-44 of 2^(e_i + f_c), about 2^-31
+      // at n_pad = 1024, i.e. 2^-29 of max_k |M_ik| max_k |r_kc| in the worst case: far below what
+      // the anchor has to resolve, while the int8 products run many times faster than FP64 ones.
       {
         double* const ra = ws64 + (int64_t)blockIdx.x * ws64_per_wg;
         const int n64 = pad64(n_pad);
