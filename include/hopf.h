@@ -66,7 +66,7 @@ typedef enum {
   HOPF_H_L2 = 1,      /* H(p) = ||p||_2                    (support function of a ball) */
   HOPF_H_L2_WL1 = 2,  /* H(p) = ||p||_2 + sum_i w_i |p_i|  (their Minkowski sum)        */
   HOPF_H_WL2 = 3,     /* H(p) = sqrt(sum_i w_i p_i^2), w_i > 0: the norm sqrt(<p, D p>),
-                         D = diag(w), of section 4.4 (support function of the ellipsoid
+                         D = diag(w), of section 4.3 (support function of the ellipsoid
                          sum_i y_i^2 / w_i <= 1).  Its prox is z minus the projection onto
                          that ellipsoid (eq. (prox-projection)), one Newton solve for the
                          Lagrange multiplier per iteration.  Supported where a point's
@@ -74,7 +74,7 @@ typedef enum {
                          (any precision), or HOPF_F32 with n <= 64; other problems are
                          rejected with HOPF_EINVAL at create time. */
   HOPF_H_AL2 = 4,     /* H(p) = sqrt(<p, HA p>) for a full SPD matrix HA (the norm ||.||_A of
-                         section 4.4; HA in the descriptor).  The library diagonalises HA on the
+                         section 4.3; HA in the descriptor).  The library diagonalises HA on the
                          device (HA = P diag(s) P^T, FP64 Jacobi) and holds the problem in that
                          basis, where H is HOPF_H_WL2 with weights s, A becomes P^T A P and the
                          centres P^T c; points are rotated in before the solve and gradients /
@@ -148,7 +148,8 @@ hopf_status hopf_problem_destroy(hopf_problem_t problem);
  * v0 = d0 = x - c_k, b0 = 0).  Inputs: x (npts*n), t (npts, > 0).  Outputs:
  * phi (npts), grad (npts*n) = p* of the attaining copy, dphidt (npts) =
  * -H(p*), iters (npts, nullable), kstar (npts, nullable; lowest index
- * attaining the min over k).  A point stops when the squared change of the
+ * attaining the min over k).  npts * K must stay below 2^31 (HOPF_EINVAL
+ * otherwise).  A point stops when the squared change of the
  * split-Bregman iterate between two iterations, summed over the last two
  * iterations as (sqrt(a) + sqrt(b))^2, is <= tol; this bounds all three
  * squared norms of the stopping test of section 4.5 by tol.  npts == 0 is a
@@ -167,13 +168,19 @@ hopf_status hopf_eval(hopf_problem_t problem, int64_t npts, const void* x, const
  * -2 if a cap was hit, -1 for a non-finite y).  s_tol: Newton stops when
  * |s_{l+1} - s_l| <= s_tol * max(1, s).  Every inner solve has its own
  * max_iter budget; a solve that hits it (or stalls, HOPF_F32) still gives
- * the Newton step, and the point is then reported with newton = -2. */
+ * the Newton step, and the point is then reported with newton = -2.
+ * npts * K must stay below 2^31 (HOPF_EINVAL otherwise). */
 hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void* y, double s_tol,
                                void* dist, void* cp, int32_t* kstar, int32_t* inside,
                                int32_t* newton, void* stream);
 
 /* Ragged batch: nprob problems (any n, K, A, w; one precision for all, not
- * HOPF_F64) evaluated in one launch sequence.  pt_offset (host, nprob+1)
+ * HOPF_F64; the ellipsoidal norms only with HOPF_F32 and n <= 64; no
+ * HOPF_H_LINF or squared-norm J).  The problems are grouped into kernel
+ * classes by padded size (the launch shape of each class); each class is one
+ * persistent launch over its problems' points, and the host waits for one
+ * class's launch before it enqueues the next (they share the per-device
+ * workspace).  Every problem's npts * K must stay below 2^31.  pt_offset (host, nprob+1)
  * gives the points of problem q as [pt_offset[q], pt_offset[q+1]); x_packed
  * holds the points of problem q contiguously starting at element
  * sum_{r<q} (pt_offset[r+1]-pt_offset[r]) * n_r, and grad_packed likewise.

@@ -96,7 +96,7 @@ static double shrink1(double z, double a) {
 }
 
 /* H(p) for the supported family (support functions of a box, a ball, their Minkowski sum, and
- * of the ellipsoid sum y_i^2 / w_i <= 1: the norm sqrt(<p, D p>) with D = diag(w), section 4.4). */
+ * of the ellipsoid sum y_i^2 / w_i <= 1: the norm sqrt(<p, D p>) with D = diag(w), section 4.3). */
 static double ham(const oh_problem* pb, int hkind, const double* p) {
   const int n = pb->n;
   const double* w = pb->w;
@@ -127,7 +127,7 @@ static double ham(const oh_problem* pb, int hkind, const double* p) {
  * L2 + WL1: shrink2(shrink1(z, theta*w), theta), the composition of the two maps
  * (the prox of a sum of a group norm and a separable norm that both act on
  * the same single group). */
-/* prox of theta * sqrt(<., D .>), D = diag(w) > 0 (section 4.4).  By eq. (prox-projection) it is
+/* prox of theta * sqrt(<., D .>), D = diag(w) > 0 (section 4.3).  By eq. (prox-projection) it is
  * z - pi_C(z), C the Wulff shape of theta H: the ellipsoid sum y_i^2 / s_i <= 1 with squared
  * semi-axes s_i = theta^2 w_i.  For z in C the prox is 0.  Otherwise the projection is
  * s_i z_i / (s_i + mu), with mu > 0 the Lagrange multiplier solving sum s_i z_i^2 / (s_i + mu)^2 = 1,
@@ -162,7 +162,7 @@ static void prox_wl2(int n, const double* w, double theta, const double* z, doub
   }
 }
 
-/* prox of theta * sqrt(<., HA .>) for a full SPD HA = Q diag(sig) Q^T (section 4.4, the case
+/* prox of theta * sqrt(<., HA .>) for a full SPD HA = Q diag(sig) Q^T (section 4.3, the case
  * ||.||_A): the Wulff shape is the ellipsoid y^T HA^{-1} y <= 1 and, as the paper states, the
  * projection onto it is Q pi_D(Q^T w) with pi_D the projection onto the axis-aligned ellipsoid of
  * the eigenvalues; so d = z - Q pi_D(Q^T z) = Q (u - pi_D(u)), u = Q^T z, the diagonal prox in

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhopf.so")
-SOURCES = ["setup.hip", "dense.hip", "dense_small.hip", "diag.hip", "backward.hip", "rotate.hip", "control.hip", "api.hip"]
+SOURCES = ["checks.cpp", "setup.hip", "dense.hip", "dense_small.hip", "diag.hip", "backward.hip", "rotate.hip", "control.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions in any kernel
@@ -25,7 +25,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()

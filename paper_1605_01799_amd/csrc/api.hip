@@ -14,6 +14,7 @@
 
 #include "../../include/hopf.h"
 #include "backward.hpp"
+#include "checks.hpp"
 #include "common.hpp"
 #include "dense.hpp"
 #include "control.hpp"
@@ -150,71 +151,15 @@ static int env_int(const char* name, int dflt) {
 // create / destroy
 // ---------------------------------------------------------------------------
 static hopf_status validate(const hopf_problem_desc* d) {
-  if (!d) return fail(HOPF_EINVAL, "desc is NULL");
-  if (d->n < 1 || d->n > 2048) return fail(HOPF_EINVAL, "n = %d outside [1, 2048]", d->n);
-  if (d->K < 1 || d->K > 64) return fail(HOPF_EINVAL, "K = %d outside [1, 64]", d->K);
-  if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) return fail(HOPF_EINVAL, "lambda must be finite and > 0");
-  if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return fail(HOPF_EINVAL, "tol must be finite and >= 0");
-  if (d->max_iter < 1) return fail(HOPF_EINVAL, "max_iter must be >= 1");
-  if (d->hkind < HOPF_H_WL1 || d->hkind > HOPF_H_LINF) return fail(HOPF_EINVAL, "unknown hkind %d", (int)d->hkind);
-  if (d->jkind < HOPF_J_QUADRATIC || d->jkind > HOPF_J_LINFSQ) return fail(HOPF_EINVAL, "unknown jkind %d", (int)d->jkind);
-  if (d->precision < HOPF_F64 || d->precision > HOPF_BF16_REFINED)
-    return fail(HOPF_EINVAL, "unknown precision %d", (int)d->precision);
-  const int n = d->n;
-  if (d->w)
-    for (int i = 0; i < n; ++i)
-      if (!(d->w[i] >= 0.0) || !std::isfinite(d->w[i])) return fail(HOPF_EINVAL, "w[%d] must be finite and >= 0", i);
-      else if (d->hkind == HOPF_H_WL2 && !(d->w[i] > 0.0))
-        return fail(HOPF_EINVAL, "w[%d] must be > 0 for HOPF_H_WL2 (D = diag(w) positive definite)", i);
-  if (d->centres)
-    for (int64_t i = 0; i < (int64_t)d->K * n; ++i)
-      if (!std::isfinite(d->centres[i])) return fail(HOPF_EINVAL, "centres[%lld] is not finite", (long long)i);
-  const bool normsq = d->jkind != HOPF_J_QUADRATIC;
-  const bool diag = normsq || d->A == nullptr || d->A_is_diagonal;
-  if (d->A && !normsq) {
-    const int64_t m = d->A_is_diagonal ? n : (int64_t)n * n;
-    for (int64_t i = 0; i < m; ++i)
-      if (!std::isfinite(d->A[i])) return fail(HOPF_EINVAL, "A[%lld] is not finite", (long long)i);
-    if (d->A_is_diagonal) {
-      for (int i = 0; i < n; ++i)
-        if (!(d->A[i] > 0.0)) return fail(HOPF_ENOTSPD, "diagonal A[%d] = %g is not > 0", i, d->A[i]);
-    } else {
-      for (int i = 0; i < n; ++i)
-        for (int j = 0; j < i; ++j) {
-          double a = d->A[(size_t)i * n + j], b = d->A[(size_t)j * n + i];
-          if (std::fabs(a - b) > 1e-12 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))))
-            return fail(HOPF_EINVAL, "A is not symmetric at (%d, %d)", i, j);
-        }
-    }
-  }
-  if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
-    return fail(HOPF_EINVAL, "HOPF_F64 supports diagonal A with n <= %d; use HOPF_F32 or HOPF_BF16_REFINED", kDiagMaxN);
-  // the ellipsoid projection needs whole-column reductions inside its Newton loop: supported by
-  // the per-thread diagonal kernel and the wave-local small dense kernel
-  if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= 64)))
-    return fail(HOPF_EINVAL, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= 64", kDiagMaxN);
-  // the breakpoint searches run in the per-thread kernel
-  if (normsq && (n > kDiagMaxN || d->precision == HOPF_BF16_REFINED))
-    return fail(HOPF_EINVAL, "squared-norm J supports n <= %d with HOPF_F64 or HOPF_F32", kDiagMaxN);
-  if (d->hkind == HOPF_H_LINF && !(diag && n <= kDiagMaxN && d->precision != HOPF_BF16_REFINED))
-    return fail(HOPF_EINVAL, "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32",
-                kDiagMaxN);
-  if (normsq && d->hkind == HOPF_H_AL2) return fail(HOPF_EINVAL, "HOPF_H_AL2 needs the quadratic J");
-  if (d->hkind == HOPF_H_AL2) {
-    // solved in HA's eigenbasis, where A becomes dense: the wave-local FP32 kernel
-    if (d->precision != HOPF_F32 || n > kRotMaxN)
-      return fail(HOPF_EINVAL, "HOPF_H_AL2 supports HOPF_F32 with n <= %d", kRotMaxN);
-    if (!d->HA) return fail(HOPF_EINVAL, "HOPF_H_AL2 needs the matrix HA");
-    for (int64_t i = 0; i < (int64_t)n * n; ++i)
-      if (!std::isfinite(d->HA[i])) return fail(HOPF_EINVAL, "HA[%lld] is not finite", (long long)i);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < i; ++j) {
-        double a = d->HA[(size_t)i * n + j], b = d->HA[(size_t)j * n + i];
-        if (std::fabs(a - b) > 1e-12 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))))
-          return fail(HOPF_EINVAL, "HA is not symmetric at (%d, %d)", i, j);
-      }
-  }
-  return HOPF_OK;
+  char why[512];
+  const hopf_status st = check_desc(d, why, sizeof why);
+  return st ? fail(st, "%s", why) : HOPF_OK;
+}
+
+static hopf_status validate_columns(int64_t npts, int32_t K) {
+  char why[256];
+  const hopf_status st = check_columns(npts, K, why, sizeof why);
+  return st ? fail(st, "%s", why) : HOPF_OK;
 }
 
 static void free_problem(hopf_problem* p) {
@@ -678,10 +623,9 @@ static hopf_status run_dense_rotated(std::vector<DenseCall>& calls, int mode, in
 extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, const void* t, void* phi,
                                  void* grad, void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
   if (!p) return fail(HOPF_EINVAL, "problem is NULL");
-  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (hopf_status cs = validate_columns(npts, p->K)) return cs;
   if (npts == 0) return HOPF_OK;
   if (!x || !t || !phi || !grad || !dphidt) return fail(HOPF_EINVAL, "NULL array argument");
-  if (npts > ((int64_t)1 << 31) - 1) return fail(HOPF_EINVAL, "npts too large");
   hipStream_t s = (hipStream_t)stream;
   if (p->diagonal && p->n <= kDiagMaxN) {
     DiagProb dp;
@@ -760,7 +704,7 @@ extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const 
   if (p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "closest point needs the quadratic J (ellipsoids)");
   if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "closest point needs HOPF_F32 or HOPF_BF16_REFINED");
   if (!(s_tol > 0.0) || !std::isfinite(s_tol)) return fail(HOPF_EINVAL, "s_tol must be finite and > 0");
-  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (hopf_status cs = validate_columns(npts, p->K)) return cs;
   if (npts == 0) return HOPF_OK;
   if (!y || !dist || !cp || !kstar) return fail(HOPF_EINVAL, "NULL array argument");
   std::vector<DenseCall> calls(1);
@@ -785,12 +729,12 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
   for (int q = 0; q < nprob; ++q) {
     hopf_problem* p = probs[q];
     if (!p) return fail(HOPF_EINVAL, "problem %d is NULL", q);
-    if (p->precision != prec) return fail(HOPF_EINVAL, "problems of a ragged batch must share one precision");
-    if (prec == HOPF_F64) return fail(HOPF_EINVAL, "ragged batches need HOPF_F32 or HOPF_BF16_REFINED");
-    if (p->jkind != HOPF_J_QUADRATIC || p->hkind == HOPF_H_LINF)
-      return fail(HOPF_EINVAL, "problem %d: squared-norm J and HOPF_H_LINF run per point (hopf_eval), not in ragged batches", q);
+    char why[256];
+    if (hopf_status cs = check_ragged_member(q, p->precision, prec, p->hkind, p->jkind, p->n, why, sizeof why))
+      return fail(cs, "%s", why);
     const int64_t np = pt_offset[q + 1] - pt_offset[q];
     if (np < 0) return fail(HOPF_EINVAL, "pt_offset must be nondecreasing");
+    if (hopf_status cs = check_columns(np, p->K, why, sizeof why)) return fail(cs, "problem %d: %s", q, why);
     DenseCall c;
     c.p = p;
     c.view = make_view(p);

@@ -1,0 +1,130 @@
+// Host-side argument checks of the C ABI (declarations and rules in checks.hpp).
+#include "checks.hpp"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace hopf {
+
+static hopf_status say(hopf_status st, char* why, size_t len, const char* fmt, ...) {
+  if (why && len > 0) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(why, len, fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+static bool symmetric(const double* S, int n, int* bi, int* bj) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double a = S[(size_t)i * n + j], b = S[(size_t)j * n + i];
+      if (std::fabs(a - b) > 1e-12 * std::fmax(1.0, std::fmax(std::fabs(a), std::fabs(b)))) {
+        *bi = i; *bj = j;
+        return false;
+      }
+    }
+  return true;
+}
+
+hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
+  if (!d) return say(HOPF_EINVAL, why, len, "desc is NULL");
+  if (d->n < 1 || d->n > kMaxN) return say(HOPF_EINVAL, why, len, "n = %d outside [1, %d]", d->n, kMaxN);
+  if (d->K < 1 || d->K > kMaxK) return say(HOPF_EINVAL, why, len, "K = %d outside [1, %d]", d->K, kMaxK);
+  if (!(d->lambda > 0.0) || !std::isfinite(d->lambda))
+    return say(HOPF_EINVAL, why, len, "lambda must be finite and > 0");
+  if (!(d->tol >= 0.0) || !std::isfinite(d->tol)) return say(HOPF_EINVAL, why, len, "tol must be finite and >= 0");
+  if (d->max_iter < 1) return say(HOPF_EINVAL, why, len, "max_iter must be >= 1");
+  // a C caller may store any int in the enum fields: read them as integers (loading an
+  // out-of-range value through the C++ enum type would be undefined)
+  int hk = 0, prec = 0;
+  static_assert(sizeof(d->hkind) == sizeof(int) && sizeof(d->precision) == sizeof(int), "enum fields are ints");
+  std::memcpy(&hk, &d->hkind, sizeof hk);
+  std::memcpy(&prec, &d->precision, sizeof prec);
+  if (hk < HOPF_H_WL1 || hk > HOPF_H_LINF) return say(HOPF_EINVAL, why, len, "unknown hkind %d", hk);
+  if (d->jkind < HOPF_J_QUADRATIC || d->jkind > HOPF_J_LINFSQ)
+    return say(HOPF_EINVAL, why, len, "unknown jkind %d", (int)d->jkind);
+  if (prec < HOPF_F64 || prec > HOPF_BF16_REFINED) return say(HOPF_EINVAL, why, len, "unknown precision %d", prec);
+  const int n = d->n;
+  if (d->w)
+    for (int i = 0; i < n; ++i) {
+      if (!(d->w[i] >= 0.0) || !std::isfinite(d->w[i]))
+        return say(HOPF_EINVAL, why, len, "w[%d] must be finite and >= 0", i);
+      if (d->hkind == HOPF_H_WL2 && !(d->w[i] > 0.0))
+        return say(HOPF_EINVAL, why, len, "w[%d] must be > 0 for HOPF_H_WL2 (D = diag(w) positive definite)", i);
+    }
+  if (d->centres)
+    for (int64_t i = 0; i < (int64_t)d->K * n; ++i)
+      if (!std::isfinite(d->centres[i])) return say(HOPF_EINVAL, why, len, "centres[%lld] is not finite", (long long)i);
+  const bool normsq = d->jkind != HOPF_J_QUADRATIC;
+  const bool diag = normsq || d->A == nullptr || d->A_is_diagonal;
+  if (d->A && !normsq) {
+    const int64_t m = d->A_is_diagonal ? n : (int64_t)n * n;
+    for (int64_t i = 0; i < m; ++i)
+      if (!std::isfinite(d->A[i])) return say(HOPF_EINVAL, why, len, "A[%lld] is not finite", (long long)i);
+    if (d->A_is_diagonal) {
+      for (int i = 0; i < n; ++i)
+        if (!(d->A[i] > 0.0)) return say(HOPF_ENOTSPD, why, len, "diagonal A[%d] = %g is not > 0", i, d->A[i]);
+    } else {
+      int bi = 0, bj = 0;
+      if (!symmetric(d->A, n, &bi, &bj)) return say(HOPF_EINVAL, why, len, "A is not symmetric at (%d, %d)", bi, bj);
+    }
+  }
+  if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
+    return say(HOPF_EINVAL, why, len,
+               "HOPF_F64 supports diagonal A with n <= %d; use HOPF_F32 or HOPF_BF16_REFINED", kDiagMaxN);
+  // the ellipsoid projection needs whole-column reductions inside its Newton loop: supported by
+  // the per-thread diagonal kernel and the wave-local small dense kernel
+  if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= kSmallMaxN)))
+    return say(HOPF_EINVAL, why, len, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= %d",
+               kDiagMaxN, kSmallMaxN);
+  // the breakpoint searches run in the per-thread kernel
+  if (normsq && (n > kDiagMaxN || d->precision == HOPF_BF16_REFINED))
+    return say(HOPF_EINVAL, why, len, "squared-norm J supports n <= %d with HOPF_F64 or HOPF_F32", kDiagMaxN);
+  if (d->hkind == HOPF_H_LINF && !(diag && n <= kDiagMaxN && d->precision != HOPF_BF16_REFINED))
+    return say(HOPF_EINVAL, why, len,
+               "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32", kDiagMaxN);
+  if (normsq && d->hkind == HOPF_H_AL2) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the quadratic J");
+  if (d->hkind == HOPF_H_AL2) {
+    // solved in HA's eigenbasis, where A becomes dense: the wave-local FP32 kernel
+    if (d->precision != HOPF_F32 || n > kRotMaxN)
+      return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 supports HOPF_F32 with n <= %d", kRotMaxN);
+    if (!d->HA) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the matrix HA");
+    for (int64_t i = 0; i < (int64_t)n * n; ++i)
+      if (!std::isfinite(d->HA[i])) return say(HOPF_EINVAL, why, len, "HA[%lld] is not finite", (long long)i);
+    int bi = 0, bj = 0;
+    if (!symmetric(d->HA, n, &bi, &bj)) return say(HOPF_EINVAL, why, len, "HA is not symmetric at (%d, %d)", bi, bj);
+  }
+  return HOPF_OK;
+}
+
+hopf_status check_columns(int64_t npts, int32_t K, char* why, size_t len) {
+  if (npts < 0) return say(HOPF_EINVAL, why, len, "npts < 0");
+  if (K < 1) return say(HOPF_EINVAL, why, len, "K = %d < 1", K);
+  if (npts > kMaxColumns / K)
+    return say(HOPF_EINVAL, why, len, "npts * K = %lld * %d exceeds %lld (split the call)", (long long)npts, K,
+               (long long)kMaxColumns);
+  return HOPF_OK;
+}
+
+hopf_status check_ragged_member(int32_t q, int32_t precision, int32_t batch_precision, int32_t hkind, int32_t jkind,
+                                int32_t n, char* why, size_t len) {
+  if (precision != batch_precision)
+    return say(HOPF_EINVAL, why, len, "problem %d: problems of a ragged batch must share one precision", q);
+  if (precision == HOPF_F64)
+    return say(HOPF_EINVAL, why, len, "problem %d: ragged batches need HOPF_F32 or HOPF_BF16_REFINED", q);
+  if (jkind != HOPF_J_QUADRATIC || hkind == HOPF_H_LINF)
+    return say(HOPF_EINVAL, why, len,
+               "problem %d: squared-norm J and HOPF_H_LINF run per point (hopf_eval), not in ragged batches", q);
+  // the ellipsoid projection runs only where a point stays in one wave
+  if ((hkind == HOPF_H_WL2 || hkind == HOPF_H_AL2) && !(precision == HOPF_F32 && n <= kSmallMaxN))
+    return say(HOPF_EINVAL, why, len,
+               "problem %d: the ellipsoidal norms run in ragged batches with HOPF_F32 and n <= %d only", q,
+               kSmallMaxN);
+  return HOPF_OK;
+}
+
+}  // namespace hopf

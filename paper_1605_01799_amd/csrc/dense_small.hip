@@ -314,7 +314,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         gd[ct] = (first || !HL2) ? 1.f : gam[ct];
       }
       // sqrt(<p, D p>): prox_{theta H}(z) = z - pi(z), pi the projection onto the ellipsoid
-      // sum y_i^2 / s_i <= 1 with s_i = theta^2 w_i (section 4.4, eq. (prox-projection)):
+      // sum y_i^2 / s_i <= 1 with s_i = theta^2 w_i (section 4.3, eq. (prox-projection)):
       // 0 for z inside, else d_i = mu z_i / (s_i + mu) with mu > 0 solving
       // phi(mu) = sum s_i z_i^2 / (s_i + mu)^2 = 1.  Newton runs on 1 / sqrt(phi) - 1 (concave and
       // increasing in mu, so from mu = 0 the steps increase monotonically to the root, exactly in

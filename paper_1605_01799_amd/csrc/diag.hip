@@ -19,7 +19,7 @@ namespace hopf {
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// In place: z <- prox of theta sqrt(<., D .>), D = diag(w) (section 4.4): z minus its projection
+// In place: z <- prox of theta sqrt(<., D .>), D = diag(w) (section 4.3): z minus its projection
 // onto the Wulff ellipsoid sum y_i^2 / s_i <= 1, s_i = theta^2 w_i (eq. (prox-projection)).  Zero
 // inside; otherwise z_i mu / (s_i + mu) with mu > 0 the root of phi(mu) = sum s_i z_i^2 /
 // (s_i + mu)^2 = 1, by Newton on 1 / sqrt(phi) - 1 (concave and increasing: monotone from mu = 0,

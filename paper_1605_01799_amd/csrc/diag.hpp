@@ -1,9 +1,9 @@
 #pragma once
+#include "checks.hpp"
 #include "common.hpp"
 
 namespace hopf {
 
-constexpr int kDiagMaxN = 32;
 
 struct DiagProb {
   int n, ld, K, level_set, hkind, max_iter;  // ld: stride of the centre rows

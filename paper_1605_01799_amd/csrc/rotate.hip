@@ -1,4 +1,4 @@
-// The eigenbasis of the Hamiltonian's matrix for H(p) = sqrt(<p, HA p>) (section 4.4, the norm
+// The eigenbasis of the Hamiltonian's matrix for H(p) = sqrt(<p, HA p>) (section 4.3, the norm
 // ||.||_A).  The paper projects onto the Wulff ellipsoid of HA as P pi_D(P^T w), HA = P D P^T.
 // Here the rotation is applied to the whole problem once instead of twice per iteration: with
 // p = P q,

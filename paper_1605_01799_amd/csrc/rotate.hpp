@@ -1,10 +1,9 @@
 #pragma once
+#include "checks.hpp"
 #include "common.hpp"
 
 namespace hopf {
 
-// Largest n of a problem with H = sqrt(<p, HA p>) (its solver holds a point in one wave).
-constexpr int kRotMaxN = 64;
 
 // HA (n x n, FP64, device) = P diag(sig) P^T; P row-major with the eigenvectors as columns.
 // *sweeps receives the number of Jacobi sweeps taken.

@@ -252,14 +252,50 @@ def max_over_hamiltonians(outs: Sequence[dict], stream=None):
     return res
 
 
+def _held_like(problem: Problem, which: str, like: torch.Tensor) -> torch.Tensor:
+    """The problem's own A (n x n, or its n diagonal entries) or centres (K x n), as a tensor of
+    like's dtype and device: what the forward actually solves with."""
+    if which == "A":
+        if problem.A is None:
+            held = np.eye(problem.n) if like.dim() == 2 else np.ones(problem.n)
+        elif problem.diagonal and like.dim() == 2:
+            held = np.diag(problem.A)
+        else:
+            held = problem.A
+    else:
+        held = problem.centres if problem.centres is not None else np.zeros((problem.K, problem.n))
+    return torch.as_tensor(np.asarray(held), dtype=like.dtype, device=like.device)
+
+
+def _check_held(problem: Problem, which: str, value):
+    """The autograd inputs A and centres must be the problem's own: the forward solves with the
+    matrices the problem was created with, so a different tensor would get phi and gradients of
+    another problem."""
+    if value is None:
+        return
+    if not isinstance(value, torch.Tensor):
+        raise TypeError("%s must be a tensor" % which)
+    held = _held_like(problem, which, value.detach())
+    if tuple(value.shape) != tuple(held.shape):
+        raise ValueError("%s has shape %s; the problem holds %s" % (which, tuple(value.shape), tuple(held.shape)))
+    if not torch.equal(value.detach(), held):
+        raise ValueError("%s differs from the problem's own (create a new Problem for new values)" % which)
+
+
 class HopfValue(torch.autograd.Function):
     """phi(x, t; A, centres) with envelope-theorem gradients wrt x, t, A and centres.
-    Only phi is differentiable; grad and dphidt are returned detached."""
+    Only phi is differentiable; grad and dphidt are returned detached.  A and centres must hold
+    the problem's own values (checked); gA comes back in A's shape and dtype (the diagonal of the
+    gradient for a diagonal A given as a vector)."""
 
     @staticmethod
     def forward(ctx, x, t, A, centres, problem: Problem):
+        _check_held(problem, "A", A)
+        _check_held(problem, "centres", centres)
         out = problem.eval(x.detach(), t.detach())
         ctx.problem = problem
+        ctx.a_meta = None if A is None else (tuple(A.shape), A.dtype)
+        ctx.c_dtype = None if centres is None else centres.dtype
         ctx.save_for_backward(out["grad"], out["dphidt"], out["kstar"])
         ctx.mark_non_differentiable(out["grad"], out["dphidt"])
         return out["phi"], out["grad"], out["dphidt"]
@@ -279,7 +315,12 @@ class HopfValue(torch.autograd.Function):
             want.append("gc")
         b = prob.backward(gphi.contiguous().float(), grad, dphidt, kstar, want=tuple(want))
         gA = b.get("gA")
+        if gA is not None:
+            shape, dt = ctx.a_meta
+            gA = (torch.diagonal(gA) if len(shape) == 1 else gA).to(dt)
         gc = b.get("gc")
+        if gc is not None:
+            gc = gc.to(ctx.c_dtype)
         return b.get("gx"), b.get("gt"), gA, gc, None
 
 

@@ -1,4 +1,4 @@
-"""GPU parity for H = sqrt(<p, HA p>) with a full SPD matrix HA (section 4.4, the norm ||.||_A):
+"""GPU parity for H = sqrt(<p, HA p>) with a full SPD matrix HA (section 4.3, the norm ||.||_A):
 the problem is diagonalised on the device (FP64 Jacobi), solved in HA's eigenbasis by the
 wave-local FP32 kernel and rotated back.  Compared element by element with the FP64 oracle
 (which projects in the eigenbasis and rotates back every iteration, as the paper states it)."""

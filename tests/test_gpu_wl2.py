@@ -1,4 +1,4 @@
-"""GPU parity for H = sqrt(<p, D p>), D = diag(w) (section 4.4): the HIP path through the C ABI
+"""GPU parity for H = sqrt(<p, D p>), D = diag(w) (section 4.3): the HIP path through the C ABI
 against the FP64 oracle, element by element, on seeded inputs.  Covered paths: the per-thread
 diagonal kernel (FP64 and FP32 I/O) in the setting of the paper's timing tables, and the
 wave-local dense kernel (FP32, n <= 64) on dense SPD A, unions of level sets, the paper's

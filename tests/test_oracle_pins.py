@@ -165,7 +165,7 @@ def al2_kkt_residual(A, HA, x, t, p):
 
 
 def test_al2_pins(oracle_lib):
-    """H = sqrt(<p, HA p>) with a full SPD HA (section 4.4, ||.||_A): KKT at convergence (also
+    """H = sqrt(<p, HA p>) with a full SPD HA (section 4.3, ||.||_A): KKT at convergence (also
     for points inside t C), the duality-gap bracket, HA = c I against l2 at time sqrt(c) t, and
     covariance under a rotation R of the whole problem (A -> R A R^T, HA -> R HA R^T, x -> R x:
     phi unchanged, p -> R p), which exercises the rotation into HA's eigenbasis."""
