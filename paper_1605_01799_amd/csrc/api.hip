@@ -760,8 +760,8 @@ extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void*
   if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "backward needs HOPF_F32 or HOPF_BF16_REFINED");
   if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
   if (npts > 0 && (!gphi || !grad_saved)) return fail(HOPF_EINVAL, "gphi and grad_saved are required");
-  if (gt && !dphidt_saved) return fail(HOPF_EINVAL, "gt needs dphidt_saved");
-  if (gc && p->K > 1 && !kstar_saved) return fail(HOPF_EINVAL, "gc needs kstar_saved when K > 1");
+  if (npts > 0 && gt && !dphidt_saved) return fail(HOPF_EINVAL, "gt needs dphidt_saved");
+  if (npts > 0 && gc && p->K > 1 && !kstar_saved) return fail(HOPF_EINVAL, "gc needs kstar_saved when K > 1");
   if (gA && p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "gA needs the quadratic J");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -769,14 +769,14 @@ extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void*
   hopf_status st = ws_get(dev, &w);
   if (st) return st;
   std::lock_guard<std::mutex> lk(w->mu);
-  const int nsplit = backward_splits(npts);
-  const size_t need = sizeof(double) * (size_t)nsplit * ((size_t)p->n * p->n + (size_t)p->K * p->n);
-  if ((st = ws_grow((void**)&w->scratch, &w->scratch_bytes, need))) return st;
+  const BackwardPlan plan = backward_plan(npts, p->n, p->K, gA != nullptr, gc != nullptr, (size_t)-1);
+  if ((st = ws_grow((void**)&w->scratch, &w->scratch_bytes, std::max<size_t>(plan.bytes_a + plan.bytes_c, 256))))
+    return st;
   BackwardArgs a;
   a.npts = npts; a.n = p->n; a.K = p->K;
   a.g = (const float*)gphi; a.grad = (const float*)grad_saved; a.dphidt = (const float*)dphidt_saved;
   a.kstar = kstar_saved; a.gx = (float*)gx; a.gt = (float*)gt; a.gA = (float*)gA; a.gc = (float*)gc;
-  hipError_t e = launch_backward(a, w->scratch, (hipStream_t)stream);
+  hipError_t e = launch_backward(a, plan, w->scratch, (hipStream_t)stream);
   if (e) return fail(HOPF_EDEVICE, "backward launch: %s", hipGetErrorString(e));
   return HOPF_OK;
 }
