@@ -203,6 +203,24 @@ hopf_status hopf_backward(hopf_problem_t problem, int64_t npts, const void* gphi
                           const int32_t* kstar_saved, void* gx, void* gt, void* gA, void* gc,
                           void* stream);
 
+/* hopf_backward for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same arguments, results
+ * and kernels, with the split partials of the sums in a fixed 32 MiB device array that
+ * the library holds on every GPU it runs on until the process ends, instead of the
+ * per-device workspace.  No device or host memory is allocated by this call.  The gA
+ * partials of one point range take 16 KiB per 64 x 64 tile of gA's lower triangle and
+ * must fit beside the gc partials (at most a quarter of the array), which holds for
+ * n <= 3456 (every problem the library accepts, n <= 2048); larger sizes would return
+ * HOPF_EINVAL.  Point counts are not limited: the number of point ranges is reduced to
+ * what fits (results then differ from hopf_backward's only by the order of the sums;
+ * for n <= 256 and K <= 8 the counts, and so the bits, are the same).  The array keeps the last call's
+ * contents; every byte a call reads was written by that call.  Calls that overlap on one
+ * GPU (several streams or threads) race on the array: serialise them. */
+hopf_status hopf_backward_noalloc(hopf_problem_t problem, int64_t npts, const void* gphi,
+                                  const void* grad_saved, const void* dphidt_saved,
+                                  const int32_t* kstar_saved, void* gx, void* gt, void* gA, void* gc,
+                                  void* stream);
+
 /* Optimal-control read-out (section 2, optimal control): from the points x (npts*n), times t
  * (npts) and an evaluation's grad (npts*n, p*) and kstar (npts; nullable when K = 1), writes the
  * terminal value xT = c_k* + A p* (the Hopf-Lax minimiser, where p* is a subgradient of J_k*) and

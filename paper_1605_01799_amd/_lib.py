@@ -20,6 +20,7 @@ EXPORTS = [
     "hopf_problem_create", "hopf_problem_create_batch", "hopf_problem_destroy", "hopf_eval",
     "hopf_closest_point", "hopf_eval_ragged", "hopf_backward", "hopf_problem_get_inverse",
     "hopf_problem_info", "hopf_last_error", "hopf_version", "hopf_control", "hopf_max_over_hamiltonians",
+    "hopf_backward_noalloc",
 ]
 
 
@@ -61,6 +62,7 @@ def load():
         "hopf_closest_point": [P, I64, V, D, V, V, V, V, V, V],
         "hopf_eval_ragged": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, V, V, V, V, V, V, V],
         "hopf_backward": [P, I64, V, V, V, V, V, V, V, V, V],
+        "hopf_backward_noalloc": [P, I64, V, V, V, V, V, V, V, V, V],
         "hopf_control": [P, I64, V, V, V, V, V, V, V],
         "hopf_max_over_hamiltonians": [I32, I64, I32, I32, ctypes.POINTER(V), ctypes.POINTER(V),
                                        ctypes.POINTER(V), V, V, V, V, V],

@@ -780,3 +780,59 @@ extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void*
   if (e) return fail(HOPF_EDEVICE, "backward launch: %s", hipGetErrorString(e));
   return HOPF_OK;
 }
+
+// ---------------------------------------------------------------------------
+// backward without allocations: the split partials live in a fixed device array
+// ---------------------------------------------------------------------------
+// Every GPU the library runs on holds this array from the library's first use on it until the
+// process ends.  Host code never passes the array's own name to a kernel (on the host it is a
+// stand-in, not a device address): its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static void* g_scratch_ptr[64];
+static std::mutex g_scratch_mu;
+
+static hopf_status scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HOPF_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_backward_noalloc(hopf_problem_t p, int64_t npts, const void* gphi,
+                                             const void* grad_saved, const void* dphidt_saved,
+                                             const int32_t* kstar_saved, void* gx, void* gt, void* gA, void* gc,
+                                             void* stream) {
+  if (!p) return fail(HOPF_EINVAL, "problem is NULL");
+  if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "backward needs HOPF_F32 or HOPF_BF16_REFINED");
+  if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
+  if (npts > 0 && (!gphi || !grad_saved)) return fail(HOPF_EINVAL, "gphi and grad_saved are required");
+  if (npts > 0 && gt && !dphidt_saved) return fail(HOPF_EINVAL, "gt needs dphidt_saved");
+  if (npts > 0 && gc && p->K > 1 && !kstar_saved) return fail(HOPF_EINVAL, "gc needs kstar_saved when K > 1");
+  if (gA && p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "gA needs the quadratic J");
+  const BackwardPlan plan = backward_plan(npts, p->n, p->K, gA != nullptr, gc != nullptr, kNoAllocScratchBytes);
+  if (!plan.ok || plan.bytes_a + plan.bytes_c > kNoAllocScratchBytes)
+    return fail(HOPF_EINVAL,
+                "hopf_backward_noalloc: n = %d, K = %d needs more than its %zu-byte scratch (one split of the gA "
+                "tiles takes %zu bytes); use hopf_backward",
+                p->n, p->K, kNoAllocScratchBytes, (size_t)plan.ntl * 64 * 64 * sizeof(float));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(HOPF_EDEVICE, "device index %d out of range", dev);
+  void* ptr = nullptr;
+  if (hopf_status st = scratch_address(dev, &ptr)) return st;
+  BackwardArgs a;
+  a.npts = npts; a.n = p->n; a.K = p->K;
+  a.g = (const float*)gphi; a.grad = (const float*)grad_saved; a.dphidt = (const float*)dphidt_saved;
+  a.kstar = kstar_saved; a.gx = (float*)gx; a.gt = (float*)gt; a.gA = (float*)gA; a.gc = (float*)gc;
+  hipError_t e = launch_backward(a, plan, ptr, (hipStream_t)stream);
+  if (e) return fail(HOPF_EDEVICE, "backward launch: %s", hipGetErrorString(e));
+  return HOPF_OK;
+}

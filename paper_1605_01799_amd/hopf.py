@@ -159,7 +159,10 @@ class Problem:
                                            _ptr(out["newton"]), _stream_ptr(stream)))
         return out
 
-    def backward(self, gphi, grad, dphidt, kstar=None, want=("gx", "gt", "gA", "gc"), stream=None):
+    def backward(self, gphi, grad, dphidt, kstar=None, want=("gx", "gt", "gA", "gc"), stream=None,
+                 noalloc=False):
+        """Envelope-theorem gradients (C ABI hopf_backward; hopf_backward_noalloc with noalloc=True,
+        which keeps its partial sums in the library's fixed device array instead of allocating)."""
         npts = grad.shape[0]
         dev = grad.device
         gphi = _device_array(gphi, torch.float32, "gphi", (npts,))
@@ -174,7 +177,8 @@ class Problem:
             out["gA"] = torch.empty(self.n, self.n, dtype=torch.float32, device=dev)
         if "gc" in want:
             out["gc"] = torch.empty(self.K, self.n, dtype=torch.float32, device=dev)
-        check(self._lib.hopf_backward(self._handle, npts, _ptr(gphi), _ptr(grad), _ptr(dphidt), _ptr(kstar),
+        fn = self._lib.hopf_backward_noalloc if noalloc else self._lib.hopf_backward
+        check(fn(self._handle, npts, _ptr(gphi), _ptr(grad), _ptr(dphidt), _ptr(kstar),
                                       _ptr(out.get("gx")), _ptr(out.get("gt")), _ptr(out.get("gA")),
                                       _ptr(out.get("gc")), _stream_ptr(stream)))
         return out
