@@ -35,7 +35,7 @@
  *    status; no state is changed on error.  hopf_last_error() returns a
  *    thread-local description of the last non-OK status.  Per-point problems
  *    are reported in iters[]: >= 1 converged after that many v-updates, -2
- *    the iteration cap was hit, or (HOPF_F32 only) the step norm stopped
+ *    the iteration cap was hit, or (plain FP32 iteration only) the step norm stopped
  *    decreasing for 64 iterations before reaching tol, i.e. the iterate
  *    stalled at FP32 precision (outputs come from the last iterate), -1 a
  *    non-finite input, or t <= 0 or not finite (outputs are NaN).
@@ -95,7 +95,10 @@ typedef enum {
 
 typedef enum {
   HOPF_F64 = 0,          /* double I/O and arithmetic (diagonal A only) */
-  HOPF_F32 = 1,          /* float I/O; FP32 state and FP32 MFMA products */
+  HOPF_F32 = 1,          /* float I/O; FP32 MFMA products and FP32 state on increments,
+                            refined by exact anchor products every few iterations (FP64 MFMA
+                            for n <= 64, integer slices above); the ellipsoidal norms
+                            (HOPF_H_WL2, HOPF_H_AL2) run the plain FP32 iteration */
   HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined by
                             anchor products every few iterations that are exact up to
                             ~2^-31 of the row and column scales (integer slices) */
@@ -167,7 +170,7 @@ hopf_status hopf_eval(hopf_problem_t problem, int64_t npts, const void* x, const
  * and cp = y), newton (npts, nullable: Newton steps of the nearest ellipsoid,
  * -2 if a cap was hit, -1 for a non-finite y).  s_tol: Newton stops when
  * |s_{l+1} - s_l| <= s_tol * max(1, s).  Every inner solve has its own
- * max_iter budget; a solve that hits it (or stalls, HOPF_F32) still gives
+ * max_iter budget; a solve that hits it still gives
  * the Newton step, and the point is then reported with newton = -2.
  * npts * K must stay below 2^31 (HOPF_EINVAL otherwise). */
 hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void* y, double s_tol,

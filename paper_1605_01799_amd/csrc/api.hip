@@ -255,7 +255,10 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP32)"));
   if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
-  if (d->precision == HOPF_BF16_REFINED &&
+  // integer slices of M for the exact anchor products of the refined tile solver (BF16 or FP32
+  // increments); the per-thread diagonal path does not use them
+  const bool diag_path = p->diagonal && n <= kDiagMaxN;
+  if (d->precision != HOPF_F64 && !diag_path &&
       (hipMalloc(&p->d_Mq, (size_t)kSlices * n_pad * pad64(n_pad)) || hipMalloc(&p->d_Mqe, sizeof(int32_t) * n_pad)))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (slices)"));
   if (p->diagonal) {
@@ -459,6 +462,11 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
   // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
   const int anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
+  // the wave-local kernel of FP32 problems: refined increments on exact FP64 anchors (mode 2),
+  // or the plain FP32 iteration (mode 0)
+  const bool small_refined = mode == 2;
+  const int small_anchor_every = std::max(1, env_int("HOPF_SMALL_ANCHOR_EVERY", 32));
+  const int small_anchor_wait = std::max(0, env_int("HOPF_SMALL_ANCHOR_WAIT", 0));
   if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
   // per-point best arrays for every point of the call
   int64_t tot = 0;
@@ -545,8 +553,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
       if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
     }
     const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
-    hipError_t e = small ? launch_dense_small(max_npad, (const DenseProb*)dmeta, dchunks, nchunks, counter, grid,
-                                              stream)
+    hipError_t e = small ? launch_dense_small(max_npad, small_refined, (const DenseProb*)dmeta, dchunks, nchunks,
+                                              counter, grid, small_anchor_every, small_anchor_wait, stream)
                          : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
                                         w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
                                         anchor_wait, stream);
@@ -569,7 +577,14 @@ static DenseProb make_view(hopf_problem* p) {
   return v;
 }
 
-static int mode_of(hopf_problem* p) { return p->precision == HOPF_BF16_REFINED ? 1 : 0; }
+// Solver mode of a precision: 1 BF16 increments on exact anchors; 2 FP32 increments on exact
+// anchors (HOPF_F32; HOPF_F32_PLAIN=1 selects 0, the plain FP32 iteration, for comparison).
+static int mode_for(int precision) {
+  if (precision == HOPF_BF16_REFINED) return 1;
+  static const bool plain = env_int("HOPF_F32_PLAIN", 0) != 0;
+  return plain ? 0 : 2;
+}
+static int mode_of(hopf_problem* p) { return mode_for(p->precision); }
 
 // Points of HOPF_H_AL2 problems are solved in HA's eigenbasis: their x (or y) is rotated into a
 // workspace buffer before the solve, and the solver's gradient (or closest point) is rotated back
@@ -750,7 +765,7 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
     xoff += np * p->n;
     calls.push_back(c);
   }
-  return run_dense_rotated(calls, prec == HOPF_BF16_REFINED ? 1 : 0, 0, (hipStream_t)stream);
+  return run_dense_rotated(calls, mode_for(prec), 0, (hipStream_t)stream);
 }
 
 extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void* gphi, const void* grad_saved,

@@ -17,8 +17,9 @@
 // l2 shrink is applied to the l1-shrunk vector).
 //
 // v^{k+1} = M r^k is the hot contraction: one GEMM of the n x n matrix M with
-// the n x P_t block of right-hand sides per iteration, on MFMA.  Two modes:
-//   F32      z in FP32, FP32 MFMA (16x16x4) products on r.
+// the n x P_t block of right-hand sides per iteration, on MFMA.  Three modes:
+//   F32      z in FP32, FP32 MFMA (16x16x4) products on r (the plain method).
+//   F32 REFINED  as REFINED below with FP32 MFMA (16x16x4) products of FP32 increments.
 //   REFINED  BF16 MFMA (16x16x32) products, FP32 accumulate, applied to the
 //            INCREMENT r^k - r^a since an anchor state; the anchor product
 //            v^a = M r^a is formed every `anchor_every` iterations from the
@@ -44,7 +45,8 @@
 
 namespace hopf {
 
-// MODE 0: FP32 products; MODE 1: BF16 increments + exact anchors.  CT column tiles of 16, RG row
+// MODE 0: FP32 products; MODE 1: BF16 increments + exact anchors; MODE 2: FP32 increments + exact
+// anchors.  CT column tiles of 16, RG row
 // tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
 // OCC workgroups per CU.  With two waves per SIMD (NW = 8, or OCC = 2) each wave keeps at most
 // 256 registers per lane, and one wave's products overlap another's epilogue.
@@ -94,7 +96,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     const int RT = n_pad >> 4;
 
     // ================================================================ anchor (REFINED mode)
-    if (MODE == 1 && S.ctl[CTL_ANCHOR]) {
+    if (MODE >= 1 && S.ctl[CTL_ANCHOR]) {
       // pass A (block order, as the epilogue): renormalise z = za + dz (za the nearest float, dz
       // the remainder), the exact anchor reference s_a in FP64, and the norms of the shrink2 factors
       {
@@ -556,14 +558,14 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     // Block order: wave w takes the row tiles w, w+4, ... of every column tile; lane l works on
     // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
     {
-      const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;
+      const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;  // BF16 (MODE 1) or FP32 right-hand sides
       constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + (l & 15);
         const int st = S.state[c];
         const bool on = st == COL_ACTIVE || st == COL_PHI;
-        const bool deltac = MODE == 1 && S.phase[c] == PH_DELTA;
+        const bool deltac = MODE >= 1 && S.phase[c] == PH_DELTA;
         const bool first = S.flags[c] & FLAG_FIRST;
         const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c], gf = (float)S.gam[c];
         const float th1f = (float)S.th1[c];
@@ -649,7 +651,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const int c = 16 * ct + (l & 15);
         const int st = S.state[c];
         if (st != COL_ACTIVE && st != COL_PHI) continue;
-        const bool delta = MODE == 1 && S.phase[c] == PH_DELTA;
+        const bool delta = MODE >= 1 && S.phase[c] == PH_DELTA;
         const float th1f = (float)S.th1[c];
         // the state of all RG row tiles of this column is requested before any of it is used
         f32x4 zst[RG], dst[RG], est[RG], wst[RG];
@@ -795,8 +797,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       for (int w = 0; w < NW; ++w) { sm[0] += S.red[w][c][0]; sm[1] += S.red[w][c][1]; }
 #pragma unroll
       for (int q = 2; q < kNRed; ++q) sm[q] = S.redv[c][q - 2];
-      const bool delta = MODE == 1 && S.phase[c] == PH_DELTA;
-      const bool stepped = st == COL_ACTIVE || (MODE == 1 && st == COL_PHI);
+      const bool delta = MODE >= 1 && S.phase[c] == PH_DELTA;
+      const bool stepped = st == COL_ACTIVE || (MODE >= 1 && st == COL_PHI);
       bool evaluate = (MODE == 0 && st == COL_PHI);
       if (stepped) {
         S.iters[c] += 1;
@@ -873,7 +875,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         nact += S.state[c] == COL_ACTIVE;
         nwait += S.state[c] == COL_WAITING;
       }
-      if (MODE == 1) {
+      if (MODE >= 1) {
         const int kn = k_it + 1;
         if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0) ||
             (anchor_wait > 0 && nwait >= anchor_wait))
@@ -890,7 +892,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 // ---------------------------------------------------------------------------
 DenseVariant dense_variant(int mode, int n_pad) {
   // refined mode up to n_pad = 1024: two 32-column workgroups of 4 waves per CU (default), or
-  // one 64-column workgroup of 8 waves (HOPF_DENSE=1) or of 4 waves (HOPF_DENSE=2)
+  // one 64-column workgroup of 8 waves (HOPF_DENSE=1) or of 4 waves (HOPF_DENSE=2); FP32 modes
+  // (plain and refined) by size
   static const int pick = [] {
     const char* v = getenv("HOPF_DENSE");
     return v ? atoi(v) : 0;
@@ -908,9 +911,11 @@ DenseVariant dense_variant(int mode, int n_pad) {
 
 size_t dense_lds_bytes(int mode, int n_pad) {
   const int pt = dense_variant(mode, n_pad).pt;
-  // refined: the BF16 right-hand sides, or a block of the anchor right-hand sides' slices
+  // refined: the BF16 (FP32) right-hand sides, or a block of the anchor right-hand sides' slices
   if (mode == 1)
     return std::max((size_t)pt * (n_pad + 8) * 2, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
+  if (mode == 2)
+    return std::max((size_t)pt * (n_pad + 4) * 4, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
   return (size_t)pt * (n_pad + 4) * 4;
 }
 
@@ -957,6 +962,10 @@ hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, co
     if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4);
     if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1, 4);
     if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1, 4);
+  } else if (mode == 2) {
+    if (ct == 4) HOPF_LAUNCH(2, 4, 4, 1, 4);
+    if (ct == 2) HOPF_LAUNCH(2, 2, 4, 1, 4);
+    if (ct == 1) HOPF_LAUNCH(2, 1, 4, 1, 4);
   } else {
     if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1, 4);
     if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1, 4);

@@ -18,12 +18,13 @@ hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, co
                         int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
                         hipStream_t stream);
 
-// Small problems (dense_small.hip): FP32 evaluation of n_pad <= 64, one wave per 64-column tile
-// with the iteration in registers.
+// Small problems (dense_small.hip): FP32 evaluation of n_pad <= 64, one wave per 16-column tile
+// with the iteration in registers; refined: FP32 increments on exact FP64 anchor products.
 bool dense_small_fits(int mode, int n_pad, int distance);
 int dense_small_cols();       // columns per wave
 int dense_small_occupancy();  // workgroups per CU
-hipError_t launch_dense_small(int n_pad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
-                              int* counter, int grid, hipStream_t stream);
+hipError_t launch_dense_small(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              hipStream_t stream);
 
 }  // namespace hopf

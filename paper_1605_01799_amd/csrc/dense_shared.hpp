@@ -29,8 +29,14 @@ __device__ __forceinline__ size_t st_index(int c, int i, int RT) {
 
 __device__ __forceinline__ float clampf(float z, float lo, float hi) { return fminf(fmaxf(z, lo), hi); }
 // FP32 threshold of coordinate i, used for the per-iteration increments (every use of a slot's
-// threshold goes through this one formula, so all of them agree bit for bit).
-__device__ __forceinline__ float theta_f(float th1f, float wf) { return th1f * wf; }
+// threshold goes through this one formula, so all of them agree bit for bit).  The product is
+// rounded here and may not be contracted into a later operation: -th - ca fused into one FMA with
+// the unrounded product would make the increment interval [-th - ca, th - ca] miss 0 by the
+// product's rounding error, and the increments would no longer vanish at a fixed point.
+__device__ __forceinline__ float theta_f(float th1f, float wf) {
+#pragma clang fp contract(off)
+  return th1f * wf;
+}
 // shrink1 of an anchor value in FP64 with the FP64 threshold: the anchor reference d^a must be
 // exact, since every increment of the following iterations is measured from it.
 __device__ __forceinline__ double anchor_shrink(float za, double th1, const double* w, int i) {
@@ -215,8 +221,9 @@ struct ColShared {
   int ctl[16];
 };
 // FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
-// FLAG_CAPPED: some solve of this slot did (reported as -2).
-enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16 };
+// FLAG_CAPPED: some solve of this slot did (reported as -2); FLAG_EXACT: the column has had an
+// exact anchor product (refined wave-local kernel: only then may it stop).
+enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16, FLAG_EXACT = 32 };
 // FP32 mode: the split-Bregman step norm is nonincreasing in exact arithmetic (the iteration
 // map is firmly nonexpansive), so a step that has not reached a new minimum for this many
 // iterations is rounding noise: the iterate has stalled at the working precision.

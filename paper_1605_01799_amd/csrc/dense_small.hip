@@ -13,6 +13,20 @@
 //
 // Columns are (point, copy) pairs; a wave takes chunks of whole points from the launch's queue,
 // so the copies of a point are settled by one wave, in column order.
+//
+// Refined FP32 (REF): plain FP32 products of the whole right-hand side stall at the FP32
+// rounding floor of the fixed point (about kappa(A) u / (1 - rho)).  With REF the iteration is
+// carried, as in the refined tile solver, on an anchor za and an increment dz (z = za + dz):
+// every `anchor_every` passes (and when converged columns wait with nothing else iterating) the
+// wave re-bases za <- za + dz and takes the anchor product v^a = M r^a of the FP64 right-hand
+// side r^a = x' + lambda (2 d^a - za), d^a the prox of za with FP64 thresholds, in FP64 (FP64
+// MFMA 16x16x4 on the FP64 copy of M), and keeps ea = v^a - d^a.  Between anchors a pass
+// computes only increments in FP32: dd = prox(za + dz) - prox(za) from the anchor's shrink
+// decomposition, dr = lambda (2 dd - dz), dv = M dr (FP32 MFMA), and dz <- dz + ea + dv - dd, so
+// every rounding is relative to a vanishing increment and the fixed point is that of the exact
+// product.  A column that passes the stopping test waits for the next anchor and is accepted only
+// if the test still passes on the fresh anchor (its value pass).  The ellipsoidal norm
+// sqrt(<p, D p>) runs the plain FP32 pass.
 #include <cstdint>
 #include <type_traits>
 
@@ -30,8 +44,7 @@ namespace hopf {
 namespace {
 
 // Sum over the four lanes of a column (l, l ^ 16, l ^ 32, l ^ 48), in FP64.
-__device__ __forceinline__ double col_sum(float f) {
-  double v = (double)f;
+__device__ __forceinline__ double col_sum(double v) {
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
   return v;
@@ -58,11 +71,12 @@ constexpr float kWl2Rel = 2.5e-7f;       // a step below this fraction of mu end
 
 }  // namespace
 
-// RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU.
-template <int RTM, int CT, int OCC>
+// RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU, REF the
+// refined FP32 iteration (above).
+template <int RTM, int CT, int OCC, bool REF>
 __global__ void __launch_bounds__(kBlock, OCC)
 dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
-                   int* __restrict__ chunk_counter) {
+                   int* __restrict__ chunk_counter, int anchor_every, int anchor_wait) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   // wave-uniform values go through readfirstlane so that the queue state, the problem's scalars
@@ -79,10 +93,24 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     prob = uni(chunks[c0].prob); nextcol = uni(chunks[c0].col0); cend = nextcol + uni(chunks[c0].ncols);
   }
 
-  // per-problem registers; rows and columns beyond n_pad (n_pad < 16 RTM) are zero in M, w and x',
-  // so their coordinates stay zero and the products need no bounds
+  // per-problem operands; rows and columns beyond n_pad (n_pad < 16 RTM) are zero in M, w and x',
+  // so their coordinates stay zero and the products need no bounds.  M's fragments are held in
+  // registers (plain) or, in the refined kernel (whose state takes more registers), in the wave's
+  // own LDS region, each lane reading back only what it wrote; during an anchor that region
+  // holds the FP64 staging of s^a (the shrink of za) and r^a, [rt * 4 + q][lane] each, and M is
+  // reloaded after it.
   DenseProb pb = probs[prob];
-  f32x4 Mf[RTM][RTM];
+  constexpr int RM = REF ? 1 : RTM;
+  f32x4 Mf[RM][RM];
+  constexpr int kRegion = REF ? (RTM * RTM * 16 > RTM * 4 * 16 ? RTM * RTM * 16 : RTM * 4 * 16) : 16;  // x 64 bytes
+  __shared__ __attribute__((aligned(16))) unsigned char lds_small[REF ? 4 : 1][kRegion * 64];
+  const int wave = REF ? (int)(threadIdx.x >> 6) : 0;
+  f32x4* const Ms = (f32x4*)lds_small[wave];                    // [rt * RTM + kt][64]
+  double* const sbuf = (double*)lds_small[wave];                // [rt * 4 + q][64]
+  double* const rbuf = (double*)lds_small[wave] + RTM * 4 * 64;  // [rt * 4 + q][64]
+  auto mfrag = [&](int rt, int kt) -> f32x4 {
+    return REF ? Ms[(rt * RTM + kt) * 64 + l] : Mf[REF ? 0 : rt][REF ? 0 : kt];
+  };
   f32x4 wv[RTM];
   auto load_problem = [&]() {
     pb = probs[prob];
@@ -93,28 +121,39 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
 #pragma unroll
       for (int kt = 0; kt < RTM; ++kt) {
         const int ktc = kt < nks ? kt : 0;
-        Mf[rt][kt] = (rt < nks && kt < nks) ? *gp((const f32x4*)pb.Mf + ((size_t)rtc * nks + ktc) * 64 + l)
-                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 m = (rt < nks && kt < nks) ? *gp((const f32x4*)pb.Mf + ((size_t)rtc * nks + ktc) * 64 + l)
+                                               : f32x4{0.f, 0.f, 0.f, 0.f};
+        if (REF) Ms[(rt * RTM + kt) * 64 + l] = m;
+        else Mf[REF ? 0 : rt][REF ? 0 : kt] = m;
       }
       wv[rt] = rt < nks ? *gp((const f32x4*)(pb.wf + 16 * rtc + 4 * lg)) : f32x4{0.f, 0.f, 0.f, 0.f};
     }
   };
   load_problem();
 
-  // per-column registers (column 16 ct + lr; replicated in the four lanes of the column)
-  f32x4 z[RTM][CT], xp[RTM][CT];
+  // per-column registers (column 16 ct + lr; replicated in the four lanes of the column).
+  // Plain pass: z the iterate, xp = x' (FP32).  REF: z the anchor za, dz the increment, xp = x'
+  // until the column's first pass and ea = v^a - d^a after it.  p replaces z once the value is taken.
+  constexpr int RD = REF ? RTM : 1;
+  f32x4 z[RTM][CT], xp[RTM][CT], dz[RD][CT];
   int st[CT], flags[CT], iters[CT], stall[CT], jj[CT], kk[CT];
   float thr[CT], gam[CT];  // t / lambda, the shrink2 factor
   float prev[CT], bst[CT];
   double phi[CT], hp[CT];
+  double gama[CT], ssa2[CT];  // REF: the anchor's shrink2 factor and |shrink1(za)|^2 (FP64)
+  float dgam[CT];             // REF: gam - gama
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     st[ct] = COL_EMPTY; flags[ct] = 0; iters[ct] = 0; stall[ct] = 0; jj[ct] = 0; kk[ct] = 0;
     thr[ct] = 0.f; gam[ct] = 1.f;
     prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
+    gama[ct] = 1.0; ssa2[ct] = 0.0; dgam[ct] = 0.f;
 #pragma unroll
     for (int rt = 0; rt < RTM; ++rt) { z[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f}; xp[rt][ct] = z[rt][ct]; }
+#pragma unroll
+    for (int rt = 0; rt < RD; ++rt) dz[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
+  int since = 0;  // REF: passes since the wave's last anchor
 
   while (true) {
     const int n = uni(pb.n), n_pad = uni(pb.n_pad), K = uni(pb.K), hkind = uni(pb.hkind);
@@ -233,6 +272,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         thr[ct] = (float)((double)tv / pb.lambda);
         gam[ct] = 1.f; iters[ct] = 0; stall[ct] = 0; flags[ct] = FLAG_FIRST;
         prev[ct] = 3e38f; bst[ct] = 3e38f; phi[ct] = 0.0; hp[ct] = 0.0;
+        gama[ct] = 1.0; ssa2[ct] = 0.0; dgam[ct] = 0.f;
         const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
         const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
         bool nf = false;
@@ -250,6 +290,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             xp[rt][ct][q] = v;
             z[rt][ct][q] = v;
           }
+          if (REF) dz[rt < RD ? rt : 0][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
         st[ct] = tok ? COL_ACTIVE : COL_INVALID;
         if (nf) st[ct] = COL_INVALID;  // combined over the column's lanes below
@@ -268,6 +309,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         cend = nextcol + uni(chunks[pending].ncols);
         pending = -1;
         load_problem();
+        since = 0;
         continue;
       }
       break;
@@ -284,13 +326,14 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         if (__any(any_inv)) continue;
       }
     }
+    const bool refined = REF && hkind != HK_WL2;
     int phi_lane = 0;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      if (st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass evaluates the value
+      if (!refined && st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass evaluates the value
       phi_lane |= st[ct] == COL_PHI ? 1 : 0;
     }
-    const bool any_phi = __any(phi_lane);
+    const bool any_phi = !refined && __any(phi_lane);
 
     // one pass of every column: the Hamiltonian's kind fixed at compile time, so that the pass is
     // straight-line code the scheduler can interleave (products of one row tile with the update
@@ -401,12 +444,14 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
 #pragma unroll
       for (int rt = 0; rt < RTM; ++rt)
 #pragma unroll
-        for (int kt = 0; kt < RTM; ++kt)
+        for (int kt = 0; kt < RTM; ++kt) {
+          const f32x4 a = mfrag(rt, kt);
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
-              u[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(Mf[rt][kt][q], r[kt][ct][q], u[rt][ct], 0, 0, 0);
+              u[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], r[kt][ct][q], u[rt][ct], 0, 0, 0);
+        }
 
       float s0[CT], s1[CT];
 #pragma unroll
@@ -499,27 +544,370 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         }
       }
     };
-    if (hkind == HK_WL2) pass(std::integral_constant<int, 2>{});
-    else if (has_l2) pass(std::integral_constant<int, 1>{});
-    else pass(std::integral_constant<int, 0>{});
+    // ============================================================ refined pass (REF; l1 / l2 kinds)
+    // Every column runs in increment form: za (z), dz, ea (xp).  A fresh column's first pass takes
+    // its FP32 start: za = x', d^a = prox(za), r^a = x' + lambda (2 d^a - za) as the B operand and
+    // -d^a as the C operand, so the product returns ea = M r^a - d^a (an FP32 estimate, replaced at
+    // the column's first exact anchor), which is also its first increment.  Only columns anchored
+    // exactly (FLAG_EXACT) may stop.
+    auto pass_ref = [&](auto kindtag) {
+      constexpr int KIND = decltype(kindtag)::value;
+      constexpr bool HL2 = KIND == 1;
+      const double lam = pb.lambda;
+      // row tile rt of a register array in a rolled loop (selects: the arrays stay in registers);
+      // the rare blocks below (anchor, value terms) run one row tile at a time this way, so that
+      // they add few live registers to the iteration's
+      auto get4 = [&](const f32x4 (&a)[RTM][CT], int rt, int ct) -> f32x4 {
+        f32x4 v = a[0][ct];
+#pragma unroll
+        for (int i = 1; i < RTM; ++i) v = rt == i ? a[i][ct] : v;
+        return v;
+      };
+      auto set4 = [&](f32x4 (&a)[RTM][CT], int rt, int ct, f32x4 v) {
+#pragma unroll
+        for (int i = 0; i < RTM; ++i) a[i][ct] = rt == i ? v : a[i][ct];
+      };
+      auto getw = [&](int rt) -> f32x4 {
+        f32x4 v = wv[0];
+#pragma unroll
+        for (int i = 1; i < RTM; ++i) v = rt == i ? wv[i] : v;
+        return v;
+      };
+
+      // ---------------------------------------------------------- anchor
+      {
+        int nact = 0, nwait = 0;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          nact += __popcll(__ballot(st[ct] == COL_ACTIVE && lg == 0));
+          nwait += __popcll(__ballot(st[ct] == COL_WAITING && lg == 0));
+        }
+        const bool take = (nact > 0 && since >= anchor_every) || (nwait > 0 && nact == 0) ||
+                          (anchor_wait > 0 && nwait >= anchor_wait);
+        if (take) {
+          since = 0;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const bool on = (st[ct] == COL_ACTIVE && !(flags[ct] & FLAG_FIRST)) || st[ct] == COL_WAITING;
+            const int j = jj[ct], k = kk[ct];
+            const double tv = on ? (double)pb.t[j] : 0.0;
+            const double th1 = has_l1 ? tv / lam : 0.0, th2 = HL2 ? tv / lam : 0.0;
+            const float thn = has_l1 ? thr[ct] : 0.f;
+            const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
+            const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
+            // re-base z = za + dz (za the nearest float, dz the remainder); s^a = shrink1(za) with
+            // FP64 thresholds, to the staging
+            double pss = 0.0, pinc = 0.0;
+#pragma unroll 1
+            for (int rt = 0; rt < RTM; ++rt) {
+              f32x4 zv = get4(z, rt, ct), dv = get4(dz, rt, ct);
+              const f32x4 w4 = getw(rt);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int row = 16 * rt + 4 * lg + q;
+                const bool inb = on && rt < nrt && row < n;
+                const double zd = (double)zv[q] + (double)dv[q];
+                const float zan = (float)zd, dzn = (float)(zd - (double)zan);
+                const float th = theta_f(thn, w4[q]);
+                const float ca = med3f(zan, -th, th), sav = zan - ca;
+                const float ds = dzn - med3f(dzn + sav, -th - ca, th - ca);
+                const double sa = inb ? (has_l1 ? anchor_shrink(zan, th1, pb.w, row) : (double)zan) : 0.0;
+                pss += sa * sa;
+                pinc += inb ? (double)ds * (2.0 * (double)sav + (double)ds) : 0.0;
+                if (on) { zv[q] = zan; dv[q] = dzn; }
+                sbuf[(rt * 4 + q) * 64 + l] = sa;
+              }
+              set4(z, rt, ct, zv); set4(dz, rt, ct, dv);
+            }
+            const double ssa = col_sum(pss), sinc = col_sum(pinc);
+            double ga = 1.0, g = 1.0;
+            if (HL2) {
+              const double na = sqrt(ssa), nz = sqrt(fmax(ssa + sinc, 0.0));
+              ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
+              g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
+            }
+            if (on) { gama[ct] = ga; ssa2[ct] = ssa; gam[ct] = (float)g; dgam[ct] = (float)(g - ga); }
+            // r^a = x' + lambda (2 d^a - za) in FP64 (d^a = ga s^a), the B operand of the FP64 products
+#pragma unroll 1
+            for (int rt = 0; rt < RTM; ++rt) {
+              const f32x4 zv = get4(z, rt, ct);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int row = 16 * rt + 4 * lg + q;
+                const bool inb = on && rt < nrt && row < n;
+                const double xpd = inb ? (double)xj[row] - (cen ? cen[row] : 0.0) : 0.0;
+                const double sa = sbuf[(rt * 4 + q) * 64 + l];
+                rbuf[(rt * 4 + q) * 64 + l] = inb ? xpd + lam * (2.0 * ga * sa - (double)zv[q]) : 0.0;
+              }
+            }
+            // v^a = M r^a by FP64 MFMA 16x16x4.  Its operands are laid out as the FP32 product's (A[i][k]
+            // in lane i + 16 k, B[k][j] in lane j + 16 k: B is the lane's own r^a row), but its output
+            // row i sits in lane j + 16 (i % 4), register i / 4, where the FP32 product has lane
+            // j + 16 (i / 4), register i % 4.  Feeding A's row i from M's row 16 rt + 4 (i % 4) + i / 4
+            // puts row 4 (l / 16) + q of the tile into register q of lane l, the state's layout.
+            // ea = v^a - d^a
+#pragma unroll 1
+            for (int rt = 0; rt < nrt; ++rt) {
+              f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int kt = 0; kt < RTM; ++kt) {
+                if (kt >= nrt) continue;  // wave-uniform
+                const int arow = 16 * rt + 4 * (lr & 3) + (lr >> 2);
+                const f64x4 a = *gp((const f64x4*)(pb.Md + (size_t)arow * n_pad + 16 * kt + 4 * lg));
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], rbuf[(kt * 4 + q) * 64 + l], acc, 0, 0, 0);
+              }
+              f32x4 ev = get4(xp, rt, ct);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int row = 16 * rt + 4 * lg + q;
+                const double sa = sbuf[(rt * 4 + q) * 64 + l];
+                if (on) ev[q] = row < n ? (float)(acc[q] - ga * sa) : 0.f;
+              }
+              set4(xp, rt, ct, ev);
+            }
+            if (on) flags[ct] |= FLAG_EXACT;
+            if (st[ct] == COL_WAITING) st[ct] = COL_PHI;  // converged: this pass re-tests and evaluates
+          }
+          // M's FP32 fragments back into the wave's LDS region (zeros beyond n_pad: the staging
+          // overwrote them too)
+          const int nks = n_pad >> 4;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+            for (int kt = 0; kt < RTM; ++kt)
+              Ms[(rt * RTM + kt) * 64 + l] = (rt < nks && kt < nks)
+                                                 ? *gp((const f32x4*)pb.Mf + ((size_t)rt * nks + kt) * 64 + l)
+                                                 : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      ++since;
+      int phi_lane = 0, fresh_lane = 0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        phi_lane |= st[ct] == COL_PHI ? 1 : 0;
+        fresh_lane |= (st[ct] == COL_ACTIVE && (flags[ct] & FLAG_FIRST)) ? 1 : 0;
+      }
+      const bool any_phi = __any(phi_lane);
+
+      // ---------------------------------------------------------- l2 factor of fresh columns' start
+      if (HL2 && __any(fresh_lane)) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const float thn = has_l1 ? thr[ct] : 0.f;
+          float a = 0.f;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float th = theta_f(thn, wv[rt][q]);
+              const float sa = z[rt][ct][q] - med3f(z[rt][ct][q], -th, th);
+              a += sa * sa;
+            }
+          const double s = (double)col_sumf(a);
+          if (st[ct] == COL_ACTIVE && (flags[ct] & FLAG_FIRST)) {
+            const double na = sqrt(s);
+            const double ga = na > 0.0 ? fmax(na - (double)thr[ct], 0.0) / na : 0.0;
+            gama[ct] = ga; ssa2[ct] = s; gam[ct] = (float)ga; dgam[ct] = 0.f;
+          }
+        }
+      }
+
+      // ---------------------------------------------------------- right-hand sides
+      // increment: dd = prox(za + dz) - prox(za) from za's shrink decomposition (exact in FP32 for
+      // the shrink), r = lambda (2 dd - dz), u = dz + ea - dd: the products return the next dz;
+      // a value pass takes u = 0 (the plain product)
+      auto inc = [&](int ct, int rt, int q, float dzv, float* sa, float* lo, float* hi) -> float {
+        const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
+        const float za = z[rt][ct][q];
+        const float ca = med3f(za, -th, th);
+        *sa = za - ca; *lo = -th - ca; *hi = th - ca;
+        const float ds = dzv - med3f(dzv + *sa, *lo, *hi);
+        return HL2 ? (float)gama[ct] * ds + dgam[ct] * (*sa + ds) : ds;
+      };
+      f32x4 r[RTM][CT], u[RTM][CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const bool isphi = st[ct] == COL_PHI;
+        const bool fresh = flags[ct] & FLAG_FIRST;
+        const float gaf = (float)gama[ct];
+#pragma unroll
+        for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float dzv = dz[rt][ct][q];
+            float sa, lo, hi;
+            const float dd = inc(ct, rt, q, dzv, &sa, &lo, &hi);
+            const float da = HL2 ? gaf * sa : sa;
+            const float zz = z[rt][ct][q];
+            r[rt][ct][q] = fresh ? xp[rt][ct][q] + flam * (2.f * da - zz) : flam * (2.f * dd - dzv);
+            u[rt][ct][q] = fresh ? -da : (isphi ? 0.f : dzv + xp[rt][ct][q] - dd);
+          }
+        }
+      }
+
+      // ---------------------------------------------------------- products, then the step sums
+#pragma unroll
+      for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+        for (int kt = 0; kt < RTM; ++kt) {
+          const f32x4 a = mfrag(rt, kt);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              u[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], r[kt][ct][q], u[rt][ct], 0, 0, 0);
+        }
+
+      float s0[CT], s1[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const bool act = st[ct] == COL_ACTIVE;
+        const bool isphi = st[ct] == COL_PHI;
+        const bool fresh = flags[ct] & FLAG_FIRST;
+        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+        for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float res = u[rt][ct][q];
+            const float dzv = dz[rt][ct][q];
+            float sa, lo, hi;
+            const float dd = inc(ct, rt, q, dzv, &sa, &lo, &hi);
+            const float dzn = isphi ? dzv + xp[rt][ct][q] + res - dd : res;
+            const float step = dzn - dzv;
+            const float dsn = dzn - med3f(dzn + sa, lo, hi);
+            a0 += step * step;
+            a1 += dsn * (2.f * sa + dsn);
+            if (act) {
+              dz[rt][ct][q] = dzn;
+              if (fresh) xp[rt][ct][q] = res;  // ea (FP32 estimate)
+            }
+          }
+        }
+        s0[ct] = col_sumf(a0);
+        s1[ct] = col_sumf(a1);
+      }
+
+      // ---------------------------------------------------------- value terms (value passes)
+      // From the exact-product identity at the current iterate, in FP64: d = d^a + dd,
+      // v = v^a + dv (v^a = ea + d^a), r = r^a + dr; the pass's increment is applied here too.
+      double v2s[CT], v3s[CT], v4s[CT], v5s[CT];
+      f32x4 pd[RTM][CT];  // p of a value pass
+      if (any_phi) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const bool isphi = st[ct] == COL_PHI;
+          double w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
+          const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)jj[ct] * n);
+          const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)kk[ct] * n_pad) : nullptr;
+          const double th1 = has_l1 ? (double)pb.t[jj[ct]] / lam : 0.0;
+          const float thn = has_l1 ? thr[ct] : 0.f;
+          const float gaf = (float)gama[ct];
+#pragma unroll 1
+          for (int rt = 0; rt < RTM; ++rt) {
+            const f32x4 zv = get4(z, rt, ct), ev = get4(xp, rt, ct), uv = get4(u, rt, ct), w4v = getw(rt);
+            f32x4 dv = get4(dz, rt, ct), pv;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = 16 * rt + 4 * lg + q;
+              const bool inb = isphi && rt < nrt && row < n;
+              const float dzv = dv[q], za = zv[q];
+              const float th = theta_f(thn, w4v[q]);
+              const float ca = med3f(za, -th, th), sa = za - ca;
+              const float ds = dzv - med3f(dzv + sa, -th - ca, th - ca);
+              const float dd = HL2 ? gaf * ds + dgam[ct] * (sa + ds) : ds;
+              const double wr = inb ? *gp(pb.w + row) : 0.0;
+              const double da = gama[ct] * (has_l1 ? (double)za - fmin(fmax((double)za, -th1 * wr), th1 * wr) : (double)za);
+              const double d = inb ? da + (double)dd : 0.0;
+              const double vv = (double)ev[q] + da + (double)uv[q];
+              const double xpd = inb ? (double)xj[row] - (cen ? cen[row] : 0.0) : 0.0;
+              const double rr = xpd + lam * (2.0 * da - (double)za) + lam * (2.0 * (double)dd - (double)dzv);
+              w2 += xpd * d;
+              w3 += (2.0 * d - vv) * (rr - lam * vv);
+              w4 += wr * fabs(d);
+              w5 += d * d;
+              pv[q] = (float)d;
+              if (isphi) dv[q] = dzv + ev[q] + uv[q] - dd;
+            }
+            set4(pd, rt, ct, pv);
+            set4(dz, rt, ct, dv);
+          }
+          v2s[ct] = col_sum(w2); v3s[ct] = col_sum(w3); v4s[ct] = col_sum(w4); v5s[ct] = col_sum(w5);
+        }
+      }
+
+      // ---------------------------------------------------------- per-column update
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const bool isphi = st[ct] == COL_PHI;
+        if (!(st[ct] == COL_ACTIVE || isphi)) continue;
+        const double sm0 = (double)s0[ct];
+        iters[ct] += 1;
+        if (HL2) {
+          const double nz = sqrt(fmax(ssa2[ct] + (double)s1[ct], 0.0));
+          const double gg = nz > 0.0 ? fmax(nz - (double)thr[ct], 0.0) / nz : 0.0;
+          gam[ct] = (float)gg;
+          dgam[ct] = (float)(gg - gama[ct]);
+        }
+        flags[ct] &= ~FLAG_FIRST;
+        // (|dz_k| + |dz_{k-1}|)^2 <= tol, on increments measured from an exact anchor
+        const double pv = (double)prev[ct];
+        prev[ct] = (float)sm0;
+        const bool conv = (flags[ct] & FLAG_EXACT) && sm0 + pv + 2.0 * sqrt(sm0 * pv) <= pb.tol;
+        const bool capped = iters[ct] >= pb.max_iter;
+        if (!isphi) {
+          if (conv) st[ct] = COL_WAITING;
+          else if (capped) { st[ct] = COL_WAITING; flags[ct] |= FLAG_SOLVE_CAP | FLAG_CAPPED; }
+        } else {
+          if (capped && !conv) flags[ct] |= FLAG_SOLVE_CAP | FLAG_CAPPED;
+          if (conv || (flags[ct] & FLAG_SOLVE_CAP)) {
+            const double pn = sqrt(v5s[ct]);
+            const double H = (has_l1 ? v4s[ct] : 0.0) + (HL2 ? pn : 0.0);
+            const double tv = (double)pb.t[jj[ct]];
+            phi[ct] = v2s[ct] - 0.5 * v3s[ct] - tv * H - (pb.level_set ? 0.5 : 0.0);
+            hp[ct] = H;
+            st[ct] = COL_DONE;
+#pragma unroll
+            for (int rt = 0; rt < RTM; ++rt) z[rt][ct] = pd[rt][ct];  // p replaces za
+          } else {
+            st[ct] = COL_ACTIVE;
+          }
+        }
+      }
+    };
+    if (hkind == HK_WL2) {
+      pass(std::integral_constant<int, 2>{});
+    } else if constexpr (REF) {
+      if (has_l2) pass_ref(std::integral_constant<int, 1>{});
+      else pass_ref(std::integral_constant<int, 0>{});
+    } else {
+      if (has_l2) pass(std::integral_constant<int, 1>{});
+      else pass(std::integral_constant<int, 0>{});
+    }
   }
 }
 
-bool dense_small_fits(int mode, int n_pad, int distance) { return mode == 0 && !distance && n_pad <= 64; }
+bool dense_small_fits(int mode, int n_pad, int distance) { return mode != 1 && !distance && n_pad <= 64; }
 
 int dense_small_cols() { return 16 * SMALL_CT; }
 int dense_small_occupancy() { return SMALL_OCC; }
 
-hipError_t launch_dense_small(int n_pad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
-                              int* counter, int grid, hipStream_t stream) {
-  if (n_pad <= 32)
-    hipLaunchKernelGGL((dense_small_kernel<2, SMALL_CT, SMALL_OCC>), dim3(grid), dim3(kBlock), 0, stream, d_probs,
-                       d_chunks, nchunks, counter);
-  else if (n_pad <= 64)
-    hipLaunchKernelGGL((dense_small_kernel<4, SMALL_CT, SMALL_OCC>), dim3(grid), dim3(kBlock), 0, stream, d_probs,
-                       d_chunks, nchunks, counter);
-  else
+hipError_t launch_dense_small(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              hipStream_t stream) {
+#define HOPF_SMALL(R, F)                                                                                    \
+  hipLaunchKernelGGL((dense_small_kernel<R, SMALL_CT, SMALL_OCC, F>), dim3(grid), dim3(kBlock), 0, stream, \
+                     d_probs, d_chunks, nchunks, counter, anchor_every, anchor_wait)
+  if (n_pad <= 32) {
+    if (refined) HOPF_SMALL(2, true); else HOPF_SMALL(2, false);
+  } else if (n_pad <= 64) {
+    if (refined) HOPF_SMALL(4, true); else HOPF_SMALL(4, false);
+  } else {
     return hipErrorInvalidValue;
+  }
+#undef HOPF_SMALL
   return hipGetLastError();
 }
 
