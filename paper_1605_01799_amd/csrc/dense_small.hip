@@ -25,8 +25,12 @@
 // decomposition, dr = lambda (2 dd - dz), dv = M dr (FP32 MFMA), and dz <- dz + ea + dv - dd, so
 // every rounding is relative to a vanishing increment and the fixed point is that of the exact
 // product.  A column that passes the stopping test waits for the next anchor and is accepted only
-// if the test still passes on the fresh anchor (its value pass).  The ellipsoidal norm
-// sqrt(<p, D p>) runs the plain FP32 pass.
+// if the test still passes on the fresh anchor (its value pass).  For the ellipsoidal norm
+// sqrt(<p, D p>) the prox is d = mu z / (s + mu) (section 4.3) with the multiplier mu of the
+// projection: the anchor solves for mu^a in FP64, and a pass solves for the increment dmu of the
+// multiplier by Newton on the difference phi(mu^a + dmu; za + dz) - phi(mu^a; za), whose terms
+// are products of increments (so dmu is resolved relative to the increments), then
+// dd = (mu dz (s + mu^a) + za s dmu) / ((s + mu)(s + mu^a)).
 #include <cstdint>
 #include <type_traits>
 
@@ -326,7 +330,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         if (__any(any_inv)) continue;
       }
     }
-    const bool refined = REF && hkind != HK_WL2;
+    const bool refined = REF;
     int phi_lane = 0;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
@@ -550,9 +554,12 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
     // -d^a as the C operand, so the product returns ea = M r^a - d^a (an FP32 estimate, replaced at
     // the column's first exact anchor), which is also its first increment.  Only columns anchored
     // exactly (FLAG_EXACT) may stop.
+    // For the ellipsoidal norm (KIND 2) a column's gama holds the anchor's multiplier mu^a (FP64),
+    // dgam the current increment dmu, ssa2 the anchor's residual phi(mu^a; za) - 1, and
+    // FLAG_INSIDE (no distances here) that za lies inside the Wulff ellipsoid (d^a = 0).
     auto pass_ref = [&](auto kindtag) {
       constexpr int KIND = decltype(kindtag)::value;
-      constexpr bool HL2 = KIND == 1;
+      constexpr bool HL2 = KIND == 1, WL = KIND == 2;
       const double lam = pb.lambda;
       // row tile rt of a register array in a rolled loop (selects: the arrays stay in registers);
       // the rare blocks below (anchor, value terms) run one row tile at a time this way, so that
@@ -592,6 +599,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             const int j = jj[ct], k = kk[ct];
             const double tv = on ? (double)pb.t[j] : 0.0;
             const double th1 = has_l1 ? tv / lam : 0.0, th2 = HL2 ? tv / lam : 0.0;
+            const double thw = tv / lam;  // WL: s_i = thw^2 w_i
             const float thn = has_l1 ? thr[ct] : 0.f;
             const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)j * n);
             const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)k * n_pad) : nullptr;
@@ -611,11 +619,11 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
                 const float th = theta_f(thn, w4[q]);
                 const float ca = med3f(zan, -th, th), sav = zan - ca;
                 const float ds = dzn - med3f(dzn + sav, -th - ca, th - ca);
-                const double sa = inb ? (has_l1 ? anchor_shrink(zan, th1, pb.w, row) : (double)zan) : 0.0;
+                const double sa = inb ? ((has_l1 && !WL) ? anchor_shrink(zan, th1, pb.w, row) : (double)zan) : 0.0;
                 pss += sa * sa;
                 pinc += inb ? (double)ds * (2.0 * (double)sav + (double)ds) : 0.0;
                 if (on) { zv[q] = zan; dv[q] = dzn; }
-                sbuf[(rt * 4 + q) * 64 + l] = sa;
+                sbuf[(rt * 4 + q) * 64 + l] = sa;  // WL: za, replaced by d^a below
               }
               set4(z, rt, ct, zv); set4(dz, rt, ct, dv);
             }
@@ -626,7 +634,59 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
               ga = na > 0.0 ? fmax(na - th2, 0.0) / na : 0.0;
               g = nz > 0.0 ? fmax(nz - th2, 0.0) / nz : 0.0;
             }
-            if (on) { gama[ct] = ga; ssa2[ct] = ssa; gam[ct] = (float)g; dgam[ct] = (float)(g - ga); }
+            if (WL) {
+              // the projection of za onto sum y_i^2 / s_i <= 1 in FP64: inside, or mu^a > 0 solving
+              // phi(mu) = sum s_i za_i^2 / (s_i + mu)^2 = 1 by Newton on 1 / sqrt(phi) - 1 from 0
+              auto sums = [&](double mu, double* ph, double* ps, double* qi) {
+                double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll 1
+                for (int rt = 0; rt < nrt; ++rt) {
+                  const f32x4 w4 = getw(rt);
+                  (void)w4;
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * rt + 4 * lg + q;
+                    if (row >= n) continue;
+                    const double zz = sbuf[(rt * 4 + q) * 64 + l];
+                    const double sv = thw * thw * *gp(pb.w + row);
+                    if (!(sv > 0.0)) continue;
+                    const double inv = 1.0 / (sv + mu);
+                    const double e = sv * zz * zz * inv * inv;
+                    a += e; b += e * inv; c += zz * zz / sv;
+                  }
+                }
+                *ph = col_sum(a); *ps = col_sum(b); *qi = col_sum(c);
+              };
+              double ph, ps, qi;
+              sums(0.0, &ph, &ps, &qi);
+              const bool ins = !(qi > 1.0);
+              double mu = 0.0;
+              if (!ins) {
+                for (int it = 0; it < 100; ++it) {
+                  const double stp = ph * (sqrt(ph) - 1.0) / ps;
+                  if (!(stp > 1e-15 * mu)) break;
+                  mu += stp;
+                  sums(mu, &ph, &ps, &qi);
+                }
+              }
+              if (on) {
+                gama[ct] = mu; dgam[ct] = 0.f; ssa2[ct] = ins ? qi - 1.0 : ph - 1.0;
+                flags[ct] = ins ? (flags[ct] | FLAG_INSIDE) : (flags[ct] & ~FLAG_INSIDE);
+              }
+              // d^a = mu^a za / (s + mu^a), or 0 inside
+#pragma unroll 1
+              for (int rt = 0; rt < RTM; ++rt) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int row = 16 * rt + 4 * lg + q;
+                  const double zz = sbuf[(rt * 4 + q) * 64 + l];
+                  const double sv = (rt < nrt && row < n) ? thw * thw * *gp(pb.w + row) : 0.0;
+                  sbuf[(rt * 4 + q) * 64 + l] = (ins || !(sv > 0.0)) ? 0.0 : mu * zz / (sv + mu);
+                }
+              }
+              ga = 1.0;
+            }
+            if (on && !WL) { gama[ct] = ga; ssa2[ct] = ssa; gam[ct] = (float)g; dgam[ct] = (float)(g - ga); }
             // r^a = x' + lambda (2 d^a - za) in FP64 (d^a = ga s^a), the B operand of the FP64 products
 #pragma unroll 1
             for (int rt = 0; rt < RTM; ++rt) {
@@ -714,13 +774,127 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         }
       }
 
+      // ---------------------------------------------------------- ellipsoidal norm: multipliers
+      // A fresh column's start: mu of za by FP32 Newton from 0 (its ea is an FP32 estimate anyway).
+      // Every other column: whether z = za + dz is inside the Wulff ellipsoid (then d = 0), else the
+      // increment dmu by two Newton steps, warm-started from the last pass, on
+      //   F(dmu) = sum_i s_i a_i b_i / ((s_i + mu)^2 (s_i + mu^a)^2) + (phi(mu^a; za) - 1),
+      //   a_i = dz_i (s_i + mu^a) - za_i dmu,  b_i = z_i (s_i + mu^a) + za_i (s_i + mu),
+      // which is phi(mu; z) - 1 written with increments, F' = -2 sum_i s_i z_i^2 / (s_i + mu)^3.
+      bool cin[CT];
+      if (WL) {
+        if (__any(fresh_lane)) {
+          float mu[CT], th2[CT], ph[CT];
+          bool go[CT], ins[CT];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            th2[ct] = thr[ct] * thr[ct];
+            float qa = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const float zz = z[rt][ct][q], sv = th2[ct] * wv[rt][q];
+                qa += sv > 0.f ? zz * zz * __builtin_amdgcn_rcpf(sv) : 0.f;
+              }
+            const float qs = col_sumf(qa);
+            ins[ct] = !(qs > 1.f);
+            go[ct] = (st[ct] == COL_ACTIVE && (flags[ct] & FLAG_FIRST)) && !ins[ct];
+            mu[ct] = 0.f;
+            ph[ct] = qs;
+          }
+          for (int it = 0; it < kWl2Newton; ++it) {
+            int any = 0;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              float pa = 0.f, pb3 = 0.f;
+#pragma unroll
+              for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const float zz = z[rt][ct][q], sv = th2[ct] * wv[rt][q];
+                  const float inv = sv > 0.f ? __builtin_amdgcn_rcpf(sv + mu[ct]) : 0.f;
+                  const float e = sv * zz * zz * inv * inv;
+                  pa += e;
+                  pb3 += e * inv;
+                }
+              const float phs = col_sumf(pa), ps = col_sumf(pb3);
+              const float stp = phs * (__builtin_sqrtf(phs) - 1.f) / ps;
+              go[ct] = go[ct] && stp > kWl2Rel * mu[ct];
+              if (go[ct]) { mu[ct] += stp; ph[ct] = phs; }
+              any |= go[ct] ? 1 : 0;
+            }
+            if (!__any(any)) break;
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+            if (st[ct] == COL_ACTIVE && (flags[ct] & FLAG_FIRST)) {
+              gama[ct] = ins[ct] ? 0.0 : (double)mu[ct];
+              dgam[ct] = 0.f;
+              ssa2[ct] = 0.0;
+              flags[ct] = ins[ct] ? (flags[ct] | FLAG_INSIDE) : (flags[ct] & ~FLAG_INSIDE);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const float th2 = thr[ct] * thr[ct];
+          float qa = 0.f;
+#pragma unroll
+          for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float zz = z[rt][ct][q] + dz[rt][ct][q], sv = th2 * wv[rt][q];
+              qa += sv > 0.f ? zz * zz * __builtin_amdgcn_rcpf(sv) : 0.f;
+            }
+          cin[ct] = !(col_sumf(qa) > 1.f);
+        }
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const float th2 = thr[ct] * thr[ct];
+            const float mua = (float)gama[ct], dm = dgam[ct], mu = mua + dm;
+            float fa = 0.f, ga2 = 0.f;
+#pragma unroll
+            for (int rt = 0; rt < RTM; ++rt)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const float sv = th2 * wv[rt][q];
+                const float za = z[rt][ct][q], dzv = dz[rt][ct][q], zz = za + dzv;
+                const float A = sv + mua, B = sv + mu;
+                const float iA = sv > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f;
+                const float iB = sv > 0.f ? __builtin_amdgcn_rcpf(B) : 0.f;
+                const float a = dzv * A - za * dm, b = zz * A + za * B;
+                fa += sv * a * b * (iB * iB) * (iA * iA);
+                ga2 += sv * zz * zz * (iB * iB * iB);
+              }
+            const float F = col_sumf(fa) + (float)ssa2[ct], G = col_sumf(ga2);
+            const bool upd = !(flags[ct] & FLAG_FIRST) && !cin[ct] && G > 0.f;
+            float dn = upd ? dm + F / (2.f * G) : dm;
+            dn = fmaxf(dn, -mua);  // mu stays >= 0
+            dgam[ct] = dn;
+          }
+        }
+      }
+
       // ---------------------------------------------------------- right-hand sides
       // increment: dd = prox(za + dz) - prox(za) from za's shrink decomposition (exact in FP32 for
       // the shrink), r = lambda (2 dd - dz), u = dz + ea - dd: the products return the next dz;
       // a value pass takes u = 0 (the plain product)
       auto inc = [&](int ct, int rt, int q, float dzv, float* sa, float* lo, float* hi) -> float {
-        const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
         const float za = z[rt][ct][q];
+        if (WL) {  // dd = (mu dz (s + mu^a) + za s dmu) / ((s + mu)(s + mu^a)), or -d^a inside
+          const float sv = thr[ct] * thr[ct] * wv[rt][q];
+          const float mua = (float)gama[ct], dm = dgam[ct], mu = mua + dm;
+          const float A = sv + mua, B = sv + mu;
+          const bool ains = flags[ct] & FLAG_INSIDE;
+          const float da = (ains || !(sv > 0.f)) ? 0.f : mua * za * __builtin_amdgcn_rcpf(A);
+          const float inside_dd = -da;
+          const float out_dd = sv > 0.f ? (mu * dzv * A + za * sv * dm) * __builtin_amdgcn_rcpf(B * A) : 0.f;
+          *sa = da; *lo = 0.f; *hi = 0.f;  // sa returns d^a (FP32) for a fresh column's start
+          return cin[ct] ? inside_dd : out_dd;
+        }
+        const float th = theta_f(has_l1 ? thr[ct] : 0.f, wv[rt][q]);
         const float ca = med3f(za, -th, th);
         *sa = za - ca; *lo = -th - ca; *hi = th - ca;
         const float ds = dzv - med3f(dzv + *sa, *lo, *hi);
@@ -777,9 +951,11 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             const float dd = inc(ct, rt, q, dzv, &sa, &lo, &hi);
             const float dzn = isphi ? dzv + xp[rt][ct][q] + res - dd : res;
             const float step = dzn - dzv;
-            const float dsn = dzn - med3f(dzn + sa, lo, hi);
             a0 += step * step;
-            a1 += dsn * (2.f * sa + dsn);
+            if (!WL) {
+              const float dsn = dzn - med3f(dzn + sa, lo, hi);
+              a1 += dsn * (2.f * sa + dsn);
+            }
             if (act) {
               dz[rt][ct][q] = dzn;
               if (fresh) xp[rt][ct][q] = res;  // ea (FP32 estimate)
@@ -803,6 +979,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
           const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)jj[ct] * n);
           const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)kk[ct] * n_pad) : nullptr;
           const double th1 = has_l1 ? (double)pb.t[jj[ct]] / lam : 0.0;
+          const double wl_th = (double)pb.t[jj[ct]] / lam;  // WL: s_i = wl_th^2 w_i
           const float thn = has_l1 ? thr[ct] : 0.f;
           const float gaf = (float)gama[ct];
 #pragma unroll 1
@@ -814,19 +991,32 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
               const int row = 16 * rt + 4 * lg + q;
               const bool inb = isphi && rt < nrt && row < n;
               const float dzv = dv[q], za = zv[q];
-              const float th = theta_f(thn, w4v[q]);
-              const float ca = med3f(za, -th, th), sa = za - ca;
-              const float ds = dzv - med3f(dzv + sa, -th - ca, th - ca);
-              const float dd = HL2 ? gaf * ds + dgam[ct] * (sa + ds) : ds;
+              float dd;
+              double da;
               const double wr = inb ? *gp(pb.w + row) : 0.0;
-              const double da = gama[ct] * (has_l1 ? (double)za - fmin(fmax((double)za, -th1 * wr), th1 * wr) : (double)za);
+              if (WL) {
+                const float sv = thr[ct] * thr[ct] * w4v[q];
+                const float mua = (float)gama[ct], dm = dgam[ct], mu = mua + dm;
+                const float A = sv + mua, B = sv + mu;
+                const bool ains = flags[ct] & FLAG_INSIDE;
+                const float daf = (ains || !(sv > 0.f)) ? 0.f : mua * za * __builtin_amdgcn_rcpf(A);
+                dd = cin[ct] ? -daf : (sv > 0.f ? (mu * dzv * A + za * sv * dm) * __builtin_amdgcn_rcpf(B * A) : 0.f);
+                const double s64 = wl_th * wl_th * wr;
+                da = (ains || !(s64 > 0.0)) ? 0.0 : gama[ct] * (double)za / (s64 + gama[ct]);
+              } else {
+                const float th = theta_f(thn, w4v[q]);
+                const float ca = med3f(za, -th, th), sa = za - ca;
+                const float ds = dzv - med3f(dzv + sa, -th - ca, th - ca);
+                dd = HL2 ? gaf * ds + dgam[ct] * (sa + ds) : ds;
+                da = gama[ct] * (has_l1 ? (double)za - fmin(fmax((double)za, -th1 * wr), th1 * wr) : (double)za);
+              }
               const double d = inb ? da + (double)dd : 0.0;
               const double vv = (double)ev[q] + da + (double)uv[q];
               const double xpd = inb ? (double)xj[row] - (cen ? cen[row] : 0.0) : 0.0;
               const double rr = xpd + lam * (2.0 * da - (double)za) + lam * (2.0 * (double)dd - (double)dzv);
               w2 += xpd * d;
               w3 += (2.0 * d - vv) * (rr - lam * vv);
-              w4 += wr * fabs(d);
+              w4 += WL ? wr * d * d : wr * fabs(d);
               w5 += d * d;
               pv[q] = (float)d;
               if (isphi) dv[q] = dzv + ev[q] + uv[q] - dd;
@@ -864,7 +1054,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
           if (capped && !conv) flags[ct] |= FLAG_SOLVE_CAP | FLAG_CAPPED;
           if (conv || (flags[ct] & FLAG_SOLVE_CAP)) {
             const double pn = sqrt(v5s[ct]);
-            const double H = (has_l1 ? v4s[ct] : 0.0) + (HL2 ? pn : 0.0);
+            const double H = WL ? sqrt(v4s[ct]) : (has_l1 ? v4s[ct] : 0.0) + (HL2 ? pn : 0.0);
             const double tv = (double)pb.t[jj[ct]];
             phi[ct] = v2s[ct] - 0.5 * v3s[ct] - tv * H - (pb.level_set ? 0.5 : 0.0);
             hp[ct] = H;
@@ -877,11 +1067,12 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         }
       }
     };
-    if (hkind == HK_WL2) {
-      pass(std::integral_constant<int, 2>{});
-    } else if constexpr (REF) {
-      if (has_l2) pass_ref(std::integral_constant<int, 1>{});
+    if constexpr (REF) {
+      if (hkind == HK_WL2) pass_ref(std::integral_constant<int, 2>{});
+      else if (has_l2) pass_ref(std::integral_constant<int, 1>{});
       else pass_ref(std::integral_constant<int, 0>{});
+    } else if (hkind == HK_WL2) {
+      pass(std::integral_constant<int, 2>{});
     } else {
       if (has_l2) pass(std::integral_constant<int, 1>{});
       else pass(std::integral_constant<int, 0>{});
