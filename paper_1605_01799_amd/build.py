@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhopf.so")
-SOURCES = ["checks.cpp", "setup.hip", "dense.hip", "dense_small.hip", "diag.hip", "backward.hip", "rotate.hip", "control.hip", "api.hip"]
+SOURCES = ["checks.cpp", "setup.hip", "dense.hip", "dense_small.hip", "dense_rs.hip", "diag.hip", "backward.hip", "rotate.hip", "control.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions in any kernel

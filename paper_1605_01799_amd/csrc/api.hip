@@ -481,12 +481,15 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   }
   // one launch per kernel class: the launch shape of the padded size (kSmallClass: the
   // one-wave-per-tile kernel of small FP32 problems)
-  constexpr int kSmallClass = 1 << 20;
+  // (kRsClass: the on-chip-state kernel of refined problems with one point per column)
+  constexpr int kSmallClass = 1 << 20, kRsClass = 1 << 21;
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
+  static const bool use_rs = env_int("HOPF_RS", 1) != 0;
   auto class_of = [&](const hopf_problem* p) -> int {
     // sqrt(<p, D p>) runs only in the small kernel (distance problems use l2 whatever the kind)
     const bool need_small = (p->hkind == HOPF_H_WL2 || p->hkind == HOPF_H_AL2) && !distance;
     if ((use_small || need_small) && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
+    if (use_rs && dense_rs_fits(mode, p->n_pad, p->K, p->hkind, distance)) return kRsClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;
   };
@@ -498,8 +501,9 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   std::sort(classes.begin(), classes.end());
   int cls = 0;
   for (int key : classes) {
-    const bool small = key == kSmallClass;
+    const bool small = key == kSmallClass, rs = key == kRsClass;
     const DenseVariant var = small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4}
+                             : rs  ? DenseVariant{dense_rs_cols(), 1, 4}
                                    : DenseVariant{key / 100, (key / 10) % 10, key % 10};
     const int pt = var.pt, occ = var.occ;
     std::vector<DenseProb> views;
@@ -538,13 +542,15 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
     // the small kernel: four independent waves per workgroup, each taking chunks
     const int grid = small ? std::min((nchunks + 3) / 4, occ * w->ncu) : std::min(nchunks, occ * w->ncu);
-    const int64_t ws_per_wg = small ? 0 : 4 * (int64_t)pt * max_npad;
+    const int64_t ws_per_wg = small ? 0 : rs ? dense_rs_ws_floats(max_npad) : 4 * (int64_t)pt * max_npad;
     // FP64 anchor staging, then its integer slices (kSlices x pt x pad64 bytes)
     const int64_t ws64_per_wg = (int64_t)pt * max_npad + (int64_t)kSlices * pt * pad64(max_npad) / 8;
     if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
     if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * ws64_per_wg * grid))) return st;
     size_t lds = 0;
-    if (!small)
+    if (rs)
+      lds = dense_rs_lds_bytes(max_npad);
+    else if (!small)
       for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
     int* counter = w->counter + cls;
     // reset the counter, and the best arrays of this class's problems
@@ -555,6 +561,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
     hipError_t e = small ? launch_dense_small(max_npad, small_refined, (const DenseProb*)dmeta, dchunks, nchunks,
                                               counter, grid, small_anchor_every, small_anchor_wait, stream)
+                   : rs  ? launch_dense_rs(max_npad, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state64,
+                                           ws64_per_wg, w->state, ws_per_wg, grid, lds, anchor_every, stream)
                          : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
                                         w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
                                         anchor_wait, stream);

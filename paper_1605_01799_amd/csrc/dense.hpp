@@ -27,4 +27,14 @@ hipError_t launch_dense_small(int n_pad, bool refined, const DenseProb* d_probs,
                               int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
                               hipStream_t stream);
 
+// Refined BF16 problems of one point per column (K = 1) with 64 <= n_pad <= 1024
+// (dense_rs.hip): the column state on chip, one persistent workgroup of 32 columns per CU.
+bool dense_rs_fits(int mode, int n_pad, int K, int hkind, int distance);
+int dense_rs_cols();                     // columns per workgroup
+size_t dense_rs_lds_bytes(int n_pad);     // dynamic LDS of a launch whose largest problem has n_pad
+int64_t dense_rs_ws_floats(int n_pad);    // float staging per workgroup
+hipError_t launch_dense_rs(int max_npad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
+                           int* counter, double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid,
+                           size_t lds, int anchor_every, hipStream_t stream);
+
 }  // namespace hopf

@@ -52,7 +52,9 @@ template <int RG, int CT, int PF = 3>
 __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pad,
                                                  const __bf16* B, int ldb, const int* rt, int nrt,
                                                  f32x4 (&acc)[RG][CT]) {
-  // A fragments (rows of M, L2-resident) stream with PF k-steps in flight; B is in LDS.
+  // A fragments (rows of M, L2-resident) stream with PF k-steps in flight; B is in LDS.  Every
+  // k-step issues its prefetch (past the end it re-reads the last k-step), so the loads in flight
+  // are the same on every path and each MFMA waits only for its own fragments.
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   // M is stored in fragment order (mb_index): row tile rt, k-step kk at (rt nk + kk) 64 + l
@@ -66,31 +68,34 @@ __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pa
   constexpr int NB = PF + 1;  // register buffers of A fragments
   bf16x8 a[NB][RG];
 #pragma unroll
-  for (int u = 0; u < PF; ++u)
-    if (u < nk) {
+  for (int u = 0; u < PF; ++u) {
+    const int kl = u < nk ? u : nk - 1;
 #pragma unroll
-      for (int r = 0; r < RG; ++r) a[u][r] = arow[r][64 * u];
-    }
-  for (int ks = 0; ks < nk; ks += NB) {
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int kk = ks + u;
-      if (kk < nk) {
-        if (kk + PF < nk) {
-#pragma unroll
-          for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][64 * (kk + PF)];
-        }
-        bf16x8 b[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) b[c] = bcol[c * bstride + 4 * kk];
-#pragma unroll
-        for (int r = 0; r < RG; ++r)
-#pragma unroll
-          for (int c = 0; c < CT; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][r], b[c], acc[r][c], 0, 0, 0);
-      }
-    }
+    for (int r = 0; r < RG; ++r) a[u][r] = arow[r][64 * kl];
   }
+  auto step = [&](int kk, int u) {  // u = kk mod NB, a compile-time constant at every call
+    const int kl = kk + PF < nk ? kk + PF : nk - 1;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][64 * kl];
+    bf16x8 b[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = bcol[c * bstride + 4 * kk];
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][r], b[c], acc[r][c], 0, 0, 0);
+  };
+  // whole groups of NB k-steps without branches between them, then the tail
+  const int nmain = nk - nk % NB;
+  int kk = 0;
+  for (; kk < nmain; kk += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) step(kk + u, u);
+  }
+#pragma unroll
+  for (int u = 0; u < NB - 1; ++u)
+    if (kk + u < nk) step(kk + u, u);
 }
 
 template <int RG, int CT>
@@ -152,35 +157,39 @@ __device__ __forceinline__ void gemm_slices(const int8_t* __restrict__ Mq, int R
   const int8_t* bbase = Bq + lr * ldq + 16 * lg;
   constexpr int NB = PF + 1;
   i32x4 a[NB][kSlices];
+  // every k-step issues its prefetch (past the end it re-reads the last k-step), so the loads in
+  // flight are the same on every path (as in gemm_bf16)
 #pragma unroll
-  for (int u = 0; u < PF; ++u)
-    if (u < nkb) {
+  for (int u = 0; u < PF; ++u) {
+    const int kl = u < nkb ? u : nkb - 1;
 #pragma unroll
-      for (int s = 0; s < kSlices; ++s) a[u][s] = abase[s * astride + 64 * u];
-    }
-  for (int ks = 0; ks < nkb; ks += NB) {
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int kk = ks + u;
-      if (kk < nkb) {
-        if (kk + PF < nkb) {
-#pragma unroll
-          for (int s = 0; s < kSlices; ++s) a[(u + PF) % NB][s] = abase[s * astride + 64 * (kk + PF)];
-        }
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          i32x4 b[kSlices];
-#pragma unroll
-          for (int s = 0; s < kSlices; ++s) b[s] = *(const i32x4*)(bbase + (s * PT + 16 * c) * ldq + 64 * kk);
-#pragma unroll
-          for (int sa = 0; sa < kSlices; ++sa)
-#pragma unroll
-            for (int sb = 0; sa + sb < kSlices; ++sb)
-              acc[sa + sb][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][sa], b[sb], acc[sa + sb][c], 0, 0, 0);
-        }
-      }
-    }
+    for (int s = 0; s < kSlices; ++s) a[u][s] = abase[s * astride + 64 * kl];
   }
+  auto step = [&](int kk, int u) {
+    const int kl = kk + PF < nkb ? kk + PF : nkb - 1;
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) a[(u + PF) % NB][s] = abase[s * astride + 64 * kl];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      i32x4 b[kSlices];
+#pragma unroll
+      for (int s = 0; s < kSlices; ++s) b[s] = *(const i32x4*)(bbase + (s * PT + 16 * c) * ldq + 64 * kk);
+#pragma unroll
+      for (int sa = 0; sa < kSlices; ++sa)
+#pragma unroll
+        for (int sb = 0; sa + sb < kSlices; ++sb)
+          acc[sa + sb][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[u][sa], b[sb], acc[sa + sb][c], 0, 0, 0);
+    }
+  };
+  const int nmain = nkb - nkb % NB;
+  int kk = 0;
+  for (; kk < nmain; kk += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) step(kk + u, u);
+  }
+#pragma unroll
+  for (int u = 0; u < NB - 1; ++u)
+    if (kk + u < nkb) step(kk + u, u);
 }
 
 // p of a value iteration written straight to the output row g (rows row0 .. row0 + 3 below n):
@@ -230,7 +239,7 @@ enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FL
 constexpr int kStallIters = 64;
 enum {
   CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
-  CTL_EXIT, CTL_BETTER, CTL_ANY
+  CTL_EXIT, CTL_BETTER, CTL_ANY, CTL_PHIPASS
 };
 enum { PH_WARMUP = 0, PH_DELTA = 1 };
 
