@@ -49,6 +49,8 @@ __device__ __forceinline__ f32x4 f4(bf16x4 v) { return f32x4{(float)v[0], (float
 __device__ __forceinline__ bf16x4 b4(f32x4 v) {
   return bf16x4{to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3])};
 }
+// clamp of x to [lo, hi] (lo <= hi) in one instruction
+__device__ __forceinline__ float med3f(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 // ea storage in LDS: FP32 or BF16
 __device__ __forceinline__ f32x4 edec(f32x4 v) { return v; }
 __device__ __forceinline__ f32x4 edec(bf16x4 v) { return f4(v); }
@@ -64,6 +66,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
                 int* __restrict__ chunk_counter, double* __restrict__ ws64, int64_t ws64_per_wg,
                 float* __restrict__ ws, int64_t ws_per_wg, int anchor_every) {
   constexpr int NW = kNW, CT = kCT, PT = kPT;
+  static_assert(PT <= 64, "the slot bookkeeping takes one lane of wave 0 per slot");
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ ColShared<PT, NW> S;
   __shared__ __attribute__((aligned(16))) float Wl[1024];  // the problem's FP32 weights
@@ -163,8 +166,8 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
               const float zan = (float)z;
               const float dzn = (float)(z - (double)zan);
               const float th = theta_f(th1f, wv[q]);
-              const float ca = clampf(zan, -th, th), sa = zan - ca;
-              const float ds = dzn - clampf(dzn + sa, -th - ca, th - ca);
+              const float ca = med3f(zan, -th, th), sa = zan - ca;
+              const float ds = dzn - med3f(dzn + sa, -th - ca, th - ca);
               const double sa64 = row < n ? anchor_shrink(zan, th1, pb.w, row) : 0.0;
               if (on) {
                 pss[ct] += sa64 * sa64;
@@ -423,7 +426,27 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
     }
 
     // ============================================================ refill empty slots
-    if (tid == 0) {
+    // wave 0, one lane per slot: when the current chunk has a column for every empty slot, the
+    // slots take consecutive columns in slot order; otherwise lane 0 walks the slots and fetches
+    // chunks
+    bool refilled = false;
+    if (wave == 0) {
+      const int st = l < PT ? S.state[l] : COL_ACTIVE;
+      if (l < PT) S.fresh[l] = 0;
+      const uint64_t em = __ballot(st == COL_EMPTY);
+      const int nempty = __popcll(em);
+      const int nextcol = S.ctl[CTL_NEXTCOL], cend = S.ctl[CTL_CHUNKEND];
+      if (nempty <= cend - nextcol) {  // wave-uniform
+        if ((em >> l) & 1) {
+          const int col = nextcol + __popcll(em & ((1ull << l) - 1));
+          S.col[l] = col; S.j[l] = col; S.k[l] = 0;
+          S.fresh[l] = 1;
+        }
+        if (l == 0) { S.ctl[CTL_NEXTCOL] = nextcol + nempty; S.ctl[CTL_ANY] = 0; S.ctl[CTL_EXIT] = 0; }
+        refilled = true;
+      }
+    }
+    if (tid == 0 && !refilled) {
       int prob = S.ctl[CTL_PROB], nextcol = S.ctl[CTL_NEXTCOL], cend = S.ctl[CTL_CHUNKEND];
       int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE];
       int live = 0;
@@ -512,7 +535,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
               const float xp = (float)((double)xv - (cen ? cen[row] : 0.0));
               v[q] = xp;
               const float th = theta_f(th1f, wv[q]);
-              const float sa = xp - clampf(xp, -th, th);
+              const float sa = xp - med3f(xp, -th, th);
               ps[ct] += sa * sa;
             }
           }
@@ -547,14 +570,15 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
       if (tid == 0) S.ctl[CTL_ANY] = 0;
       __syncthreads();
     }
-    {  // anything to iterate?
-      if (tid == 0) {
-        int live = 0;
-        for (int c = 0; c < PT; ++c) {
-          const int st = S.state[c];
-          live |= (st == COL_ACTIVE || st == COL_PHI) ? 1 : (st == COL_INVALID ? 2 : 0);
+    {  // anything to iterate? (wave 0, one lane per slot; also whether a value pass is due)
+      if (wave == 0) {
+        const int st = l < PT ? S.state[l] : COL_EMPTY;
+        const uint64_t m_it = __ballot(st == COL_ACTIVE || st == COL_PHI);
+        const uint64_t m_inv = __ballot(st == COL_INVALID), m_phi = __ballot(st == COL_PHI);
+        if (l == 0) {
+          S.ctl[CTL_ANY] = (m_it ? 1 : 0) | (m_inv ? 2 : 0);
+          S.ctl[CTL_PHIPASS] = m_phi != 0;
         }
-        S.ctl[CTL_ANY] = live;
       }
       __syncthreads();
       if (!(S.ctl[CTL_ANY] & 1)) {
@@ -568,44 +592,51 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
 #pragma unroll
       for (int q = 0; q < 4; ++q) S.redv[tid][q] = 0.0;
     }
-    if (tid == 0) {
-      int phi = 0;
-      for (int c = 0; c < PT; ++c) phi |= S.state[c] == COL_PHI;
-      S.ctl[CTL_PHIPASS] = phi;
-    }
 
     lanes();
     // ============================================================ prologue: right-hand sides
     // dd = prox(za + dz) - prox(za): shrink1 increment ds from za's decomposition (ca = clamp(za),
     // sa = za - ca), then the l2 factors: dd = ga ds + (g - ga)(sa + ds).  Fresh columns:
     // r = x' + lambda (2 d^a - za) with d^a = ga sa (za = x').
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int c = 16 * ct + lr;
-      const int st = S.state[c];
-      const bool on = st == COL_ACTIVE || st == COL_PHI;
-      const bool fresh = S.fresh[c];
-      const float th1f = (float)S.th1[c], gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
-#pragma unroll
-      for (int i = 0; i < RW; ++i) {
-        if (i >= nrw) continue;
-        const int rt = wave + NW * i;
-        const int row0 = 16 * rt + 4 * lg;
+    {
+      // a wave with all RW row tiles (every wave once n_pad = 16 NW RW) runs the tiles without
+      // branches between them, so their anchor loads are in flight together
+      auto prologue_tile = [&](int i, int ct, int c, int onmask, bool fresh, float th1f, float gaf, float dgf,
+                               f32x4 zv) {
+        const int row0 = 16 * (wave + NW * i) + 4 * lg;
         const f32x4 wv = *(const f32x4*)(Wl + row0);
-        const f32x4 zv = ld_nt4(sst + sidx(0, i, ct));
         bf16x4 o;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float zz = zv[q], dzv = dz[i][ct][q];
           const float th = theta_f(th1f, wv[q]);
-          const float ca = clampf(zz, -th, th), sa = zz - ca;
-          const float ds = dzv - clampf(dzv + sa, -th - ca, th - ca);
+          const float ca = med3f(zz, -th, th), sa = zz - ca;
+          const float ds = dzv - med3f(dzv + sa, -th - ca, th - ca);
           const float dd = gaf * ds + dgf * (sa + ds);
-          const float r = fresh ? zz + flam * (2.f * gaf * sa - zz) : flam * (2.f * dd - dzv);
-          o[q] = to_bf16(on ? r : 0.f);
+          const float rn = flam * (2.f * dd - dzv), rf = zz + flam * (2.f * gaf * sa - zz);
+          // columns not iterated get +0 (a bit mask: no branch per element)
+          o[q] = to_bf16(__int_as_float(__float_as_int(fresh ? rf : rn) & onmask));
         }
         *(bf16x4*)(Bbuf + c * ldb + row0) = o;
-        __builtin_amdgcn_sched_barrier(0);
+      };
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = 16 * ct + lr;
+        const int st = S.state[c];
+        const int onmask = (st == COL_ACTIVE || st == COL_PHI) ? -1 : 0;
+        const bool fresh = S.fresh[c];
+        const float th1f = (float)S.th1[c], gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
+        if (nrw == RW) {
+          f32x4 zl[RW];
+#pragma unroll
+          for (int i = 0; i < RW; ++i) zl[i] = ld_nt4(sst + sidx(0, i, ct));
+#pragma unroll
+          for (int i = 0; i < RW; ++i) prologue_tile(i, ct, c, onmask, fresh, th1f, gaf, dgf, zl[i]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < RW; ++i)
+            if (i < nrw) prologue_tile(i, ct, c, onmask, fresh, th1f, gaf, dgf, ld_nt4(sst + sidx(0, i, ct)));
+        }
       }
     }
     __syncthreads();
@@ -629,53 +660,63 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
         for (int ct = 0; ct < CT; ++ct) acc[r][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
       gemm_bf16<kRG, CT, kPF>(pb.Mb, n_pad, Bbuf, ldb, rt, nr, acc);
       __builtin_amdgcn_sched_barrier(0);
+      // one row tile of one column tile; columns not iterated (empty, waiting, done) keep dz
+      auto epi_tile = [&](int r, int ct, int st, bool fresh, float th1f, float gaf, float dgf, f32x4 zv, f32x4 eb) {
+        const bool on = st == COL_ACTIVE || st == COL_PHI;
+        const int i = i0 + r;
+        const int row0 = 16 * rt[r] + 4 * lg;
+        const f32x4 wv = *(const f32x4*)(Wl + row0);
+        const f32x4 v = acc[r][ct];
+        const f32x4 dz0 = dz[i][ct];
+        f32x4 dv, enew;
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float th = theta_f(th1f, wv[q]);
+          const float ca = med3f(zv[q], -th, th), sa = zv[q] - ca;
+          const float lo = -th - ca, hi = th - ca;
+          const float ds = dz0[q] - med3f(dz0[q] + sa, lo, hi);
+          const float dd = gaf * ds + dgf * (sa + ds);
+          // fresh: v is M r^a, so ea = v - d^a (estimate) and the first step is ea
+          const float ef = v[q] - gaf * sa, sn = eb[q] + v[q] - dd;
+          const float step = fresh ? ef : sn;
+          const float dzn = dz0[q] + step;
+          const float dsn = dzn - med3f(dzn + sa, lo, hi);
+          s0 += step * step;
+          s1 += dsn * (2.f * sa + dsn);
+          dv[q] = on ? dzn : dz0[q];
+          enew[q] = ef;
+        }
+        part[ct][0] += on ? s0 : 0.f;
+        part[ct][1] += on ? s1 : 0.f;
+        if (on && fresh) Ebuf[eidx(i, ct)] = eenc<EV>(enew);
+        if (st == COL_PHI) {  // the value phase below takes it from here
+          st_nt4(sst + sidx(1, i, ct), dz0);
+          st_nt4(sst + sidx(2, i, ct), v);
+        }
+        dz[i][ct] = dv;
+      };
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + lr;
         const int st = S.state[c];
-        if (st != COL_ACTIVE && st != COL_PHI) continue;
         const bool fresh = S.fresh[c];
         const float th1f = (float)S.th1[c], gaf = (float)S.gama[c], dgf = (float)S.dgam[c];
+        if (nr == kRG) {  // the group's anchors and ea loaded together
+          f32x4 zg[kRG];
+          EV eg[kRG];
 #pragma unroll
-        for (int r = 0; r < kRG; ++r) {
-          if (r >= nr) continue;
-          const int i = i0 + r;
-          const int row0 = 16 * rt[r] + 4 * lg;
-          const f32x4 wv = *(const f32x4*)(Wl + row0);
-          const f32x4 eb = edec(Ebuf[eidx(i, ct)]);
-          const f32x4 v = acc[r][ct];
-          const f32x4 zv = ld_nt4(sst + sidx(0, i, ct));
-          f32x4 dv = dz[i][ct];
-          float s0 = 0.f, s1 = 0.f;
-          const f32x4 dz0 = dv;
-          f32x4 enew;
+          for (int r = 0; r < kRG; ++r) { zg[r] = ld_nt4(sst + sidx(0, i0 + r, ct)); eg[r] = Ebuf[eidx(i0 + r, ct)]; }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float th = theta_f(th1f, wv[q]);
-            const float ca = clampf(zv[q], -th, th), sa = zv[q] - ca;
-            const float lo = -th - ca, hi = th - ca;
-            const float ds = dv[q] - clampf(dv[q] + sa, lo, hi);
-            const float dd = gaf * ds + dgf * (sa + ds);
-            // fresh: v is M r^a, so ea = v - d^a (estimate) and the first step is ea
-            const float ea = fresh ? v[q] - gaf * sa : eb[q];
-            const float step = fresh ? ea : ea + v[q] - dd;
-            const float dzn = dv[q] + step;
-            const float dsn = dzn - clampf(dzn + sa, lo, hi);
-            s0 += step * step;
-            s1 += dsn * (2.f * sa + dsn);
-            dv[q] = dzn;
-            enew[q] = ea;
-          }
-          part[ct][0] += s0;
-          part[ct][1] += s1;
-          if (fresh) Ebuf[eidx(i, ct)] = eenc<EV>(enew);
-          if (st == COL_PHI) {  // the value phase below takes it from here
-            st_nt4(sst + sidx(1, i, ct), dz0);
-            st_nt4(sst + sidx(2, i, ct), v);
-          }
-          dz[i][ct] = dv;
-          __builtin_amdgcn_sched_barrier(0);
+          for (int r = 0; r < kRG; ++r) epi_tile(r, ct, st, fresh, th1f, gaf, dgf, zg[r], edec(eg[r]));
+        } else {
+#pragma unroll
+          for (int r = 0; r < kRG; ++r)
+            if (r < nr)
+              epi_tile(r, ct, st, fresh, th1f, gaf, dgf, ld_nt4(sst + sidx(0, i0 + r, ct)),
+                       edec(Ebuf[eidx(i0 + r, ct)]));
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // ============================================================ value pass
@@ -704,8 +745,8 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
           for (int q = 0; q < 4; ++q) {
             const int row = row0 + q;
             const float th = theta_f(th1f, wv[q]);
-            const float ca = clampf(zv[q], -th, th), sa = zv[q] - ca;
-            const float ds = dz0[q] - clampf(dz0[q] + sa, -th - ca, th - ca);
+            const float ca = med3f(zv[q], -th, th), sa = zv[q] - ca;
+            const float ds = dz0[q] - med3f(dz0[q] + sa, -th - ca, th - ca);
             const float dd = gaf * ds + dgf * (sa + ds);
             const double da = ga * anchor_shrink(zv[q], th1, pb.w, row < n ? row : 0);
             double d = da + (double)dd;
@@ -777,15 +818,13 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
       S.fresh[c] = 0;
     }
     __syncthreads();
-    if (tid == 0) {
-      int nact = 0, nwait = 0;
-      for (int c = 0; c < PT; ++c) {
-        nact += S.state[c] == COL_ACTIVE;
-        nwait += S.state[c] == COL_WAITING;
+    if (wave == 0) {  // the anchor decision, one lane per slot
+      const int st = l < PT ? S.state[l] : COL_EMPTY;
+      const uint64_t m_act = __ballot(st == COL_ACTIVE), m_wait = __ballot(st == COL_WAITING);
+      if (l == 0) {
+        const int kn = k_it + 1;
+        if ((m_act && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (m_wait && !m_act)) S.ctl[CTL_ANCHOR] = 1;
       }
-      const int kn = k_it + 1;
-      if ((nact > 0 && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (nwait > 0 && nact == 0))
-        S.ctl[CTL_ANCHOR] = 1;
     }
     __syncthreads();
     ++k_it;
