@@ -460,6 +460,9 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   if (st) return st;
   std::lock_guard<std::mutex> lk(w->mu);
   const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
+  // the on-chip kernel's anchors cost about ten of its passes: every 24 passes gave the fewest
+  // cycles on n = 1024 (16: more anchors than iterations saved, 32 and above: more iterations)
+  const int rs_anchor_every = std::max(1, env_int("HOPF_RS_ANCHOR_EVERY", 24));
   // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
   const int anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
   // the wave-local kernel of FP32 problems: refined increments on exact FP64 anchors (mode 2),
@@ -562,7 +565,8 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     hipError_t e = small ? launch_dense_small(max_npad, small_refined, (const DenseProb*)dmeta, dchunks, nchunks,
                                               counter, grid, small_anchor_every, small_anchor_wait, stream)
                    : rs  ? launch_dense_rs(max_npad, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state64,
-                                           ws64_per_wg, w->state, ws_per_wg, grid, lds, anchor_every, stream)
+                                           ws64_per_wg, w->state, ws_per_wg, grid, lds, rs_anchor_every,
+                                           anchor_wait, stream)
                          : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
                                         w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
                                         anchor_wait, stream);

@@ -35,6 +35,6 @@ size_t dense_rs_lds_bytes(int n_pad);     // dynamic LDS of a launch whose large
 int64_t dense_rs_ws_floats(int n_pad);    // float staging per workgroup
 hipError_t launch_dense_rs(int max_npad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
                            int* counter, double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid,
-                           size_t lds, int anchor_every, hipStream_t stream);
+                           size_t lds, int anchor_every, int anchor_wait, hipStream_t stream);
 
 }  // namespace hopf

@@ -64,7 +64,7 @@ template <int RW, typename EV>
 __global__ void __launch_bounds__(kNW * 64, 1)
 dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
                 int* __restrict__ chunk_counter, double* __restrict__ ws64, int64_t ws64_per_wg,
-                float* __restrict__ ws, int64_t ws_per_wg, int anchor_every) {
+                float* __restrict__ ws, int64_t ws_per_wg, int anchor_every, int anchor_wait) {
   constexpr int NW = kNW, CT = kCT, PT = kPT;
   static_assert(PT <= 64, "the slot bookkeeping takes one lane of wave 0 per slot");
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -823,7 +823,9 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
       const uint64_t m_act = __ballot(st == COL_ACTIVE), m_wait = __ballot(st == COL_WAITING);
       if (l == 0) {
         const int kn = k_it + 1;
-        if ((m_act && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (m_wait && !m_act)) S.ctl[CTL_ANCHOR] = 1;
+        if ((m_act && kn - S.ctl[CTL_LAST_ANCHOR] >= anchor_every) || (m_wait && !m_act) ||
+            (anchor_wait > 0 && __popcll(m_wait) >= anchor_wait))
+          S.ctl[CTL_ANCHOR] = 1;
       }
     }
     __syncthreads();
@@ -860,7 +862,7 @@ int64_t dense_rs_ws_floats(int n_pad) {
 template <int RW, typename EV>
 static hipError_t launch_rs_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                               double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid, size_t lds,
-                              int anchor_every, hipStream_t stream) {
+                              int anchor_every, int anchor_wait, hipStream_t stream) {
   auto kern = dense_rs_kernel<RW, EV>;
   static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
   int dev = 0;
@@ -873,19 +875,19 @@ static hipError_t launch_rs_t(const DenseProb* d_probs, const DenseChunk* d_chun
     attr_bytes[dev] = lds;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kNW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws64,
-                     ws64_per_wg, ws, ws_per_wg, anchor_every);
+                     ws64_per_wg, ws, ws_per_wg, anchor_every, anchor_wait);
   return hipGetLastError();
 }
 
 hipError_t launch_dense_rs(int max_npad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
                            int* counter, double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid,
-                           size_t lds, int anchor_every, hipStream_t stream) {
+                           size_t lds, int anchor_every, int anchor_wait, hipStream_t stream) {
   if (max_npad <= 512)
     return launch_rs_t<kRWsmall, f32x4>(d_probs, d_chunks, nchunks, counter, ws64, ws64_per_wg, ws, ws_per_wg, grid, lds,
-                          anchor_every, stream);
+                          anchor_every, anchor_wait, stream);
   if (max_npad <= 1024)
     return launch_rs_t<kRWlarge, bf16x4>(d_probs, d_chunks, nchunks, counter, ws64, ws64_per_wg, ws, ws_per_wg, grid, lds,
-                          anchor_every, stream);
+                          anchor_every, anchor_wait, stream);
   return hipErrorInvalidValue;
 }
 
