@@ -27,11 +27,11 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (matrix)
 METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % roofline"
 
-# HBM traffic of the dense kernel on the default workload, from two rocprofv3 counter runs
-# (FETCH_SIZE, WRITE_SIZE; profiles/dense_kernel_n1024_65536pts_l2wl1_bf16refined.md), each
-# scaled by what the counter reads for a plain 256 MiB device copy.  Valid only for the kernel
-# source it was measured on (hash of dense.hip + dense_shared.hpp + common.hpp); reported as null
-# otherwise.
+# HBM traffic of the dominant kernel on the default workload, from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE; the profiles/ summary of the n=1024 workload), each scaled by what the
+# counter reads for a plain 256 MiB device copy.  Valid only for the kernel source it was measured
+# on (hash of TRAFFIC_SOURCES); reported as null otherwise.
+TRAFFIC_SOURCES = ("dense_rs.hip", "dense_shared.hpp", "common.hpp")
 TRAFFIC = {"source_sha256": "bd47e58b121fcf47c7b878017d4639ad30c4c1807da805068054299b4a9680d3",
            "read_bytes": 352.483e9, "write_bytes": 49.273e9, "precision": "bf16_refined", "npts": 1 << 16,
            "tol": 1e-12}
@@ -40,7 +40,7 @@ TRAFFIC = {"source_sha256": "bd47e58b121fcf47c7b878017d4639ad30c4c1807da80506805
 def measured_traffic(precision, npts, tol):
     import hashlib
     h = hashlib.sha256()
-    for f in ("dense.hip", "dense_shared.hpp", "common.hpp"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1605_01799_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if (h.hexdigest() != TRAFFIC["source_sha256"] or precision != TRAFFIC["precision"]
@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "f32"])
     ap.add_argument("--npts", type=int, default=1 << 16)
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="most points of the CPU baseline's stratified sample (it is sized to ~15 s)")
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c3",
@@ -161,7 +162,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": measured_traffic(a.precision, npts, tol), "traffic_unit": "HBM bytes read + written per launch",
-                     "kernel": "dense_kernel (one launch per step)",
+                     "kernel": ("dense_rs_kernel<8, bf16x4> (on-chip column state; one launch per step)"
+                                if a.precision == "bf16_refined" and os.environ.get("HOPF_RS", "1") != "0"
+                                else "dense_kernel (one launch per step)"),
                      "algorithmic": "sum over points of iterations x 2 n^2 FLOP",
                      "flop_per_launch": flops, "launch_ms": eval_ms},
         "eval_only": {"ms": eval_ms, "value": npts / (eval_ms / 1e3)},
@@ -177,7 +180,7 @@ def main():
         idx = np.sort(rng.choice(npts, size=min(a.acc_sample, npts), replace=False))
         xs = p.x[idx].astype(np.float64)
         ts = p.t[idx].astype(np.float64)
-        threads = min(16, os.cpu_count() or 1)
+        threads = max(1, min(host_info()["affinity"], CPU_SHARE))
         ref = oracle.oracle_eval(p.A, xs, ts, "l2_wl1", w=p.w, tol=1e-28, nthreads=threads)
         g = out["grad"].cpu().numpy()[idx]
         ph = out["phi"].cpu().numpy()[idx]
@@ -186,21 +189,51 @@ def main():
         rec["accuracy"] = {"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()),
                            "max_rel_err_phi": float(ef.max()), "bound": 1e-6,
                            "ok": bool(ep.max() <= 1e-6 and ef.max() <= 1e-6)}
+        if a.precision == "bf16_refined":
+            rec["bf16_only"] = bf16_only_error(p, idx, ref["grad"], dev)
         if not a.no_cpu:
-            m = min(a.cpu_sample, npts)
-            xs = p.x[:m].astype(np.float64)
-            ts = p.t[:m].astype(np.float64)
-            c0 = time.perf_counter()
-            oracle.oracle_eval(p.A, xs, ts, "l2_wl1", w=p.w, tol=tol, nthreads=threads)
-            c1 = time.perf_counter()
-            rec["cpu_baseline"] = {"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads,
-                                   "kind": "oracle",
-                                   "sample": "first %d points of the same workload, same tol (%g), FP64 "
-                                             "oracle (triangular solves, compensated sums), %d threads"
-                                             % (m, tol, threads)}
+            rec["cpu_baseline"] = cpu_baseline(
+                lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64),
+                                                   "l2_wl1", w=p.w, tol=tol, nthreads=nt),
+                p.t, a.cpu_sample, "same tol (%g), FP64 oracle (triangular solves, compensated sums)" % tol)
     except Exception as e:  # the oracle is test infrastructure; its absence only drops these fields
         rec["accuracy_error"] = str(e)
     print(json.dumps(rec), flush=True)
+
+
+def bf16_only_error(p, idx, ref_grad, dev, lam=1.0, iters=4000):
+    """Error of the plain split-Bregman iteration with BF16 products alone (no exact anchors) on
+    the accuracy sample, beside the a-priori kappa(A + lambda I) 2^-8: M and every right-hand
+    side rounded to BF16, products accumulated and the state kept in FP32, run to its own fixed
+    point.  A measurement of the precision form (torch operations on the GPU), not the solver."""
+    import torch
+    Ad = np.asarray(p.A, np.float64)
+    n = Ad.shape[0]
+    ev = np.linalg.eigvalsh(Ad)
+    kappa = float((ev.max() + lam) / (ev.min() + lam))
+    M = np.linalg.inv(Ad + lam * np.eye(n))
+    Mb = torch.from_numpy(M).to(dev).to(torch.bfloat16).float()
+    X = torch.from_numpy(p.x[idx].astype(np.float32)).to(dev).T.contiguous()      # n x m
+    T = torch.from_numpy(p.t[idx].astype(np.float32)).to(dev)
+    w = torch.from_numpy(np.asarray(p.w, np.float32)).to(dev)[:, None]
+    th1 = w * (T / lam)[None, :]
+    th2 = (T / lam)[None, :]
+
+    def prox(z):  # H = |.|_2 + sum w_i |.|: shrink1 then shrink2
+        s1 = z - torch.clamp(torch.maximum(z, -th1), max=th1)
+        nz = torch.linalg.norm(s1, dim=0, keepdim=True)
+        return s1 * torch.clamp(nz - th2, min=0) / torch.where(nz > 0, nz, torch.ones_like(nz))
+    z = X.clone()
+    for _ in range(iters):
+        d = prox(z)
+        r = X + lam * (2 * d - z)
+        z = z - d + Mb @ r.to(torch.bfloat16).float()
+    g = prox(z).T.cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(g - ref_grad, axis=1) / np.maximum(np.linalg.norm(ref_grad, axis=1), 1)
+    return {"max_rel_err_grad": float(e.max()), "median_rel_err_grad": float(np.median(e)),
+            "kappa_A_plus_lambda_I": kappa, "kappa_times_2^-8": kappa * 2.0 ** -8,
+            "how": "plain iteration, %d passes, BF16-rounded M and right-hand sides, FP32 accumulation and state "
+                   "(torch on the GPU), same %d points as accuracy" % (iters, len(idx))}
 
 
 def timed_steps(step, steps, warmup):
@@ -219,6 +252,55 @@ def timed_steps(step, steps, warmup):
     return (t1 - t0) * 1e3 / steps, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
 
 
+# host threads per GPU on the shared GPU hosts: the baseline uses at most this many
+CPU_SHARE = 16
+
+
+def host_info():
+    """CPU model, logical CPU count and the CPUs this process may run on."""
+    import platform
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"cpu_model": model or platform.processor(), "nproc": os.cpu_count(), "affinity": aff}
+
+
+def stratified(t, m):
+    """m indices spread evenly over the points sorted by t (iteration counts follow t)."""
+    order = np.argsort(np.asarray(t), kind="stable")
+    pos = np.unique(np.linspace(0, len(order) - 1, max(1, m)).round().astype(int))
+    return np.sort(order[pos])
+
+
+def cpu_baseline(run, t, cap, what, budget_s=15.0, one_thread_pts=8):
+    """The oracle's rate on the host: first one thread on a few stratified points, then all
+    threads of the GPU's CPU share on a stratified sample sized to about budget_s seconds (at
+    most cap points).  run(idx, nthreads) evaluates the oracle on the points idx."""
+    info = host_info()
+    threads = max(1, min(info["affinity"], CPU_SHARE))
+    idx1 = stratified(t, min(one_thread_pts, len(t)))
+    c0 = time.perf_counter()
+    run(idx1, 1)
+    rate1 = len(idx1) / (time.perf_counter() - c0)
+    m = int(min(cap, len(t), max(threads, rate1 * threads * budget_s)))
+    idx = stratified(t, m)
+    c0 = time.perf_counter()
+    run(idx, threads)
+    rate = len(idx) / (time.perf_counter() - c0)
+    return {"value": rate, "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+            "one_thread": rate1, **info,
+            "sample": "%d points stratified by t (sized to ~%.0f s, at most %d), %s, %d threads (the GPU's "
+                      "CPU share); one_thread: %d points on one thread" % (len(idx), budget_s, cap, what, threads,
+                                                                           len(idx1))}
+
+
 def bench_other(a):
     import torch
     from paper_1605_01799_amd import hopf as H
@@ -226,7 +308,7 @@ def bench_other(a):
     import oracle
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    threads = min(16, os.cpu_count() or 1)
+    threads = max(1, min(host_info()["affinity"], CPU_SHARE))
     rec = {"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
            "unit": "point-evals/s"}
 
@@ -254,10 +336,9 @@ def bench_other(a):
         # the closed form of this workload (A = I, H = l1): p = sign(x) max(|x| - t, 0)
         g = out["grad"].cpu().numpy()
         pcf = np.sign(p.x) * np.maximum(np.abs(p.x) - p.t[:, None], 0)
-        m = min(npts, 1 << 20)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(np.eye(p.n), p.x[:m], p.t[:m], "wl1", tol=1e-24, max_iter=500, nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(np.eye(p.n), p.x[idx], p.t[idx], "wl1", tol=1e-24,
+                                                              max_iter=500, nthreads=nt),
+                           p.t, 1 << 22, "same tol, FP64 oracle", one_thread_pts=1 << 14)
         rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=8 FP64 diagonal path; % HBM roofline",
                    value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f64",
                    config={"workload": "n=8, A=I, H=l1, %d points x~N(0,1), t~U(0.1,2), FP64, tol 1e-24, "
@@ -266,8 +347,7 @@ def bench_other(a):
                              "frac": achieved / 8000.0, "traffic": None, "kernel": "diag_kernel<double, 8>",
                              "algorithmic": "%d B per point (in and out)" % per_point, "launch_ms": kms},
                    accuracy={"max_abs_err_grad_vs_closed_form": float(np.abs(g - pcf).max()), "points": npts},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload == "pd16":
         npts = a.npts if a.npts != 1 << 16 else 1 << 22
         p = W.workload_paper_d(16, npts, True)
@@ -299,10 +379,9 @@ def bench_other(a):
         ref = oracle.oracle_eval(p.A, p.x[idx], p.t[idx], "wl2", w=p.w, tol=1e-28, nthreads=threads)
         g = out["grad"].cpu().numpy()[idx]
         ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
-        m = min(npts, 1 << 18)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(p.A, p.x[:m], p.t[:m], "wl2", w=p.w, tol=tol, max_iter=20000, nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx], p.t[idx], "wl2", w=p.w, tol=tol,
+                                                              max_iter=20000, nthreads=nt),
+                           p.t, 1 << 20, "same tol, FP64 oracle", one_thread_pts=1 << 12)
         value = npts / (ms / 1e3)
         paper_s = 6.64e-06   # Table 4, H = ||.||_D, n = 16: seconds per evaluation on one laptop core
         rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16 FP64 diagonal path, H=sqrt(<p,Dp>); "
@@ -323,8 +402,7 @@ def bench_other(a):
                                      "(squared norms <= 1e-8) itself leaves errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "one core of an i5-5300U (Table 4)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload == "t5n16":
         npts = a.npts if a.npts != 1 << 16 else 1 << 22
         p = W.workload_paper_norms(16, npts, "linf")
@@ -359,11 +437,9 @@ def bench_other(a):
         ref = oracle.oracle_eval(np.eye(p.n), p.x[idx], p.t[idx], "linf", jkind="l1sq", tol=1e-28, nthreads=threads)
         g = out["grad"].cpu().numpy()[idx]
         ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
-        m = min(npts, 1 << 16)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(np.eye(p.n), p.x[:m], p.t[:m], "linf", jkind="l1sq", tol=tol, max_iter=20000,
-                           nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(np.eye(p.n), p.x[idx], p.t[idx], "linf", jkind="l1sq",
+                                                              tol=tol, max_iter=20000, nthreads=nt),
+                           p.t, 1 << 20, "same tol, FP64 oracle", one_thread_pts=1 << 10)
         value = npts / (ms / 1e3)
         paper_s = 2.22e-05   # Table 5, n = 16, 16 cores: seconds per evaluation
         rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16, J=1/2|y|_1^2, H=|p|_inf, FP64; % FP64 vector roofline",
@@ -383,8 +459,7 @@ def bench_other(a):
                                      "errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "16 cores of 2x Xeon E5-2690 (Table 5)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload == "pa16":
         npts = a.npts if a.npts != 1 << 16 else 1 << 22
         p = W.round_inputs(W.workload_paper_a(16, npts))
@@ -415,11 +490,10 @@ def bench_other(a):
                                  tol=1e-28, nthreads=threads)
         g = out["grad"].cpu().numpy()[idx]
         ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
-        m = min(npts, 1 << 16)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), "al2", HA=HA, tol=tol,
-                           max_iter=20000, nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx].astype(np.float64),
+                                                              p.t[idx].astype(np.float64), "al2", HA=HA, tol=tol,
+                                                              max_iter=20000, nthreads=nt),
+                           p.t, 1 << 20, "same tol, FP64 oracle", one_thread_pts=1 << 10)
         rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16, H=sqrt(<p,HA p>) in HA's eigenbasis, FP32; "
                           "% FP32 MFMA roofline",
                    value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
@@ -437,8 +511,7 @@ def bench_other(a):
                                      "errors of this size"},
                    paper={"seconds_per_eval": 1.04e-05, "hardware": "one core of an i5-5300U (Table 4, FP64)",
                           "note": "context only: another machine, one core, FP64"},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload in ("c2", "c2wl2"):
         npts = a.npts if a.npts != 1 << 16 else 1 << 20
         hk = "wl1" if a.workload == "c2" else "wl2"
@@ -469,11 +542,10 @@ def bench_other(a):
                                  tol=1e-28, nthreads=threads)
         g = out["grad"].cpu().numpy()[idx]
         ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
-        m = min(npts, 1 << 14)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), hk, w=p.w, tol=tol,
-                           nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx].astype(np.float64),
+                                                              p.t[idx].astype(np.float64), hk, w=p.w, tol=tol,
+                                                              nthreads=nt),
+                           p.t, 1 << 16, "same tol, FP64 oracle", one_thread_pts=64)
         hname = "weighted l1" if hk == "wl1" else "sqrt(<p, diag(w) p>)"
         rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=64 dense FP32%s; %% FP32 MFMA roofline"
                           % ("" if hk == "wl1" else ", H=sqrt(<p,Dp>)"),
@@ -485,8 +557,7 @@ def bench_other(a):
                              "algorithmic": "sum over points of iterations x 2 n^2 FLOP", "launch_ms": kms},
                    iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
                    accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": 1e-6},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points, same tol, FP64 oracle, %d threads" % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload == "c5":  # forward over the union of 4 ellipsoids, then the envelope backward
         npts = a.npts if a.npts != 1 << 16 else 1 << 18
         p = W.round_inputs(W.workload5(npts))
@@ -512,10 +583,15 @@ def bench_other(a):
                 e3.record(stream)
                 bw_ms.append((e2, e3))
             step.out, step.b = out, b
-        ms, kms = timed_steps(step, a.steps, a.warmup)
+        for _ in range(a.warmup):
+            step(None)
+        torch.cuda.synchronize()
+        prob.iterations(reset=True)
+        ms, kms = timed_steps(step, a.steps, 0)
+        passes = prob.iterations(reset=True) / a.steps   # every copy's passes, counted on the device
         bms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in bw_ms]))
         it = step.out["iters"].cpu().numpy()
-        flops = float(p.K * np.sum(np.abs(it)).astype(np.float64) * 2.0 * p.n * p.n)
+        flops = float(passes * 2.0 * p.n * p.n)
         achieved = flops / (kms / 1e3) / 1e12
         bw_bytes = npts * (4 * (2 * p.n + 2) + 4 * (p.n + 1) + 4)
         rng = np.random.default_rng(8)
@@ -523,28 +599,27 @@ def bench_other(a):
         ref = oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64), "wl1", w=p.w,
                                  centres=p.centres, level_set=True, tol=1e-28, nthreads=threads)
         ef = np.abs(step.out["phi"].cpu().numpy()[idx] - ref["phi"]) / np.maximum(np.abs(ref["phi"]), 1)
-        m = min(npts, 512)
-        c0 = time.perf_counter()
-        oracle.oracle_eval(p.A, p.x[:m].astype(np.float64), p.t[:m].astype(np.float64), "wl1", w=p.w,
-                           centres=p.centres, level_set=True, tol=tol, nthreads=threads)
-        c1 = time.perf_counter()
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx].astype(np.float64),
+                                                              p.t[idx].astype(np.float64), "wl1", w=p.w,
+                                                              centres=p.centres, level_set=True, tol=tol,
+                                                              nthreads=nt),
+                           p.t, 4096, "forward only, same tol, FP64 oracle", one_thread_pts=8)
         rec.update(metric="Hopf point-evals/sec (φ forward + envelope backward), n=256, union of 4 ellipsoids, FP32",
                    value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f32",
                    config={"workload": "n=256, J = min over 4 ellipsoid level sets, H=weighted l1, %d points, FP32, "
                                        "tol %g; step = forward + backward (x, t, A, centres)" % (npts, tol),
                            "npts": npts},
                    roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<0, 4, 4, 1, 4>",
-                             "algorithmic": "K x iterations of the attaining copy x 2 n^2 FLOP per point "
-                                            "(the other copies' counts are not returned)", "launch_ms": kms},
+                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<2, ...> (FP32 refined)",
+                             "algorithmic": "passes of every copy of every point (hopf_problem_iterations) x "
+                                            "2 n^2 FLOP", "passes_per_step": passes, "launch_ms": kms},
                    backward={"ms": bms, "hbm_GBps": bw_bytes / (bms / 1e3) / 1e9,
                              "hbm_frac": bw_bytes / (bms / 1e3) / 1e9 / 8000.0,
                              "algorithmic_bytes": bw_bytes},
-                   iterations={"mean_attaining_copy": float(np.abs(it).mean())},
+                   iterations={"mean_attaining_copy": float(np.abs(it).mean()),
+                               "mean_per_copy": passes / (npts * p.K)},
                    accuracy={"sample": int(len(idx)), "max_rel_err_phi": float(ef.max()), "bound": 1e-6},
-                   cpu_baseline={"value": m / (c1 - c0), "unit": "point-evals/s", "cores": threads, "kind": "oracle",
-                                 "sample": "first %d points (forward only), same tol, FP64 oracle, %d threads"
-                                           % (m, threads)})
+                   cpu_baseline=cpu)
     elif a.workload == "c4":
         # workload 4: 4096 problems, each its own n (log-uniform in [4, 2048]), A, w, t and point
         # count (log-uniform in [1, 4096]), J = min over K = 8 ellipsoid level sets, H = weighted
@@ -573,36 +648,52 @@ def bench_other(a):
             return a.tol if a.tol is not None else 1e-12
         specs = [dict(A=p.A, centres=p.centres, level_set=True, hkind="wl1", w=p.w, precision="f32",
                       tol=tol4(p.n), max_iter=20000) for p in probs]
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        hp = H.Problem.batch(specs)
-        torch.cuda.synchronize()
-        setup_ms = (time.perf_counter() - s0) * 1e3
         xs = [torch.from_numpy(p.x).to(dev) for p in probs]
         ts = [torch.from_numpy(p.t).to(dev) for p in probs]
         npts = int(pall.sum())
+        phases = []
 
+        # one step: the problems' FP64 set-up (host A in, batched Gauss-Jordan), the ragged
+        # evaluation, the ragged closest points and the release; events split the first three
         def step(ev):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)] if ev is not None else None
+            if ev is not None:
+                e[0].record(stream)
+            hp = H.Problem.batch(specs)
             if ev is not None:
                 ev[0].record(stream)
             step.out = H.eval_ragged(hp, xs, ts)
             if ev is not None:
                 ev[1].record(stream)
-        print("workload 4: problems created (%.0f ms); evaluating" % setup_ms, file=sys.stderr, flush=True)
+            step.cp = H.closest_point_ragged(hp, xs, s_tol=1e-7)
+            if ev is not None:
+                e[1].record(stream)
+                phases.append((e[0], ev[0], ev[1], e[1]))
+            hp.clear()  # hopf_problem_destroy of every problem
+        print("workload 4: evaluating", file=sys.stderr, flush=True)
         ms, kms = timed_steps(step, a.steps, a.warmup)
         print("workload 4: %d steps of %.0f ms" % (a.steps, ms), file=sys.stderr, flush=True)
+        setup_ms = float(np.mean([p0.elapsed_time(p1) for p0, p1, _, _ in phases]))
+        dist_ms = float(np.mean([p2.elapsed_time(p3) for _, _, p2, p3 in phases]))
         out = step.out
         it = np.abs(out["iters"].cpu().numpy()).astype(np.float64)
         npt = np.repeat(nall, pall).astype(np.float64)
-        flops_pt = W.W4_K * it * 2.0 * npt * npt  # K copies x iterations of the attaining copy x 2 n^2
-        flops = float(flops_pt.sum())
+        # counted work: one more evaluation (untimed) with each problem's pass counter read after it
+        hp = H.Problem.batch(specs)
+        H.eval_ragged(hp, xs, ts)
+        passes = np.array([q.iterations(reset=True) for q in hp], np.float64)
+        H.closest_point_ragged(hp, xs, s_tol=1e-7)
+        passes_d = np.array([q.iterations(reset=True) for q in hp], np.float64)
+        del hp
+        flops_q = passes * 2.0 * nall.astype(np.float64) ** 2      # per problem, every copy
+        flops = float(flops_q.sum())
+        flops_d = float((passes_d * 2.0 * nall.astype(np.float64) ** 2).sum())
         # the survey's mixed roofline: per problem max(FLOP / FP32 MFMA peak, bytes / HBM), summed
         off = out["offsets"]
         t_roof = 0.0
         for q in range(nprob):
-            fq = float(flops_pt[off[q]:off[q + 1]].sum())
             bq = float(pall[q] * 4 * (3 * nall[q] + 4) + 4 * nall[q] * nall[q])
-            t_roof += max(fq / 157.3e12, bq / 8e12)
+            t_roof += max(flops_q[q] / 157.3e12, bq / 8e12)
         achieved = flops / (kms / 1e3) / 1e12
         # accuracy and CPU baseline: one point of each of 48 seeded problems drawn from the whole
         # batch (so the sample has the batch's mix of n); the accuracy reference is the oracle at
@@ -632,26 +723,32 @@ def bench_other(a):
                    config={"workload": "4096 problems, n = round(logU[4,2048]), A = Q diag(a^2) Q^T (a~U(0.5,3)), "
                                        "w~U(0.5,2), one t~U(0.05,3) per problem, round(logU[1,4096]) points "
                                        "x~N(0,4I), J = min over K=8 ellipsoid level sets (centres ~N(0,9I)), "
-                                       "H = weighted l1, FP32, tol 1e-12; step = the "
-                                       "ragged evaluation (problems created once, timed separately)",
+                                       "H = weighted l1, FP32, tol 1e-12; step = FP64 set-up of the 4096 "
+                                       "problems + ragged evaluation (phi, grad, dphi/dt) + ragged closest "
+                                       "points and distances (s_tol 1e-7) + release",
                            "problems": nprob, "npts": npts, "K": W.W4_K},
                    roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
                              "frac": achieved / 157.3, "traffic": None,
                              "mixed_frac": t_roof / (kms / 1e3),
                              "mixed": "sum over problems of max(FLOP / 157.3 TFLOP/s, bytes / 8 TB/s), "
                                       "bytes = 4 (3 n + 4) per point + 4 n^2 per problem, over the measured time",
-                             "kernel": "dense_small_kernel and dense_kernel<0, ...> (one launch per class)",
-                             "algorithmic": "K x iterations of the attaining copy x 2 n^2 FLOP per point "
-                                            "(the other copies' counts are not returned)", "launch_ms": kms},
-                   setup={"ms": setup_ms, "what": "host A copied in + batched FP64 Gauss-Jordan of 4096 problems"},
-                   iterations={"mean_attaining_copy": float(it.mean()), "max": int(it.max())},
+                             "kernel": "dense_small_kernel<...> and dense_kernel<2, ...> (FP32 refined; one "
+                                       "launch per class)",
+                             "algorithmic": "passes of every copy of every point, counted on the device per problem "
+                                            "(hopf_problem_iterations), x 2 n^2 FLOP; the evaluation only",
+                             "launch_ms": kms},
+                   phases_ms={"setup": setup_ms, "evaluation": kms, "closest_points": dist_ms,
+                              "setup_what": "host A copied in + batched FP64 Gauss-Jordan of 4096 problems",
+                              "closest_points_tflops": flops_d / (dist_ms / 1e3) / 1e12},
+                   iterations={"mean_attaining_copy": float(it.mean()), "max": int(it.max()),
+                               "passes_all_copies": float(passes.sum()), "passes_closest_points": float(passes_d.sum())},
                    accuracy={"sample": "1 point of each of %d problems (n %d .. %d)" % (len(qs), nall[qs].min(),
                                                                                     nall[qs].max()),
                              "max_rel_err_phi": max(errs), "bound": 1e-6},
                    cpu_baseline={"value": cpu_n / cpu_s, "unit": "point-evals/s", "cores": threads,
-                                 "kind": "oracle",
+                                 "kind": "oracle", **host_info(),
                                  "sample": "the same %d points (one problem per thread), same tol, FP64 "
-                                           "oracle, %d threads" % (cpu_n, threads)})
+                                           "oracle, %d threads (the GPU's CPU share)" % (cpu_n, threads)})
     print(json.dumps(rec), flush=True)
 
 

@@ -193,6 +193,17 @@ hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* problems,
                              void* phi, void* grad_packed, void* dphidt, int32_t* iters,
                              int32_t* kstar, void* stream);
 
+/* Ragged batch of closest points and distances (section 3.2, the Newton iteration on s of
+ * eq. Newton_zero, with the inner evaluations of section 3.1): hopf_closest_point over nprob
+ * ellipsoid level-set problems (level_set = 1, quadratic J; one precision for all, not
+ * HOPF_F64) in the launches of hopf_eval_ragged.  pt_offset as there; y_packed and cp_packed
+ * hold the points of problem q contiguously (n_q floats each) in problem order; dist, kstar,
+ * inside and newton are indexed by the global point index (inside, newton nullable).  Results
+ * and errors as hopf_closest_point, per problem. */
+hopf_status hopf_closest_point_ragged(int32_t nprob, const hopf_problem_t* problems, const int64_t* pt_offset,
+                                      const void* y_packed, double s_tol, void* dist, void* cp_packed,
+                                      int32_t* kstar, int32_t* inside, int32_t* newton, void* stream);
+
 /* Envelope-theorem gradients of L = sum_j gphi_j phi_j (phi is the optimal
  * value of eq. (3.3), an objective affine in x, t, A and c_k at fixed p):
  *   gx[j] = gphi_j p*_j,  gt[j] = gphi_j dphidt_j (= -gphi_j H(p*_j)),
@@ -242,6 +253,15 @@ hopf_status hopf_control(hopf_problem_t problem, int64_t npts, const void* x, co
 hopf_status hopf_max_over_hamiltonians(int32_t k, int64_t npts, int32_t n, int32_t f64, const void* const* phis,
                                        const void* const* grads, const void* const* dphidts, void* phi,
                                        void* grad, void* dphidt, int32_t* istar, void* stream);
+
+/* Work done for the problem so far: *total = the number of split-Bregman passes (each one
+ * product with M = (A + lambda I)^{-1}, the v-update of eq. (3.4a)) summed over every column the
+ * dense solvers ran for it: every copy of a union of level sets (section 3.1), every Newton solve
+ * of a distance (section 3.2), every call since creation or the last reset.  Counted on the device
+ * when a column finishes; the diagonal per-thread path does not count (its per-point iteration
+ * count is the total).  Synchronises the device.  reset != 0 then clears the count.
+ * Errors: HOPF_EINVAL for a NULL argument, HOPF_EDEVICE. */
+hopf_status hopf_problem_iterations(hopf_problem_t problem, int64_t* total, int32_t reset);
 
 /* Device-side factor of the problem, for inspection and tests: copies
  * M = (A + lambda I)^{-1} (n*n, row-major, FP64) to the host array out.  For a HOPF_H_AL2

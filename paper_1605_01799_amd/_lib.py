@@ -20,7 +20,7 @@ EXPORTS = [
     "hopf_problem_create", "hopf_problem_create_batch", "hopf_problem_destroy", "hopf_eval",
     "hopf_closest_point", "hopf_eval_ragged", "hopf_backward", "hopf_problem_get_inverse",
     "hopf_problem_info", "hopf_last_error", "hopf_version", "hopf_control", "hopf_max_over_hamiltonians",
-    "hopf_backward_noalloc",
+    "hopf_backward_noalloc", "hopf_problem_iterations", "hopf_closest_point_ragged",
 ]
 
 
@@ -61,12 +61,14 @@ def load():
         "hopf_eval": [P, I64, V, V, V, V, V, V, V, V],
         "hopf_closest_point": [P, I64, V, D, V, V, V, V, V, V],
         "hopf_eval_ragged": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, V, V, V, V, V, V, V],
+        "hopf_closest_point_ragged": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, D, V, V, V, V, V, V],
         "hopf_backward": [P, I64, V, V, V, V, V, V, V, V, V],
         "hopf_backward_noalloc": [P, I64, V, V, V, V, V, V, V, V, V],
         "hopf_control": [P, I64, V, V, V, V, V, V, V],
         "hopf_max_over_hamiltonians": [I32, I64, I32, I32, ctypes.POINTER(V), ctypes.POINTER(V),
                                        ctypes.POINTER(V), V, V, V, V, V],
         "hopf_problem_get_inverse": [P, V],
+        "hopf_problem_iterations": [P, ctypes.POINTER(I64), I32],
         "hopf_problem_info": [P, V, V, V, V],
     }
     for name, args in sig.items():

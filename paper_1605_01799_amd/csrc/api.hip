@@ -72,6 +72,7 @@ struct hopf_problem {
   double* d_HP = nullptr;
   float* d_Af = nullptr;          // dense A (n x n, FP32, original basis) for the control read-out
   double* d_centres0 = nullptr;   // HOPF_H_AL2: the centres in the original basis (K x n_pad)
+  unsigned long long* d_iter_total = nullptr;  // passes of the dense kernels over all columns
 };
 
 // ---------------------------------------------------------------------------
@@ -166,6 +167,7 @@ static void free_problem(hopf_problem* p) {
   hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
   hipFree(p->d_Mq); hipFree(p->d_Mqe);
   hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP); hipFree(p->d_Af); hipFree(p->d_centres0);
+  hipFree(p->d_iter_total);
   delete p;
 }
 
@@ -241,6 +243,8 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     if (hipMemcpy(p->d_wf, hwf.data(), sizeof(float) * n_pad, hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy wf"));
   }
+  if (hipMalloc(&p->d_iter_total, sizeof(unsigned long long))) return bail(fail(HOPF_ENOMEM, "hipMalloc counter"));
+  if (hipMemset(p->d_iter_total, 0, sizeof(unsigned long long))) return bail(fail(HOPF_EDEVICE, "clear counter"));
   if (d->centres) {
     std::vector<double> hc((size_t)d->K * n_pad, 0.0);
     for (int k = 0; k < d->K; ++k)
@@ -434,6 +438,16 @@ extern "C" hopf_status hopf_problem_info(hopf_problem_t p, int32_t* n, int32_t* 
   return HOPF_OK;
 }
 
+extern "C" hopf_status hopf_problem_iterations(hopf_problem_t p, int64_t* total, int32_t reset) {
+  if (!p || !total) return fail(HOPF_EINVAL, "NULL argument");
+  unsigned long long v = 0;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&v, p->d_iter_total, sizeof v, hipMemcpyDeviceToHost));
+  *total = (int64_t)v;
+  if (reset) HIP_TRY(hipMemset(p->d_iter_total, 0, sizeof v));
+  return HOPF_OK;
+}
+
 extern "C" hopf_status hopf_problem_get_inverse(hopf_problem_t p, double* out) {
   if (!p || !out) return fail(HOPF_EINVAL, "NULL argument");
   std::vector<double> h((size_t)p->n_pad * p->n_pad);
@@ -586,6 +600,7 @@ static DenseProb make_view(hopf_problem* p) {
   v.max_iter = p->max_iter; v.lambda = p->lambda; v.tol = p->tol;
   v.Mb = p->d_Mb; v.Mf = p->d_Mf; v.Md = p->d_Md; v.Mq = p->d_Mq; v.Mqe = p->d_Mqe; v.w = p->d_w; v.wf = p->d_wf; v.centres = p->d_centres;
   v.max_newton = 50;
+  v.iter_total = p->d_iter_total;
   return v;
 }
 
@@ -778,6 +793,46 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
     calls.push_back(c);
   }
   return run_dense_rotated(calls, mode_for(prec), 0, (hipStream_t)stream);
+}
+
+extern "C" hopf_status hopf_closest_point_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
+                                                 const void* y_packed, double s_tol, void* dist, void* cp_packed,
+                                                 int32_t* kstar, int32_t* inside, int32_t* newton, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!probs || !pt_offset))) return fail(HOPF_EINVAL, "bad ragged arguments");
+  if (nprob == 0) return HOPF_OK;
+  if (!(s_tol > 0.0) || !std::isfinite(s_tol)) return fail(HOPF_EINVAL, "s_tol must be finite and > 0");
+  if (!y_packed || !dist || !cp_packed || !kstar) return fail(HOPF_EINVAL, "NULL array argument");
+  if (pt_offset[0] != 0) return fail(HOPF_EINVAL, "pt_offset[0] must be 0");
+  const int prec = probs[0] ? probs[0]->precision : -1;
+  std::vector<DenseCall> calls;
+  int64_t yoff = 0;
+  for (int q = 0; q < nprob; ++q) {
+    hopf_problem* p = probs[q];
+    if (!p) return fail(HOPF_EINVAL, "problem %d is NULL", q);
+    if (p->precision != prec) return fail(HOPF_EINVAL, "problem %d: problems of a ragged batch must share one precision", q);
+    if (p->precision == HOPF_F64) return fail(HOPF_EINVAL, "problem %d: closest point needs HOPF_F32 or HOPF_BF16_REFINED", q);
+    if (!p->level_set || p->jkind != HOPF_J_QUADRATIC)
+      return fail(HOPF_EINVAL, "problem %d: closest point needs ellipsoid level sets (level_set = 1, quadratic J)", q);
+    const int64_t np = pt_offset[q + 1] - pt_offset[q];
+    if (np < 0) return fail(HOPF_EINVAL, "pt_offset must be nondecreasing");
+    char why[256];
+    if (hopf_status cs = check_columns(np, p->K, why, sizeof why)) return fail(cs, "problem %d: %s", q, why);
+    DenseCall c;
+    c.p = p;
+    c.view = make_view(p);
+    const int64_t g0 = pt_offset[q];
+    c.view.x = (const float*)y_packed + yoff;
+    c.view.npts = np;
+    c.view.grad = (float*)cp_packed + yoff;
+    c.view.dist = (float*)dist + g0;
+    c.view.kstar = kstar + g0;
+    c.view.inside = inside ? inside + g0 : nullptr;
+    c.view.newton = newton ? newton + g0 : nullptr;
+    c.view.s_tol = s_tol;
+    yoff += np * p->n;
+    calls.push_back(c);
+  }
+  return run_dense_rotated(calls, mode_for(prec), 1, (hipStream_t)stream);
 }
 
 extern "C" hopf_status hopf_backward(hopf_problem_t p, int64_t npts, const void* gphi, const void* grad_saved,

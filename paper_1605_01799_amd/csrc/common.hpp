@@ -98,6 +98,9 @@ struct DenseProb {
   int max_newton;
   // per-point best value over the K copies found so far (workspace, reset before every call)
   double* bestv; int32_t* bestk;
+  // passes (products with M) summed over every column (every copy, every Newton solve) of the
+  // problem's calls, or null
+  unsigned long long* iter_total;
 };
 
 // A run of columns (col = point * K + k) of one problem; always whole points.

@@ -347,6 +347,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         int better = 0;
         if (st == COL_DONE || st == COL_INVALID) {
           const int64_t j = S.j[c];
+          if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)S.iters[c]);
           const float qnan = __builtin_nanf("");
           if (st == COL_INVALID) {
             better = 2;
@@ -374,6 +375,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const int st = S.state[c];
         if (st != COL_DONE && st != COL_INVALID) continue;
         any = 1;
+        if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)S.iters[c]);
         const int64_t j = S.j[c];
         const int kk = S.k[c];
         int better;
@@ -860,6 +862,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               S.gam[c] = g; S.dgam[c] = g - S.gama[c];
               // a new solve: its own iteration budget and stall watch (a capped solve still
               // gives a usable psi and gradient, so Newton goes on and the result is flagged)
+              if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)S.iters[c]);
               S.prev[c] = 1e300; S.best[c] = 1e300; S.stall[c] = 0; S.iters[c] = 0;
               S.flags[c] &= ~FLAG_SOLVE_CAP;
               S.state[c] = COL_ACTIVE;

@@ -393,6 +393,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
         S.better[c] = 0;
         if (st == COL_DONE || st == COL_INVALID) {
           const int64_t j = S.j[c];
+          if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)S.iters[c]);
           if (st == COL_INVALID) {
             const float qnan = __builtin_nanf("");
             pb.phi[j] = qnan; pb.dphidt[j] = qnan;

@@ -189,6 +189,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             }
           }
           if (lg == 0) {
+            if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)iters[ct]);
             pb.phi[j] = bad ? __builtin_nanf("") : (float)phi[ct];
             pb.dphidt[j] = bad ? __builtin_nanf("") : (float)(-hp[ct]);
             if (pb.iters) pb.iters[j] = bad ? -1 : ((flags[ct] & FLAG_CAPPED) ? -2 : iters[ct]);
@@ -208,6 +209,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         const int fl = __shfl(flags[ct], c0), itk = __shfl(iters[ct], c0);
         int better = 0;
         if (l == 0) {
+          if (pb.iter_total) atomicAdd(pb.iter_total, (unsigned long long)itk);
           if (s == COL_INVALID) {
             better = 2;
             pb.bestk[j] = -2;

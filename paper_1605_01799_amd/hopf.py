@@ -201,10 +201,44 @@ class Problem:
         check(self._lib.hopf_problem_get_inverse(self._handle, out.ctypes.data))
         return out
 
+    def iterations(self, reset: bool = False) -> int:
+        """Passes of the dense solvers summed over every column (every copy, every Newton solve)
+        of this problem's calls since creation or the last reset (hopf_problem_iterations)."""
+        v = ctypes.c_int64()
+        check(self._lib.hopf_problem_iterations(self._handle, ctypes.byref(v), 1 if reset else 0))
+        return v.value
+
     def info(self):
         v = [ctypes.c_int32() for _ in range(4)]
         check(self._lib.hopf_problem_info(self._handle, *[ctypes.byref(x) for x in v]))
         return dict(n=v[0].value, n_pad=v[1].value, K=v[2].value, precision=v[3].value)
+
+
+def closest_point_ragged(problems: Sequence[Problem], ys: Sequence[torch.Tensor], s_tol: float = 1e-6, stream=None):
+    """Closest points and distances for a ragged batch of ellipsoid level-set problems in one call
+    (hopf_closest_point_ragged)."""
+    lib = _lib.load()
+    nprob = len(problems)
+    counts = [int(y.shape[0]) for y in ys]
+    off = np.zeros(nprob + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    y_packed = torch.cat([y.reshape(-1) for y in ys]).contiguous()
+    dev = y_packed.device
+    tot = int(off[-1])
+    dist = torch.empty(tot, dtype=torch.float32, device=dev)
+    cp = torch.empty_like(y_packed)
+    kstar = torch.empty(tot, dtype=torch.int32, device=dev)
+    inside = torch.empty(tot, dtype=torch.int32, device=dev)
+    newton = torch.empty(tot, dtype=torch.int32, device=dev)
+    handles = (ctypes.c_void_p * nprob)(*[p._handle.value for p in problems])
+    offs = (ctypes.c_int64 * (nprob + 1))(*off.tolist())
+    check(lib.hopf_closest_point_ragged(nprob, handles, offs, _ptr(y_packed), float(s_tol), _ptr(dist), _ptr(cp),
+                                        _ptr(kstar), _ptr(inside), _ptr(newton), _stream_ptr(stream)))
+    cps, o = [], 0
+    for p, c in zip(problems, counts):
+        cps.append(cp[o:o + c * p.n].view(c, p.n))
+        o += c * p.n
+    return dict(dist=dist, cp=cps, kstar=kstar, inside=inside, newton=newton, offsets=off)
 
 
 def eval_ragged(problems: Sequence[Problem], xs: Sequence[torch.Tensor], ts: Sequence[torch.Tensor],

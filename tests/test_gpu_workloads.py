@@ -18,7 +18,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
-from tests.helpers import rel_err_phi, rel_err_vec
+from tests.helpers import rand_problem, rel_err_phi, rel_err_vec
 
 pytestmark = pytest.mark.gpu
 
@@ -311,3 +311,57 @@ def test_workload5_backward_vs_oracle_and_fd(oracle_lib):
         e = abs(fd - an) / max(1.0, abs(fd))
         print("  FD %-8s fd %+.6e gpu %+.6e rel %.2e" % (name, fd, an, e), flush=True)
         assert e <= 1e-4
+
+
+@pytest.mark.parametrize("precision", ["bf16_refined", "f32"])
+def test_workload4_closest_point_ragged(oracle_lib, precision):
+    """The ragged closest-point call (one call for the whole batch) against the oracle's
+    secular-equation route, on the problems of the ragged evaluation (H is ignored: distances
+    use the l2 norm)."""
+    probs = w4_problems()
+    bound = REFINED_TOL if precision == "bf16_refined" else FP32_TOL
+    print("case workload4 ragged closest point: %d problems, %s" % (len(probs), precision), flush=True)
+    hp = H.Problem.batch([dict(A=p.A, centres=p.centres, level_set=True, hkind="wl1", w=p.w, precision=precision,
+                               tol=w4_tol(precision, p.n), max_iter=20000) for p in probs])
+    out = H.closest_point_ragged(hp, [torch.from_numpy(p.x).to(DEV) for p in probs], s_tol=1e-7)
+    torch.cuda.synchronize()
+    off = out["offsets"]
+    dist, inside = out["dist"].cpu().numpy(), out["inside"].cpu().numpy()
+
+    def check(q):
+        p = probs[q]
+        idx = sample(p.npts, 4, 600 + q)
+        ref = oracle_lib.oracle_distance_secular(p.A, p.x[idx].astype(np.float64), centres=p.centres)
+        sl = slice(off[q], off[q + 1])
+        ins = bool(np.array_equal(inside[sl][idx], ref["inside"]))
+        ed = rel_err_phi(dist[sl][idx], ref["dist"]).max()
+        outp = ref["inside"] == 0
+        cp = out["cp"][q].cpu().numpy()[idx]
+        ec = rel_err_vec(cp[outp], ref["cp"][outp]).max() if outp.any() else 0.0
+        return p.n, p.npts, ed, ec, ins
+
+    with ThreadPoolExecutor(THREADS) as ex:
+        res = list(ex.map(check, range(len(probs))))
+    for r in res:
+        print("  n=%4d P=%4d  err dist %.2e cp %.2e inside ok %s" % r, flush=True)
+    assert all(r[4] for r in res)
+    assert max(r[2] for r in res) <= bound and max(r[3] for r in res) <= 10 * bound
+    assert all(p.iterations() > 0 for p in hp)
+
+
+@pytest.mark.parametrize("precision,n", [("bf16_refined", 300), ("bf16_refined", 1024), ("f32", 40), ("f32", 200)])
+def test_iteration_counter_matches_iters(precision, n):
+    """hopf_problem_iterations: with one copy per point and no capped point, the passes summed
+    on the device equal the per-point iteration counts summed on the host."""
+    rng = np.random.default_rng(7000 + n)
+    A = rand_problem(n, rng)
+    w = rng.uniform(0.5, 2, n)
+    x = torch.from_numpy(rng.normal(0, 2, (777, n)).astype(np.float32)).to(DEV)
+    t = torch.from_numpy(rng.uniform(0.05, 3, 777).astype(np.float32)).to(DEV)
+    prob = H.Problem(A, hkind="l2_wl1", w=w, precision=precision, tol=1e-16 * n, max_iter=20000)
+    prob.iterations(reset=True)
+    out = prob.eval(x, t)
+    it = out["iters"].cpu().numpy()
+    assert np.all(it > 0)
+    assert prob.iterations(reset=True) == int(it.astype(np.int64).sum())
+    assert prob.iterations() == 0
