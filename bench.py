@@ -32,8 +32,8 @@ METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % rooflin
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel source it was measured
 # on (hash of TRAFFIC_SOURCES); reported as null otherwise.
 TRAFFIC_SOURCES = ("dense_rs.hip", "dense_shared.hpp", "common.hpp")
-TRAFFIC = {"source_sha256": "bd47e58b121fcf47c7b878017d4639ad30c4c1807da805068054299b4a9680d3",
-           "read_bytes": 352.483e9, "write_bytes": 49.273e9, "precision": "bf16_refined", "npts": 1 << 16,
+TRAFFIC = {"source_sha256": "f8e03790cccbc00ec901856b219523f41f5601184fd3d5323e784d8528e1a230",
+           "read_bytes": 115.699e9, "write_bytes": 10.946e9, "precision": "bf16_refined", "npts": 1 << 16,
            "tol": 1e-12}
 
 
@@ -44,7 +44,8 @@ def measured_traffic(precision, npts, tol):
         with open(os.path.join(ROOT, "paper_1605_01799_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if (h.hexdigest() != TRAFFIC["source_sha256"] or precision != TRAFFIC["precision"]
-            or npts != TRAFFIC["npts"] or tol != TRAFFIC["tol"]):
+            or npts != TRAFFIC["npts"] or tol != TRAFFIC["tol"] or os.environ.get("HOPF_RS", "1") == "0"
+            or os.environ.get("HOPF_RS_ANCHOR_EVERY", "24") != "24"):
         return None
     return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
 
@@ -57,6 +58,9 @@ def parse():
     ap.add_argument("--precision", default="bf16_refined", choices=["bf16_refined", "f32"])
     ap.add_argument("--npts", type=int, default=1 << 16)
     ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the BF16-only error measurement (thousands of small torch launches: "
+                         "left out of profiled runs)")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="most points of the CPU baseline's stratified sample (it is sized to ~15 s)")
     ap.add_argument("--acc-sample", type=int, default=48)
@@ -189,7 +193,7 @@ def main():
         rec["accuracy"] = {"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()),
                            "max_rel_err_phi": float(ef.max()), "bound": 1e-6,
                            "ok": bool(ep.max() <= 1e-6 and ef.max() <= 1e-6)}
-        if a.precision == "bf16_refined":
+        if a.precision == "bf16_refined" and not a.no_bf16:
             rec["bf16_only"] = bf16_only_error(p, idx, ref["grad"], dev)
         if not a.no_cpu:
             rec["cpu_baseline"] = cpu_baseline(
