@@ -181,9 +181,9 @@ hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void*
  * HOPF_F64; the ellipsoidal norms only with HOPF_F32 and n <= 64; no
  * HOPF_H_LINF or squared-norm J).  The problems are grouped into kernel
  * classes by padded size (the launch shape of each class); each class is one
- * persistent launch over its problems' points, and the host waits for one
- * class's launch before it enqueues the next (they share the per-device
- * workspace).  Every problem's npts * K must stay below 2^31.  pt_offset (host, nprob+1)
+ * persistent launch over its problems' points; the classes are enqueued
+ * back to back on stream, each with its own metadata, staging and chunk counter in the
+ * per-device workspace (no host wait between them; calls on one stream are ordered).  Every problem's npts * K must stay below 2^31.  pt_offset (host, nprob+1)
  * gives the points of problem q as [pt_offset[q], pt_offset[q+1]); x_packed
  * holds the points of problem q contiguously starting at element
  * sum_{r<q} (pt_offset[r+1]-pt_offset[r]) * n_r, and grad_packed likewise.
@@ -192,6 +192,24 @@ hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* problems,
                              const int64_t* pt_offset, const void* x_packed, const void* t,
                              void* phi, void* grad_packed, void* dphidt, int32_t* iters,
                              int32_t* kstar, void* stream);
+
+/* A ragged evaluation bound once to its arguments (a plan), for callers that relaunch the same
+ * batch: hopf_ragged_plan_create checks and groups the problems exactly as hopf_eval_ragged (same
+ * arguments and layouts; the device arrays are referenced, not copied, and must stay valid and
+ * unmoved while the plan lives), allocates the plan's own metadata, staging and counters and
+ * uploads the metadata (synchronously).  hopf_ragged_plan_launch then enqueues only kernels on
+ * stream (the counters' and per-point bests' resets are kernels too): no allocation, no copy, no
+ * host synchronisation, so it can be captured in a HIP graph and replayed; each launch evaluates
+ * the points in place (results as hopf_eval_ragged, read from the arrays at launch time).  Launches
+ * of one plan must not overlap (they share its staging), and it must be launched on the device it
+ * was made on (HOPF_EINVAL otherwise).  hopf_ragged_plan_destroy synchronises the device and frees
+ * the plan.  Errors: as hopf_eval_ragged; HOPF_ENOMEM; HOPF_EDEVICE. */
+typedef struct hopf_ragged_plan* hopf_ragged_plan_t;
+hopf_status hopf_ragged_plan_create(int32_t nprob, const hopf_problem_t* problems, const int64_t* pt_offset,
+                                    const void* x_packed, const void* t, void* phi, void* grad_packed, void* dphidt,
+                                    int32_t* iters, int32_t* kstar, hopf_ragged_plan_t* out);
+hopf_status hopf_ragged_plan_launch(hopf_ragged_plan_t plan, void* stream);
+hopf_status hopf_ragged_plan_destroy(hopf_ragged_plan_t plan);
 
 /* Ragged batch of closest points and distances (section 3.2, the Newton iteration on s of
  * eq. Newton_zero, with the inner evaluations of section 3.1): hopf_closest_point over nprob

@@ -21,6 +21,7 @@ EXPORTS = [
     "hopf_closest_point", "hopf_eval_ragged", "hopf_backward", "hopf_problem_get_inverse",
     "hopf_problem_info", "hopf_last_error", "hopf_version", "hopf_control", "hopf_max_over_hamiltonians",
     "hopf_backward_noalloc", "hopf_problem_iterations", "hopf_closest_point_ragged",
+    "hopf_ragged_plan_create", "hopf_ragged_plan_launch", "hopf_ragged_plan_destroy",
 ]
 
 
@@ -62,6 +63,10 @@ def load():
         "hopf_closest_point": [P, I64, V, D, V, V, V, V, V, V],
         "hopf_eval_ragged": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, V, V, V, V, V, V, V],
         "hopf_closest_point_ragged": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, D, V, V, V, V, V, V],
+        "hopf_ragged_plan_create": [I32, ctypes.POINTER(P), ctypes.POINTER(I64), V, V, V, V, V, V, V,
+                                    ctypes.POINTER(P)],
+        "hopf_ragged_plan_launch": [P, V],
+        "hopf_ragged_plan_destroy": [P],
         "hopf_backward": [P, I64, V, V, V, V, V, V, V, V, V],
         "hopf_backward_noalloc": [P, I64, V, V, V, V, V, V, V, V, V],
         "hopf_control": [P, I64, V, V, V, V, V, V, V],

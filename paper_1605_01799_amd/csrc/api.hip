@@ -466,40 +466,40 @@ struct DenseCall {
   DenseProb view;
 };
 
-static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distance, hipStream_t stream) {
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  Workspace* w;
-  hopf_status st = ws_get(dev, &w);
-  if (st) return st;
-  std::lock_guard<std::mutex> lk(w->mu);
-  const int anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
+// A dense call split into kernel classes (one persistent launch each, by launch shape): every
+// class has its own metadata (problem views, then chunks of whole points), staging and chunk
+// counter, so the classes are enqueued back to back without the host waiting between them.
+struct DenseClass {
+  int key = 0;              // kSmallClass, kRsClass or 100 pt + 10 occ + nw
+  DenseVariant var{};
+  bool small = false, rs = false;
+  int nchunks = 0, grid = 0, max_npad = 32;
+  size_t lds = 0;
+  int64_t ws_per_wg = 0, ws64_per_wg = 0;
+  size_t views_off = 0, chunks_off = 0;    // bytes into the metadata blob
+  size_t state_off = 0, state64_off = 0;   // floats / doubles into the staging
+  std::vector<int> members;                // call indices, in view order
+  std::vector<DenseChunk> chunks;
+};
+struct DensePlan {
+  int mode = 0, distance = 0;
+  int anchor_every = 32, anchor_wait = 0, rs_anchor_every = 24, small_anchor_every = 32, small_anchor_wait = 0;
+  std::vector<DenseClass> cls;
+  size_t blob_bytes = 0, state_floats = 0, state64_doubles = 0;
+  int64_t total_pts = 0;
+};
+constexpr int kSmallClass = 1 << 20, kRsClass = 1 << 21;
+
+static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distance, int ncu, DensePlan* P) {
+  P->mode = mode; P->distance = distance;
+  P->anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
+  // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
+  P->anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
   // the on-chip kernel's anchors cost about ten of its passes: every 24 passes gave the fewest
   // cycles on n = 1024 (16: more anchors than iterations saved, 32 and above: more iterations)
-  const int rs_anchor_every = std::max(1, env_int("HOPF_RS_ANCHOR_EVERY", 24));
-  // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
-  const int anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
-  // the wave-local kernel of FP32 problems: refined increments on exact FP64 anchors (mode 2),
-  // or the plain FP32 iteration (mode 0)
-  const bool small_refined = mode == 2;
-  const int small_anchor_every = std::max(1, env_int("HOPF_SMALL_ANCHOR_EVERY", 32));
-  const int small_anchor_wait = std::max(0, env_int("HOPF_SMALL_ANCHOR_WAIT", 0));
-  if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
-  // per-point best arrays for every point of the call
-  int64_t tot = 0;
-  for (auto& c : calls) tot += c.view.npts;
-  if ((st = ws_grow((void**)&w->best, &w->best_bytes, (sizeof(double) + sizeof(int32_t)) * (size_t)std::max<int64_t>(tot, 1))))
-    return st;
-  double* bestv = (double*)w->best;
-  int32_t* bestk = (int32_t*)(w->best + sizeof(double) * (size_t)std::max<int64_t>(tot, 1));
-  {
-    int64_t o = 0;
-    for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
-  }
-  // one launch per kernel class: the launch shape of the padded size (kSmallClass: the
-  // one-wave-per-tile kernel of small FP32 problems)
-  // (kRsClass: the on-chip-state kernel of refined problems with one point per column)
-  constexpr int kSmallClass = 1 << 20, kRsClass = 1 << 21;
+  P->rs_anchor_every = std::max(1, env_int("HOPF_RS_ANCHOR_EVERY", 24));
+  P->small_anchor_every = std::max(1, env_int("HOPF_SMALL_ANCHOR_EVERY", 32));
+  P->small_anchor_wait = std::max(0, env_int("HOPF_SMALL_ANCHOR_WAIT", 0));
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
   static const bool use_rs = env_int("HOPF_RS", 1) != 0;
   auto class_of = [&](const hopf_problem* p) -> int {
@@ -510,86 +510,138 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
     const DenseVariant v = dense_variant(mode, p->n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;
   };
-  std::vector<int> classes;
+  P->total_pts = 0;
+  for (auto& c : calls) P->total_pts += c.view.npts;
+  std::vector<int> keys;
   for (auto& c : calls) {
     const int key = class_of(c.p);
-    if (c.view.npts > 0 && std::find(classes.begin(), classes.end(), key) == classes.end()) classes.push_back(key);
+    if (c.view.npts > 0 && std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
   }
-  std::sort(classes.begin(), classes.end());
-  int cls = 0;
-  for (int key : classes) {
-    const bool small = key == kSmallClass, rs = key == kRsClass;
-    const DenseVariant var = small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4}
-                             : rs  ? DenseVariant{dense_rs_cols(), 1, 4}
-                                   : DenseVariant{key / 100, (key / 10) % 10, key % 10};
-    const int pt = var.pt, occ = var.occ;
-    std::vector<DenseProb> views;
+  std::sort(keys.begin(), keys.end());
+  size_t off = 0, st = 0, st64 = 0;
+  for (int key : keys) {
+    DenseClass C;
+    C.key = key;
+    C.small = key == kSmallClass;
+    C.rs = key == kRsClass;
+    C.var = C.small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4}
+          : C.rs    ? DenseVariant{dense_rs_cols(), 1, 4}
+                    : DenseVariant{key / 100, (key / 10) % 10, key % 10};
     std::vector<std::pair<double, int>> order;  // (cost, view index)
-    int max_npad = 32;
-    for (auto& c : calls) {
+    for (int i = 0; i < (int)calls.size(); ++i) {
+      const DenseCall& c = calls[i];
       if (class_of(c.p) != key || c.view.npts == 0) continue;
-      order.push_back({(double)c.p->n_pad * c.p->n_pad * c.p->K * (double)c.view.npts, (int)views.size()});
-      views.push_back(c.view);
-      max_npad = std::max(max_npad, c.p->n_pad);
+      order.push_back({(double)c.p->n_pad * c.p->n_pad * c.p->K * (double)c.view.npts, (int)C.members.size()});
+      C.members.push_back(i);
+      C.max_npad = std::max(C.max_npad, c.p->n_pad);
     }
     // largest problems first; chunks of whole points, about one tile of columns each
-    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
-      return a.first > b.first;
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+      return x.first > y.first;
     });
-    std::vector<DenseChunk> ch;
     for (auto& o : order) {
-      const DenseProb& v = views[o.second];
-      const int ppc = std::max(1, pt / v.K);
+      const DenseProb& v = calls[C.members[o.second]].view;
+      const int ppc = std::max(1, C.var.pt / v.K);
       for (int64_t p0 = 0; p0 < v.npts; p0 += ppc) {
-        DenseChunk c;
-        c.prob = o.second;
-        c.col0 = (int)(p0 * v.K);
-        c.ncols = (int)(std::min<int64_t>(ppc, v.npts - p0) * v.K);
-        c.pad = 0;
-        ch.push_back(c);
+        DenseChunk ch;
+        ch.prob = o.second;
+        ch.col0 = (int)(p0 * v.K);
+        ch.ncols = (int)(std::min<int64_t>(ppc, v.npts - p0) * v.K);
+        ch.pad = 0;
+        C.chunks.push_back(ch);
       }
     }
-    const int nchunks = (int)ch.size();
-    const size_t vbytes = sizeof(DenseProb) * views.size();
-    const size_t off_c = (vbytes + 255) / 256 * 256;
-    std::vector<unsigned char> blob(off_c + sizeof(DenseChunk) * nchunks);
-    std::memcpy(blob.data(), views.data(), vbytes);
-    std::memcpy(blob.data() + off_c, ch.data(), sizeof(DenseChunk) * nchunks);
-    void* dmeta = nullptr;
-    if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
+    C.nchunks = (int)C.chunks.size();
     // the small kernel: four independent waves per workgroup, each taking chunks
-    const int grid = small ? std::min((nchunks + 3) / 4, occ * w->ncu) : std::min(nchunks, occ * w->ncu);
-    const int64_t ws_per_wg = small ? 0 : rs ? dense_rs_ws_floats(max_npad) : 4 * (int64_t)pt * max_npad;
+    C.grid = C.small ? std::min((C.nchunks + 3) / 4, C.var.occ * ncu) : std::min(C.nchunks, C.var.occ * ncu);
+    C.ws_per_wg = C.small ? 0 : C.rs ? dense_rs_ws_floats(C.max_npad) : 4 * (int64_t)C.var.pt * C.max_npad;
     // FP64 anchor staging, then its integer slices (kSlices x pt x pad64 bytes)
-    const int64_t ws64_per_wg = (int64_t)pt * max_npad + (int64_t)kSlices * pt * pad64(max_npad) / 8;
-    if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * ws_per_wg * grid))) return st;
-    if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * ws64_per_wg * grid))) return st;
-    size_t lds = 0;
-    if (rs)
-      lds = dense_rs_lds_bytes(max_npad);
-    else if (!small)
-      for (auto& v : views) lds = std::max(lds, dense_lds_bytes(mode, v.n_pad));
-    int* counter = w->counter + cls;
-    // reset the counter, and the best arrays of this class's problems
-    for (auto& v : views) {
+    C.ws64_per_wg = (int64_t)C.var.pt * C.max_npad + (int64_t)kSlices * C.var.pt * pad64(C.max_npad) / 8;
+    if (C.rs)
+      C.lds = dense_rs_lds_bytes(C.max_npad);
+    else if (!C.small)
+      for (int i : C.members) C.lds = std::max(C.lds, dense_lds_bytes(mode, calls[i].p->n_pad));
+    C.views_off = off;
+    off += (sizeof(DenseProb) * C.members.size() + 255) / 256 * 256;
+    C.chunks_off = off;
+    off += (sizeof(DenseChunk) * C.chunks.size() + 255) / 256 * 256;
+    C.state_off = st;
+    st += (size_t)C.ws_per_wg * C.grid;
+    C.state64_off = st64;
+    st64 += (size_t)C.ws64_per_wg * C.grid;
+    P->cls.push_back(std::move(C));
+  }
+  P->blob_bytes = std::max<size_t>(off, 256);
+  P->state_floats = std::max<size_t>(st, 1);
+  P->state64_doubles = std::max<size_t>(st64, 1);
+}
+
+// Fills the metadata blob: the views (with their per-point best arrays, bestv/bestk of
+// total_pts entries in call order) and the chunks of every class.
+static void plan_blob(const DensePlan& P, std::vector<DenseCall>& calls, double* bestv, int32_t* bestk,
+                      std::vector<unsigned char>* blob) {
+  int64_t o = 0;
+  for (auto& c : calls) { c.view.bestv = bestv + o; c.view.bestk = bestk + o; o += c.view.npts; }
+  blob->assign(P.blob_bytes, 0);
+  for (const DenseClass& C : P.cls) {
+    for (size_t m = 0; m < C.members.size(); ++m)
+      std::memcpy(blob->data() + C.views_off + m * sizeof(DenseProb), &calls[C.members[m]].view, sizeof(DenseProb));
+    if (!C.chunks.empty())
+      std::memcpy(blob->data() + C.chunks_off, C.chunks.data(), sizeof(DenseChunk) * C.chunks.size());
+  }
+}
+
+// Enqueues every class: the resets of its chunk counter and best arrays (kernels), then its
+// persistent launch.  No host synchronisation, no allocation.
+static hopf_status plan_launch(const DensePlan& P, const std::vector<DenseCall>& calls, const unsigned char* meta,
+                               float* state, double* state64, int* counters, hipStream_t stream) {
+  for (size_t ci = 0; ci < P.cls.size(); ++ci) {
+    const DenseClass& C = P.cls[ci];
+    int* counter = counters + ci;
+    for (int i : C.members) {
+      const DenseProb& v = calls[i].view;
       hipError_t e = launch_reset(counter, v.bestv, v.bestk, v.npts, stream);
       if (e) return fail(HOPF_EDEVICE, "reset launch: %s", hipGetErrorString(e));
     }
-    const DenseChunk* dchunks = (const DenseChunk*)((unsigned char*)dmeta + off_c);
-    hipError_t e = small ? launch_dense_small(max_npad, small_refined, (const DenseProb*)dmeta, dchunks, nchunks,
-                                              counter, grid, small_anchor_every, small_anchor_wait, stream)
-                   : rs  ? launch_dense_rs(max_npad, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state64,
-                                           ws64_per_wg, w->state, ws_per_wg, grid, lds, rs_anchor_every,
-                                           anchor_wait, stream)
-                         : launch_dense(mode, var, (const DenseProb*)dmeta, dchunks, nchunks, counter, w->state,
-                                        w->state64, ws_per_wg, ws64_per_wg, grid, lds, distance, anchor_every,
-                                        anchor_wait, stream);
+    const DenseProb* dv = (const DenseProb*)(meta + C.views_off);
+    const DenseChunk* dc = (const DenseChunk*)(meta + C.chunks_off);
+    float* ws = state + C.state_off;
+    double* ws64 = state64 + C.state64_off;
+    hipError_t e =
+        C.small ? launch_dense_small(C.max_npad, P.mode == 2, dv, dc, C.nchunks, counter, C.grid,
+                                     P.small_anchor_every, P.small_anchor_wait, stream)
+        : C.rs  ? launch_dense_rs(C.max_npad, dv, dc, C.nchunks, counter, ws64, C.ws64_per_wg, ws, C.ws_per_wg, C.grid,
+                                  C.lds, P.rs_anchor_every, P.anchor_wait, stream)
+                : launch_dense(P.mode, C.var, dv, dc, C.nchunks, counter, ws, ws64, C.ws_per_wg, C.ws64_per_wg, C.grid,
+                               C.lds, P.distance, P.anchor_every, P.anchor_wait, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
-    ++cls;
-    // the next class reuses the metadata/staging buffers and the workspace: wait for this one
-    if (cls < (int)classes.size()) HIP_TRY(hipStreamSynchronize(stream));
   }
   return HOPF_OK;
+}
+
+constexpr int kMaxClasses = 64;  // chunk counters per workspace / plan
+
+static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distance, hipStream_t stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  Workspace* w;
+  hopf_status st = ws_get(dev, &w);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(w->mu);
+  DensePlan P;
+  plan_dense(calls, mode, distance, w->ncu, &P);
+  if (P.cls.empty()) return HOPF_OK;
+  if ((int)P.cls.size() > kMaxClasses) return fail(HOPF_EINVAL, "too many kernel classes in one call");
+  if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * kMaxClasses));
+  const size_t nb = (size_t)std::max<int64_t>(P.total_pts, 1);
+  if ((st = ws_grow((void**)&w->best, &w->best_bytes, (sizeof(double) + sizeof(int32_t)) * nb))) return st;
+  if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * P.state_floats))) return st;
+  if ((st = ws_grow((void**)&w->state64, &w->state64_bytes, sizeof(double) * P.state64_doubles))) return st;
+  std::vector<unsigned char> blob;
+  plan_blob(P, calls, (double*)w->best, (int32_t*)(w->best + sizeof(double) * nb), &blob);
+  void* dmeta = nullptr;
+  if ((st = ws_upload(w, blob.data(), blob.size(), stream, &dmeta))) return st;
+  return plan_launch(P, calls, (const unsigned char*)dmeta, w->state, w->state64, w->counter, stream);
 }
 
 static DenseProb make_view(hopf_problem* p) {
@@ -758,15 +810,15 @@ extern "C" hopf_status hopf_closest_point(hopf_problem_t p, int64_t npts, const 
   return run_dense_rotated(calls, mode_of(p), 1, (hipStream_t)stream);
 }
 
-extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
-                                        const void* x_packed, const void* t, void* phi, void* grad_packed,
-                                        void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
+// The calls of a ragged evaluation (the argument checks of hopf_eval_ragged).
+static hopf_status ragged_calls(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
+                                const void* x_packed, const void* t, void* phi, void* grad_packed, void* dphidt,
+                                int32_t* iters, int32_t* kstar, std::vector<DenseCall>* calls, int* prec_out) {
   if (nprob < 0 || (nprob > 0 && (!probs || !pt_offset))) return fail(HOPF_EINVAL, "bad ragged arguments");
   if (nprob == 0) return HOPF_OK;
   if (!x_packed || !t || !phi || !grad_packed || !dphidt) return fail(HOPF_EINVAL, "NULL array argument");
   const int prec = probs[0] ? probs[0]->precision : -1;
   if (pt_offset[0] != 0) return fail(HOPF_EINVAL, "pt_offset[0] must be 0");
-  std::vector<DenseCall> calls;
   int64_t xoff = 0;
   for (int q = 0; q < nprob; ++q) {
     hopf_problem* p = probs[q];
@@ -790,9 +842,117 @@ extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* pro
     c.view.iters = iters ? iters + g0 : nullptr;
     c.view.kstar = kstar ? kstar + g0 : nullptr;
     xoff += np * p->n;
-    calls.push_back(c);
+    calls->push_back(c);
   }
+  *prec_out = prec;
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_eval_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
+                                        const void* x_packed, const void* t, void* phi, void* grad_packed,
+                                        void* dphidt, int32_t* iters, int32_t* kstar, void* stream) {
+  std::vector<DenseCall> calls;
+  int prec = 0;
+  if (hopf_status st = ragged_calls(nprob, probs, pt_offset, x_packed, t, phi, grad_packed, dphidt, iters, kstar,
+                                    &calls, &prec))
+    return st;
+  if (calls.empty()) return HOPF_OK;
   return run_dense_rotated(calls, mode_for(prec), 0, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// A ragged evaluation bound once to its arguments, relaunched by kernels alone
+// ---------------------------------------------------------------------------
+struct RotIn {
+  const float* src; float* dst; const double* P; int n; int64_t npts;
+};
+struct hopf_ragged_plan {
+  int device = 0;
+  DensePlan P;
+  std::vector<DenseCall> calls;
+  std::vector<RotIn> rot_in;
+  std::vector<RotBack> rot_back;
+  unsigned char* meta = nullptr;
+  float* state = nullptr;
+  double* state64 = nullptr;
+  unsigned char* best = nullptr;
+  int* counters = nullptr;
+  float* rot = nullptr;
+};
+
+static void free_plan(hopf_ragged_plan* pl) {
+  hipFree(pl->meta); hipFree(pl->state); hipFree(pl->state64); hipFree(pl->best); hipFree(pl->counters);
+  hipFree(pl->rot);
+  delete pl;
+}
+
+extern "C" hopf_status hopf_ragged_plan_create(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,
+                                               const void* x_packed, const void* t, void* phi, void* grad_packed,
+                                               void* dphidt, int32_t* iters, int32_t* kstar,
+                                               hopf_ragged_plan_t* out) {
+  if (!out) return fail(HOPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  hopf_ragged_plan* pl = new hopf_ragged_plan();
+  auto bail = [&](hopf_status st) { free_plan(pl); return st; };
+  int prec = 0;
+  if (hopf_status st = ragged_calls(nprob, probs, pt_offset, x_packed, t, phi, grad_packed, dphidt, iters, kstar,
+                                    &pl->calls, &prec))
+    return bail(st);
+  if (hipGetDevice(&pl->device)) return bail(fail(HOPF_EDEVICE, "hipGetDevice"));
+  Workspace* w;
+  if (hopf_status st = ws_get(pl->device, &w)) return bail(st);
+  // points of HOPF_H_AL2 problems are solved in HA's eigenbasis: buffers of the plan's own
+  size_t need = 0;
+  for (auto& c : pl->calls)
+    if (c.p->hkind == HOPF_H_AL2) need += 2 * (size_t)c.view.npts * c.p->n;
+  if (need && hipMalloc(&pl->rot, sizeof(float) * need)) return bail(fail(HOPF_ENOMEM, "hipMalloc rotations"));
+  float* q = pl->rot;
+  for (auto& c : pl->calls) {
+    if (c.p->hkind != HOPF_H_AL2 || c.view.npts == 0) continue;
+    const int n = c.p->n;
+    float* xr = q; q += (size_t)c.view.npts * n;
+    float* qr = q; q += (size_t)c.view.npts * n;
+    pl->rot_in.push_back(RotIn{c.view.x, xr, c.p->d_HP, n, c.view.npts});
+    pl->rot_back.push_back(RotBack{qr, c.view.grad, c.p->d_HP, n, c.view.npts});
+    c.view.x = xr;
+    c.view.grad = qr;
+  }
+  plan_dense(pl->calls, mode_for(prec), 0, w->ncu, &pl->P);
+  if ((int)pl->P.cls.size() > kMaxClasses) return bail(fail(HOPF_EINVAL, "too many kernel classes in one call"));
+  const size_t nb = (size_t)std::max<int64_t>(pl->P.total_pts, 1);
+  if (hipMalloc(&pl->meta, pl->P.blob_bytes) || hipMalloc(&pl->state, sizeof(float) * pl->P.state_floats) ||
+      hipMalloc(&pl->state64, sizeof(double) * pl->P.state64_doubles) ||
+      hipMalloc(&pl->best, (sizeof(double) + sizeof(int32_t)) * nb) ||
+      hipMalloc(&pl->counters, sizeof(int) * kMaxClasses))
+    return bail(fail(HOPF_ENOMEM, "hipMalloc plan buffers"));
+  std::vector<unsigned char> blob;
+  plan_blob(pl->P, pl->calls, (double*)pl->best, (int32_t*)(pl->best + sizeof(double) * nb), &blob);
+  if (hipMemcpy(pl->meta, blob.data(), blob.size(), hipMemcpyHostToDevice))
+    return bail(fail(HOPF_EDEVICE, "upload plan metadata"));
+  *out = pl;
+  return HOPF_OK;
+}
+
+extern "C" hopf_status hopf_ragged_plan_launch(hopf_ragged_plan_t pl, void* stream) {
+  if (!pl) return fail(HOPF_EINVAL, "plan is NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != pl->device) return fail(HOPF_EINVAL, "the plan was made on device %d, the current device is %d",
+                                     pl->device, dev);
+  hipStream_t s = (hipStream_t)stream;
+  for (const RotIn& r : pl->rot_in) {
+    hipError_t e = launch_rotate_points_in(r.src, r.dst, r.P, r.n, r.npts, s);
+    if (e) return fail(HOPF_EDEVICE, "rotate points: %s", hipGetErrorString(e));
+  }
+  if (hopf_status st = plan_launch(pl->P, pl->calls, pl->meta, pl->state, pl->state64, pl->counters, s)) return st;
+  return rotate_calls_out(pl->rot_back, s);
+}
+
+extern "C" hopf_status hopf_ragged_plan_destroy(hopf_ragged_plan_t pl) {
+  if (!pl) return HOPF_OK;
+  hipDeviceSynchronize();
+  free_plan(pl);
+  return HOPF_OK;
 }
 
 extern "C" hopf_status hopf_closest_point_ragged(int32_t nprob, const hopf_problem_t* probs, const int64_t* pt_offset,

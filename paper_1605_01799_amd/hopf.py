@@ -241,6 +241,52 @@ def closest_point_ragged(problems: Sequence[Problem], ys: Sequence[torch.Tensor]
     return dict(dist=dist, cp=cps, kstar=kstar, inside=inside, newton=newton, offsets=off)
 
 
+class RaggedPlan:
+    """A ragged evaluation bound to its problems, inputs and (owned) outputs once
+    (hopf_ragged_plan_create); launch() enqueues kernels only (hopf_ragged_plan_launch), so it can
+    be captured in a HIP graph.  The inputs are packed into buffers the plan owns; refill them in
+    place (x_packed, t) to evaluate other points of the same shape."""
+
+    def __init__(self, problems: Sequence[Problem], xs: Sequence[torch.Tensor], ts: Sequence[torch.Tensor]):
+        self._lib = _lib.load()
+        self.problems = list(problems)
+        nprob = len(self.problems)
+        counts = [int(x.shape[0]) for x in xs]
+        off = np.zeros(nprob + 1, np.int64)
+        off[1:] = np.cumsum(counts)
+        self.offsets = off
+        self.x_packed = torch.cat([x.reshape(-1) for x in xs]).contiguous()
+        self.t = torch.cat(list(ts)).contiguous()
+        dev = self.x_packed.device
+        tot = int(off[-1])
+        self.phi = torch.empty(tot, dtype=torch.float32, device=dev)
+        self.grad_packed = torch.empty_like(self.x_packed)
+        self.dphidt = torch.empty(tot, dtype=torch.float32, device=dev)
+        self.iters = torch.empty(tot, dtype=torch.int32, device=dev)
+        self.kstar = torch.empty(tot, dtype=torch.int32, device=dev)
+        handles = (ctypes.c_void_p * nprob)(*[p._handle.value for p in self.problems])
+        offs = (ctypes.c_int64 * (nprob + 1))(*off.tolist())
+        self._handle = ctypes.c_void_p()
+        check(self._lib.hopf_ragged_plan_create(nprob, handles, offs, _ptr(self.x_packed), _ptr(self.t),
+                                                _ptr(self.phi), _ptr(self.grad_packed), _ptr(self.dphidt),
+                                                _ptr(self.iters), _ptr(self.kstar), ctypes.byref(self._handle)))
+
+    def launch(self, stream=None):
+        check(self._lib.hopf_ragged_plan_launch(self._handle, _stream_ptr(stream)))
+
+    def grads(self):
+        out, o = [], 0
+        for p, c in zip(self.problems, np.diff(self.offsets)):
+            out.append(self.grad_packed[o:o + int(c) * p.n].view(int(c), p.n))
+            o += int(c) * p.n
+        return out
+
+    def __del__(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self._lib.hopf_ragged_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+
 def eval_ragged(problems: Sequence[Problem], xs: Sequence[torch.Tensor], ts: Sequence[torch.Tensor],
                 stream=None):
     """Evaluate a ragged batch (each problem its own n, A, K, w; points packed) in one call."""

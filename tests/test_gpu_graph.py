@@ -1,0 +1,86 @@
+"""A ragged evaluation as a plan (hopf_ragged_plan_*): its launch enqueues kernels only, so it is
+captured in a HIP graph and replayed.  Every replay (with the program's own eager work and
+synchronisations between replays) is checked against the plan's eager launch and the one-call
+path (hopf_eval_ragged) to the parity bar, and on sampled points against the FP64 oracle.  The
+persistent kernels take chunks from an atomic queue, so the anchor schedule of a column can
+differ between launches: results agree to the parity bar, not bit for bit."""
+import numpy as np
+import pytest
+
+from tests.helpers import rand_problem, rel_err_phi, rel_err_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1605_01799_amd import hopf as H  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-6
+
+
+def batch(precision, ns, K, seed):
+    rng = np.random.default_rng(seed)
+    specs, xs, ts, cases = [], [], [], []
+    for q, n in enumerate(ns):
+        A = rand_problem(n, rng)
+        w = rng.uniform(0.5, 2, n)
+        C = rng.normal(0, 3, (K, n))
+        npts = 40 + 17 * q
+        x = rng.normal(0, 2, (npts, n)).astype(np.float32)
+        t = rng.uniform(0.05, 3, npts).astype(np.float32)
+        specs.append(dict(A=A, hkind="l2_wl1", w=w, centres=C, level_set=True, precision=precision,
+                          tol=1e-16 * n, max_iter=20000))
+        xs.append(torch.from_numpy(x).to(DEV))
+        ts.append(torch.from_numpy(t).to(DEV))
+        cases.append(dict(A=A, w=w, C=C, x=x, t=t, n=n))
+    return specs, xs, ts, cases
+
+
+@pytest.mark.parametrize("precision,ns,K", [("f32", (5, 33, 70, 300), 2), ("bf16_refined", (40, 300, 1100), 1)])
+def test_plan_graph_replay(oracle_lib, precision, ns, K):
+    print("case plan graph %s n=%s K=%d" % (precision, list(ns), K), flush=True)
+    specs, xs, ts, cases = batch(precision, ns, K, 31 + K)
+    hp = H.Problem.batch(specs)
+    plan = H.RaggedPlan(hp, xs, ts)
+    plan.launch()
+    torch.cuda.synchronize()
+    eager = dict(phi=plan.phi.clone(), grad=plan.grad_packed.clone(), iters=plan.iters.clone())
+    assert (eager["iters"] > 0).all().item()
+    one_call = H.eval_ragged(hp, xs, ts)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.launch()
+    torch.cuda.synchronize()
+    ref_phi = eager["phi"].cpu().numpy()
+    ref_grad = eager["grad"].cpu().numpy().reshape(-1)
+    assert rel_err_phi(one_call["phi"].cpu().numpy(), ref_phi).max() <= TOL
+    for k in range(3):
+        plan.phi.fill_(float("nan"))          # eager work between replays
+        plan.grad_packed.fill_(float("nan"))
+        plan.iters.fill_(0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        phi = plan.phi.cpu().numpy()
+        assert np.isfinite(phi).all() and (plan.iters > 0).all().item()
+        ef = rel_err_phi(phi, ref_phi).max()
+        g = plan.grad_packed.cpu().numpy()
+        eg = np.abs(g - ref_grad).max() / max(np.abs(ref_grad).max(), 1.0)
+        print("  replay %d: vs eager phi %.2e grad %.2e" % (k, ef, eg), flush=True)
+        assert ef <= TOL and eg <= TOL
+    # the last replay against the oracle on a few points of each problem
+    off = plan.offsets
+    grads = plan.grads()
+    for q, c in enumerate(cases):
+        idx = np.array([0, c["x"].shape[0] // 2, c["x"].shape[0] - 1])
+        ref = oracle_lib.oracle_eval(c["A"], c["x"][idx].astype(np.float64), c["t"][idx].astype(np.float64),
+                                     "l2_wl1", w=c["w"], centres=c["C"], level_set=True, tol=1e-28, nthreads=3)
+        assert rel_err_phi(plan.phi.cpu().numpy()[off[q]:off[q + 1]][idx], ref["phi"]).max() <= TOL
+        if K == 1:
+            assert rel_err_vec(grads[q].cpu().numpy()[idx], ref["grad"]).max() <= TOL
+    del graph
+    del plan
