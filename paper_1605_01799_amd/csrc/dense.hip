@@ -39,6 +39,9 @@
 // t = s and the ellipsoid level set; Newton on s (eq. Newton_zero,
 // d psi / ds = -|grad psi|) starts at s = 0 where psi = L_k(y) and grad psi =
 // grad L_k(y), each Newton step warm-starting the inner iteration.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.hpp"
 #include "dense.hpp"
 #include "dense_shared.hpp"
@@ -893,18 +896,26 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Launch shapes picked by the project's autotuner (autotune.py: every launchable shape timed on a
+// synthetic union-of-level-sets workload per mode and padded size), {mode, largest n_pad, pt, occ, nw}.
+struct TunedShape { int mode, npad_max, pt, occ, nw; };
+static const TunedShape kTuned[] = {
+#include "tune_table.inc"
+};
+
 DenseVariant dense_variant(int mode, int n_pad) {
-  // refined mode up to n_pad = 1024: two 32-column workgroups of 4 waves per CU (default), or
-  // one 64-column workgroup of 8 waves (HOPF_DENSE=1) or of 4 waves (HOPF_DENSE=2); FP32 modes
+  // HOPF_DENSE_VARIANT=pt:occ:nw forces a shape (the autotuner's sweeps), else the tuned table,
+  // else the rules below
+  if (const char* v = getenv("HOPF_DENSE_VARIANT")) {
+    DenseVariant f{0, 0, 0};
+    if (sscanf(v, "%d:%d:%d", &f.pt, &f.occ, &f.nw) == 3 && f.pt > 0) return f;
+  }
+  for (const TunedShape& t : kTuned)
+    if (t.mode == mode && n_pad <= t.npad_max) return DenseVariant{t.pt, t.occ, t.nw};
+  // refined mode up to n_pad = 1024: two 32-column workgroups of 4 waves per CU; FP32 modes
   // (plain and refined) by size
-  static const int pick = [] {
-    const char* v = getenv("HOPF_DENSE");
-    return v ? atoi(v) : 0;
-  }();
   if (mode == 1) {
     if (n_pad > 1024) return DenseVariant{32, 1, 4};
-    if (pick == 1) return DenseVariant{64, 1, 8};
-    if (pick == 2) return DenseVariant{64, 1, 4};
     return DenseVariant{32, 2, 4};
   }
   if (n_pad <= 512) return DenseVariant{64, 1, 4};
@@ -940,12 +951,18 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
                            int distance, int anchor_every, int anchor_wait, hipStream_t stream) {
   auto kern = dense_kernel<MODE, CT, RG, OCC, NW>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(136 * 1024));
-    if (e != hipSuccess) return e;
-    attr_set = true;
+  static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (lds > attr_bytes[dev]) {
+    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) {  // more LDS than a workgroup may have: report it without leaving it pending
+      (void)hipGetLastError();
+      return e;
+    }
+    attr_bytes[dev] = lds;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
                      ws_per_wg, ws64_per_wg, distance, anchor_every, anchor_wait);

@@ -872,7 +872,10 @@ static hipError_t launch_rs_t(const DenseProb* d_probs, const DenseChunk* d_chun
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   if (lds > attr_bytes[dev]) {
     e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {  // more LDS than a workgroup may have: report it without leaving it pending
+      (void)hipGetLastError();
+      return e;
+    }
     attr_bytes[dev] = lds;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kNW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws64,
