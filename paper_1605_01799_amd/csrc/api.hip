@@ -78,6 +78,11 @@ struct hopf_problem {
 // ---------------------------------------------------------------------------
 // per-device workspace
 // ---------------------------------------------------------------------------
+// chunk counters of a workspace or plan: one per kernel class of a call, and the per-thread
+// kernel's point queue in the last
+constexpr int kMaxClasses = 64;
+constexpr int kCounters = kMaxClasses + 1;
+
 struct Workspace {
   std::mutex mu;
   float* state = nullptr; size_t state_bytes = 0;
@@ -171,6 +176,32 @@ static void free_problem(hopf_problem* p) {
   delete p;
 }
 
+// HOPF_H_AL2 on the per-thread path: HA = P diag(sig) P^T on the device (Jacobi, FP64) into
+// p->d_HP, and sig as the problem's weights; the problem stays in the caller's basis.
+static hopf_status eig_HA(hopf_problem* p, const hopf_problem_desc* d, hipStream_t stream) {
+  const int n = p->n;
+  const size_t nn = (size_t)n * n;
+  double *dHA = nullptr, *sig = nullptr;
+  int* sweeps = nullptr;
+  auto cleanup = [&]() { hipFree(dHA); hipFree(sig); hipFree(sweeps); };
+  if (hipMalloc(&p->d_HP, sizeof(double) * nn) || hipMalloc(&dHA, sizeof(double) * nn) ||
+      hipMalloc(&sig, sizeof(double) * n) || hipMalloc(&sweeps, sizeof(int))) {
+    cleanup();
+    return fail(HOPF_ENOMEM, "hipMalloc HA eigenbasis");
+  }
+  hipError_t e = hipMemcpy(dHA, d->HA, sizeof(double) * nn, hipMemcpyHostToDevice);
+  if (!e) e = launch_jacobi_eig(dHA, n, p->d_HP, sig, sweeps, stream);
+  if (!e) e = launch_set_weights(sig, n, p->n_pad, p->d_w, p->d_wf, stream);
+  std::vector<double> hs(n);
+  if (!e) e = hipStreamSynchronize(stream);
+  if (!e) e = hipMemcpy(hs.data(), sig, sizeof(double) * n, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e) return fail(HOPF_EDEVICE, "HA eigenbasis: %s", hipGetErrorString(e));
+  for (int i = 0; i < n; ++i)
+    if (!(hs[i] > 0.0)) return fail(HOPF_ENOTSPD, "HA is not positive definite (eigenvalue %g)", hs[i]);
+  return HOPF_OK;
+}
+
 // HOPF_H_AL2: HA = P diag(sig) P^T on the device (Jacobi, FP64); the problem is moved into that
 // basis in place: A (device, n x n) <- P^T A P, weights <- sig, centres <- P^T c.  Synchronises
 // to check that HA is positive definite.
@@ -225,7 +256,10 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   p->precision = d->precision; p->lambda = d->lambda; p->tol = d->tol; p->max_iter = d->max_iter;
   const bool al2 = d->hkind == HOPF_H_AL2;
   p->jkind = d->jkind;
-  p->diagonal = (!al2 && (p->jkind != HOPF_J_QUADRATIC || d->A == nullptr || d->A_is_diagonal)) ? 1 : 0;
+  // HOPF_H_AL2 in FP64 stays in the caller's basis on the per-thread path (the prox rotates);
+  // otherwise it is solved in HA's eigenbasis, where A is dense
+  const bool al2_rot = al2 && d->precision != HOPF_F64;
+  p->diagonal = (!al2_rot && (p->jkind != HOPF_J_QUADRATIC || d->A == nullptr || d->A_is_diagonal)) ? 1 : 0;
   const int n = d->n;
   const int n_pad = (n + 31) / 32 * 32;
   p->n_pad = n_pad;
@@ -275,6 +309,9 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     e = launch_diag_inverse(p->d_adiag, n, n_pad, d->lambda, p->d_Md, p->d_Mf, p->d_Mb, p->d_minv, stream);
     if (!e && p->d_Mq) e = launch_slice_rows(p->d_Md, n_pad, p->d_Mq, p->d_Mqe, stream);
     if (e) return bail(fail(HOPF_EDEVICE, "diag inverse: %s", hipGetErrorString(e)));
+    if (al2) {  // HA = P diag(sig) P^T (FP64 Jacobi on the device); the weights become sig
+      if ((st = eig_HA(p, d, stream))) return bail(st);
+    }
   } else {
     // A + lambda I in FP64 on the device; the Gauss-Jordan batch is run by the caller
     double* dA = nullptr;
@@ -619,8 +656,6 @@ static hopf_status plan_launch(const DensePlan& P, const std::vector<DenseCall>&
   return HOPF_OK;
 }
 
-constexpr int kMaxClasses = 64;  // chunk counters per workspace / plan
-
 static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distance, hipStream_t stream) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -632,7 +667,7 @@ static hopf_status run_dense(std::vector<DenseCall>& calls, int mode, int distan
   plan_dense(calls, mode, distance, w->ncu, &P);
   if (P.cls.empty()) return HOPF_OK;
   if ((int)P.cls.size() > kMaxClasses) return fail(HOPF_EINVAL, "too many kernel classes in one call");
-  if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * kMaxClasses));
+  if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * kCounters));
   const size_t nb = (size_t)std::max<int64_t>(P.total_pts, 1);
   if ((st = ws_grow((void**)&w->best, &w->best_bytes, (sizeof(double) + sizeof(int32_t)) * nb))) return st;
   if ((st = ws_grow((void**)&w->state, &w->state_bytes, sizeof(float) * P.state_floats))) return st;
@@ -727,6 +762,7 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
     dp.jkind = p->jkind;
     dp.max_iter = p->max_iter; dp.lambda = p->lambda; dp.tol = p->tol;
     dp.minv = p->d_minv; dp.adiag = p->d_adiag; dp.w = p->d_w; dp.centres = p->d_centres;
+    dp.P = p->hkind == HOPF_H_AL2 ? p->d_HP : nullptr;
     dp.x = x; dp.t = t; dp.npts = npts; dp.phi = phi; dp.grad = grad; dp.dphidt = dphidt;
     dp.iters = iters; dp.kstar = kstar;
     int dev = 0;
@@ -736,10 +772,10 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
     if (st) return st;
     {
       std::lock_guard<std::mutex> lk(w->mu);
-      if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * 16));
+      if (!w->counter) HIP_TRY(hipMalloc(&w->counter, sizeof(int) * kCounters));
     }
     // the last counter slot is the per-thread kernel's point queue (the tile kernels use the first)
-    hipError_t e = launch_diag(dp, p->precision == HOPF_F64, w->counter + 15, w->ncu, s);
+    hipError_t e = launch_diag(dp, p->precision == HOPF_F64, w->counter + kMaxClasses, w->ncu, s);
     if (e) return fail(HOPF_EDEVICE, "diag launch: %s", hipGetErrorString(e));
     return HOPF_OK;
   }

@@ -89,9 +89,12 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
                "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32", kDiagMaxN);
   if (normsq && d->hkind == HOPF_H_AL2) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the quadratic J");
   if (d->hkind == HOPF_H_AL2) {
-    // solved in HA's eigenbasis, where A becomes dense: the wave-local FP32 kernel
-    if (d->precision != HOPF_F32 || n > kRotMaxN)
-      return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 supports HOPF_F32 with n <= %d", kRotMaxN);
+    // FP64: the per-thread kernel with diagonal A, the prox rotating into HA's eigenbasis; FP32:
+    // solved in HA's eigenbasis, where A becomes dense, by the wave-local kernel
+    const bool f64_diag = d->precision == HOPF_F64 && diag && n <= kDiagMaxN;
+    if (!f64_diag && (d->precision != HOPF_F32 || n > kRotMaxN))
+      return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 supports HOPF_F64 with diagonal A and n <= %d, or HOPF_F32 "
+                 "with n <= %d", kDiagMaxN, kRotMaxN);
     if (!d->HA) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the matrix HA");
     for (int64_t i = 0; i < (int64_t)n * n; ++i)
       if (!std::isfinite(d->HA[i])) return say(HOPF_EINVAL, why, len, "HA[%lld] is not finite", (long long)i);

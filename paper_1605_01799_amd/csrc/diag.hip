@@ -317,8 +317,16 @@ __device__ __forceinline__ void store_point(const DiagProb& pb, int64_t j, doubl
 // compiled only into that instance (it would otherwise hold registers, and so occupancy, from the
 // memory-bound norms).  ONE: a single copy without a centre (the plain J), where the point's own
 // x is the iteration's x' and p is written from the final iterate.
-template <typename T, int NMAX, bool WL2, bool ONE>
+// ROT (with WL2): H = sqrt(<p, HA p>), the paper's |.|_A case of section 4.3, in the caller's
+// basis: the prox rotates z into HA's eigenbasis (HA = P diag(sig) P^T; the weights are sig),
+// projects there onto the diagonal ellipsoid and rotates back, P staged in LDS.
+template <typename T, int NMAX, bool WL2, bool ONE, bool ROT = false>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
+  __shared__ double sP[ROT ? NMAX * NMAX : 1];
+  if constexpr (ROT) {
+    for (int e = threadIdx.x; e < pb.n * pb.n; e += blockDim.x) sP[e] = pb.P[e];
+    __syncthreads();
+  }
   // grid-stride over the points (loading the next point before solving the current one was
   // measured slower: the extra registers cost a wave per SIMD)
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -422,7 +430,28 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
 #pragma unroll
           for (int i = 0; i < NMAX; ++i) dn[i] *= f;
         }
-        if constexpr (WL2) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
+        if constexpr (WL2 && !ROT) wl2_prox<NMAX>(n, cw, th, dn);  // (3.4b), z - projection
+        if constexpr (ROT) {  // (3.4b) in HA's eigenbasis: P prox(P^T z)
+          double zr[NMAX];
+#pragma unroll
+          for (int a = 0; a < NMAX; ++a) zr[a] = 0.0;
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i) {  // static indices: the vectors stay in registers
+            if (i >= n) continue;
+#pragma unroll
+            for (int a = 0; a < NMAX; ++a)
+              if (a < n) zr[a] += sP[i * n + a] * dn[i];
+          }
+          wl2_prox<NMAX>(n, cw, th, zr);
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < NMAX; ++a)
+              if (a < n) s += sP[i * n + a] * zr[a];
+            dn[i] = i < n ? s : 0.0;
+          }
+        }
         double r1 = 0.0, r2 = 0.0, r3 = 0.0;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
@@ -451,7 +480,15 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
         else ai = pb.adiag[i];
         q += ai * d[i] * d[i];
         const double wi = cw[i];
-        h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
+        if constexpr (ROT) {  // <d, HA d> = sum_a sig_a (P^T d)_a^2
+          double s = 0.0;
+#pragma unroll
+          for (int k2 = 0; k2 < NMAX; ++k2)
+            if (k2 < n) s += sP[k2 * n + i] * d[k2];
+          h1 += wi * s * s;
+        } else {
+          h1 += wl2 ? wi * d[i] * d[i] : wi * fabs(d[i]);
+        }
         h2 += d[i] * d[i];
       }
       const double H = wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
@@ -530,7 +567,9 @@ static hipError_t launch_n(const DiagProb& pb, bool ext, int* counter, int ncu, 
     // takes several points
     const int64_t need = (pb.npts + kBlock - 1) / kBlock;
     const unsigned grid = (unsigned)std::min<int64_t>(need, (int64_t)8 * ncu);
-    if (pb.hkind == HK_WL2)
+    if (pb.hkind == HK_AL2)
+      hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false, true>), dim3(grid), dim3(kBlock), 0, stream, pb);
+    else if (pb.hkind == HK_WL2)
       hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false>), dim3(grid), dim3(kBlock), 0, stream, pb);
     else if (pb.K == 1 && pb.centres == nullptr)
       hipLaunchKernelGGL((diag_kernel<T, NMAX, false, true>), dim3(grid), dim3(kBlock), 0, stream, pb);
@@ -559,6 +598,7 @@ hipError_t launch_diag(const DiagProb& pb, bool f64, int* counter, int ncu, hipS
   if (pb.npts == 0) return hipSuccess;
   const bool ext = pb.jkind != JK_QUAD || pb.hkind == HK_LINF;
   if (ext && (!counter || pb.npts > INT32_MAX)) return hipErrorInvalidValue;
+  if (pb.hkind == HK_AL2 && (!pb.P || ext)) return hipErrorInvalidValue;
   return f64 ? launch_t<double>(pb, ext, counter, ncu, stream) : launch_t<float>(pb, ext, counter, ncu, stream);
 }
 

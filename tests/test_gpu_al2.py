@@ -1,7 +1,9 @@
-"""GPU parity for H = sqrt(<p, HA p>) with a full SPD matrix HA (section 4.3, the norm ||.||_A):
-the problem is diagonalised on the device (FP64 Jacobi), solved in HA's eigenbasis by the
-wave-local FP32 kernel and rotated back.  Compared element by element with the FP64 oracle
-(which projects in the eigenbasis and rotates back every iteration, as the paper states it)."""
+"""GPU parity for H = sqrt(<p, HA p>) with a full SPD matrix HA (section 4.3, the norm ||.||_A).
+FP32: the problem is diagonalised on the device (FP64 Jacobi), solved in HA's eigenbasis by the
+wave-local FP32 kernel and rotated back.  FP64 (diagonal A, n <= 32, the paper's timing-table
+setting): the per-thread kernel in the caller's basis, its prox rotating into HA's eigenbasis
+and back every iteration.  Compared element by element with the FP64 oracle (which projects in
+the eigenbasis and rotates back every iteration, as the paper states it)."""
 import numpy as np
 import pytest
 
@@ -18,6 +20,7 @@ from paper_1605_01799_amd import workloads as W  # noqa: E402
 
 DEV = "cuda:0"
 FP32_TOL = 1e-6   # FP32 increments on exact anchors (test_gpu_parity); the rotations add FP32 roundings only
+FP64_TOL = 1e-10
 
 
 def to_np(out):
@@ -67,6 +70,49 @@ def test_paper_table_matrices(oracle_lib, n):
         ref = oracle_lib.oracle_eval(np.diag(Adiag), x.astype(np.float64), t.astype(np.float64), "al2", HA=HA,
                                      tol=1e-28)
         check(out, ref, "paper matrices n=%d" % n)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16, 32])
+def test_paper_table_fp64(oracle_lib, n):
+    """Section 4.5's FP64 setting for the ||.||_A column: D_ii = 1 + (i-1)/(n-1),
+    J = 1/2 <y, D^{-1} y>, HA = I + 1 1^T, (x, t) uniform in [-10, 10]^n x (0, 10]."""
+    p = W.workload_paper_a(n, 2000)
+    print("case al2 fp64 paper table n=%d" % n, flush=True)
+    prob = H.Problem(np.diag(p.A).copy(), diagonal=True, hkind="al2", HA=p.HA, precision="f64", tol=1e-26,
+                     max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(p.x).to(DEV), torch.from_numpy(p.t).to(DEV)))
+    ref = oracle_lib.oracle_eval(p.A, p.x, p.t, "al2", HA=p.HA, tol=1e-26, max_iter=20000)
+    ep = rel_err_vec(out["grad"], ref["grad"])
+    ef = rel_err_phi(out["phi"], ref["phi"])
+    et = rel_err_phi(out["dphidt"], ref["dphidt"])
+    print("  max err grad %.2e phi %.2e dphidt %.2e iters med %d" % (ep.max(), ef.max(), et.max(),
+                                                                    np.median(out["iters"])), flush=True)
+    assert np.all(out["iters"] > 0)
+    assert ep.max() <= FP64_TOL and ef.max() <= FP64_TOL and et.max() <= FP64_TOL
+
+
+def test_fp64_random_HA_union(oracle_lib):
+    """FP64 per-thread path with a random SPD HA, weights ignored, and a union of 3 shifted level
+    sets (the copy loop and the minimum over copies)."""
+    rng = np.random.default_rng(5500)
+    n, K = 11, 3
+    a = rng.uniform(0.5, 3, n)
+    HA = rand_problem(n, rng, 0.5, 3.0)
+    C = rng.normal(0, 3, (K, n))
+    x = rng.normal(0, 2, (300, n))
+    t = rng.uniform(0.05, 3, 300)
+    prob = H.Problem(a, diagonal=True, hkind="al2", HA=HA, centres=C, level_set=True, precision="f64",
+                     tol=1e-26, max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    ref = oracle_lib.oracle_eval(np.diag(a), x, t, "al2", HA=HA, centres=C, level_set=True, tol=1e-26,
+                                 max_iter=20000)
+    per_k = [oracle_lib.oracle_eval(np.diag(a), x - C[k], t, "al2", HA=HA, level_set=True, tol=1e-26,
+                                    max_iter=20000)["phi"] for k in range(K)]
+    srt = np.sort(np.stack(per_k), axis=0)
+    clear = (srt[1] - srt[0]) > 1e-8 * np.maximum(1, np.abs(srt[0]))
+    assert np.all(out["kstar"][clear] == ref["kstar"][clear])
+    assert rel_err_phi(out["phi"], ref["phi"]).max() <= FP64_TOL
+    assert rel_err_vec(out["grad"][clear], ref["grad"][clear]).max() <= FP64_TOL
 
 
 def test_union_and_ragged(oracle_lib):
@@ -136,11 +182,13 @@ def test_closest_point_rotated(oracle_lib):
 def test_rejected():
     rng = np.random.default_rng(5400)
     HA = rand_problem(8, rng, 0.5, 3.0)
-    for kw in (dict(precision="bf16_refined"), dict(precision="f64", diagonal=True)):
-        A = np.ones(8) if kw.get("diagonal") else rand_problem(8, rng)
+    for kw in (dict(precision="bf16_refined"), dict(precision="f64")):   # FP64 needs diagonal A
         with pytest.raises(H._lib.HopfError) as e:
-            H.Problem(A, hkind="al2", HA=HA, **kw)
+            H.Problem(rand_problem(8, rng), hkind="al2", HA=HA, **kw)
         assert e.value.status == H._lib.HOPF_EINVAL
+    with pytest.raises(H._lib.HopfError) as e:   # FP64 beyond the per-thread kernel's n <= 32
+        H.Problem(np.ones(40), diagonal=True, hkind="al2", HA=rand_problem(40, rng), precision="f64")
+    assert e.value.status == H._lib.HOPF_EINVAL
     with pytest.raises(H._lib.HopfError) as e:   # beyond one wave's tile
         H.Problem(rand_problem(80, rng), hkind="al2", HA=rand_problem(80, rng), precision="f32")
     assert e.value.status == H._lib.HOPF_EINVAL
