@@ -69,16 +69,18 @@ typedef enum {
                          D = diag(w), of section 4.3 (support function of the ellipsoid
                          sum_i y_i^2 / w_i <= 1).  Its prox is z minus the projection onto
                          that ellipsoid (eq. (prox-projection)), one Newton solve for the
-                         Lagrange multiplier per iteration.  Supported where a point's
-                         state stays in one wave or one thread: diagonal A with n <= 32
-                         (any precision), or HOPF_F32 with n <= 64; other problems are
-                         rejected with HOPF_EINVAL at create time. */
+                         Lagrange multiplier per iteration (in the refined modes: on the
+                         multiplier's increment since the anchor, FP64 at the anchor).
+                         Every precision and size of the quadratic J (HOPF_F64: diagonal
+                         A with n <= 32, as for every H). */
   HOPF_H_AL2 = 4,     /* H(p) = sqrt(<p, HA p>) for a full SPD matrix HA (the norm ||.||_A of
                          section 4.3; HA in the descriptor).  The library diagonalises HA on the
                          device (HA = P diag(s) P^T, FP64 Jacobi) and holds the problem in that
                          basis, where H is HOPF_H_WL2 with weights s, A becomes P^T A P and the
                          centres P^T c; points are rotated in before the solve and gradients /
-                         closest points rotated back after it.  HOPF_F32 with n <= 64. */
+                         closest points rotated back after it.  HOPF_F32 and
+                         HOPF_BF16_REFINED with n <= 64; HOPF_F64 with diagonal A and
+                         n <= 32 (there the prox rotates, A stays diagonal). */
   HOPF_H_LINF = 5     /* H(p) = ||p||_inf (section 4.2): its prox is z minus the projection onto
                          the l1 ball (the Wulff shape), found by a breakpoint search.  On the
                          per-thread path only: diagonal A or a squared-norm J, n <= 32. */
@@ -97,8 +99,7 @@ typedef enum {
   HOPF_F64 = 0,          /* double I/O and arithmetic (diagonal A only) */
   HOPF_F32 = 1,          /* float I/O; FP32 MFMA products and FP32 state on increments,
                             refined by exact anchor products every few iterations (FP64 MFMA
-                            for n <= 64, integer slices above); the ellipsoidal norms
-                            (HOPF_H_WL2, HOPF_H_AL2) run the plain FP32 iteration */
+                            for n <= 64, integer slices above) */
   HOPF_BF16_REFINED = 2  /* float I/O; BF16 MFMA products on increments, refined by
                             anchor products every few iterations that are exact up to
                             ~2^-31 of the row and column scales (integer slices) */
@@ -178,8 +179,7 @@ hopf_status hopf_closest_point(hopf_problem_t problem, int64_t npts, const void*
                                int32_t* newton, void* stream);
 
 /* Ragged batch: nprob problems (any n, K, A, w; one precision for all, not
- * HOPF_F64; the ellipsoidal norms only with HOPF_F32 and n <= 64; no
- * HOPF_H_LINF or squared-norm J).  The problems are grouped into kernel
+ * HOPF_F64; no HOPF_H_LINF or squared-norm J).  The problems are grouped into kernel
  * classes by padded size (the launch shape of each class); each class is one
  * persistent launch over its problems' points; the classes are enqueued
  * back to back on stream, each with its own metadata, staging and chunk counter in the

@@ -294,9 +294,9 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
   // integer slices of M for the exact anchor products of the refined tile solver (BF16 or FP32
-  // increments); the per-thread diagonal path does not use them
-  const bool diag_path = p->diagonal && n <= kDiagMaxN;
-  if (d->precision != HOPF_F64 && !diag_path &&
+  // increments); also for a diagonal problem that hopf_eval runs per thread, since a ragged batch
+  // runs it in the dense kernels
+  if (d->precision != HOPF_F64 &&
       (hipMalloc(&p->d_Mq, (size_t)kSlices * n_pad * pad64(n_pad)) || hipMalloc(&p->d_Mqe, sizeof(int32_t) * n_pad)))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (slices)"));
   if (p->diagonal) {
@@ -540,9 +540,7 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
   static const bool use_rs = env_int("HOPF_RS", 1) != 0;
   auto class_of = [&](const hopf_problem* p) -> int {
-    // sqrt(<p, D p>) runs only in the small kernel (distance problems use l2 whatever the kind)
-    const bool need_small = (p->hkind == HOPF_H_WL2 || p->hkind == HOPF_H_AL2) && !distance;
-    if ((use_small || need_small) && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
+    if (use_small && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
     if (use_rs && dense_rs_fits(mode, p->n_pad, p->K, p->hkind, distance)) return kRsClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
     return 100 * v.pt + 10 * v.occ + v.nw;

@@ -76,11 +76,8 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
   if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
     return say(HOPF_EINVAL, why, len,
                "HOPF_F64 supports diagonal A with n <= %d; use HOPF_F32 or HOPF_BF16_REFINED", kDiagMaxN);
-  // the ellipsoid projection needs whole-column reductions inside its Newton loop: supported by
-  // the per-thread diagonal kernel and the wave-local small dense kernel
-  if (d->hkind == HOPF_H_WL2 && !((diag && n <= kDiagMaxN) || (d->precision == HOPF_F32 && n <= kSmallMaxN)))
-    return say(HOPF_EINVAL, why, len, "HOPF_H_WL2 supports diagonal A with n <= %d, or HOPF_F32 with n <= %d",
-               kDiagMaxN, kSmallMaxN);
+  // the ellipsoid projection (whole-column reductions inside its Newton loop) runs in every kernel
+  // of the quadratic J: per-thread (diagonal A), wave-local and tile kernels (dense A)
   // the breakpoint searches run in the per-thread kernel
   if (normsq && (n > kDiagMaxN || d->precision == HOPF_BF16_REFINED))
     return say(HOPF_EINVAL, why, len, "squared-norm J supports n <= %d with HOPF_F64 or HOPF_F32", kDiagMaxN);
@@ -89,12 +86,12 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
                "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32", kDiagMaxN);
   if (normsq && d->hkind == HOPF_H_AL2) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the quadratic J");
   if (d->hkind == HOPF_H_AL2) {
-    // FP64: the per-thread kernel with diagonal A, the prox rotating into HA's eigenbasis; FP32:
-    // solved in HA's eigenbasis, where A becomes dense, by the wave-local kernel
+    // FP64: the per-thread kernel with diagonal A, the prox rotating into HA's eigenbasis; FP32 and
+    // refined: solved in HA's eigenbasis, where A becomes dense, by the dense kernels
     const bool f64_diag = d->precision == HOPF_F64 && diag && n <= kDiagMaxN;
-    if (!f64_diag && (d->precision != HOPF_F32 || n > kRotMaxN))
+    if (!f64_diag && (d->precision == HOPF_F64 || n > kRotMaxN))
       return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 supports HOPF_F64 with diagonal A and n <= %d, or HOPF_F32 "
-                 "with n <= %d", kDiagMaxN, kRotMaxN);
+                 "and HOPF_BF16_REFINED with n <= %d", kDiagMaxN, kRotMaxN);
     if (!d->HA) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the matrix HA");
     for (int64_t i = 0; i < (int64_t)n * n; ++i)
       if (!std::isfinite(d->HA[i])) return say(HOPF_EINVAL, why, len, "HA[%lld] is not finite", (long long)i);
@@ -122,11 +119,7 @@ hopf_status check_ragged_member(int32_t q, int32_t precision, int32_t batch_prec
   if (jkind != HOPF_J_QUADRATIC || hkind == HOPF_H_LINF)
     return say(HOPF_EINVAL, why, len,
                "problem %d: squared-norm J and HOPF_H_LINF run per point (hopf_eval), not in ragged batches", q);
-  // the ellipsoid projection runs only where a point stays in one wave
-  if ((hkind == HOPF_H_WL2 || hkind == HOPF_H_AL2) && !(precision == HOPF_F32 && n <= kSmallMaxN))
-    return say(HOPF_EINVAL, why, len,
-               "problem %d: the ellipsoidal norms run in ragged batches with HOPF_F32 and n <= %d only", q,
-               kSmallMaxN);
+  (void)n;  // the ellipsoidal norms run in every dense kernel
   return HOPF_OK;
 }
 

@@ -12,7 +12,7 @@ namespace hopf {
 constexpr int kMaxN = 2048;     // largest dimension
 constexpr int kMaxK = 64;       // largest number of translated copies / ellipsoids
 constexpr int kDiagMaxN = 32;   // per-thread path: a point's state in one thread's registers
-constexpr int kRotMaxN = 64;    // sqrt(<p, HA p>): the rotated problem is solved by the wave-local kernel
+constexpr int kRotMaxN = 64;    // sqrt(<p, HA p>): HA's eigenbasis by Jacobi with the matrix in one workgroup's LDS
 constexpr int kSmallMaxN = 64;  // wave-local kernel: a point's state in one wave
 // Columns of one call are (point, copy) pairs numbered point * K + copy in 32-bit integers on the
 // device, so npts * K must stay below 2^31.
@@ -29,8 +29,7 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len);
 hopf_status check_columns(int64_t npts, int32_t K, char* why, size_t len);
 
 // A member of a ragged batch (hopf_eval_ragged runs the dense kernels only): one shared precision
-// other than HOPF_F64, the quadratic J, no HOPF_H_LINF, and the ellipsoidal norms only where the
-// wave-local kernel takes them (HOPF_F32, n <= kSmallMaxN).
+// other than HOPF_F64, the quadratic J and no HOPF_H_LINF.
 hopf_status check_ragged_member(int32_t q, int32_t precision, int32_t batch_precision, int32_t hkind, int32_t jkind,
                                 int32_t n, char* why, size_t len);
 

@@ -14,7 +14,14 @@
 // Hamiltonians is gamma * shrink1(z, theta_i) with theta_i = (t/lambda) w_i
 // (weights present) and gamma = max(|s|_2 - t/lambda, 0) / |s|_2 (l2 present),
 // 1 otherwise (eqs. shrink1_def, shrink2_def; for l2 + weighted l1 the
-// l2 shrink is applied to the l1-shrunk vector).
+// l2 shrink is applied to the l1-shrunk vector).  For H = sqrt(<p, D p>), D = diag(w) (section
+// 4.3; also sqrt(<p, HA p>), solved in HA's eigenbasis), the prox is z minus the projection of z
+// onto the Wulff ellipsoid sum y_i^2 / s_i <= 1, s_i = (t/lambda)^2 w_i:
+//     d_i = mu z_i / (s_i + mu),  mu > 0 solving phi(mu) = sum_i s_i z_i^2 / (s_i + mu)^2 = 1,
+// or d = 0 when z lies inside.  mu is found by Newton on 1/sqrt(phi) - 1 (concave, increasing),
+// whose sums over the rows of a column are workgroup reductions: in FP64 from 0 at an anchor
+// (mu^a of za), in FP32 warm-started in the plain iterations, and in REFINED mode two Newton
+// steps per pass on the increment dmu = mu - mu^a written with products of increments (below).
 //
 // v^{k+1} = M r^k is the hot contraction: one GEMM of the n x n matrix M with
 // the n x P_t block of right-hand sides per iteration, on MFMA.  Three modes:
@@ -48,6 +55,25 @@
 
 namespace hopf {
 
+// sqrt(<p, D p>): the prox of z for multiplier mu (s = (t/lambda)^2 w_i), 0 inside the ellipsoid
+__device__ __forceinline__ float wl2_d(float z, float s, float mu, bool inside) {
+  return (inside || !(s > 0.f)) ? 0.f : mu * z * __builtin_amdgcn_rcpf(s + mu);
+}
+// its increment prox(za + dz) - prox(za) at mu = mu^a + dmu, from products of increments:
+//   (mu dz (s + mu^a) + za s dmu) / ((s + mu)(s + mu^a)),  or -d^a when z lies inside
+__device__ __forceinline__ float wl2_dd(float za, float dz, float s, float mua, float dm, bool ains, bool cin) {
+  if (!(s > 0.f)) return 0.f;
+  const float A = s + mua, mu = mua + dm, B = s + mu;
+  if (cin) return ains ? 0.f : -mua * za * __builtin_amdgcn_rcpf(A);
+  return (mu * dz * A + za * s * dm) * __builtin_amdgcn_rcpf(B * A);
+}
+// the anchor's d^a in FP64
+__device__ __forceinline__ double wl2_da(float za, double s, double mua, bool ains) {
+  return (ains || !(s > 0.0)) ? 0.0 : mua * (double)za / (s + mua);
+}
+constexpr int kWl2PlainNewton = 12;   // cap on a plain pass's Newton steps (warm-started)
+constexpr int kWl2AnchorNewton = 100; // cap on an anchor's FP64 Newton steps (from 0)
+
 // MODE 0: FP32 products; MODE 1: BF16 increments + exact anchors; MODE 2: FP32 increments + exact
 // anchors.  CT column tiles of 16, RG row
 // tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
@@ -61,6 +87,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
   constexpr int PT = 16 * CT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ ColShared<PT, NW> S;
+  __shared__ double red3[NW][PT];  // third partial of the multiplier sums (sqrt(<p, D p>))
+  __shared__ int wsel[PT];         // columns in a multiplier solve: 1 plain, 2 increment, 3 anchor
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, l = tid & 63;
@@ -91,12 +119,134 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     const float flam = (float)lam;
     const bool has_l1 = !distance && hk_has_l1(pb.hkind);
     const bool has_l2 = distance || hk_has_l2(pb.hkind);
+    const bool wl2 = !distance && pb.hkind == HK_WL2;  // sqrt(<p, D p>) (HA's, in its eigenbasis)
     float* const za = wsb;
     float* const dz = wsb + (int64_t)PT * n_pad;
     float* const ea = wsb + 2 * (int64_t)PT * n_pad;
     float* const pout = wsb + 3 * (int64_t)PT * n_pad;
     const int nq = n_pad >> 2;
     const int RT = n_pad >> 4;
+
+    // sqrt(<p, D p>): multiplier solves.  A sweep sums three terms over the rows of every column
+    // with wsel != 0 (wave w takes the row tiles w, w + NW, ...; a lane's rows as in the epilogue)
+    // into S.red[w][c][0..1] and red3[w][c]; then `update` (thread c of wave 0) takes the column
+    // sums and says whether the column needs another sweep; at most `cap` sweeps.
+    auto wl2_solve = [&](int cap, auto&& term, auto&& update) {
+      for (int it = 0; it < cap; ++it) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const int c = 16 * ct + (l & 15);
+          double p[3] = {0.0, 0.0, 0.0};
+          const int sel = wsel[c];
+          if (sel)
+            for (int rt = wave; rt < RT; rt += NW) term(c, sel, st_block(rt, ct, RT) + 4 * l, 16 * rt + 4 * (l >> 4), p);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) { p[q] += __shfl_xor(p[q], 16); p[q] += __shfl_xor(p[q], 32); }
+          if (l < 16) { S.red[wave][c][0] = p[0]; S.red[wave][c][1] = p[1]; red3[wave][c] = p[2]; }
+        }
+        __syncthreads();
+        if (wave == 0) {
+          bool more = false;
+          if (tid < PT && wsel[tid]) {
+            double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { q0 += S.red[w][tid][0]; q1 += S.red[w][tid][1]; q2 += red3[w][tid]; }
+            more = update(tid, it, q0, q1, q2, it + 1 == cap);
+            if (!more) wsel[tid] = 0;
+          }
+          const bool any = __any(more);
+          if (l == 0) S.ctl[CTL_WL2] = any ? 1 : 0;
+        }
+        __syncthreads();
+        if (!S.ctl[CTL_WL2]) break;
+      }
+    };
+    // an anchor: phi(mu; za) = sum s za^2 / (s + mu)^2 and -1/2 its derivative in FP64, and
+    // sum za^2 / s (= phi(0; za): za lies inside when it is <= 1)
+    auto term_anchor = [&](int c, int sel, size_t et, int row0, double* p) {
+      const f32x4 zv = ld_nt4(za + et);
+      const double th2 = S.th2[c], mu = S.gama[c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double sv = th2 * *gp(pb.w + row0 + q);
+        if (!(sv > 0.0)) continue;
+        const double z = (double)zv[q], inv = 1.0 / (sv + mu), e = sv * z * z * inv * inv;
+        p[0] += z * z / sv; p[1] += e; p[2] += e * inv;
+      }
+    };
+    // Newton on 1/sqrt(phi) - 1 from mu = 0 (increasing monotonically to the root); FP64
+    auto upd_anchor = [&](int c, int it, double qi, double ph, double ps, bool last) -> bool {
+      if (it == 0 && !(qi > 1.0)) {  // za inside: d^a = 0
+        S.gama[c] = 0.0; S.ssa2[c] = qi - 1.0; S.flags[c] |= FLAG_INSIDE | FLAG_CIN;
+        return false;
+      }
+      const double mu = S.gama[c], stp = ph * (sqrt(ph) - 1.0) / ps;
+      if (!(stp > 1e-15 * mu) || last) {  // phi(mu^a; za) - 1: the increments' reference
+        S.ssa2[c] = ph - 1.0; S.flags[c] &= ~(FLAG_INSIDE | FLAG_CIN);
+        return false;
+      }
+      S.gama[c] = mu + stp;
+      return true;
+    };
+    // a pass, FP32 terms.  Plain (wsel 1): the sums of the anchor's form for z = za at mu.
+    // Increment (wsel 2): sum z^2 / s, F(dmu) - (phi(mu^a; za) - 1) and -F'(dmu) / 2 with
+    //   F(dmu) = sum s a b / ((s + mu)^2 (s + mu^a)^2) + phi(mu^a; za) - 1,
+    //   a = dz (s + mu^a) - za dmu,  b = z (s + mu^a) + za (s + mu),  z = za + dz,
+    // which is phi(mu; z) - 1 written with increments; F' = -2 sum s z^2 / (s + mu)^3.
+    auto term_pass = [&](int c, int sel, size_t et, int row0, double* p) {
+      const f32x4 zv = ld_nt4(za + et);
+      const f32x4 dv = sel == 2 ? ld_nt4(dz + et) : f32x4{0.f, 0.f, 0.f, 0.f};
+      const f32x4 wv = *gp((const f32x4*)(pb.wf + row0));
+      const float th2f = (float)S.th2[c];
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      if (sel == 1) {
+        const float mu = (float)S.gam[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float sv = theta_f(th2f, wv[q]);
+          if (!(sv > 0.f)) continue;
+          const float z = zv[q], iB = __builtin_amdgcn_rcpf(sv + mu), e = sv * z * z * iB * iB;
+          a0 += z * z * __builtin_amdgcn_rcpf(sv); a1 += e; a2 += e * iB;
+        }
+      } else {
+        const float mua = (float)S.gama[c], dm = (float)S.dgam[c], mu = mua + dm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float sv = theta_f(th2f, wv[q]);
+          if (!(sv > 0.f)) continue;
+          const float zA = zv[q], d = dv[q], z = zA + d, A = sv + mua, B = sv + mu;
+          const float iA = __builtin_amdgcn_rcpf(A), iB = __builtin_amdgcn_rcpf(B);
+          const float a = d * A - zA * dm, b = z * A + zA * B;
+          a0 += z * z * __builtin_amdgcn_rcpf(sv);
+          a1 += sv * a * b * (iB * iB) * (iA * iA);
+          a2 += sv * z * z * (iB * iB * iB);
+        }
+      }
+      p[0] += (double)a0; p[1] += (double)a1; p[2] += (double)a2;
+    };
+    // plain: warm-started Newton on 1/sqrt(phi) - 1 (a step from the right of the root lands
+    // left of it, clamped at 0; from the left the steps increase monotonically); increment: two
+    // Newton steps on F, warm-started from the last pass's dmu (mu stays >= 0)
+    auto upd_pass = [&](int c, int it, double q0, double q1, double q2, bool last) -> bool {
+      if (wsel[c] == 1) {
+        if (it == 0) {
+          if (!(q0 > 1.0)) { S.gam[c] = 0.0; S.flags[c] |= FLAG_CIN; return false; }
+          S.flags[c] &= ~FLAG_CIN;
+        }
+        if (!(q2 > 0.0)) return false;
+        const double stp = q1 * (sqrt(q1) - 1.0) / q2;
+        const double mu = fmax(S.gam[c] + stp, 0.0);
+        S.gam[c] = mu;
+        return !last && fabs(stp) > (MODE == 0 ? 1e-6 : 1e-5) * mu;
+      }
+      if (it == 0) {
+        if (!(q0 > 1.0)) S.flags[c] |= FLAG_CIN;
+        else S.flags[c] &= ~FLAG_CIN;
+      }
+      if (!(S.flags[c] & FLAG_CIN) && q2 > 0.0)
+        S.dgam[c] = fmax(S.dgam[c] + (q1 + S.ssa2[c]) / (2.0 * q2), -S.gama[c]);
+      return it == 0 && !last;
+    };
 
     // ================================================================ anchor (REFINED mode)
     if (MODE >= 1 && S.ctl[CTL_ANCHOR]) {
@@ -174,6 +324,16 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         }
       }
       __syncthreads();
+      if (wl2) {  // the anchor's multiplier mu^a of za (as renormalised above), in FP64
+        if (tid < PT) {
+          const int st = S.state[tid];
+          const bool on = st == COL_ACTIVE || st == COL_WAITING;
+          wsel[tid] = on ? 3 : 0;
+          if (on) { S.gama[tid] = 0.0; S.dgam[tid] = 0.0; }
+        }
+        __syncthreads();
+        wl2_solve(kWl2AnchorNewton, term_anchor, upd_anchor);
+      }
       // v^a = M r^a; ea = v^a - d^a.  r^a = x' + lambda (2 d^a - z^a) is formed once per anchor in
       // FP64 (the workgroup's staging, column-major, n_pad per column) and the product is taken in
       // integer slices (the kSlices definitions): M and r^a are split into kSlices 7-bit slices
@@ -194,7 +354,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const int c = 16 * ct + (l & 15);
           const int st = S.state[c];
           const bool on = st == COL_ACTIVE || st == COL_WAITING;
-          const double th1 = S.th1[c], ga = S.gama[c];
+          const double th1 = S.th1[c], ga = S.gama[c], th2 = S.th2[c];
+          const bool ains = S.flags[c] & FLAG_INSIDE;
           const HOPF_GLOBAL float* xj = gp(pb.x + (size_t)S.j[c] * n);
           const HOPF_GLOBAL double* cen = pb.centres ? gp(pb.centres + (size_t)S.k[c] * n_pad) : nullptr;
           constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
@@ -216,9 +377,10 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 for (int q = 0; q < 4; ++q) {
                   const int row = row0 + q;
                   if (row < n) {
-                    const double sa64 = anchor_shrink(zv[u][q], th1, pb.w, row);
+                    const double da = wl2 ? wl2_da(zv[u][q], th2 * *gp(pb.w + row), ga, ains)
+                                          : ga * anchor_shrink(zv[u][q], th1, pb.w, row);
                     const double xp = (double)xj[row] - (cen ? cen[row] : 0.0);
-                    rv[q] = xp + lam * (2.0 * ga * sa64 - (double)zv[u][q]);
+                    rv[q] = xp + lam * (2.0 * da - (double)zv[u][q]);
                     cmax[ct] = fmax(cmax[ct], fabs(rv[q]));
                   }
                 }
@@ -316,8 +478,9 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               double v = 0.0;  // smallest terms first
 #pragma unroll
               for (int s = kSlices - 1; s >= 0; --s) v += ldexp((double)acc[s][ct][i], rexp_row[i] + fe - 7 * (s + 2));
-              const double sa64 = anchor_shrink(zv[i], S.th1[c], pb.w, row);
-              ev[i] = (row < n) ? (float)(v - ga * sa64) : 0.f;
+              const double da = wl2 ? wl2_da(zv[i], S.th2[c] * *gp(pb.w + row), ga, S.flags[c] & FLAG_INSIDE)
+                                    : ga * anchor_shrink(zv[i], S.th1[c], pb.w, row);
+              ev[i] = (row < n) ? (float)(v - da) : 0.f;
             }
             st_nt4(ea + et, ev);
           }
@@ -506,6 +669,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       S.th1[c] = has_l1 ? tv / lam : 0.0;
       S.th2[c] = (!distance && has_l2) ? tv / lam : 0.0;
       S.gam[c] = 1.0; S.gama[c] = 1.0; S.dgam[c] = 0.0; S.ssa2[c] = 0.0; S.ssq[c] = 0.0;
+      if (wl2) { S.th2[c] = (tv / lam) * (tv / lam); S.gam[c] = 0.0; S.gama[c] = 0.0; }  // s_i = th2 w_i; mu
       S.prev[c] = 1e300; S.s[c] = 0.0; S.phi[c] = 0.0; S.hp[c] = 0.0; S.pn[c] = 0.0;
       S.best[c] = 1e300; S.stall[c] = 0;
       S.iters[c] = 0; S.newton[c] = 0; S.flags[c] = FLAG_FIRST; S.phase[c] = PH_WARMUP;
@@ -573,7 +737,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const bool deltac = MODE >= 1 && S.phase[c] == PH_DELTA;
         const bool first = S.flags[c] & FLAG_FIRST;
         const float gaf = (float)S.gama[c], dgf = (float)S.dgam[c], gf = (float)S.gam[c];
-        const float th1f = (float)S.th1[c];
+        const float th1f = (float)S.th1[c], th2f = (float)S.th2[c];
+        const bool ains = S.flags[c] & FLAG_INSIDE, cin = S.flags[c] & FLAG_CIN;
         // batches of PB row tiles: all their state loads are in flight before any is used
         const float* sv_src = deltac ? dz : ea;  // increment (delta phase) or x' (plain)
         for (int rtb = wave; rtb < RT; rtb += NW * PB) {
@@ -604,7 +769,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                   const float th = theta_f(th1f, wv[u][q]);
                   const float ca = clampf(zv[u][q], -th, th), sa = zv[u][q] - ca;
                   const float ds = sv[u][q] - clampf(sv[u][q] + sa, -th - ca, th - ca);
-                  const float dd = gaf * ds + dgf * (sa + ds);
+                  const float dd = wl2 ? wl2_dd(zv[u][q], sv[u][q], theta_f(th2f, wv[u][q]), gaf, dgf, ains, cin)
+                                       : gaf * ds + dgf * (sa + ds);
                   rv[q] = flam * (2.f * dd - sv[u][q]);
                 }
               } else {
@@ -612,7 +778,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 for (int q = 0; q < 4; ++q) {
                   const float z = zv[u][q];
                   const float th = theta_f(th1f, wv[u][q]);
-                  const float d = first ? z : gf * (z - clampf(z, -th, th));
+                  const float d = first ? z
+                                  : (wl2 ? wl2_d(z, theta_f(th2f, wv[u][q]), gf, cin) : gf * (z - clampf(z, -th, th)));
                   rv[q] = sv[u][q] + flam * (2.f * d - z);
                 }
               }
@@ -657,7 +824,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const int st = S.state[c];
         if (st != COL_ACTIVE && st != COL_PHI) continue;
         const bool delta = MODE >= 1 && S.phase[c] == PH_DELTA;
-        const float th1f = (float)S.th1[c];
+        const float th1f = (float)S.th1[c], th2f = (float)S.th2[c];
+        const bool ains = S.flags[c] & FLAG_INSIDE, cin = S.flags[c] & FLAG_CIN;
         // the state of all RG row tiles of this column is requested before any of it is used
         f32x4 zst[RG], dst[RG], est[RG], wst[RG];
 #pragma unroll
@@ -691,7 +859,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               const float ca = clampf(zav[q], -th, th), sa = zav[q] - ca;
               const float lo = -th - ca, hi = th - ca;
               const float ds = dzv[q] - clampf(dzv[q] + sa, lo, hi);
-              const float dd = gaf * ds + dgf * (sa + ds);
+              const float dd = wl2 ? wl2_dd(zav[q], dzv[q], theta_f(th2f, wst[r][q]), gaf, dgf, ains, cin)
+                                   : gaf * ds + dgf * (sa + ds);
               const float step = eav[q] + v[q] - dd;      // z^{k+1} - z^k
               const float dzn = dzv[q] + step;
               const float dsn = dzn - clampf(dzn + sa, lo, hi);
@@ -712,7 +881,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = row0 + q;
-                const double da = ga * anchor_shrink(zav[q], th1, pb.w, i);
+                const double da = wl2 ? wl2_da(zav[q], S.th2[c] * *gp(pb.w + i), ga, ains)
+                                      : ga * anchor_shrink(zav[q], th1, pb.w, i);
                 double d = da + (double)ddv[q];
                 const double vv = (double)eav[q] + da + (double)v[q];
                 const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
@@ -720,7 +890,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 if (i >= n) d = 0.0;
                 v2 += xp * d;
                 v3 += (2.0 * d - vv) * (rr - lam * vv);
-                v4 += (double)wst[r][q] * fabs(d);
+                v4 += wl2 ? *gp(pb.w + i) * d * d : (double)wst[r][q] * fabs(d);
                 v5 += d * d;
                 pv[q] = (float)d;
               }
@@ -739,7 +909,8 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               for (int q = 0; q < 4; ++q) {
                 const float th = theta_f(th1f, wst[r][q]);
                 const float z = zav[q];
-                const float d = first ? z : gf * (z - clampf(z, -th, th));
+                const float d = first ? z
+                                : (wl2 ? wl2_d(z, theta_f(th2f, wst[r][q]), gf, cin) : gf * (z - clampf(z, -th, th)));
                 const float zn = z - d + v[q];
                 const float step = zn - z;
                 const float sn = zn - clampf(zn, -th, th);
@@ -762,13 +933,15 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 const int i = row0 + q;
                 const float th = theta_f(th1f, wst[r][q]);
                 const float z = zav[q];
-                const double d = (i < n) ? (double)(first ? z : gf * (z - clampf(z, -th, th))) : 0.0;
+                const float df = first ? z
+                                 : (wl2 ? wl2_d(z, theta_f(th2f, wst[r][q]), gf, cin) : gf * (z - clampf(z, -th, th)));
+                const double d = (i < n) ? (double)df : 0.0;
                 const double vv = (double)v[q];
                 const double rr = (double)B32[c * ldb + i];
                 const double xp = (i < n) ? (double)xj[i < n ? i : 0] - (cen ? *gp(cen + i) : 0.0) : 0.0;
                 v2 += xp * d;
                 v3 += (2.0 * d - vv) * (rr - lam * vv);
-                v4 += (double)wst[r][q] * fabs(d);
+                v4 += wl2 ? *gp(pb.w + (i < n ? i : 0)) * d * d : (double)wst[r][q] * fabs(d);
                 v5 += d * d;
                 pv[q] = (float)d;
               }
@@ -814,8 +987,10 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
           const double nz = sqrt(fmax(ssq, 0.0));
           g = nz > 0.0 ? fmax(nz - S.th2[c], 0.0) / nz : 0.0;
         }
-        S.gam[c] = g;
-        S.dgam[c] = g - S.gama[c];
+        if (!wl2) {  // (for sqrt(<p, D p>) gam and dgam hold multipliers, set below)
+          S.gam[c] = g;
+          S.dgam[c] = g - S.gama[c];
+        }
         S.flags[c] &= ~FLAG_FIRST;
         const bool can_stop = (MODE == 0) || delta;
         const double a = sqrt(sm[0]), b = sqrt(S.prev[c]);
@@ -839,7 +1014,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       if (evaluate) {
         const double tt = distance ? S.s[c] : S.t[c];
         const double pn = sqrt(sm[5]);
-        const double H = (has_l1 ? sm[4] : 0.0) + (has_l2 ? pn : 0.0);
+        const double H = wl2 ? sqrt(sm[4]) : (has_l1 ? sm[4] : 0.0) + (has_l2 ? pn : 0.0);
         const double val = sm[2] - 0.5 * sm[3] - tt * H - (pb.level_set ? 0.5 : 0.0);
         S.phi[c] = val; S.hp[c] = H; S.pn[c] = pn;
         if (!distance) {
@@ -875,6 +1050,15 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       }
     }
     __syncthreads();
+    if (wl2) {  // the multipliers of the next pass's prox
+      if (tid < PT) {
+        const int st = S.state[tid];
+        const bool go = st == COL_ACTIVE || (MODE == 0 && st == COL_WAITING);
+        wsel[tid] = go ? ((MODE >= 1 && S.phase[tid] == PH_DELTA) ? 2 : 1) : 0;
+      }
+      __syncthreads();
+      wl2_solve(kWl2PlainNewton, term_pass, upd_pass);
+    }
     if (tid == 0) {
       int nact = 0, nwait = 0;
       for (int c = 0; c < PT; ++c) {

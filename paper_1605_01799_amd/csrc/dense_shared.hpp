@@ -232,14 +232,19 @@ struct ColShared {
 // FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
 // FLAG_CAPPED: some solve of this slot did (reported as -2); FLAG_EXACT: the column has had an
 // exact anchor product (refined wave-local kernel: only then may it stop).
-enum { FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16, FLAG_EXACT = 32 };
+// FLAG_CIN (tile kernel, sqrt(<p, D p>)): the current z lies inside the Wulff ellipsoid (d = 0);
+// FLAG_INSIDE there: the anchor's za does (d^a = 0).
+enum {
+  FLAG_FIRST = 1, FLAG_CAPPED = 2, FLAG_INSIDE = 4, FLAG_NEWTON_CAP = 8, FLAG_SOLVE_CAP = 16, FLAG_EXACT = 32,
+  FLAG_CIN = 64
+};
 // FP32 mode: the split-Bregman step norm is nonincreasing in exact arithmetic (the iteration
 // map is firmly nonexpansive), so a step that has not reached a new minimum for this many
 // iterations is rounding noise: the iterate has stalled at the working precision.
 constexpr int kStallIters = 64;
 enum {
   CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
-  CTL_EXIT, CTL_BETTER, CTL_ANY, CTL_PHIPASS
+  CTL_EXIT, CTL_BETTER, CTL_ANY, CTL_PHIPASS, CTL_WL2
 };
 enum { PH_WARMUP = 0, PH_DELTA = 1 };
 

@@ -70,15 +70,24 @@ int main() {
     d.precision = HOPF_F64; why[0] = 0;
     expect("F64 beyond the per-thread path", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
     d = base(65); d.hkind = HOPF_H_WL2; why[0] = 0;
-    expect("sqrt(<p, D p>) at n = 65 (identity A is diagonal, n > 32)", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+    expect("sqrt(<p, D p>) at n = 65 (tile kernel)", check_desc(&d, why, sizeof why), HOPF_OK, why);
     std::vector<double> A(64 * 64, 0.0);
     for (int i = 0; i < 64; ++i) A[i * 64 + i] = 1.5;
     d = base(64); d.A = A.data(); d.hkind = HOPF_H_WL2; why[0] = 0;
     expect("sqrt(<p, D p>), dense n = 64, F32", check_desc(&d, why, sizeof why), HOPF_OK, why);
     d.precision = HOPF_BF16_REFINED; why[0] = 0;
-    expect("sqrt(<p, D p>), dense, refined", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+    expect("sqrt(<p, D p>), dense, refined", check_desc(&d, why, sizeof why), HOPF_OK, why);
     d = base(16); d.hkind = HOPF_H_AL2; why[0] = 0;
     expect("sqrt(<p, HA p>) without HA", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+    {
+      std::vector<double> HA(65 * 65, 0.0), HA16(16 * 16, 0.0);
+      for (int i = 0; i < 65; ++i) HA[i * 65 + i] = 2.0;
+      for (int i = 0; i < 16; ++i) HA16[i * 16 + i] = 2.0;
+      d = base(16); d.hkind = HOPF_H_AL2; d.HA = HA16.data(); d.precision = HOPF_BF16_REFINED; why[0] = 0;
+      expect("sqrt(<p, HA p>), refined, n = 16", check_desc(&d, why, sizeof why), HOPF_OK, why);
+      d = base(65); d.hkind = HOPF_H_AL2; d.HA = HA.data(); why[0] = 0;
+      expect("sqrt(<p, HA p>) beyond the eigenbasis solver's n", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+    }
     d = base(16); d.jkind = HOPF_J_L1SQ; d.hkind = HOPF_H_LINF; why[0] = 0;
     expect("1/2 |y|_1^2 with |p|_inf", check_desc(&d, why, sizeof why), HOPF_OK, why);
     d.precision = HOPF_BF16_REFINED; why[0] = 0;
@@ -109,15 +118,15 @@ int main() {
     expect("ragged: F64", check_ragged_member(0, HOPF_F64, HOPF_F64, HOPF_H_WL1, HOPF_J_QUADRATIC, 8, why, sizeof why),
            HOPF_EINVAL, why);
     why[0] = 0;
-    expect("ragged: sqrt(<p, D p>) refined (no kernel takes it)",
+    expect("ragged: sqrt(<p, D p>) refined",
            check_ragged_member(1, HOPF_BF16_REFINED, HOPF_BF16_REFINED, HOPF_H_WL2, HOPF_J_QUADRATIC, 8, why, sizeof why),
-           HOPF_EINVAL, why);
+           HOPF_OK, why);
     why[0] = 0;
     expect("ragged: sqrt(<p, D p>) F32, n = 32",
            check_ragged_member(1, HOPF_F32, HOPF_F32, HOPF_H_WL2, HOPF_J_QUADRATIC, 32, why, sizeof why), HOPF_OK, why);
     why[0] = 0;
-    expect("ragged: sqrt(<p, HA p>) F32, n = 65",
-           check_ragged_member(1, HOPF_F32, HOPF_F32, HOPF_H_AL2, HOPF_J_QUADRATIC, 65, why, sizeof why), HOPF_EINVAL, why);
+    expect("ragged: sqrt(<p, D p>) F32, n = 500",
+           check_ragged_member(1, HOPF_F32, HOPF_F32, HOPF_H_WL2, HOPF_J_QUADRATIC, 500, why, sizeof why), HOPF_OK, why);
     why[0] = 0;
     expect("ragged: |p|_inf", check_ragged_member(2, HOPF_F32, HOPF_F32, HOPF_H_LINF, HOPF_J_QUADRATIC, 8, why, sizeof why),
            HOPF_EINVAL, why);

@@ -182,14 +182,13 @@ def test_closest_point_rotated(oracle_lib):
 def test_rejected():
     rng = np.random.default_rng(5400)
     HA = rand_problem(8, rng, 0.5, 3.0)
-    for kw in (dict(precision="bf16_refined"), dict(precision="f64")):   # FP64 needs diagonal A
-        with pytest.raises(H._lib.HopfError) as e:
-            H.Problem(rand_problem(8, rng), hkind="al2", HA=HA, **kw)
-        assert e.value.status == H._lib.HOPF_EINVAL
+    with pytest.raises(H._lib.HopfError) as e:   # FP64 needs diagonal A
+        H.Problem(rand_problem(8, rng), hkind="al2", HA=HA, precision="f64")
+    assert e.value.status == H._lib.HOPF_EINVAL
     with pytest.raises(H._lib.HopfError) as e:   # FP64 beyond the per-thread kernel's n <= 32
         H.Problem(np.ones(40), diagonal=True, hkind="al2", HA=rand_problem(40, rng), precision="f64")
     assert e.value.status == H._lib.HOPF_EINVAL
-    with pytest.raises(H._lib.HopfError) as e:   # beyond one wave's tile
+    with pytest.raises(H._lib.HopfError) as e:   # beyond the eigenbasis solver's n <= 64
         H.Problem(rand_problem(80, rng), hkind="al2", HA=rand_problem(80, rng), precision="f32")
     assert e.value.status == H._lib.HOPF_EINVAL
     with pytest.raises(H._lib.HopfError) as e:   # HA missing

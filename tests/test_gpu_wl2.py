@@ -124,14 +124,6 @@ def test_union_level_sets(oracle_lib):
 
 
 def test_unsupported_paths_are_rejected():
-    rng = np.random.default_rng(4300)
-    A = rand_problem(100, rng)
-    with pytest.raises(H._lib.HopfError) as e:   # dense beyond one wave's tile
-        H.Problem(A, hkind="wl2", w=np.ones(100), precision="f32")
-    assert e.value.status == H._lib.HOPF_EINVAL
-    with pytest.raises(H._lib.HopfError) as e:   # the refined mode has no increment form of the projection
-        H.Problem(rand_problem(16, rng), hkind="wl2", w=np.ones(16), precision="bf16_refined")
-    assert e.value.status == H._lib.HOPF_EINVAL
     w = np.ones(8)
     w[3] = 0.0                                   # D must be positive definite
     with pytest.raises(H._lib.HopfError) as e:

@@ -1,0 +1,182 @@
+"""GPU parity for the ellipsoidal norms (section 4.3) on the tile kernel: H = sqrt(<p, D p>) with
+dense A beyond the wave-local kernel's n <= 64 and in the BF16 refined mode at any n, and
+H = sqrt(<p, HA p>) in the refined mode (solved in HA's eigenbasis by the tile kernel).  The
+tile kernel solves the projection's multiplier by Newton with workgroup-wide sums: in FP64 at an
+anchor, warm-started FP32 in the plain warm-up passes, and on the multiplier's increment in the
+refined passes.  The HIP path runs through the C ABI and is compared element by element with the
+FP64 oracle on seeded inputs: sizes that span several row tiles with a ragged last tile, point
+counts that leave a ragged last column tile, points inside t C (where p* = 0 exactly), unions of
+level sets (several copies per point in one workgroup), ragged batches that hold these problems
+beside other kinds, and enough points that workgroups refill their column slots many times.
+Bar: 1e-6 relative (the refined paths' target)."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from tests.helpers import rand_problem, rel_err_phi, rel_err_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1605_01799_amd import hopf as H  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-6
+
+
+def to_np(out):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+
+
+def check(out, ref, label, idx=None):
+    g, f, dt = out["grad"], out["phi"], out["dphidt"]
+    if idx is not None:
+        g, f, dt = g[idx], f[idx], dt[idx]
+    ep = rel_err_vec(g, ref["grad"])
+    ef = rel_err_phi(f, ref["phi"])
+    et = rel_err_phi(dt, ref["dphidt"])
+    print("  %s: max err grad %.2e phi %.2e dphidt %.2e iters med %d" %
+          (label, ep.max(), ef.max(), et.max(), np.median(out["iters"])), flush=True)
+    assert ep.max() <= TOL and ef.max() <= TOL and et.max() <= TOL
+
+
+def oracle_par(oracle_lib, A, x, t, **kw):
+    """The oracle on row blocks in parallel (each call single-threaded)."""
+    blocks = np.array_split(np.arange(x.shape[0]), min(8, x.shape[0]))
+    def one(b):
+        return oracle_lib.oracle_eval(A, x[b].astype(np.float64), t[b].astype(np.float64), nthreads=1, **kw)
+    with ThreadPoolExecutor(8) as ex:
+        parts = list(ex.map(one, blocks))
+    return {k: np.concatenate([p[k] for p in parts]) for k in ("phi", "grad", "dphidt")}
+
+
+def make(n, npts, seed, inside=6):
+    rng = np.random.default_rng(seed)
+    A = rand_problem(n, rng)
+    w = rng.uniform(0.5, 2, n)
+    x = rng.normal(0, 2, (npts, n)).astype(np.float32)
+    t = rng.uniform(0.05, 3, npts).astype(np.float32)
+    x[:inside] *= 0.01   # inside t C: p* = 0
+    t[:inside] = 2.5
+    return rng, A, w, x, t
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16_refined"])
+@pytest.mark.parametrize("n", [65, 200, 513])
+def test_dense_tile(oracle_lib, n, precision):
+    npts = 150 if n < 500 else 90
+    rng, A, w, x, t = make(n, npts, 6000 + n)
+    print("case wl2 tile n=%d %s" % (n, precision), flush=True)
+    prob = H.Problem(A, hkind="wl2", w=w, precision=precision, tol=1e-16 * n, max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    assert np.all(out["iters"] > 0)
+    ref = oracle_par(oracle_lib, A, x, t, hkind="wl2", w=w, tol=1e-28)
+    assert np.all(ref["grad"][:6] == 0)
+    assert np.all(out["grad"][:6] == 0) and np.all(np.abs(out["phi"][:6]) <= 1e-8)
+    check(out, ref, "wl2 tile n=%d %s" % (n, precision))
+
+
+@pytest.mark.parametrize("n", [5, 16, 64])
+def test_refined_small_n(oracle_lib, n):
+    """The refined mode below 65: the tile kernel takes these (the wave-local kernel is FP32)."""
+    rng, A, w, x, t = make(n, 200, 6100 + n)
+    print("case wl2 refined n=%d" % n, flush=True)
+    prob = H.Problem(A, hkind="wl2", w=w, precision="bf16_refined", tol=1e-16 * n, max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    ref = oracle_par(oracle_lib, A, x, t, hkind="wl2", w=w, tol=1e-28)
+    assert np.all(out["grad"][:6] == 0)
+    check(out, ref, "wl2 refined n=%d" % n)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16_refined"])
+def test_union_level_sets_tile(oracle_lib, precision):
+    n, K, npts = 150, 3, 80
+    rng = np.random.default_rng(6200)
+    A = rand_problem(n, rng)
+    w = rng.uniform(0.5, 2, n)
+    C = rng.normal(0, 3, (K, n))
+    x = rng.normal(0, 2, (npts, n)).astype(np.float32)
+    t = rng.uniform(0.05, 3, npts).astype(np.float32)
+    print("case wl2 tile union K=%d %s" % (K, precision), flush=True)
+    prob = H.Problem(A, hkind="wl2", w=w, centres=C, level_set=True, precision=precision, tol=1e-16 * n,
+                     max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    ref = oracle_par(oracle_lib, A, x, t, hkind="wl2", w=w, centres=C, level_set=True, tol=1e-28)
+    per_k = [oracle_par(oracle_lib, A, x.astype(np.float64) - C[k], t, hkind="wl2", w=w, level_set=True,
+                        tol=1e-28)["phi"] for k in range(K)]
+    srt = np.sort(np.stack(per_k), axis=0)
+    clear = (srt[1] - srt[0]) > 1e-5 * np.maximum(1, np.abs(srt[0]))
+    assert clear.sum() >= npts // 2
+    assert np.all(out["kstar"][clear] == np.argmin(np.stack(per_k), axis=0)[clear])
+    assert rel_err_phi(out["phi"], ref["phi"]).max() <= TOL
+    assert rel_err_vec(out["grad"][clear], ref["grad"][clear]).max() <= TOL
+
+
+@pytest.mark.parametrize("n", [16, 100])
+def test_al2_refined(oracle_lib, n):
+    """sqrt(<p, HA p>) in the refined mode: HA's eigenbasis, the tile kernel in BF16 mode."""
+    rng = np.random.default_rng(6300 + n)
+    A = rand_problem(n, rng)
+    HA = rand_problem(n, rng, 0.5, 3.0)
+    npts = 150
+    x = rng.normal(0, 2, (npts, n)).astype(np.float32)
+    t = rng.uniform(0.05, 3, npts).astype(np.float32)
+    if n > 64:
+        with pytest.raises(H._lib.HopfError):
+            H.Problem(A, hkind="al2", HA=HA, precision="bf16_refined")
+        return
+    print("case al2 refined n=%d" % n, flush=True)
+    prob = H.Problem(A, hkind="al2", HA=HA, precision="bf16_refined", tol=1e-16 * n, max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    ref = oracle_par(oracle_lib, A, x, t, hkind="al2", HA=HA, tol=1e-28)
+    check(out, ref, "al2 refined n=%d" % n)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16_refined"])
+def test_ragged_with_ellipsoidal_norms(oracle_lib, precision):
+    """A ragged batch: sqrt(<p, D p>) at n = 8 with diagonal A, n = 40 and n = 150 dense, beside
+    an l2 + weighted l1 problem, in one call (several kernel classes)."""
+    rng = np.random.default_rng(6400)
+    specs = [(8, "wl2", True), (40, "wl2", False), (150, "wl2", False), (100, "l2_wl1", False)]
+    cases, descs = [], []
+    for q, (n, hk, diag) in enumerate(specs):
+        A = np.diag(rng.uniform(0.5, 3, n)) if diag else rand_problem(n, rng)
+        w = rng.uniform(0.5, 2, n)
+        npts = 40 + 17 * q
+        x = rng.normal(0, 2, (npts, n)).astype(np.float32)
+        t = rng.uniform(0.05, 3, npts).astype(np.float32)
+        cases.append((A, w, x, t, hk))
+        descs.append(dict(A=np.diag(A).copy() if diag else A, diagonal=diag, hkind=hk, w=w, precision=precision,
+                          tol=1e-16 * n, max_iter=20000))
+    print("case ragged wl2 %s" % precision, flush=True)
+    probs = H.Problem.batch(descs)
+    out = H.eval_ragged(probs, [torch.from_numpy(c[2]).to(DEV) for c in cases],
+                        [torch.from_numpy(c[3]).to(DEV) for c in cases])
+    torch.cuda.synchronize()
+    off = out["offsets"]
+    phi = out["phi"].cpu().numpy()
+    for q, (A, w, x, t, hk) in enumerate(cases):
+        ref = oracle_par(oracle_lib, A, x, t, hkind=hk, w=w, tol=1e-28)
+        g = out["grad"][q].cpu().numpy()
+        ef = rel_err_phi(phi[off[q]:off[q + 1]], ref["phi"]).max()
+        ep = rel_err_vec(g, ref["grad"]).max()
+        print("  problem %d (n=%d %s): err phi %.2e grad %.2e" % (q, A.shape[0], hk, ef, ep), flush=True)
+        assert ef <= TOL and ep <= TOL
+
+
+def test_many_refills_tile(oracle_lib):
+    """Enough points that every workgroup refills its slots many times (sampled check)."""
+    n, npts = 128, 20000
+    rng, A, w, x, t = make(n, npts, 6500, inside=20)
+    print("case wl2 tile refills n=%d npts=%d" % (n, npts), flush=True)
+    prob = H.Problem(A, hkind="wl2", w=w, precision="bf16_refined", tol=1e-16 * n, max_iter=20000)
+    out = to_np(prob.eval(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)))
+    assert np.all(out["iters"] > 0)
+    assert np.isfinite(out["grad"]).all() and np.isfinite(out["phi"]).all()
+    idx = np.unique(np.concatenate([np.arange(20), [npts - 1], rng.choice(npts, 40, replace=False)]))
+    ref = oracle_par(oracle_lib, A, x[idx], t[idx], hkind="wl2", w=w, tol=1e-28)
+    check(out, ref, "wl2 tile refills", idx)
