@@ -12,7 +12,7 @@ namespace hopf {
 constexpr int kMaxN = 2048;     // largest dimension
 constexpr int kMaxK = 64;       // largest number of translated copies / ellipsoids
 constexpr int kDiagMaxN = 32;   // per-thread path: a point's state in one thread's registers
-constexpr int kRotMaxN = 64;    // sqrt(<p, HA p>): HA's eigenbasis by Jacobi with the matrix in one workgroup's LDS
+constexpr int kRotMaxN = kMaxN;  // sqrt(<p, HA p>): HA's eigenbasis (FP64 Jacobi on the device)
 constexpr int kSmallMaxN = 64;  // wave-local kernel: a point's state in one wave
 // Columns of one call are (point, copy) pairs numbered point * K + copy in 32-bit integers on the
 // device, so npts * K must stay below 2^31.

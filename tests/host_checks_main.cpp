@@ -86,7 +86,9 @@ int main() {
       d = base(16); d.hkind = HOPF_H_AL2; d.HA = HA16.data(); d.precision = HOPF_BF16_REFINED; why[0] = 0;
       expect("sqrt(<p, HA p>), refined, n = 16", check_desc(&d, why, sizeof why), HOPF_OK, why);
       d = base(65); d.hkind = HOPF_H_AL2; d.HA = HA.data(); why[0] = 0;
-      expect("sqrt(<p, HA p>) beyond the eigenbasis solver's n", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+      expect("sqrt(<p, HA p>), n = 65", check_desc(&d, why, sizeof why), HOPF_OK, why);
+      d.precision = HOPF_F64; why[0] = 0;
+      expect("sqrt(<p, HA p>), F64 beyond the per-thread path", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
     }
     d = base(16); d.jkind = HOPF_J_L1SQ; d.hkind = HOPF_H_LINF; why[0] = 0;
     expect("1/2 |y|_1^2 with |p|_inf", check_desc(&d, why, sizeof why), HOPF_OK, why);

@@ -188,9 +188,6 @@ def test_rejected():
     with pytest.raises(H._lib.HopfError) as e:   # FP64 beyond the per-thread kernel's n <= 32
         H.Problem(np.ones(40), diagonal=True, hkind="al2", HA=rand_problem(40, rng), precision="f64")
     assert e.value.status == H._lib.HOPF_EINVAL
-    with pytest.raises(H._lib.HopfError) as e:   # beyond the eigenbasis solver's n <= 64
-        H.Problem(rand_problem(80, rng), hkind="al2", HA=rand_problem(80, rng), precision="f32")
-    assert e.value.status == H._lib.HOPF_EINVAL
     with pytest.raises(H._lib.HopfError) as e:   # HA missing
         H.Problem(rand_problem(8, rng), hkind="al2", precision="f32")
     assert e.value.status == H._lib.HOPF_EINVAL
