@@ -12,6 +12,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   projection of section 4.3 (Lagrange multiplier, Newton on mu); the
   eigendecomposition A = Q diag(sigma) Q^T is a library primitive
   (``numpy.linalg.eigh``).
+* ``oracle_eval_linear_control``: the time-dependent Hamiltonian of linear controls (section
+  2.2, some extensions and future work) for diagonal drift and input matrices and box controls,
+  by the time-integrated Hopf formula over ``oracle_eval``.
 * ``oracle_backward``: envelope-theorem gradients of phi with respect to x, t,
   A and the centres (phi is the optimal value of eq. (3.3), whose objective is
   affine in x, t, A and c at fixed p).  Parity unpinned by any printed value:
@@ -237,3 +240,55 @@ def oracle_max_over_hamiltonians(A, x, t, hkinds, ws=None, **kw):
     j = np.arange(phis.shape[1])
     return dict(phi=phis[istar, j], grad=np.stack([r["grad"] for r in rs])[istar, j],
                 dphidt=np.stack([r["dphidt"] for r in rs])[istar, j], istar=istar.astype(np.int32))
+
+
+def linear_control_weights(t, drift, nu):
+    """W_i(t) = integral over s in [0, t] of |(e^{-sM} N)_ii| = |nu_i| (1 - e^{-t m_i}) / m_i
+    (t |nu_i| for m_i = 0), M = diag(m), N = diag(nu); one row per entry of t."""
+    t = _f64(t).reshape(-1, 1)
+    m = _f64(drift).reshape(1, -1)
+    a = np.abs(_f64(nu)).reshape(1, -1)
+    tm = t * m
+    safe = np.where(m != 0.0, m, 1.0)
+    return a * np.where(m != 0.0, -np.expm1(-tm) / safe, t)
+
+
+def oracle_eval_linear_control(A, z, t, drift, nu, centres=None, level_set=False, lam=1.0, tol=1e-28,
+                               max_iter=100000, nthreads=None):
+    """Section 2.2 (some extensions and future work), Hamiltonians of linear controls: the state
+    follows dx/ds = M x + N beta(s) with beta(s) in C; with z(s) = e^{-sM} x(s) the Hamiltonian
+    becomes H(p, s) = -min_{c in C} <e^{-sM} N c, p>, and for convex J
+        phi(z, t) = -min_u ( J*(u) + int_0^t H(u, s) ds - <z, u> ).
+    Here M = diag(drift), N = diag(nu) and C = [-1, 1]^n, so H(p, s) = sum_i e^{-s m_i} |nu_i| |p_i|
+    and the integral is sum_i W_i(t) |u_i| (``linear_control_weights``).  For each point the
+    minimisation is the weighted-l1 Hopf problem (split Bregman, ``oracle_eval``) with weights
+    W_i(t) / t at its time t, so that t H = sum_i W_i(t) |u_i|.  grad phi = the minimiser u*;
+    dphi/dt = -H(grad phi, t), the HJ equation at time t (the integrand at s = t, not the
+    integral).  z is the state in the transformed coordinates; J(y) = 1/2 y^T A^{-1} y (min over
+    the translated copies with centres)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    A = _f64(A)
+    n = A.shape[0]
+    z = _f64(z).reshape(-1, n)
+    t = _f64(t).reshape(-1)
+    m = z.shape[0]
+    if t.shape[0] != m:
+        raise ValueError("t must have one entry per point")
+    W = linear_control_weights(t, drift, nu)
+
+    def one(j):
+        if not (t[j] > 0.0 and np.isfinite(t[j])):  # no evaluation: flagged as invalid
+            return dict(phi=np.full(1, np.nan), grad=np.full((1, n), np.nan), dphidt=np.full(1, np.nan),
+                        iters=np.full(1, -1, np.int32), kstar=np.full(1, -1, np.int32))
+        return oracle_eval(A, z[j:j + 1], t[j:j + 1], "wl1", w=W[j] / t[j], centres=centres,
+                           level_set=level_set, lam=lam, tol=tol, max_iter=max_iter, nthreads=1)
+
+    with ThreadPoolExecutor(_threads(nthreads)) as ex:
+        rs = list(ex.map(one, range(m)))
+    out = {k: np.concatenate([r[k] for r in rs]) for k in ("phi", "grad", "dphidt", "iters", "kstar")}
+    inst = np.abs(_f64(nu)).reshape(1, -1) * np.exp(-t.reshape(-1, 1) * _f64(drift).reshape(1, -1))
+    ok = np.isfinite(out["phi"])
+    out["dphidt"] = np.where(ok, -(inst * np.abs(out["grad"])).sum(1), np.nan)
+    return out
+
