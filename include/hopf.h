@@ -81,9 +81,20 @@ typedef enum {
                          closest points rotated back after it.  HOPF_F32 and
                          HOPF_BF16_REFINED with n <= 64; HOPF_F64 with diagonal A and
                          n <= 32 (there the prox rotates, A stays diagonal). */
-  HOPF_H_LINF = 5     /* H(p) = ||p||_inf (section 4.2): its prox is z minus the projection onto
+  HOPF_H_LINF = 5,    /* H(p) = ||p||_inf (section 4.2): its prox is z minus the projection onto
                          the l1 ball (the Wulff shape), found by a breakpoint search.  On the
                          per-thread path only: diagonal A or a squared-norm J, n <= 32. */
+  HOPF_H_LINCTRL = 6  /* The time-dependent Hamiltonian of linear controls (section 2.2, "some
+                         extensions"): the state follows dx/ds = M x + N beta(s), beta(s) in the
+                         box [-1, 1]^n, with M = diag(drift) and N = diag(w) (w_i >= 0: the
+                         box's half-widths scaled by |N_ii|).  In the variables z = e^{-sM} x,
+                         H(p, s) = sum_i e^{-s m_i} w_i |p_i|, and the Hopf formula takes its
+                         integral, phi(z, t) = -min_u (J*(u) + sum_i W_i(t) |u_i| - <z, u>),
+                         W_i(t) = w_i (1 - e^{-t m_i}) / m_i (t w_i for m_i = 0).  The points
+                         passed to hopf_eval are z; grad = the minimiser u*, dphidt =
+                         -H(grad, t) (the Hamiltonian at time t).  Per-thread path only:
+                         diagonal A (or A = I), n <= 32, HOPF_F64 or HOPF_F32, quadratic J;
+                         not in ragged batches, no control read-out. */
 } hopf_hkind;
 
 /* Initial data J (section 4.4).  HOPF_J_QUADRATIC uses the descriptor's A; the squared norms
@@ -125,6 +136,9 @@ typedef struct {
                                 definite. */
   int32_t jkind;             /* hopf_jkind; 0 (HOPF_J_QUADRATIC) keeps the A above.  Translated
                                 copies (K, centres) apply to every kind: J_k = J(. - c_k). */
+  const double* drift;       /* host, n diagonal entries of the drift matrix M for
+                                HOPF_H_LINCTRL (finite, any sign); otherwise ignored (may be
+                                NULL). */
 } hopf_problem_desc;
 
 typedef struct hopf_problem* hopf_problem_t;

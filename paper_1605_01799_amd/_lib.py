@@ -11,7 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhopf.so")
 
 HOPF_OK, HOPF_EINVAL, HOPF_ENOTSPD, HOPF_ENOMEM, HOPF_EDEVICE = 0, -1, -2, -3, -4
-HKIND = {"wl1": 0, "l2": 1, "l2_wl1": 2, "wl2": 3, "al2": 4, "linf": 5}
+HKIND = {"wl1": 0, "l2": 1, "l2_wl1": 2, "wl2": 3, "al2": 4, "linf": 5, "linctrl": 6}
 JKIND = {"quad": 0, "l1sq": 1, "linfsq": 2}
 PRECISION = {"f64": 0, "f32": 1, "bf16_refined": 2}
 
@@ -37,7 +37,7 @@ class ProblemDesc(ctypes.Structure):
         ("K", ctypes.c_int32), ("centres", ctypes.c_void_p), ("level_set", ctypes.c_int32),
         ("hkind", ctypes.c_int), ("w", ctypes.c_void_p), ("lam", ctypes.c_double),
         ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int),
-        ("HA", ctypes.c_void_p), ("jkind", ctypes.c_int32),
+        ("HA", ctypes.c_void_p), ("jkind", ctypes.c_int32), ("drift", ctypes.c_void_p),
     ]
 
 

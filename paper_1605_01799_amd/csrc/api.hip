@@ -66,6 +66,7 @@ struct hopf_problem {
   int8_t* d_Mq = nullptr;       // BF16_REFINED: M in integer slices for the exact anchor products
   int32_t* d_Mqe = nullptr;     // their row exponents
   double* d_adiag = nullptr;    // n (diagonal A)
+  double* d_drift = nullptr;    // n (HOPF_H_LINCTRL: the drift diagonal)
   double* d_minv = nullptr;     // n (diagonal A)
   // HOPF_H_AL2: eigenvectors P of HA (n x n, FP64); the problem is held in HA's eigenbasis
   // (A' = P^T A P, weights = eigenvalues, centres P^T c) and points are rotated in and out
@@ -170,7 +171,7 @@ static hopf_status validate_columns(int64_t npts, int32_t K) {
 
 static void free_problem(hopf_problem* p) {
   hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
-  hipFree(p->d_Mq); hipFree(p->d_Mqe);
+  hipFree(p->d_Mq); hipFree(p->d_Mqe); hipFree(p->d_drift);
   hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP); hipFree(p->d_Af); hipFree(p->d_centres0);
   hipFree(p->d_iter_total);
   delete p;
@@ -278,6 +279,11 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
       return bail(fail(HOPF_EDEVICE, "copy wf"));
   }
   if (hipMalloc(&p->d_iter_total, sizeof(unsigned long long))) return bail(fail(HOPF_ENOMEM, "hipMalloc counter"));
+  if (d->hkind == HOPF_H_LINCTRL) {
+    if (hipMalloc(&p->d_drift, sizeof(double) * n)) return bail(fail(HOPF_ENOMEM, "hipMalloc drift"));
+    if (hipMemcpy(p->d_drift, d->drift, sizeof(double) * n, hipMemcpyHostToDevice))
+      return bail(fail(HOPF_EDEVICE, "copy drift"));
+  }
   if (hipMemset(p->d_iter_total, 0, sizeof(unsigned long long))) return bail(fail(HOPF_EDEVICE, "clear counter"));
   if (d->centres) {
     std::vector<double> hc((size_t)d->K * n_pad, 0.0);
@@ -761,6 +767,7 @@ extern "C" hopf_status hopf_eval(hopf_problem_t p, int64_t npts, const void* x, 
     dp.max_iter = p->max_iter; dp.lambda = p->lambda; dp.tol = p->tol;
     dp.minv = p->d_minv; dp.adiag = p->d_adiag; dp.w = p->d_w; dp.centres = p->d_centres;
     dp.P = p->hkind == HOPF_H_AL2 ? p->d_HP : nullptr;
+    dp.drift = p->d_drift;
     dp.x = x; dp.t = t; dp.npts = npts; dp.phi = phi; dp.grad = grad; dp.dphidt = dphidt;
     dp.iters = iters; dp.kstar = kstar;
     int dev = 0;
@@ -790,6 +797,8 @@ extern "C" hopf_status hopf_control(hopf_problem_t p, int64_t npts, const void* 
                                     const int32_t* kstar, void* beta, void* xT, void* stream) {
   if (!p) return fail(HOPF_EINVAL, "problem is NULL");
   if (p->jkind != HOPF_J_QUADRATIC) return fail(HOPF_EINVAL, "the control read-out needs the quadratic J");
+  if (p->hkind == HOPF_H_LINCTRL)
+    return fail(HOPF_EINVAL, "the control read-out is for time-independent Hamiltonians");
   if (npts < 0) return fail(HOPF_EINVAL, "npts < 0");
   if (npts == 0) return HOPF_OK;
   if (!x || !t || !grad || !beta || !xT) return fail(HOPF_EINVAL, "NULL array argument");

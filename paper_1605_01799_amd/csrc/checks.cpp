@@ -44,7 +44,7 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
   static_assert(sizeof(d->hkind) == sizeof(int) && sizeof(d->precision) == sizeof(int), "enum fields are ints");
   std::memcpy(&hk, &d->hkind, sizeof hk);
   std::memcpy(&prec, &d->precision, sizeof prec);
-  if (hk < HOPF_H_WL1 || hk > HOPF_H_LINF) return say(HOPF_EINVAL, why, len, "unknown hkind %d", hk);
+  if (hk < HOPF_H_WL1 || hk > HOPF_H_LINCTRL) return say(HOPF_EINVAL, why, len, "unknown hkind %d", hk);
   if (d->jkind < HOPF_J_QUADRATIC || d->jkind > HOPF_J_LINFSQ)
     return say(HOPF_EINVAL, why, len, "unknown jkind %d", (int)d->jkind);
   if (prec < HOPF_F64 || prec > HOPF_BF16_REFINED) return say(HOPF_EINVAL, why, len, "unknown precision %d", prec);
@@ -85,6 +85,15 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
     return say(HOPF_EINVAL, why, len,
                "HOPF_H_LINF supports diagonal A or a squared-norm J, n <= %d, HOPF_F64 or HOPF_F32", kDiagMaxN);
   if (normsq && d->hkind == HOPF_H_AL2) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the quadratic J");
+  if (d->hkind == HOPF_H_LINCTRL) {
+    // the per-point integrated weights run in the per-thread kernel only
+    if (normsq || !diag || n > kDiagMaxN || d->precision == HOPF_BF16_REFINED)
+      return say(HOPF_EINVAL, why, len, "HOPF_H_LINCTRL supports the quadratic J with diagonal A, n <= %d, "
+                 "HOPF_F64 or HOPF_F32", kDiagMaxN);
+    if (!d->drift) return say(HOPF_EINVAL, why, len, "HOPF_H_LINCTRL needs the drift diagonal");
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(d->drift[i])) return say(HOPF_EINVAL, why, len, "drift[%d] is not finite", i);
+  }
   if (d->hkind == HOPF_H_AL2) {
     // FP64: the per-thread kernel with diagonal A, the prox rotating into HA's eigenbasis; FP32 and
     // refined: solved in HA's eigenbasis, where A becomes dense, by the dense kernels
@@ -116,9 +125,10 @@ hopf_status check_ragged_member(int32_t q, int32_t precision, int32_t batch_prec
     return say(HOPF_EINVAL, why, len, "problem %d: problems of a ragged batch must share one precision", q);
   if (precision == HOPF_F64)
     return say(HOPF_EINVAL, why, len, "problem %d: ragged batches need HOPF_F32 or HOPF_BF16_REFINED", q);
-  if (jkind != HOPF_J_QUADRATIC || hkind == HOPF_H_LINF)
+  if (jkind != HOPF_J_QUADRATIC || hkind == HOPF_H_LINF || hkind == HOPF_H_LINCTRL)
     return say(HOPF_EINVAL, why, len,
-               "problem %d: squared-norm J and HOPF_H_LINF run per point (hopf_eval), not in ragged batches", q);
+               "problem %d: squared-norm J, HOPF_H_LINF and HOPF_H_LINCTRL run per point (hopf_eval), not in "
+               "ragged batches", q);
   (void)n;  // the ellipsoidal norms run in every dense kernel
   return HOPF_OK;
 }

@@ -53,7 +53,8 @@ __host__ __device__ inline size_t mf_index(int i, int j, int n_pad) {
 }
 
 // Hamiltonian kinds (same numbering as the public header).
-enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2, HK_WL2 = 3, HK_AL2 = 4, HK_LINF = 5 };  // HK_WL2: sqrt(<p, diag(w) p>)
+// HK_WL2: sqrt(<p, diag(w) p>); HK_LINCTRL: the time-dependent H of linear controls (diagonal drift)
+enum { HK_WL1 = 0, HK_L2 = 1, HK_L2_WL1 = 2, HK_WL2 = 3, HK_AL2 = 4, HK_LINF = 5, HK_LINCTRL = 6 };
 // initial data: quadratic 1/2 y^T A^{-1} y, 1/2 |y|_1^2 (J* = 1/2 |p|_inf^2), 1/2 |y|_inf^2 (J* = 1/2 |p|_1^2)
 enum { JK_QUAD = 0, JK_L1SQ = 1, JK_LINFSQ = 2 };
 __host__ __device__ inline bool hk_has_l1(int hk) { return hk == HK_WL1 || hk == HK_L2_WL1; }

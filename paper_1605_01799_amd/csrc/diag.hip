@@ -320,7 +320,12 @@ __device__ __forceinline__ void store_point(const DiagProb& pb, int64_t j, doubl
 // ROT (with WL2): H = sqrt(<p, HA p>), the paper's |.|_A case of section 4.3, in the caller's
 // basis: the prox rotates z into HA's eigenbasis (HA = P diag(sig) P^T; the weights are sig),
 // projects there onto the diagonal ellipsoid and rotates back, P staged in LDS.
-template <typename T, int NMAX, bool WL2, bool ONE, bool ROT = false>
+// LC: the time-dependent Hamiltonian of linear controls (section 2.2, extensions) with
+// M = diag(drift), N = diag(w) and box controls, H(p, s) = sum_i e^{-s m_i} w_i |p_i|: the Hopf
+// formula takes its integral over [0, t], sum_i W_i |p_i| with W_i = w_i (1 - e^{-t m_i}) / m_i,
+// so a point is the weighted-l1 problem with the per-point weights W_i / t (thresholds W_i /
+// lambda); dphi/dt = -H(p, t), the integrand at s = t.
+template <typename T, int NMAX, bool WL2, bool ONE, bool ROT = false, bool LC = false>
 __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   __shared__ double sP[ROT ? NMAX * NMAX : 1];
   if constexpr (ROT) {
@@ -332,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int n = pb.n;
   const double lam = pb.lambda;
-  const bool l1 = !WL2 && hk_has_l1(pb.hkind), l2 = !WL2 && hk_has_l2(pb.hkind);
+  const bool l1 = LC || (!WL2 && hk_has_l1(pb.hkind)), l2 = !LC && !WL2 && hk_has_l2(pb.hkind);
   constexpr bool wl2 = WL2;
   const DiagCoef<NMAX> coef(pb);
   const double* const cm = coef.cm;
@@ -394,6 +399,19 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
       continue;
     }
     const double th = t / lam;
+    // LC: the weights of the integrated Hamiltonian divided by t, lw_i = w_i (1 - e^{-x}) / x with
+    // x = t m_i (1 at x = 0; expm1 keeps it accurate for small x)
+    double lw[LC ? NMAX : 1];
+    if constexpr (LC) {
+      double dm[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) dm[i] = pb.drift[i < n ? i : 0];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        const double xm = t * dm[i];
+        lw[i] = i < n ? cw[i] * (xm != 0.0 ? -expm1(-xm) / xm : 1.0) : 0.0;
+      }
+    }
     double best = 0.0, bh = 0.0;
     int kbest = -1, itbest = 0;
     double pbest[NMAX];
@@ -417,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
           double z = vn[i] + b[i];
           double s = z;
           if (l1) {                                                 // (3.4b), shrink1
-            double a = th * cw[i];
+            double a = th * (LC ? lw[i] : cw[i]);
             double m = fabs(z) - a;
             s = m > 0.0 ? (z >= 0.0 ? m : -m) : 0.0;
           }
@@ -465,7 +483,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
         if (r1 <= pb.tol && r2 <= pb.tol && r3 <= pb.tol) { conv = true; break; }
       }
       // phi_k = <x', d> - 1/2 sum a_i d_i^2 - t H(d)  (- 1/2 for an ellipsoid level set)
-      double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0;
+      double xd = 0.0, q = 0.0, h1 = 0.0, h2 = 0.0, hnow = 0.0;
       double av[NMAX <= kCoefRegs ? NMAX : 1];  // diagonal of A: all loads in flight together
       if constexpr (NMAX <= kCoefRegs) {
 #pragma unroll
@@ -479,7 +497,8 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
         if constexpr (NMAX <= kCoefRegs) ai = av[i];
         else ai = pb.adiag[i];
         q += ai * d[i] * d[i];
-        const double wi = cw[i];
+        const double wi = LC ? lw[i] : cw[i];
+        if constexpr (LC) hnow += cw[i] * exp(-t * pb.drift[i]) * fabs(d[i]);  // H(d, t)
         if constexpr (ROT) {  // <d, HA d> = sum_a sig_a (P^T d)_a^2
           double s = 0.0;
 #pragma unroll
@@ -494,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) diag_kernel(DiagProb pb) {
       const double H = wl2 ? sqrt(h1) : (l1 ? h1 : 0.0) + (l2 ? sqrt(h2) : 0.0);
       const double val = xd - 0.5 * q - t * H - (pb.level_set ? 0.5 : 0.0);
       if (kbest < 0 || val < best) {
-        best = val; bh = H; kbest = k; itbest = conv ? it : -2;
+        best = val; bh = LC ? hnow : H; kbest = k; itbest = conv ? it : -2;
         if constexpr (!ONE) {
 #pragma unroll
           for (int i = 0; i < NMAX; ++i) pbest[i] = d[i];
@@ -569,6 +588,8 @@ static hipError_t launch_n(const DiagProb& pb, bool ext, int* counter, int ncu, 
     const unsigned grid = (unsigned)std::min<int64_t>(need, (int64_t)8 * ncu);
     if (pb.hkind == HK_AL2)
       hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false, true>), dim3(grid), dim3(kBlock), 0, stream, pb);
+    else if (pb.hkind == HK_LINCTRL)
+      hipLaunchKernelGGL((diag_kernel<T, NMAX, false, false, false, true>), dim3(grid), dim3(kBlock), 0, stream, pb);
     else if (pb.hkind == HK_WL2)
       hipLaunchKernelGGL((diag_kernel<T, NMAX, true, false>), dim3(grid), dim3(kBlock), 0, stream, pb);
     else if (pb.K == 1 && pb.centres == nullptr)
@@ -599,6 +620,7 @@ hipError_t launch_diag(const DiagProb& pb, bool f64, int* counter, int ncu, hipS
   const bool ext = pb.jkind != JK_QUAD || pb.hkind == HK_LINF;
   if (ext && (!counter || pb.npts > INT32_MAX)) return hipErrorInvalidValue;
   if (pb.hkind == HK_AL2 && (!pb.P || ext)) return hipErrorInvalidValue;
+  if (pb.hkind == HK_LINCTRL && (!pb.drift || ext)) return hipErrorInvalidValue;
   return f64 ? launch_t<double>(pb, ext, counter, ncu, stream) : launch_t<float>(pb, ext, counter, ncu, stream);
 }
 

@@ -14,6 +14,7 @@ struct DiagProb {
   const double* w;        // n or null
   const double* centres;  // K*ld or null
   const double* P;        // HK_AL2: eigenvectors of HA (n x n, row-major, columns the vectors); else null
+  const double* drift;    // HK_LINCTRL: the n diagonal entries m_i of the drift matrix M; else null
   const void* x; const void* t;
   int64_t npts;
   void* phi; void* grad; void* dphidt; int32_t* iters; int32_t* kstar;

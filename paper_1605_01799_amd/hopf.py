@@ -51,14 +51,16 @@ def _device_array(a: torch.Tensor, dtype, name, shape):
 class Problem:
     """One problem: J(y) = 1/2 y^T A^{-1} y (or the min over K translated copies / ellipsoid
     level sets c_k + {u^T A^{-1} u <= 1}), H in {"wl1", "l2", "l2_wl1", "wl2", "al2"} with weights w
-    ("wl2": sqrt(<p, diag(w) p>); "al2": sqrt(<p, HA p>) with the SPD matrix HA; "linf": |p|_inf).
+    ("wl2": sqrt(<p, diag(w) p>); "al2": sqrt(<p, HA p>) with the SPD matrix HA; "linf": |p|_inf;
+    "linctrl": the time-dependent H of the linear control system dx/ds = diag(drift) x + diag(w) beta,
+    beta in [-1, 1]^n, whose points are the transformed states z = e^{-sM} x).
     jkind "quad" is J(y) = 1/2 y^T A^{-1} y; "l1sq" and "linfsq" are 1/2 |y|_1^2 and 1/2 |y|_inf^2
     (A unused: pass n=...)."""
 
     def __init__(self, A=None, *, n: Optional[int] = None, diagonal: bool = False, centres=None,
                  level_set: bool = False, hkind: str = "wl1", w=None, lam: float = 1.0,
                  tol: float = 1e-12, max_iter: int = 20000, precision: str = "bf16_refined",
-                 HA=None, jkind: str = "quad", stream=None, _handle=None):
+                 HA=None, jkind: str = "quad", drift=None, stream=None, _handle=None):
         self._lib = _lib.load()
         A64 = _host64(A)
         if n is None:
@@ -79,6 +81,7 @@ class Problem:
         self.hkind = hkind
         self.w = _host64(w, (self.n,)) if w is not None else None
         self.HA = _host64(HA, (self.n, self.n)) if HA is not None else None
+        self.drift = _host64(drift, (self.n,)) if drift is not None else None
         self.jkind = jkind
         self.lam, self.tol, self.max_iter = float(lam), float(tol), int(max_iter)
         self.precision = precision
@@ -98,7 +101,7 @@ class Problem:
             None if self.centres is None else self.centres.ctypes.data, int(self.level_set),
             _lib.HKIND[self.hkind], None if self.w is None else self.w.ctypes.data, self.lam, self.tol,
             self.max_iter, _lib.PRECISION[self.precision], None if self.HA is None else self.HA.ctypes.data,
-            _lib.JKIND[self.jkind])
+            _lib.JKIND[self.jkind], None if self.drift is None else self.drift.ctypes.data)
 
     @classmethod
     def batch(cls, specs: Sequence[dict], stream=None):

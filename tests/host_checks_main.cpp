@@ -90,6 +90,26 @@ int main() {
       d.precision = HOPF_F64; why[0] = 0;
       expect("sqrt(<p, HA p>), F64 beyond the per-thread path", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
     }
+    {  // the time-dependent H of linear controls: per-thread path only, needs the drift
+      std::vector<double> drift(40, 0.5), Ad(40, 1.5), A8(64, 0.0);
+      for (int i = 0; i < 8; ++i) A8[i * 8 + i] = 2.0;
+      d = base(8); d.hkind = HOPF_H_LINCTRL; d.drift = drift.data(); d.precision = HOPF_F64; why[0] = 0;
+      expect("linear controls, A = I, F64", check_desc(&d, why, sizeof why), HOPF_OK, why);
+      d.A = Ad.data(); d.A_is_diagonal = 1; d.precision = HOPF_F32; why[0] = 0;
+      expect("linear controls, diagonal A, F32", check_desc(&d, why, sizeof why), HOPF_OK, why);
+      d.precision = HOPF_BF16_REFINED; why[0] = 0;
+      expect("linear controls, refined", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+      d.precision = HOPF_F64; d.drift = nullptr; why[0] = 0;
+      expect("linear controls without the drift", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+      d.drift = drift.data(); drift[7] = NAN; why[0] = 0;
+      expect("linear controls, NaN drift (last entry)", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+      drift[7] = 0.5;
+      d.A = A8.data(); d.A_is_diagonal = 0; why[0] = 0;
+      expect("linear controls, dense A", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+      d = base(33); d.hkind = HOPF_H_LINCTRL; d.drift = drift.data(); d.A = Ad.data(); d.A_is_diagonal = 1;
+      why[0] = 0;
+      expect("linear controls, n = 33", check_desc(&d, why, sizeof why), HOPF_EINVAL, why);
+    }
     d = base(16); d.jkind = HOPF_J_L1SQ; d.hkind = HOPF_H_LINF; why[0] = 0;
     expect("1/2 |y|_1^2 with |p|_inf", check_desc(&d, why, sizeof why), HOPF_OK, why);
     d.precision = HOPF_BF16_REFINED; why[0] = 0;
@@ -129,6 +149,9 @@ int main() {
     why[0] = 0;
     expect("ragged: sqrt(<p, D p>) F32, n = 500",
            check_ragged_member(1, HOPF_F32, HOPF_F32, HOPF_H_WL2, HOPF_J_QUADRATIC, 500, why, sizeof why), HOPF_OK, why);
+    why[0] = 0;
+    expect("ragged: linear controls",
+           check_ragged_member(1, HOPF_F32, HOPF_F32, HOPF_H_LINCTRL, HOPF_J_QUADRATIC, 8, why, sizeof why), HOPF_EINVAL, why);
     why[0] = 0;
     expect("ragged: |p|_inf", check_ragged_member(2, HOPF_F32, HOPF_F32, HOPF_H_LINF, HOPF_J_QUADRATIC, 8, why, sizeof why),
            HOPF_EINVAL, why);
