@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c3",
-                    choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16"],
+                    choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16", "lc16"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
                          "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
                          "FP32 dense at 2^20 points, c4 = the ragged batch of 4096 problems (n log-uniform "
@@ -75,7 +75,9 @@ def parse():
                          "c2wl2 = c2 with H = sqrt(<p, diag(w) p>); pd16 = the paper's timing-table setting "
                          "for that H at n=16 (J = 1/2 <y, D^-1 y>, FP64, tol 1e-8); pa16 = the same for "
                          "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis); "
-                         "t5n16 = the paper's Table 5 workload, J = 1/2 |y|_1^2, H = |p|_inf, n=16, FP64, tol 1e-8")
+                         "t5n16 = the paper's Table 5 workload, J = 1/2 |y|_1^2, H = |p|_inf, n=16, FP64, tol 1e-8; "
+                         "lc16 = the time-dependent H of linear controls (diagonal drift and inputs, box controls), "
+                         "n=16, FP64, tol 1e-20")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
                          "scale of the FETCH_SIZE / WRITE_SIZE counters")
@@ -102,6 +104,8 @@ def main():
     if a.copy_calibrate:
         copy_calibrate()
         return
+    global SKIP_CPU
+    SKIP_CPU = a.no_cpu
     if a.workload != "c3":
         bench_other(a)
         return
@@ -258,6 +262,7 @@ def timed_steps(step, steps, warmup):
 
 # host threads per GPU on the shared GPU hosts: the baseline uses at most this many
 CPU_SHARE = 16
+SKIP_CPU = False  # --no-cpu: no CPU baseline (sweeps and profiled runs)
 
 
 def host_info():
@@ -287,6 +292,8 @@ def cpu_baseline(run, t, cap, what, budget_s=15.0, one_thread_pts=8):
     """The oracle's rate on the host: first one thread on a few stratified points, then all
     threads of the GPU's CPU share on a stratified sample sized to about budget_s seconds (at
     most cap points).  run(idx, nthreads) evaluates the oracle on the points idx."""
+    if SKIP_CPU:
+        return None
     info = host_info()
     threads = max(1, min(info["affinity"], CPU_SHARE))
     idx1 = stratified(t, min(one_thread_pts, len(t)))
@@ -406,6 +413,55 @@ def bench_other(a):
                                      "(squared norms <= 1e-8) itself leaves errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "one core of an i5-5300U (Table 4)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
+                   cpu_baseline=cpu)
+    elif a.workload == "lc16":
+        npts = a.npts if a.npts != 1 << 16 else 1 << 22
+        p = W.workload_linear_control(16, npts)
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        tol = a.tol if a.tol is not None else 1e-20
+        adiag = np.diag(p.A).copy()
+        prob = H.Problem(adiag, diagonal=True, hkind="linctrl", w=p.w, drift=p.drift, precision="f64", tol=tol,
+                         max_iter=20000)
+        out = dict(phi=torch.empty(npts, dtype=torch.float64, device=dev),
+                   grad=torch.empty(npts, p.n, dtype=torch.float64, device=dev),
+                   dphidt=torch.empty(npts, dtype=torch.float64, device=dev),
+                   iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+        ms, kms = timed_steps(step, a.steps, a.warmup)
+        it = out["iters"].cpu().numpy()
+        # per point-iteration: 3n (v), 4n (z and shrink), 2n (b), 6n (three norms) FP64 operations
+        flops = float(np.sum(np.abs(it)).astype(np.float64) * 15.0 * p.n)
+        achieved = flops / (kms / 1e3) / 1e12
+        rng = np.random.default_rng(9)
+        idx = np.sort(rng.choice(npts, size=min(a.acc_sample * 4, npts), replace=False))
+        ref = oracle.oracle_eval_linear_control(p.A, p.x[idx], p.t[idx], p.drift, p.w, tol=1e-26, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval_linear_control(p.A, p.x[idx], p.t[idx], p.drift, p.w,
+                                                                             tol=tol, nthreads=nt),
+                           p.t, 1 << 18, "same tol, FP64 oracle (one oracle call per point)", one_thread_pts=1 << 10)
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=16 FP64 diagonal path, time-dependent H of linear "
+                          "controls; % FP64 vector roofline",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="f64",
+                   config={"workload": "linear controls dx/ds = diag(m) x + diag(w) beta, beta in [-1,1]^16: "
+                                       "diagonal A ~U(0.5,3), m ~U(-1,2) (every fifth 0), w ~U(0.2,2), %d points "
+                                       "z~N(0,4I), t~U(0.05,3), FP64, tol %g" % (npts, tol), "npts": npts},
+                   roofline={"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": achieved / 78.6, "traffic": None,
+                             "kernel": "diag_kernel<double, 16, false, false, false, true>",
+                             "algorithmic": "sum over points of iterations x 15 n FP64 operations (the "
+                                            "per-point weights' exp and expm1 not counted: a lower bound)",
+                             "launch_ms": kms},
+                   iterations={"mean": float(np.abs(it).mean()), "capped": int(np.sum(it == -2))},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()), "bound": 1e-10},
                    cpu_baseline=cpu)
     elif a.workload == "t5n16":
         npts = a.npts if a.npts != 1 << 16 else 1 << 22

@@ -61,6 +61,7 @@ class Problem:
     A_is_diagonal: bool = False
     spectrum: Optional[np.ndarray] = None  # eigenvalues of A (for reference only)
     HA: Optional[np.ndarray] = None        # n x n SPD matrix of H for hkind "al2"
+    drift: Optional[np.ndarray] = None     # n drift diagonal for hkind "linctrl"
 
     @property
     def npts(self) -> int:
@@ -172,6 +173,21 @@ def workload_paper_norms(n: int = 16, npts: int = 1 << 20, hkind: str = "linf") 
     x = rng.uniform(-10.0, 10.0, (npts, n))
     t = 10.0 - rng.uniform(0.0, 10.0, npts)
     return Problem(n=n, A=np.eye(n), hkind=hkind, w=None, x=x, t=t, A_is_diagonal=True, spectrum=np.ones(n))
+
+
+def workload_linear_control(n: int = 16, npts: int = 1 << 20) -> Problem:
+    """Linear controls with a time-dependent Hamiltonian (section 2.2, extensions; no workload in
+    the paper): diagonal A with entries U(0.5, 3), drift diagonal U(-1, 2) with every fifth entry 0,
+    input weights U(0.2, 2), transformed states z ~ N(0, 4I), t ~ U(0.05, 3)."""
+    rng = rng_for(10, n)
+    a = rng.uniform(0.5, 3.0, n)
+    drift = rng.uniform(-1.0, 2.0, n)
+    drift[::5] = 0.0
+    w = rng.uniform(0.2, 2.0, n)
+    x = rng.normal(0.0, 2.0, (npts, n))
+    t = rng.uniform(0.05, 3.0, npts)
+    return Problem(n=n, A=np.diag(a), hkind="linctrl", w=w, x=x, t=t, A_is_diagonal=True, spectrum=a.copy(),
+                   drift=drift)
 
 
 def workload3(npts: int = 1 << 16) -> Problem:
