@@ -816,7 +816,9 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
       if (MODE == 1) gemm_bf16<RG, CT>(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
-      else gemm_f32<RG, CT>(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
+      // (one 16-column tile: the FP32 refined shape of the largest sizes, whose M streams from
+      // beyond L2, so six k-steps of fragments are kept in flight)
+      else gemm_f32<RG, CT, (MODE == 2 && CT == 1) ? 6 : 3>(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
 
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {

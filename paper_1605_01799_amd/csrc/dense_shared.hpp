@@ -98,9 +98,10 @@ __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pa
     if (kk + u < nk) step(kk + u, u);
 }
 
-template <int RG, int CT>
+template <int RG, int CT, int PF = 3>
 __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad, const float* B,
                                                 int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
+  // as gemm_bf16: PF k-steps of A fragments in flight, every k-step issuing its prefetch
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   // M is stored in fragment order (mf_index): row tile rt, k-step ks at (rt nks + ks) 64 + l
@@ -110,27 +111,38 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad,
   for (int r = 0; r < RG; ++r)
     arow[r] = gp((const f32x4*)M + (size_t)(r < nrt ? rt[r] : 0) * nks * 64 + l);
   const float* bcol = B + lr * ldb + 4 * lg;
-  f32x4 an[RG];
+  constexpr int NB = PF + 1;
+  f32x4 a[NB][RG];
 #pragma unroll
-  for (int r = 0; r < RG; ++r) an[r] = arow[r][0];
-  for (int k0 = 0; k0 < n_pad; k0 += 16) {
-    f32x4 a[RG], b[CT];
+  for (int u = 0; u < PF; ++u) {
+    const int kl = u < nks ? u : nks - 1;
 #pragma unroll
-    for (int r = 0; r < RG; ++r) a[r] = an[r];
-    if (k0 + 16 < n_pad) {
+    for (int r = 0; r < RG; ++r) a[u][r] = arow[r][64 * kl];
+  }
+  auto step = [&](int ks, int u) {  // u = ks mod NB, a compile-time constant at every call
+    const int kl = ks + PF < nks ? ks + PF : nks - 1;
 #pragma unroll
-      for (int r = 0; r < RG; ++r) an[r] = arow[r][64 * ((k0 + 16) >> 4)];
-    }
+    for (int r = 0; r < RG; ++r) a[(u + PF) % NB][r] = arow[r][64 * kl];
+    f32x4 b[CT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + k0);
+    for (int c = 0; c < CT; ++c) b[c] = *(const f32x4*)(bcol + 16 * c * ldb + 16 * ks);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int r = 0; r < RG; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][q], b[c][q], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][r][q], b[c][q], acc[r][c], 0, 0, 0);
+  };
+  const int nmain = nks - nks % NB;
+  int ks = 0;
+  for (; ks < nmain; ks += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) step(ks + u, u);
   }
+#pragma unroll
+  for (int u = 0; u < NB - 1; ++u)
+    if (ks + u < nks) step(ks + u, u);
 }
 
 // Rows (k) of the anchor right-hand sides per LDS block of the sliced products, and the block's
