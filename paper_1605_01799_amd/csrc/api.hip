@@ -513,7 +513,7 @@ struct DenseCall {
 // class has its own metadata (problem views, then chunks of whole points), staging and chunk
 // counter, so the classes are enqueued back to back without the host waiting between them.
 struct DenseClass {
-  int key = 0;              // kSmallClass, kRsClass or 100 pt + 10 occ + nw
+  int key = 0;              // kSmallClass, kRsClass or 10000 ks + 100 pt + 10 occ + nw
   DenseVariant var{};
   bool small = false, rs = false;
   int nchunks = 0, grid = 0, max_npad = 32;
@@ -549,7 +549,7 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
     if (use_small && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
     if (use_rs && dense_rs_fits(mode, p->n_pad, p->K, p->hkind, distance)) return kRsClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
-    return 100 * v.pt + 10 * v.occ + v.nw;
+    return 10000 * v.ks + 100 * v.pt + 10 * v.occ + v.nw;
   };
   P->total_pts = 0;
   for (auto& c : calls) P->total_pts += c.view.npts;
@@ -565,9 +565,9 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
     C.key = key;
     C.small = key == kSmallClass;
     C.rs = key == kRsClass;
-    C.var = C.small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4}
-          : C.rs    ? DenseVariant{dense_rs_cols(), 1, 4}
-                    : DenseVariant{key / 100, (key / 10) % 10, key % 10};
+    C.var = C.small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4, 1}
+          : C.rs    ? DenseVariant{dense_rs_cols(), 1, 4, 1}
+                    : DenseVariant{(key % 10000) / 100, (key / 10) % 10, key % 10, key / 10000};
     std::vector<std::pair<double, int>> order;  // (cost, view index)
     for (int i = 0; i < (int)calls.size(); ++i) {
       const DenseCall& c = calls[i];
@@ -595,7 +595,10 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
     C.nchunks = (int)C.chunks.size();
     // the small kernel: four independent waves per workgroup, each taking chunks
     C.grid = C.small ? std::min((C.nchunks + 3) / 4, C.var.occ * ncu) : std::min(C.nchunks, C.var.occ * ncu);
-    C.ws_per_wg = C.small ? 0 : C.rs ? dense_rs_ws_floats(C.max_npad) : 4 * (int64_t)C.var.pt * C.max_npad;
+    // the tile kernel's staging: z^a, dz, e^a, p (and the split contraction's partial products)
+    C.ws_per_wg = C.small ? 0
+                : C.rs    ? dense_rs_ws_floats(C.max_npad)
+                          : (C.var.ks == 2 ? 5 : 4) * (int64_t)C.var.pt * C.max_npad;
     // FP64 anchor staging, then its integer slices (kSlices x pt x pad64 bytes)
     C.ws64_per_wg = (int64_t)C.var.pt * C.max_npad + (int64_t)kSlices * C.var.pt * pad64(C.max_npad) / 8;
     if (C.rs)

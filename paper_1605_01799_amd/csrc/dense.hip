@@ -79,12 +79,13 @@ constexpr int kWl2AnchorNewton = 100; // cap on an anchor's FP64 Newton steps (f
 // tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
 // OCC workgroups per CU.  With two waves per SIMD (NW = 8, or OCC = 2) each wave keeps at most
 // 256 registers per lane, and one wave's products overlap another's epilogue.
-template <int MODE, int CT, int RG, int OCC, int NW>
+template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1>
 __global__ void __launch_bounds__(NW * 64, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
              int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every, int anchor_wait) {
   constexpr int PT = 16 * CT;
+  static_assert(KS == 1 || MODE == 2, "the split contraction is for the FP32 refined mode");
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ ColShared<PT, NW> S;
   __shared__ double red3[NW][PT];  // third partial of the multiplier sums (sqrt(<p, D p>))
@@ -124,6 +125,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     float* const dz = wsb + (int64_t)PT * n_pad;
     float* const ea = wsb + 2 * (int64_t)PT * n_pad;
     float* const pout = wsb + 3 * (int64_t)PT * n_pad;
+    float* const vpart = wsb + 4 * (int64_t)PT * n_pad;  // KS = 2: the first half's partial products
     const int nq = n_pad >> 2;
     const int RT = n_pad >> 4;
 
@@ -726,9 +728,12 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     // ================================================================ prologue: right-hand sides
     // Block order: wave w takes the row tiles w, w+4, ... of every column tile; lane l works on
     // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
-    {
-      const int ldb = MODE == 1 ? n_pad + 8 : n_pad + 4;  // BF16 (MODE 1) or FP32 right-hand sides
+    // With KS = 2 the right-hand sides of one half of the rows at a time: rows of row tiles
+    // [rt_lo, rt_hi) at LDS rows from 16 rt_lo.
+    const int ldb = MODE == 1 ? n_pad + 8 : n_pad / KS + 4;  // BF16 (MODE 1) or FP32 right-hand sides
+    auto prologue = [&](int rt_lo, int rt_hi) {
       constexpr int PB = (OCC == 2 || NW == 8) ? 2 : 4;  // row tiles whose loads are in flight together
+      const int kbase = 16 * rt_lo;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = 16 * ct + (l & 15);
@@ -741,12 +746,12 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
         const bool ains = S.flags[c] & FLAG_INSIDE, cin = S.flags[c] & FLAG_CIN;
         // batches of PB row tiles: all their state loads are in flight before any is used
         const float* sv_src = deltac ? dz : ea;  // increment (delta phase) or x' (plain)
-        for (int rtb = wave; rtb < RT; rtb += NW * PB) {
+        for (int rtb = rt_lo + wave; rtb < rt_hi; rtb += NW * PB) {
           f32x4 zv[PB], sv[PB], wv[PB];
 #pragma unroll
           for (int u = 0; u < PB; ++u) {
             const int rt = rtb + NW * u;
-            const int rtc = rt < RT ? rt : 0;  // in-bounds address; result not stored
+            const int rtc = rt < rt_hi ? rt : rt_lo;  // in-bounds address; result not stored
             const size_t et = st_block(rtc, ct, RT) + 4 * l;
             if (on) {
               zv[u] = ld_nt4(za + et);
@@ -759,7 +764,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
           for (int u = 0; u < PB; ++u) {
             const int rt = rtb + NW * u;
-            if (rt >= RT) continue;  // wave-uniform
+            if (rt >= rt_hi) continue;  // wave-uniform
             const int row0 = 16 * rt + 4 * (l >> 4);
             f32x4 rv = {0.f, 0.f, 0.f, 0.f};
             if (on) {
@@ -791,12 +796,13 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
               for (int q = 0; q < 4; ++q) o[q] = to_bf16(rv[q]);
               *(bf16x4*)((__bf16*)lds_raw + c * ldb + row0) = o;
             } else {
-              *(f32x4*)((float*)lds_raw + c * ldb + row0) = rv;
+              *(f32x4*)((float*)lds_raw + c * ldb + row0 - kbase) = rv;
             }
           }
         }
       }
-    }
+    };
+    prologue(0, RT / KS);
     __syncthreads();
 
     // ================================================================ GEMM + epilogue
@@ -805,6 +811,34 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     for (int c = 0; c < CT; ++c) { part[c][0] = 0.f; part[c][1] = 0.f; }
     // the column scalars of this lane's slots (columns 16 ct + l % 16) are read from LDS where
     // they are used: registers are kept for the products
+    // (one 16-column tile: the FP32 refined shape of the largest sizes, whose M streams from
+    // beyond L2, so six k-steps of fragments are kept in flight)
+    constexpr int PFF = (MODE == 2 && CT == 1) ? 6 : 3;
+    const int nks = n_pad >> 4;  // k-steps of the FP32 products
+    if (KS == 2) {
+      // the contraction over the first half of the rows for every row group, its partial products
+      // to the staging (in the state's block layout), then the right-hand sides of the second half
+      for (int rt0 = 0; rt0 < RT; rt0 += NW * RG) {
+        int rt[RG]; int nrt = 0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) { rt[r] = rt0 + wave + NW * r; if (rt[r] < RT) nrt = r + 1; }
+        f32x4 acc[RG][CT];
+#pragma unroll
+        for (int r = 0; r < RG; ++r)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        gemm_f32<RG, CT, PFF>(pb.Mf, n_pad, (const float*)lds_raw, ldb, rt, nrt, acc, 0, nks / 2);
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          if (r >= nrt) continue;
+#pragma unroll
+          for (int c = 0; c < CT; ++c) st_nt4(vpart + st_block(rt[r], c, RT) + 4 * l, acc[r][c]);
+        }
+      }
+      __syncthreads();
+      prologue(RT / 2, RT);
+      __syncthreads();
+    }
 
     for (int rt0 = 0; rt0 < RT; rt0 += NW * RG) {
       int rt[RG]; int nrt = 0;
@@ -814,11 +848,11 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
       for (int r = 0; r < RG; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < CT; ++c)
+          acc[r][c] = (KS == 2 && r < nrt) ? ld_nt4(vpart + st_block(rt[r], c, RT) + 4 * l) : f32x4{0.f, 0.f, 0.f, 0.f};
       if (MODE == 1) gemm_bf16<RG, CT>(pb.Mb, n_pad, (const __bf16*)lds_raw, n_pad + 8, rt, nrt, acc);
-      // (one 16-column tile: the FP32 refined shape of the largest sizes, whose M streams from
-      // beyond L2, so six k-steps of fragments are kept in flight)
-      else gemm_f32<RG, CT, (MODE == 2 && CT == 1) ? 6 : 3>(pb.Mf, n_pad, (const float*)lds_raw, n_pad + 4, rt, nrt, acc);
+      else gemm_f32<RG, CT, PFF>(pb.Mf, n_pad, (const float*)lds_raw, ldb, rt, nrt, acc, KS == 2 ? nks / 2 : 0,
+                                 nks / KS);
 
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -1089,33 +1123,43 @@ static const TunedShape kTuned[] = {
 #include "tune_table.inc"
 };
 
-DenseVariant dense_variant(int mode, int n_pad) {
+// the largest dynamic LDS of the FP32 right-hand sides before the contraction is split in two
+constexpr size_t kSplitLds = 136 * 1024;
+
+static DenseVariant shape_of(int mode, int n_pad) {
   // HOPF_DENSE_VARIANT=pt:occ:nw forces a shape (the autotuner's sweeps), else the tuned table,
   // else the rules below
   if (const char* v = getenv("HOPF_DENSE_VARIANT")) {
-    DenseVariant f{0, 0, 0};
+    DenseVariant f{0, 0, 0, 1};
     if (sscanf(v, "%d:%d:%d", &f.pt, &f.occ, &f.nw) == 3 && f.pt > 0) return f;
   }
   for (const TunedShape& t : kTuned)
-    if (t.mode == mode && n_pad <= t.npad_max) return DenseVariant{t.pt, t.occ, t.nw};
+    if (t.mode == mode && n_pad <= t.npad_max) return DenseVariant{t.pt, t.occ, t.nw, 1};
   // refined mode up to n_pad = 1024: two 32-column workgroups of 4 waves per CU; FP32 modes
   // (plain and refined) by size
   if (mode == 1) {
-    if (n_pad > 1024) return DenseVariant{32, 1, 4};
-    return DenseVariant{32, 2, 4};
+    if (n_pad > 1024) return DenseVariant{32, 1, 4, 1};
+    return DenseVariant{32, 2, 4, 1};
   }
-  if (n_pad <= 512) return DenseVariant{64, 1, 4};
-  if (n_pad <= 1024) return DenseVariant{32, 1, 4};
-  return DenseVariant{16, 1, 4};
+  if (n_pad <= 512) return DenseVariant{64, 1, 4, 1};
+  if (n_pad <= 1024) return DenseVariant{32, 1, 4, 1};
+  return DenseVariant{16, 1, 4, 1};
+}
+
+DenseVariant dense_variant(int mode, int n_pad) {
+  DenseVariant v = shape_of(mode, n_pad);
+  v.ks = (mode == 2 && (size_t)v.pt * (n_pad + 4) * 4 > kSplitLds) ? 2 : 1;
+  return v;
 }
 
 size_t dense_lds_bytes(int mode, int n_pad) {
-  const int pt = dense_variant(mode, n_pad).pt;
+  const DenseVariant v = dense_variant(mode, n_pad);
+  const int pt = v.pt;
   // refined: the BF16 (FP32) right-hand sides, or a block of the anchor right-hand sides' slices
   if (mode == 1)
     return std::max((size_t)pt * (n_pad + 8) * 2, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
   if (mode == 2)
-    return std::max((size_t)pt * (n_pad + 4) * 4, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
+    return std::max((size_t)pt * (n_pad / v.ks + 4) * 4, (size_t)kSlices * pt * (anchor_kbq(n_pad) + 16));
   return (size_t)pt * (n_pad + 4) * 4;
 }
 
@@ -1132,11 +1176,11 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
   return hipGetLastError();
 }
 
-template <int MODE, int CT, int RG, int OCC, int NW>
+template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
                            int distance, int anchor_every, int anchor_wait, hipStream_t stream) {
-  auto kern = dense_kernel<MODE, CT, RG, OCC, NW>;
+  auto kern = dense_kernel<MODE, CT, RG, OCC, NW, KS>;
   static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1163,6 +1207,16 @@ hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, co
 #define HOPF_LAUNCH(M, C, R, O, W)                                                                                  \
   return launch_t<M, C, R, O, W>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
                                  distance, anchor_every, anchor_wait, stream)
+  if (mode == 2 && var.ks == 2) {  // the split contraction
+    if (ct == 4)
+      return launch_t<2, 4, 4, 1, 4, 2>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
+                                        lds, distance, anchor_every, anchor_wait, stream);
+    if (ct == 2)
+      return launch_t<2, 2, 4, 1, 4, 2>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
+                                        lds, distance, anchor_every, anchor_wait, stream);
+    return hipErrorInvalidValue;
+  }
+  if (var.ks != 1) return hipErrorInvalidValue;
   if (mode == 1) {
     if (nw == 8 && ct == 4) HOPF_LAUNCH(1, 4, 2, 1, 8);
     if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4);

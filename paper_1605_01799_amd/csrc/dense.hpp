@@ -3,11 +3,13 @@
 
 namespace hopf {
 
-// mode 0: FP32 products; mode 1: BF16 increments refined by exact (integer-sliced) anchor products.
-// The launch shape for a mode and padded size: columns per tile, workgroups per CU, waves per
-// workgroup.
+// mode 0: FP32 products; mode 1: BF16 increments refined by exact (integer-sliced) anchor products;
+// mode 2: FP32 increments on such anchors.  The launch shape for a mode and padded size: columns
+// per tile, workgroups per CU, waves per workgroup, and ks = 2 where the FP32 right-hand sides of
+// the tile do not fit LDS whole (mode 2): the contraction then runs over one half of the rows at a
+// time, the first half's partial products going through the staging.
 struct DenseVariant {
-  int pt, occ, nw;
+  int pt, occ, nw, ks;
 };
 DenseVariant dense_variant(int mode, int n_pad);
 size_t dense_lds_bytes(int mode, int n_pad);

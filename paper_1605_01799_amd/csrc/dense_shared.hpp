@@ -98,18 +98,22 @@ __device__ __forceinline__ void gemm_bf16(const __bf16* __restrict__ M, int n_pa
     if (kk + u < nk) step(kk + u, u);
 }
 
+// FP32: the contraction over the nks k-steps of 16 from k-step ks0 (all of them by default), B
+// holding those rows from its row 0.
 template <int RG, int CT, int PF = 3>
 __device__ __forceinline__ void gemm_f32(const float* __restrict__ M, int n_pad, const float* B,
-                                                int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT]) {
+                                                int ldb, const int* rt, int nrt, f32x4 (&acc)[RG][CT],
+                                                int ks0 = 0, int nks = -1) {
   // as gemm_bf16: PF k-steps of A fragments in flight, every k-step issuing its prefetch
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
-  // M is stored in fragment order (mf_index): row tile rt, k-step ks at (rt nks + ks) 64 + l
-  const int nks = n_pad >> 4;
+  // M is stored in fragment order (mf_index): row tile rt, k-step ks at (rt nks_all + ks) 64 + l
+  const int nks_all = n_pad >> 4;
+  if (nks < 0) nks = nks_all;
   const HOPF_GLOBAL f32x4* arow[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
-    arow[r] = gp((const f32x4*)M + (size_t)(r < nrt ? rt[r] : 0) * nks * 64 + l);
+    arow[r] = gp((const f32x4*)M + ((size_t)(r < nrt ? rt[r] : 0) * nks_all + ks0) * 64 + l);
   const float* bcol = B + lr * ldb + 4 * lg;
   constexpr int NB = PF + 1;
   f32x4 a[NB][RG];
