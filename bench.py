@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="c3",
-                    choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16", "lc16"],
+                    choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16", "lc16", "c3wl2"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
                          "each: c1s = n=8 FP64 diagonal path at 2^24 points (HBM roofline), c2 = n=64 "
                          "FP32 dense at 2^20 points, c4 = the ragged batch of 4096 problems (n log-uniform "
@@ -77,7 +77,8 @@ def parse():
                          "H = sqrt(<p, HA p>), HA = I + 1 1^T (FP32, the wave-local kernel in HA's eigenbasis); "
                          "t5n16 = the paper's Table 5 workload, J = 1/2 |y|_1^2, H = |p|_inf, n=16, FP64, tol 1e-8; "
                          "lc16 = the time-dependent H of linear controls (diagonal drift and inputs, box controls), "
-                         "n=16, FP64, tol 1e-20")
+                         "n=16, FP64, tol 1e-20; c3wl2 = the n=1024 workload with H = sqrt(<p, diag(w) p>) (the "
+                         "tile kernel's multiplier solves), BF16 refined")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run a plain device copy of 256 MiB (x5): the reference kernel for the "
                          "scale of the FETCH_SIZE / WRITE_SIZE counters")
@@ -413,6 +414,56 @@ def bench_other(a):
                                      "(squared norms <= 1e-8) itself leaves errors of this size"},
                    paper={"seconds_per_eval": paper_s, "hardware": "one core of an i5-5300U (Table 4)",
                           "note": "vs_baseline = value / (1 / seconds_per_eval): another machine, context only"},
+                   cpu_baseline=cpu)
+    elif a.workload == "c3wl2":
+        npts = a.npts
+        p = W.round_inputs(W.workload3_wl2(npts))
+        x = torch.from_numpy(p.x).to(dev)
+        t = torch.from_numpy(p.t).to(dev)
+        tol = a.tol if a.tol is not None else 1e-12
+        prob = H.Problem(p.A, hkind="wl2", w=p.w, precision="bf16_refined", tol=tol, max_iter=20000)
+        out = dict(phi=torch.empty(npts, device=dev), grad=torch.empty(npts, p.n, device=dev),
+                   dphidt=torch.empty(npts, device=dev), iters=torch.empty(npts, dtype=torch.int32, device=dev),
+                   kstar=torch.empty(npts, dtype=torch.int32, device=dev))
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(stream)
+            prob.eval(x, t, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+        for _ in range(a.warmup):
+            step(None)
+        torch.cuda.synchronize()
+        prob.iterations(reset=True)
+        ms, kms = timed_steps(step, a.steps, 0)
+        passes = prob.iterations(reset=True) / a.steps   # counted on the device
+        flops = float(passes) * 2.0 * p.n * p.n
+        achieved = flops / (kms / 1e3) / 1e12
+        it = out["iters"].cpu().numpy()
+        idx = stratified(p.t, min(a.acc_sample, npts))
+        ref = oracle.oracle_eval(p.A, p.x[idx].astype(np.float64), p.t[idx].astype(np.float64), "wl2", w=p.w,
+                                 tol=1e-26, nthreads=threads)
+        g = out["grad"].cpu().numpy()[idx]
+        ep = np.linalg.norm(g - ref["grad"], axis=1) / np.maximum(np.linalg.norm(ref["grad"], axis=1), 1)
+        ef = np.abs(out["phi"].cpu().numpy()[idx] - ref["phi"]) / np.maximum(np.abs(ref["phi"]), 1)
+        cpu = cpu_baseline(lambda idx, nt: oracle.oracle_eval(p.A, p.x[idx].astype(np.float64),
+                                                              p.t[idx].astype(np.float64), "wl2", w=p.w, tol=tol,
+                                                              nthreads=nt),
+                           p.t, 4096, "same tol, FP64 oracle")
+        rec.update(metric="Hopf point-evals/sec (φ+∇φ), n=1024 dense, H=sqrt(<p,Dp>), BF16 refined; % BF16 MFMA "
+                          "roofline",
+                   value=npts / (ms / 1e3), steps=a.steps, warmup=a.warmup, ms_per_step=ms, dtype="bf16",
+                   config={"workload": "n=1024 dense SPD A (workload 3's), H=sqrt(<p, diag(w) p>), %d points "
+                                       "x~N(0,4I), t~U(0.05,3), FP32 inputs, tol %g" % (npts, tol), "npts": npts},
+                   roofline={"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                             "kernel": "dense_kernel<1, 2, 2, 2, 4> (tile kernel; multiplier phase per pass)",
+                             "algorithmic": "passes counted on the device x 2 n^2 FLOP (the multiplier's Newton "
+                                            "sweeps not counted)", "launch_ms": kms},
+                   iterations={"mean": float(np.abs(it).mean()), "passes_per_point": float(passes) / npts},
+                   accuracy={"sample": int(len(idx)), "max_rel_err_grad": float(ep.max()),
+                             "max_rel_err_phi": float(ef.max()), "bound": 1e-6},
                    cpu_baseline=cpu)
     elif a.workload == "lc16":
         npts = a.npts if a.npts != 1 << 16 else 1 << 22

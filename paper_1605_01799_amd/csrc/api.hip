@@ -513,7 +513,7 @@ struct DenseCall {
 // class has its own metadata (problem views, then chunks of whole points), staging and chunk
 // counter, so the classes are enqueued back to back without the host waiting between them.
 struct DenseClass {
-  int key = 0;              // kSmallClass, kRsClass or 10000 ks + 100 pt + 10 occ + nw
+  int key = 0;              // kSmallClass, kRsClass or 100000 wl + 10000 ks + 100 pt + 10 occ + nw
   DenseVariant var{};
   bool small = false, rs = false;
   int nchunks = 0, grid = 0, max_npad = 32;
@@ -549,7 +549,9 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
     if (use_small && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
     if (use_rs && dense_rs_fits(mode, p->n_pad, p->K, p->hkind, distance)) return kRsClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
-    return 10000 * v.ks + 100 * v.pt + 10 * v.occ + v.nw;
+    // sqrt(<p, D p>) (also HA's, solved in its eigenbasis) needs the tile kernel's multiplier phase
+    const int wl = (p->hkind == HOPF_H_WL2 || p->hkind == HOPF_H_AL2) && !distance ? 1 : 0;
+    return 100000 * wl + 10000 * v.ks + 100 * v.pt + 10 * v.occ + v.nw;
   };
   P->total_pts = 0;
   for (auto& c : calls) P->total_pts += c.view.npts;
@@ -567,7 +569,7 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
     C.rs = key == kRsClass;
     C.var = C.small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4, 1}
           : C.rs    ? DenseVariant{dense_rs_cols(), 1, 4, 1}
-                    : DenseVariant{(key % 10000) / 100, (key / 10) % 10, key % 10, key / 10000};
+                    : DenseVariant{(key % 10000) / 100, (key / 10) % 10, key % 10, (key / 10000) % 10, key / 100000};
     std::vector<std::pair<double, int>> order;  // (cost, view index)
     for (int i = 0; i < (int)calls.size(); ++i) {
       const DenseCall& c = calls[i];

@@ -79,7 +79,8 @@ constexpr int kWl2AnchorNewton = 100; // cap on an anchor's FP64 Newton steps (f
 // tiles per wave and product pass, NW waves per workgroup (the waves split the row tiles),
 // OCC workgroups per CU.  With two waves per SIMD (NW = 8, or OCC = 2) each wave keeps at most
 // 256 registers per lane, and one wave's products overlap another's epilogue.
-template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1>
+// WL: every problem of the launch is H = sqrt(<p, D p>) (its multiplier phase compiled in).
+template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1, bool WL = false>
 __global__ void __launch_bounds__(NW * 64, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
@@ -120,7 +121,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     const float flam = (float)lam;
     const bool has_l1 = !distance && hk_has_l1(pb.hkind);
     const bool has_l2 = distance || hk_has_l2(pb.hkind);
-    const bool wl2 = !distance && pb.hkind == HK_WL2;  // sqrt(<p, D p>) (HA's, in its eigenbasis)
+    const bool wl2 = WL && !distance;  // sqrt(<p, D p>) (HA's, in its eigenbasis)
     float* const za = wsb;
     float* const dz = wsb + (int64_t)PT * n_pad;
     float* const ea = wsb + 2 * (int64_t)PT * n_pad;
@@ -1176,11 +1177,11 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
   return hipGetLastError();
 }
 
-template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1>
+template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1, bool WL = false>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
                            int distance, int anchor_every, int anchor_wait, hipStream_t stream) {
-  auto kern = dense_kernel<MODE, CT, RG, OCC, NW, KS>;
+  auto kern = dense_kernel<MODE, CT, RG, OCC, NW, KS, WL>;
   static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1199,40 +1200,49 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
   return hipGetLastError();
 }
 
-hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
-                        int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
-                        hipStream_t stream) {
+template <bool WL>
+static hipError_t launch_shape(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                               int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg,
+                               int64_t ws64_per_wg, int grid, size_t lds, int distance, int anchor_every,
+                               int anchor_wait, hipStream_t stream) {
   const int ct = var.pt / 16, occ = var.occ, nw = var.nw;
-#define HOPF_LAUNCH(M, C, R, O, W)                                                                                  \
-  return launch_t<M, C, R, O, W>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid, lds, \
-                                 distance, anchor_every, anchor_wait, stream)
+#define HOPF_LAUNCH(M, C, R, O, W, K)                                                                            \
+  return launch_t<M, C, R, O, W, K, WL>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, \
+                                        grid, lds, distance, anchor_every, anchor_wait, stream)
   if (mode == 2 && var.ks == 2) {  // the split contraction
-    if (ct == 4)
-      return launch_t<2, 4, 4, 1, 4, 2>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
-                                        lds, distance, anchor_every, anchor_wait, stream);
-    if (ct == 2)
-      return launch_t<2, 2, 4, 1, 4, 2>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
-                                        lds, distance, anchor_every, anchor_wait, stream);
+    if (ct == 4) HOPF_LAUNCH(2, 4, 4, 1, 4, 2);
+    if (ct == 2) HOPF_LAUNCH(2, 2, 4, 1, 4, 2);
     return hipErrorInvalidValue;
   }
   if (var.ks != 1) return hipErrorInvalidValue;
   if (mode == 1) {
-    if (nw == 8 && ct == 4) HOPF_LAUNCH(1, 4, 2, 1, 8);
-    if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4);
-    if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1, 4);
-    if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1, 4);
+    if (nw == 8 && ct == 4) HOPF_LAUNCH(1, 4, 2, 1, 8, 1);
+    if (occ == 2 && ct == 2) HOPF_LAUNCH(1, 2, 2, 2, 4, 1);
+    if (occ == 1 && ct == 4) HOPF_LAUNCH(1, 4, 4, 1, 4, 1);
+    if (occ == 1 && ct == 2) HOPF_LAUNCH(1, 2, 4, 1, 4, 1);
   } else if (mode == 2) {
-    if (ct == 4) HOPF_LAUNCH(2, 4, 4, 1, 4);
-    if (ct == 2) HOPF_LAUNCH(2, 2, 4, 1, 4);
-    if (ct == 1) HOPF_LAUNCH(2, 1, 4, 1, 4);
+    if (ct == 4) HOPF_LAUNCH(2, 4, 4, 1, 4, 1);
+    if (ct == 2) HOPF_LAUNCH(2, 2, 4, 1, 4, 1);
+    if (ct == 1) HOPF_LAUNCH(2, 1, 4, 1, 4, 1);
   } else {
-    if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1, 4);
-    if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1, 4);
-    if (ct == 1) HOPF_LAUNCH(0, 1, 4, 1, 4);
+    if (ct == 4) HOPF_LAUNCH(0, 4, 4, 1, 4, 1);
+    if (ct == 2) HOPF_LAUNCH(0, 2, 4, 1, 4, 1);
+    if (ct == 1) HOPF_LAUNCH(0, 1, 4, 1, 4, 1);
   }
 #undef HOPF_LAUNCH
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                        int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
+                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
+                        hipStream_t stream) {
+  // sqrt(<p, D p>) problems run in instances with their multiplier phase, the others without it
+  if (var.wl && !distance)
+    return launch_shape<true>(mode, var, d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
+                              lds, distance, anchor_every, anchor_wait, stream);
+  return launch_shape<false>(mode, var, d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
+                             lds, distance, anchor_every, anchor_wait, stream);
 }
 
 }  // namespace hopf

@@ -8,8 +8,11 @@ namespace hopf {
 // per tile, workgroups per CU, waves per workgroup, and ks = 2 where the FP32 right-hand sides of
 // the tile do not fit LDS whole (mode 2): the contraction then runs over one half of the rows at a
 // time, the first half's partial products going through the staging.
+// wl: the launch holds sqrt(<p, D p>) problems (their prox runs the multiplier phase; the other
+// kinds are compiled without it).
 struct DenseVariant {
   int pt, occ, nw, ks;
+  int wl = 0;
 };
 DenseVariant dense_variant(int mode, int n_pad);
 size_t dense_lds_bytes(int mode, int n_pad);

@@ -194,6 +194,11 @@ def workload3(npts: int = 1 << 16) -> Problem:
     return _dense_problem(3, 1024, 1 << 16, npts, "l2_wl1")
 
 
+def workload3_wl2(npts: int = 1 << 16) -> Problem:
+    """Workload 3 with H = sqrt(<p, diag(w) p>) (the same A, weights and points)."""
+    return _dense_problem(3, 1024, 1 << 16, npts, "wl2")
+
+
 def workload5(npts: int = 1 << 18) -> Problem:
     rng = rng_for(5)
     n, K = 256, 4
