@@ -513,7 +513,7 @@ struct DenseCall {
 // class has its own metadata (problem views, then chunks of whole points), staging and chunk
 // counter, so the classes are enqueued back to back without the host waiting between them.
 struct DenseClass {
-  int key = 0;              // kSmallClass, kRsClass or 100000 wl + 10000 ks + 100 pt + 10 occ + nw
+  int key = 0;              // kSmallClass + kind of H, kRsClass or 100000 wl + 10000 ks + 100 pt + 10 occ + nw
   DenseVariant var{};
   bool small = false, rs = false;
   int nchunks = 0, grid = 0, max_npad = 32;
@@ -546,7 +546,7 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
   const bool use_small = env_int("HOPF_SMALL", 1) != 0;
   static const bool use_rs = env_int("HOPF_RS", 1) != 0;
   auto class_of = [&](const hopf_problem* p) -> int {
-    if (use_small && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass;
+    if (use_small && dense_small_fits(mode, p->n_pad, distance)) return kSmallClass + dense_small_kind(p->hkind);
     if (use_rs && dense_rs_fits(mode, p->n_pad, p->K, p->hkind, distance)) return kRsClass;
     const DenseVariant v = dense_variant(mode, p->n_pad);
     // sqrt(<p, D p>) (also HA's, solved in its eigenbasis) needs the tile kernel's multiplier phase
@@ -565,7 +565,7 @@ static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distan
   for (int key : keys) {
     DenseClass C;
     C.key = key;
-    C.small = key == kSmallClass;
+    C.small = key >= kSmallClass && key < kSmallClass + 3;  // + the kind of H
     C.rs = key == kRsClass;
     C.var = C.small ? DenseVariant{dense_small_cols(), dense_small_occupancy(), 4, 1}
           : C.rs    ? DenseVariant{dense_rs_cols(), 1, 4, 1}
@@ -654,7 +654,7 @@ static hopf_status plan_launch(const DensePlan& P, const std::vector<DenseCall>&
     float* ws = state + C.state_off;
     double* ws64 = state64 + C.state64_off;
     hipError_t e =
-        C.small ? launch_dense_small(C.max_npad, P.mode == 2, dv, dc, C.nchunks, counter, C.grid,
+        C.small ? launch_dense_small(C.max_npad, P.mode == 2, C.key - kSmallClass, dv, dc, C.nchunks, counter, C.grid,
                                      P.small_anchor_every, P.small_anchor_wait, stream)
         : C.rs  ? launch_dense_rs(C.max_npad, dv, dc, C.nchunks, counter, ws64, C.ws64_per_wg, ws, C.ws_per_wg, C.grid,
                                   C.lds, P.rs_anchor_every, P.anchor_wait, stream)

@@ -28,7 +28,9 @@ hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, co
 bool dense_small_fits(int mode, int n_pad, int distance);
 int dense_small_cols();       // columns per wave
 int dense_small_occupancy();  // workgroups per CU
-hipError_t launch_dense_small(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
+// kind: dense_small_kind(hkind) of every problem of the launch (one instance per kind of H)
+int dense_small_kind(int hkind);
+hipError_t launch_dense_small(int n_pad, bool refined, int kind, const DenseProb* d_probs, const DenseChunk* d_chunks,
                               int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
                               hipStream_t stream);
 

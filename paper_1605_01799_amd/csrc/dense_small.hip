@@ -77,7 +77,9 @@ constexpr float kWl2Rel = 2.5e-7f;       // a step below this fraction of mu end
 
 // RTM row tiles (n_pad <= 16 RTM), CT column tiles per wave, OCC workgroups per CU, REF the
 // refined FP32 iteration (above).
-template <int RTM, int CT, int OCC, bool REF>
+// KS: the kinds of H of the launch's problems (0: weighted l1; 1: l2, l2 + weighted l1; 2:
+// sqrt(<p, D p>)); only that pass is compiled in, so the simpler kinds keep their registers.
+template <int RTM, int CT, int OCC, bool REF, int KS>
 __global__ void __launch_bounds__(kBlock, OCC)
 dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
                    int* __restrict__ chunk_counter, int anchor_every, int anchor_wait) {
@@ -1069,16 +1071,9 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         }
       }
     };
-    if constexpr (REF) {
-      if (hkind == HK_WL2) pass_ref(std::integral_constant<int, 2>{});
-      else if (has_l2) pass_ref(std::integral_constant<int, 1>{});
-      else pass_ref(std::integral_constant<int, 0>{});
-    } else if (hkind == HK_WL2) {
-      pass(std::integral_constant<int, 2>{});
-    } else {
-      if (has_l2) pass(std::integral_constant<int, 1>{});
-      else pass(std::integral_constant<int, 0>{});
-    }
+    (void)hkind;
+    if constexpr (REF) pass_ref(std::integral_constant<int, KS>{});
+    else pass(std::integral_constant<int, KS>{});
   }
 }
 
@@ -1087,20 +1082,30 @@ bool dense_small_fits(int mode, int n_pad, int distance) { return mode != 1 && !
 int dense_small_cols() { return 16 * SMALL_CT; }
 int dense_small_occupancy() { return SMALL_OCC; }
 
-hipError_t launch_dense_small(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
+int dense_small_kind(int hkind) { return hkind == HK_WL2 || hkind == HK_AL2 ? 2 : (hk_has_l2(hkind) ? 1 : 0); }
+
+template <int KS>
+static void launch_small_kind(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
                               int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
                               hipStream_t stream) {
-#define HOPF_SMALL(R, F)                                                                                    \
-  hipLaunchKernelGGL((dense_small_kernel<R, SMALL_CT, SMALL_OCC, F>), dim3(grid), dim3(kBlock), 0, stream, \
+#define HOPF_SMALL(R, F)                                                                                        \
+  hipLaunchKernelGGL((dense_small_kernel<R, SMALL_CT, SMALL_OCC, F, KS>), dim3(grid), dim3(kBlock), 0, stream, \
                      d_probs, d_chunks, nchunks, counter, anchor_every, anchor_wait)
   if (n_pad <= 32) {
     if (refined) HOPF_SMALL(2, true); else HOPF_SMALL(2, false);
-  } else if (n_pad <= 64) {
-    if (refined) HOPF_SMALL(4, true); else HOPF_SMALL(4, false);
   } else {
-    return hipErrorInvalidValue;
+    if (refined) HOPF_SMALL(4, true); else HOPF_SMALL(4, false);
   }
 #undef HOPF_SMALL
+}
+
+hipError_t launch_dense_small(int n_pad, bool refined, int kind, const DenseProb* d_probs, const DenseChunk* d_chunks,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              hipStream_t stream) {
+  if (n_pad > 64 || kind < 0 || kind > 2) return hipErrorInvalidValue;
+  if (kind == 0) launch_small_kind<0>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
+  else if (kind == 1) launch_small_kind<1>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
+  else launch_small_kind<2>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
   return hipGetLastError();
 }
 
