@@ -738,9 +738,10 @@ def bench_other(a):
     elif a.workload == "c4":
         # workload 4: 4096 problems, each its own n (log-uniform in [4, 2048]), A, w, t and point
         # count (log-uniform in [1, 4096]), J = min over K = 8 ellipsoid level sets, H = weighted
-        # l1, FP32; the whole batch is one call (one launch per kernel class).  The problems are
-        # created (host A copied in, FP64 set-up) once, outside the timed region, and timed
-        # separately; the step is the ragged evaluation.
+        # l1, FP32; the whole batch is one call (one persistent launch per kernel class, no host
+        # wait between them).  A step creates the problems (host A copied in, FP64 set-up), runs
+        # the ragged evaluation and the ragged closest points of the first 64 points of every
+        # problem, and releases the problems; each phase is also reported on its own.
         from concurrent.futures import ThreadPoolExecutor
         nall, pall = W.workload4_sizes()
         nprob = len(nall)
