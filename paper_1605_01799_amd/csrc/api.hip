@@ -337,11 +337,9 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
       hipFree(dA); hipFree(S);
       return bail(fail(HOPF_EDEVICE, "copy A"));
     }
-    {  // FP32 copy of A in the caller's basis, for the control read-out
-      std::vector<float> af((size_t)n * n);
-      for (size_t i = 0; i < af.size(); ++i) af[i] = (float)srcA[i];
-      if (hipMalloc(&p->d_Af, sizeof(float) * af.size()) ||
-          hipMemcpy(p->d_Af, af.data(), sizeof(float) * af.size(), hipMemcpyHostToDevice)) {
+    {  // FP32 copy of A in the caller's basis (before any rotation), for the control read-out
+      const int64_t nn = (int64_t)n * n;
+      if (hipMalloc(&p->d_Af, sizeof(float) * nn) || launch_to_f32(dA, p->d_Af, nn, stream)) {
         hipFree(dA); hipFree(S);
         return bail(fail(HOPF_ENOMEM, "FP32 copy of A"));
       }

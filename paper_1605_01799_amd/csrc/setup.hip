@@ -252,6 +252,17 @@ hipError_t run_gauss_jordan(const SetupProb* d_probs, const int* h_nblocks, int 
   return hipSuccess;
 }
 
+__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) b[i] = (float)a[i];
+}
+
+hipError_t launch_to_f32(const double* a, float* b, int64_t m, hipStream_t stream) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, a, b, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_shifted(const double* A, int n, int n_pad, double lambda, double* S,
                                 hipStream_t stream) {
   int64_t tot = (int64_t)n_pad * n_pad;

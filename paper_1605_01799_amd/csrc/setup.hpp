@@ -17,6 +17,8 @@ hipError_t run_gauss_jordan(const SetupProb* d_probs, const int* h_nblocks, int 
                             int* h_prefix, hipStream_t stream);
 hipError_t launch_build_shifted(const double* A, int n, int n_pad, double lambda, double* S,
                                 hipStream_t stream);
+// b = (float)a, m entries
+hipError_t launch_to_f32(const double* a, float* b, int64_t m, hipStream_t stream);
 hipError_t launch_finalize_copies(const double* S, int n, int n_pad, double* Md, float* Mf, __bf16* Mb,
                                   hipStream_t stream);
 // Integer slices of M (refined mode): kSlices * n_pad * pad64(n_pad) bytes and n_pad exponents.
