@@ -16,56 +16,58 @@ namespace hopf {
 
 constexpr int NB = 32;
 
-// Pivot block: P = S_KK^{-1} via Cholesky, one workgroup per problem.
-__global__ void __launch_bounds__(kBlock) gj_pivot_kernel(const SetupProb* probs, int nprob, int step) {
+// Pivot block: P = S_KK^{-1} via Cholesky, one wave per problem, the block in registers: lane i
+// (< NB) holds row i, and every other lane's value is read with a broadcast from a compile-time
+// lane (readlane), so the three phases run without LDS or barriers.
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ void __launch_bounds__(64) gj_pivot_kernel(const SetupProb* probs, int nprob, int step) {
   const int q = blockIdx.x;
   if (q >= nprob) return;
   const SetupProb pb = probs[q];
   if (step * NB >= pb.n_pad) return;
-  __shared__ double a[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int l = threadIdx.x;
   const int k0 = step * NB;
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    int i = e / NB, j = e % NB;
-    a[i][j] = pb.S[(size_t)(k0 + i) * pb.n_pad + k0 + j];
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
+  const int row = l < NB ? l : NB - 1;  // lanes past NB mirror the last row; they store nothing
+  double r[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) r[k] = pb.S[(size_t)(k0 + row) * pb.n_pad + k0 + k];
+  // Cholesky, lower triangle in place: column j of L, then the trailing rows
+  bool bad = false;
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = a[j][j];
-      if (!(d > 0.0)) { bad = 1; d = 1.0; }
-      a[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    if (tid > j && tid < NB) a[tid][j] /= a[j][j];
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += kBlock) {
-      int i = e / NB, k = e % NB;
-      if (k > j && i >= k) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
-  }
-  // X = L^{-1}, column c by forward substitution
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int m = c; m < i; ++m) s -= a[i][m] * X[m][c];
-      X[i][c] = (i < c) ? 0.0 : s / a[i][i];
+    double d = bcast(r[j], j);
+    if (!(d > 0.0)) { bad = true; d = 1.0; }
+    const double sj = sqrt(d);
+    r[j] = (row == j) ? sj : (row > j ? r[j] / sj : r[j]);
+#pragma unroll
+    for (int k = j + 1; k < NB; ++k) {
+      const double lkj = bcast(r[j], k);
+      if (row >= k) r[k] -= r[j] * lkj;
     }
   }
-  __syncthreads();
-  // P = X^T X
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    int i = e / NB, j = e % NB;
+  // X = L^{-1}: lane c holds column c, X_ic = (delta_ic - sum_{m < i} L_im X_mc) / L_ii
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double s = (row == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < i; ++m) s -= bcast(r[m], i) * x[m];
+    x[i] = (i < row) ? 0.0 : s / bcast(r[i], i);
+  }
+  // P = X^T X: lane j computes column j, P_ij = sum_m X_mi X_mj
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
     double s = 0.0;
-    for (int m = 0; m < NB; ++m) s += X[m][i] * X[m][j];
-    pb.P[i * NB + j] = s;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) s += bcast(x[m], i) * x[m];
+    if (l < NB) pb.P[i * NB + l] = s;
   }
-  if (tid == 0 && bad) *pb.status = 1;
+  if (l == 0 && bad) *pb.status = 1;
 }
 
 // Panels: T = S[:, K] (copy of the old column panel), R = P * S[K, :] (new row panel).
@@ -241,7 +243,7 @@ hipError_t run_gauss_jordan(const SetupProb* d_probs, const int* h_nblocks, int 
     const int* ht = hb + nprob + 1;
     const int* db = d_prefix + s * stride;
     const int* dt = db + nprob + 1;
-    hipLaunchKernelGGL(gj_pivot_kernel, dim3(nactive), dim3(kBlock), 0, stream, d_probs, nactive, s);
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(nactive), dim3(64), 0, stream, d_probs, nactive, s);
     hipLaunchKernelGGL(gj_panel_kernel, dim3(hb[nactive]), dim3(kBlock), 0, stream, d_probs, db,
                        nactive, s);
     hipLaunchKernelGGL(gj_update_kernel, dim3(ht[nactive]), dim3(kBlock), 0, stream, d_probs, dt,
