@@ -956,7 +956,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
             const float dzn = isphi ? dzv + xp[rt][ct][q] + res - dd : res;
             const float step = dzn - dzv;
             a0 += step * step;
-            if (!WL) {
+            if (HL2) {  // the shrink2 norm's increment (only the l2 kinds use it)
               const float dsn = dzn - med3f(dzn + sa, lo, hi);
               a1 += dsn * (2.f * sa + dsn);
             }
@@ -967,7 +967,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
           }
         }
         s0[ct] = col_sumf(a0);
-        s1[ct] = col_sumf(a1);
+        s1[ct] = HL2 ? col_sumf(a1) : 0.f;
       }
 
       // ---------------------------------------------------------- value terms (value passes)
