@@ -100,7 +100,7 @@ def pin_no_drift(impl):
 
 
 def all_pins(impl, impl_w):
-    """Each pin's verdict (a pin whose implementation raises counts as failed)."""
+    """Each pin's result (a pin whose implementation raises counts as failed)."""
     def run(f, arg):
         try:
             return f(arg)
