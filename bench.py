@@ -32,8 +32,8 @@ METRIC = "Hopf point-evals/sec (φ+∇φ) at n=1024, 1e-6 rel vs FP64; % rooflin
 # counter reads for a plain 256 MiB device copy.  Valid only for the kernel source it was measured
 # on (hash of TRAFFIC_SOURCES); reported as null otherwise.
 TRAFFIC_SOURCES = ("dense_rs.hip", "dense_shared.hpp", "common.hpp")
-TRAFFIC = {"source_sha256": "109ffd9cca7603b7cb688c8513a2d0b03b8f515a68d02fbaa9a670cac4016b4f",
-           "read_bytes": 114.401e9, "write_bytes": 10.946e9, "precision": "bf16_refined", "npts": 1 << 16,
+TRAFFIC = {"source_sha256": "bb3807aefc5e4b2402f105d245d2e27325dbf39aff34fc71505e1ab5037999f9",
+           "read_bytes": 121.391e9, "write_bytes": 10.149e9, "precision": "bf16_refined", "npts": 1 << 16,
            "tol": 1e-12}
 
 

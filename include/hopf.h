@@ -304,6 +304,24 @@ hopf_status hopf_problem_get_inverse(hopf_problem_t problem, double* out);
 hopf_status hopf_problem_info(hopf_problem_t problem, int32_t* n, int32_t* n_pad, int32_t* K,
                               int32_t* precision);
 
+/* Deterministic mode of the dense evaluations (hopf_eval, hopf_closest_point, their ragged
+ * forms and plans; the per-point diagonal kernels are deterministic already): on = 1 makes
+ * every later launch (a plan: every plan created later) give the same bits in every output,
+ * run after run and replay after replay, for the same problems and arguments on the same
+ * device; on = 0 (the default) restores the fastest schedule, whose results agree to the
+ * parity tolerances but not bit for bit.  Split Bregman's points are independent (section 3),
+ * but a dense workgroup iterates a tile of columns together and re-bases their anchors
+ * together, so a column's rounding depends on the columns it shares a tile with; by default
+ * workgroups take chunks of columns from a shared counter as they free up, which makes that
+ * company depend on timing.  In deterministic mode workgroup (or wave) u of U takes the
+ * chunks u, u + U, u + 2U, ... instead, which can leave some compute units idle at the end of
+ * a launch.  The value sums are always added in a fixed order.  The setting is process-wide
+ * (an atomic flag read when a launch or plan is built).  Errors: HOPF_EINVAL for on other
+ * than 0 or 1. */
+hopf_status hopf_set_deterministic(int32_t on);
+/* The current setting (0 or 1). */
+int32_t hopf_get_deterministic(void);
+
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* hopf_last_error(void);
 

@@ -22,6 +22,7 @@ EXPORTS = [
     "hopf_problem_info", "hopf_last_error", "hopf_version", "hopf_control", "hopf_max_over_hamiltonians",
     "hopf_backward_noalloc", "hopf_problem_iterations", "hopf_closest_point_ragged",
     "hopf_ragged_plan_create", "hopf_ragged_plan_launch", "hopf_ragged_plan_destroy",
+    "hopf_set_deterministic", "hopf_get_deterministic",
 ]
 
 
@@ -75,6 +76,8 @@ def load():
         "hopf_problem_get_inverse": [P, V],
         "hopf_problem_iterations": [P, ctypes.POINTER(I64), I32],
         "hopf_problem_info": [P, V, V, V, V],
+        "hopf_set_deterministic": [I32],
+        "hopf_get_deterministic": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)

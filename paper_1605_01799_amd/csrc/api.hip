@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -48,6 +49,15 @@ static hopf_status fail(hopf_status st, const char* fmt, ...) {
 
 extern "C" const char* hopf_last_error(void) { return g_err.c_str(); }
 extern "C" const char* hopf_version(void) { return "hopf-mi355x 0.1 (gfx950)"; }
+
+// Deterministic scheduling of the dense kernels (read when a launch, or a plan, is built).
+static std::atomic<int> g_deterministic{0};
+extern "C" hopf_status hopf_set_deterministic(int32_t on) {
+  if (on != 0 && on != 1) return fail(HOPF_EINVAL, "hopf_set_deterministic: on must be 0 or 1 (got %d)", (int)on);
+  g_deterministic.store(on);
+  return HOPF_OK;
+}
+extern "C" int32_t hopf_get_deterministic(void) { return g_deterministic.load(); }
 
 // ---------------------------------------------------------------------------
 // problem handle
@@ -525,6 +535,7 @@ struct DenseClass {
 struct DensePlan {
   int mode = 0, distance = 0;
   int anchor_every = 32, anchor_wait = 0, rs_anchor_every = 24, small_anchor_every = 32, small_anchor_wait = 0;
+  int det = 0;  // fixed chunk schedule (hopf_set_deterministic)
   std::vector<DenseClass> cls;
   size_t blob_bytes = 0, state_floats = 0, state64_doubles = 0;
   int64_t total_pts = 0;
@@ -533,6 +544,7 @@ constexpr int kSmallClass = 1 << 20, kRsClass = 1 << 21;
 
 static void plan_dense(const std::vector<DenseCall>& calls, int mode, int distance, int ncu, DensePlan* P) {
   P->mode = mode; P->distance = distance;
+  P->det = g_deterministic.load();
   P->anchor_every = std::max(1, env_int("HOPF_ANCHOR_EVERY", 32));
   // an anchor is also taken as soon as this many columns of a tile wait for one (0: never)
   P->anchor_wait = std::max(0, env_int("HOPF_ANCHOR_WAIT", 0));
@@ -653,11 +665,11 @@ static hopf_status plan_launch(const DensePlan& P, const std::vector<DenseCall>&
     double* ws64 = state64 + C.state64_off;
     hipError_t e =
         C.small ? launch_dense_small(C.max_npad, P.mode == 2, C.key - kSmallClass, dv, dc, C.nchunks, counter, C.grid,
-                                     P.small_anchor_every, P.small_anchor_wait, stream)
+                                     P.small_anchor_every, P.small_anchor_wait, P.det, stream)
         : C.rs  ? launch_dense_rs(C.max_npad, dv, dc, C.nchunks, counter, ws64, C.ws64_per_wg, ws, C.ws_per_wg, C.grid,
-                                  C.lds, P.rs_anchor_every, P.anchor_wait, stream)
+                                  C.lds, P.rs_anchor_every, P.anchor_wait, P.det, stream)
                 : launch_dense(P.mode, C.var, dv, dc, C.nchunks, counter, ws, ws64, C.ws_per_wg, C.ws64_per_wg, C.grid,
-                               C.lds, P.distance, P.anchor_every, P.anchor_wait, stream);
+                               C.lds, P.distance, P.anchor_every, P.anchor_wait, P.det, stream);
     if (e) return fail(HOPF_EDEVICE, "dense launch: %s", hipGetErrorString(e));
   }
   return HOPF_OK;

@@ -84,7 +84,7 @@ template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1, bool WL = false
 __global__ void __launch_bounds__(NW * 64, OCC)
 dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
              int* __restrict__ chunk_counter, float* __restrict__ ws, double* __restrict__ ws64,
-             int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every, int anchor_wait) {
+             int64_t ws_per_wg, int64_t ws64_per_wg, int distance, int anchor_every, int anchor_wait, int det) {
   constexpr int PT = 16 * CT;
   static_assert(KS == 1 || MODE == 2, "the split contraction is for the FP32 refined mode");
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -98,7 +98,9 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 
   if (tid < PT) { S.state[tid] = COL_EMPTY; S.fresh[tid] = 0; }
   if (tid == 0) {
-    const int c0 = atomicAdd(chunk_counter, 1);
+    int taken = 0;
+    const int c0 = next_chunk(chunk_counter, det, (int)blockIdx.x, (int)gridDim.x, taken);
+    S.ctl[CTL_TAKEN] = taken;
     if (c0 >= nchunks) {
       S.ctl[CTL_EXIT] = 1;
     } else {
@@ -619,13 +621,13 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
     // ================================================================ refill empty slots
     if (tid == 0) {
       int prob = S.ctl[CTL_PROB], nextcol = S.ctl[CTL_NEXTCOL], cend = S.ctl[CTL_CHUNKEND];
-      int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE];
+      int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE], taken = S.ctl[CTL_TAKEN];
       int live = 0;
       for (int c = 0; c < PT; ++c) {
         S.fresh[c] = 0;
         if (S.state[c] != COL_EMPTY) { ++live; continue; }
         while (nextcol >= cend && pending < 0 && !nomore) {
-          const int nc = atomicAdd(chunk_counter, 1);
+          const int nc = next_chunk(chunk_counter, det, (int)blockIdx.x, (int)gridDim.x, taken);
           if (nc >= nchunks) { nomore = 1; break; }
           if (chunks[nc].prob == prob) { nextcol = chunks[nc].col0; cend = nextcol + chunks[nc].ncols; }
           else pending = nc;
@@ -654,6 +656,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       }
       S.ctl[CTL_PROB] = prob; S.ctl[CTL_NEXTCOL] = nextcol; S.ctl[CTL_CHUNKEND] = cend;
       S.ctl[CTL_PENDING] = pending; S.ctl[CTL_NOMORE] = nomore; S.ctl[CTL_EXIT] = exitf;
+      S.ctl[CTL_TAKEN] = taken;
     }
     __syncthreads();
     if (S.ctl[CTL_EXIT]) break;
@@ -722,10 +725,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
       }
     }
 
-    if (tid < PT) {  // value sums of this pass (ordered before their atomic updates by the barrier below)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) S.redv[tid][q] = 0.0;
-    }
+    value_clear(S, tid);  // value sums of this pass (ordered before their updates by the barrier below)
     // ================================================================ prologue: right-hand sides
     // Block order: wave w takes the row tiles w, w+4, ... of every column tile; lane l works on
     // rows 16 rt + 4 (l/16) .. + 3 of column 16 ct + l%16, its block's contiguous 16 bytes.
@@ -931,7 +931,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 v5 += d * d;
                 pv[q] = (float)d;
               }
-              value_sums(S.redv[c], v2, v3, v4, v5);
+              value_sums(S.redv[wave][c], v2, v3, v4, v5, l);
               if (single) store_grad(pb.grad + (size_t)S.j[c] * n, row0, n, pv);
               else st_nt4(pout + e, pv);
             }
@@ -982,7 +982,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
                 v5 += d * d;
                 pv[q] = (float)d;
               }
-              value_sums(S.redv[c], v2, v3, v4, v5);
+              value_sums(S.redv[wave][c], v2, v3, v4, v5, l);
               if (single) store_grad(pb.grad + (size_t)S.j[c] * n, row0, n, pv);
               else st_nt4(pout + e, pv);
             }
@@ -1011,7 +1011,7 @@ dense_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__
 #pragma unroll
       for (int w = 0; w < NW; ++w) { sm[0] += S.red[w][c][0]; sm[1] += S.red[w][c][1]; }
 #pragma unroll
-      for (int q = 2; q < kNRed; ++q) sm[q] = S.redv[c][q - 2];
+      for (int q = 2; q < kNRed; ++q) sm[q] = value_total(S, c, q - 2);
       const bool delta = MODE >= 1 && S.phase[c] == PH_DELTA;
       const bool stepped = st == COL_ACTIVE || (MODE >= 1 && st == COL_PHI);
       bool evaluate = (MODE == 0 && st == COL_PHI);
@@ -1180,7 +1180,7 @@ hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npt
 template <int MODE, int CT, int RG, int OCC, int NW, int KS = 1, bool WL = false>
 static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                            float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg, int grid, size_t lds,
-                           int distance, int anchor_every, int anchor_wait, hipStream_t stream) {
+                           int distance, int anchor_every, int anchor_wait, int det, hipStream_t stream) {
   auto kern = dense_kernel<MODE, CT, RG, OCC, NW, KS, WL>;
   static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
   int dev = 0;
@@ -1196,7 +1196,7 @@ static hipError_t launch_t(const DenseProb* d_probs, const DenseChunk* d_chunks,
     attr_bytes[dev] = lds;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws, ws64,
-                     ws_per_wg, ws64_per_wg, distance, anchor_every, anchor_wait);
+                     ws_per_wg, ws64_per_wg, distance, anchor_every, anchor_wait, det);
   return hipGetLastError();
 }
 
@@ -1204,11 +1204,11 @@ template <bool WL>
 static hipError_t launch_shape(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                                int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg,
                                int64_t ws64_per_wg, int grid, size_t lds, int distance, int anchor_every,
-                               int anchor_wait, hipStream_t stream) {
+                               int anchor_wait, int det, hipStream_t stream) {
   const int ct = var.pt / 16, occ = var.occ, nw = var.nw;
 #define HOPF_LAUNCH(M, C, R, O, W, K)                                                                            \
   return launch_t<M, C, R, O, W, K, WL>(d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, \
-                                        grid, lds, distance, anchor_every, anchor_wait, stream)
+                                        grid, lds, distance, anchor_every, anchor_wait, det, stream)
   if (mode == 2 && var.ks == 2) {  // the split contraction
     if (ct == 4) HOPF_LAUNCH(2, 4, 4, 1, 4, 2);
     if (ct == 2) HOPF_LAUNCH(2, 2, 4, 1, 4, 2);
@@ -1235,14 +1235,14 @@ static hipError_t launch_shape(int mode, DenseVariant var, const DenseProb* d_pr
 
 hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
+                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait, int det,
                         hipStream_t stream) {
   // sqrt(<p, D p>) problems run in instances with their multiplier phase, the others without it
   if (var.wl && !distance)
     return launch_shape<true>(mode, var, d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
-                              lds, distance, anchor_every, anchor_wait, stream);
+                              lds, distance, anchor_every, anchor_wait, det, stream);
   return launch_shape<false>(mode, var, d_probs, d_chunks, nchunks, counter, ws, ws64, ws_per_wg, ws64_per_wg, grid,
-                             lds, distance, anchor_every, anchor_wait, stream);
+                             lds, distance, anchor_every, anchor_wait, det, stream);
 }
 
 }  // namespace hopf

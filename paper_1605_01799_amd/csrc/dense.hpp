@@ -20,7 +20,7 @@ size_t dense_lds_bytes(int mode, int n_pad);
 hipError_t launch_reset(int* counter, double* bestv, int32_t* bestk, int64_t npts, hipStream_t stream);
 hipError_t launch_dense(int mode, DenseVariant var, const DenseProb* d_probs, const DenseChunk* d_chunks,
                         int nchunks, int* counter, float* ws, double* ws64, int64_t ws_per_wg, int64_t ws64_per_wg,
-                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait,
+                        int grid, size_t lds, int distance, int anchor_every, int anchor_wait, int det,
                         hipStream_t stream);
 
 // Small problems (dense_small.hip): FP32 evaluation of n_pad <= 64, one wave per 16-column tile
@@ -31,7 +31,7 @@ int dense_small_occupancy();  // workgroups per CU
 // kind: dense_small_kind(hkind) of every problem of the launch (one instance per kind of H)
 int dense_small_kind(int hkind);
 hipError_t launch_dense_small(int n_pad, bool refined, int kind, const DenseProb* d_probs, const DenseChunk* d_chunks,
-                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait, int det,
                               hipStream_t stream);
 
 // Refined BF16 problems of one point per column (K = 1) with 64 <= n_pad <= 1024
@@ -42,6 +42,6 @@ size_t dense_rs_lds_bytes(int n_pad);     // dynamic LDS of a launch whose large
 int64_t dense_rs_ws_floats(int n_pad);    // float staging per workgroup
 hipError_t launch_dense_rs(int max_npad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
                            int* counter, double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid,
-                           size_t lds, int anchor_every, int anchor_wait, hipStream_t stream);
+                           size_t lds, int anchor_every, int anchor_wait, int det, hipStream_t stream);
 
 }  // namespace hopf

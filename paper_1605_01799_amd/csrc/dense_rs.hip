@@ -64,7 +64,7 @@ template <int RW, typename EV>
 __global__ void __launch_bounds__(kNW * 64, 1)
 dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
                 int* __restrict__ chunk_counter, double* __restrict__ ws64, int64_t ws64_per_wg,
-                float* __restrict__ ws, int64_t ws_per_wg, int anchor_every, int anchor_wait) {
+                float* __restrict__ ws, int64_t ws_per_wg, int anchor_every, int anchor_wait, int det) {
   constexpr int NW = kNW, CT = kCT, PT = kPT;
   static_assert(PT <= 64, "the slot bookkeeping takes one lane of wave 0 per slot");
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -106,7 +106,9 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
 
   if (tid < PT) { S.state[tid] = COL_EMPTY; S.fresh[tid] = 0; }
   if (tid == 0) {
-    const int c0 = atomicAdd(chunk_counter, 1);
+    int taken = 0;
+    const int c0 = next_chunk(chunk_counter, det, (int)blockIdx.x, (int)gridDim.x, taken);
+    S.ctl[CTL_TAKEN] = taken;
     if (c0 >= nchunks) {
       S.ctl[CTL_EXIT] = 1;
     } else {
@@ -449,13 +451,13 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
     }
     if (tid == 0 && !refilled) {
       int prob = S.ctl[CTL_PROB], nextcol = S.ctl[CTL_NEXTCOL], cend = S.ctl[CTL_CHUNKEND];
-      int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE];
+      int pending = S.ctl[CTL_PENDING], nomore = S.ctl[CTL_NOMORE], taken = S.ctl[CTL_TAKEN];
       int live = 0;
       for (int c = 0; c < PT; ++c) {
         S.fresh[c] = 0;
         if (S.state[c] != COL_EMPTY) { ++live; continue; }
         while (nextcol >= cend && pending < 0 && !nomore) {
-          const int nc = atomicAdd(chunk_counter, 1);
+          const int nc = next_chunk(chunk_counter, det, (int)blockIdx.x, (int)gridDim.x, taken);
           if (nc >= nchunks) { nomore = 1; break; }
           if (chunks[nc].prob == prob) { nextcol = chunks[nc].col0; cend = nextcol + chunks[nc].ncols; }
           else pending = nc;
@@ -484,6 +486,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
       }
       S.ctl[CTL_PROB] = prob; S.ctl[CTL_NEXTCOL] = nextcol; S.ctl[CTL_CHUNKEND] = cend;
       S.ctl[CTL_PENDING] = pending; S.ctl[CTL_NOMORE] = nomore; S.ctl[CTL_EXIT] = exitf;
+      S.ctl[CTL_TAKEN] = taken;
     }
     __syncthreads();
     if (S.ctl[CTL_EXIT]) break;
@@ -589,10 +592,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
         continue;
       }
     }
-    if (tid < PT) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) S.redv[tid][q] = 0.0;
-    }
+    value_clear(S, tid);
 
     lanes();
     // ============================================================ prologue: right-hand sides
@@ -763,7 +763,7 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
           }
           store_grad(pb.grad + (size_t)S.j[c] * n, row0, n, pv);
         }
-        value_sums(S.redv[c], v2, v3, v4, v5);
+        value_sums(S.redv[wave][c], v2, v3, v4, v5, l);
       }
     }
 #pragma unroll
@@ -806,9 +806,9 @@ dense_rs_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restric
         } else {
           if (capped && !conv) S.flags[c] |= FLAG_SOLVE_CAP | FLAG_CAPPED;
           if (conv || (S.flags[c] & FLAG_SOLVE_CAP)) {
-            const double pn = sqrt(S.redv[c][3]);
-            const double H = (has_l1 ? S.redv[c][2] : 0.0) + (has_l2 ? pn : 0.0);
-            S.phi[c] = S.redv[c][0] - 0.5 * S.redv[c][1] - S.t[c] * H - (pb.level_set ? 0.5 : 0.0);
+            const double pn = sqrt(value_total(S, c, 3));
+            const double H = (has_l1 ? value_total(S, c, 2) : 0.0) + (has_l2 ? pn : 0.0);
+            S.phi[c] = value_total(S, c, 0) - 0.5 * value_total(S, c, 1) - S.t[c] * H - (pb.level_set ? 0.5 : 0.0);
             S.hp[c] = H; S.pn[c] = pn;
             S.state[c] = COL_DONE;
           } else {
@@ -863,7 +863,7 @@ int64_t dense_rs_ws_floats(int n_pad) {
 template <int RW, typename EV>
 static hipError_t launch_rs_t(const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks, int* counter,
                               double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid, size_t lds,
-                              int anchor_every, int anchor_wait, hipStream_t stream) {
+                              int anchor_every, int anchor_wait, int det, hipStream_t stream) {
   auto kern = dense_rs_kernel<RW, EV>;
   static size_t attr_bytes[64] = {};  // dynamic LDS allowed so far, per device
   int dev = 0;
@@ -879,19 +879,19 @@ static hipError_t launch_rs_t(const DenseProb* d_probs, const DenseChunk* d_chun
     attr_bytes[dev] = lds;
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kNW * 64), lds, stream, d_probs, d_chunks, nchunks, counter, ws64,
-                     ws64_per_wg, ws, ws_per_wg, anchor_every, anchor_wait);
+                     ws64_per_wg, ws, ws_per_wg, anchor_every, anchor_wait, det);
   return hipGetLastError();
 }
 
 hipError_t launch_dense_rs(int max_npad, const DenseProb* d_probs, const DenseChunk* d_chunks, int nchunks,
                            int* counter, double* ws64, int64_t ws64_per_wg, float* ws, int64_t ws_per_wg, int grid,
-                           size_t lds, int anchor_every, int anchor_wait, hipStream_t stream) {
+                           size_t lds, int anchor_every, int anchor_wait, int det, hipStream_t stream) {
   if (max_npad <= 512)
     return launch_rs_t<kRWsmall, f32x4>(d_probs, d_chunks, nchunks, counter, ws64, ws64_per_wg, ws, ws_per_wg, grid, lds,
-                          anchor_every, anchor_wait, stream);
+                          anchor_every, anchor_wait, det, stream);
   if (max_npad <= 1024)
     return launch_rs_t<kRWlarge, bf16x4>(d_probs, d_chunks, nchunks, counter, ws64, ws64_per_wg, ws, ws_per_wg, grid, lds,
-                          anchor_every, anchor_wait, stream);
+                          anchor_every, anchor_wait, det, stream);
   return hipErrorInvalidValue;
 }
 

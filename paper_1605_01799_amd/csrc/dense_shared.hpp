@@ -216,13 +216,30 @@ __device__ __forceinline__ void store_grad(float* g, int row0, int n, f32x4 pv) 
     if (row0 + q < n) st_nt(g + row0 + q, pv[q]);
 }
 
-// Value sums of a value iteration, added by every lane that holds rows of the column (rare:
-// one iteration per solve), straight into the column's LDS slots.
-__device__ __forceinline__ void value_sums(double* slot, double v2, double v3, double v4, double v5) {
-  atomicAdd(slot + 0, v2);
-  atomicAdd(slot + 1, v3);
-  atomicAdd(slot + 2, v4);
-  atomicAdd(slot + 3, v5);
+// Value sums of a value iteration (rare: one iteration per solve).  Called by the four lanes
+// l, l ^ 16, l ^ 32, l ^ 48 that hold rows of one column, all active together: their partials are
+// summed in a fixed order by shuffles and the first lane group adds the result to the wave's own
+// slot of the column (plain adds in the wave's program order).  No atomics: the sums, and phi,
+// are the same bits on every run.
+__device__ __forceinline__ void value_sums(double* slot, double v2, double v3, double v4, double v5, int l) {
+  double v[4] = {v2, v3, v4, v5};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] += __shfl_xor(v[q], 16);
+    v[q] += __shfl_xor(v[q], 32);
+  }
+  if ((l >> 4) == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) slot[q] += v[q];
+  }
+}
+
+// The next chunk for a workgroup (or a wave) that schedules itself: the shared counter, or with
+// det a fixed schedule in which unit u of `units` takes the chunks u, u + units, u + 2 units, ...
+// (`taken` counts its chunks).  A column's passes, anchors and refills then depend only on the
+// data, so every output is the same bits on every run of the same launch.
+__device__ __forceinline__ int next_chunk(int* counter, int det, int unit, int units, int& taken) {
+  return det ? unit + units * (taken++) : atomicAdd(counter, 1);
 }
 
 // Wave-level sum of a double across the 64 lanes (result in every lane).
@@ -242,9 +259,22 @@ struct ColShared {
   int newton[P], flags[P], fresh[P], better[P];
   int rexp[P];            // column exponents of an anchor's right-hand sides
   double red[NW][P][2];  // per-wave partials of step^2 and |s|^2
-  double redv[P][4];     // value sums of a value iteration (LDS atomics)
+  double redv[NW][P][4];  // per-wave value sums of a value iteration
   int ctl[16];
 };
+// Column c's value sum q over the waves, in wave order.
+template <int P, int NW>
+__device__ __forceinline__ double value_total(const ColShared<P, NW>& S, int c, int q) {
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += S.redv[w][c][q];
+  return s;
+}
+// Clears every wave's value sums (all threads of the workgroup take part).
+template <int P, int NW>
+__device__ __forceinline__ void value_clear(ColShared<P, NW>& S, int tid) {
+  for (int i = tid; i < NW * P * 4; i += NW * 64) (&S.redv[0][0][0])[i] = 0.0;
+}
 // FLAG_SOLVE_CAP: the current solve hit the iteration cap (or stalled at FP32 precision);
 // FLAG_CAPPED: some solve of this slot did (reported as -2); FLAG_EXACT: the column has had an
 // exact anchor product (refined wave-local kernel: only then may it stop).
@@ -260,7 +290,7 @@ enum {
 constexpr int kStallIters = 64;
 enum {
   CTL_ANCHOR = 0, CTL_LAST_ANCHOR, CTL_PROB, CTL_NEXTCOL, CTL_CHUNKEND, CTL_PENDING, CTL_NOMORE,
-  CTL_EXIT, CTL_BETTER, CTL_ANY, CTL_PHIPASS, CTL_WL2
+  CTL_EXIT, CTL_BETTER, CTL_ANY, CTL_PHIPASS, CTL_WL2, CTL_TAKEN
 };
 enum { PH_WARMUP = 0, PH_DELTA = 1 };
 

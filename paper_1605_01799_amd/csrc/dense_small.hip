@@ -82,7 +82,7 @@ constexpr float kWl2Rel = 2.5e-7f;       // a step below this fraction of mu end
 template <int RTM, int CT, int OCC, bool REF, int KS>
 __global__ void __launch_bounds__(kBlock, OCC)
 dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __restrict__ chunks, int nchunks,
-                   int* __restrict__ chunk_counter, int anchor_every, int anchor_wait) {
+                   int* __restrict__ chunk_counter, int anchor_every, int anchor_wait, int det) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   // wave-uniform values go through readfirstlane so that the queue state, the problem's scalars
@@ -91,9 +91,13 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
 
   // queue position of this wave
   int prob = -1, nextcol = 0, cend = 0, pending = -1, nomore = 0;
+  // with det the waves take fixed chunks: wave unit of `units` (see next_chunk)
+  const int units = (int)gridDim.x * (int)(blockDim.x >> 6);
+  const int unit = (int)blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+  int taken = 0;  // (lane 0's count is the one used)
   {
     int c0 = 0;
-    if (l == 0) c0 = atomicAdd(chunk_counter, 1);
+    if (l == 0) c0 = next_chunk(chunk_counter, det, unit, units, taken);
     c0 = uni(__shfl(c0, 0));
     if (c0 >= nchunks) return;
     prob = uni(chunks[c0].prob); nextcol = uni(chunks[c0].col0); cend = nextcol + uni(chunks[c0].ncols);
@@ -261,7 +265,7 @@ dense_small_kernel(const DenseProb* __restrict__ probs, const DenseChunk* __rest
         emask &= emask - 1;
         while (nextcol >= cend && pending < 0 && !nomore) {
           int nc = 0;
-          if (l == 0) nc = atomicAdd(chunk_counter, 1);
+          if (l == 0) nc = next_chunk(chunk_counter, det, unit, units, taken);
           nc = uni(__shfl(nc, 0));
           if (nc >= nchunks) { nomore = 1; break; }
           if (uni(chunks[nc].prob) == prob) { nextcol = uni(chunks[nc].col0); cend = nextcol + uni(chunks[nc].ncols); }
@@ -1086,11 +1090,11 @@ int dense_small_kind(int hkind) { return hkind == HK_WL2 || hkind == HK_AL2 ? 2 
 
 template <int KS>
 static void launch_small_kind(int n_pad, bool refined, const DenseProb* d_probs, const DenseChunk* d_chunks,
-                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait, int det,
                               hipStream_t stream) {
 #define HOPF_SMALL(R, F)                                                                                        \
   hipLaunchKernelGGL((dense_small_kernel<R, SMALL_CT, SMALL_OCC, F, KS>), dim3(grid), dim3(kBlock), 0, stream, \
-                     d_probs, d_chunks, nchunks, counter, anchor_every, anchor_wait)
+                     d_probs, d_chunks, nchunks, counter, anchor_every, anchor_wait, det)
   if (n_pad <= 32) {
     if (refined) HOPF_SMALL(2, true); else HOPF_SMALL(2, false);
   } else {
@@ -1100,12 +1104,12 @@ static void launch_small_kind(int n_pad, bool refined, const DenseProb* d_probs,
 }
 
 hipError_t launch_dense_small(int n_pad, bool refined, int kind, const DenseProb* d_probs, const DenseChunk* d_chunks,
-                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait,
+                              int nchunks, int* counter, int grid, int anchor_every, int anchor_wait, int det,
                               hipStream_t stream) {
   if (n_pad > 64 || kind < 0 || kind > 2) return hipErrorInvalidValue;
-  if (kind == 0) launch_small_kind<0>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
-  else if (kind == 1) launch_small_kind<1>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
-  else launch_small_kind<2>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, stream);
+  if (kind == 0) launch_small_kind<0>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, det, stream);
+  else if (kind == 1) launch_small_kind<1>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, det, stream);
+  else launch_small_kind<2>(n_pad, refined, d_probs, d_chunks, nchunks, counter, grid, anchor_every, anchor_wait, det, stream);
   return hipGetLastError();
 }
 

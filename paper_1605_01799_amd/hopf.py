@@ -17,6 +17,18 @@ from . import _lib
 from ._lib import check
 
 
+def set_deterministic(on: bool) -> None:
+    """Deterministic mode of the dense evaluations (hopf_set_deterministic): every later launch,
+    and every plan created later, gives the same bits on every run; False restores the fastest
+    schedule (results agree to the parity tolerances, not bit for bit).  Process-wide."""
+    check(_lib.load().hopf_set_deterministic(1 if on else 0))
+
+
+def deterministic() -> bool:
+    """The current deterministic-mode setting (hopf_get_deterministic)."""
+    return bool(_lib.load().hopf_get_deterministic())
+
+
 def _stream_ptr(stream=None):
     if stream is None:
         stream = torch.cuda.current_stream()

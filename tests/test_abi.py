@@ -51,3 +51,21 @@ def test_oracle_is_not_imported_by_product_code():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", src).lower() or f == "workloads.py", f
+
+
+def test_deterministic_setting():
+    """hopf_set_deterministic: a process-wide flag that takes 0 or 1 (no device call is made)."""
+    from paper_1605_01799_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libhopf.so not built")
+    lib = _lib.load()
+    assert lib.hopf_get_deterministic() == 0
+    try:
+        assert lib.hopf_set_deterministic(1) == _lib.HOPF_OK
+        assert lib.hopf_get_deterministic() == 1
+        assert lib.hopf_set_deterministic(2) == _lib.HOPF_EINVAL
+        assert b"0 or 1" in lib.hopf_last_error()
+        assert lib.hopf_get_deterministic() == 1  # unchanged on error
+    finally:
+        assert lib.hopf_set_deterministic(0) == _lib.HOPF_OK
+    assert lib.hopf_get_deterministic() == 0

@@ -3,7 +3,8 @@ captured in a HIP graph and replayed.  Every replay (with the program's own eage
 synchronisations between replays) is checked against the plan's eager launch and the one-call
 path (hopf_eval_ragged) to the parity bar, and on sampled points against the FP64 oracle.  The
 persistent kernels take chunks from an atomic queue, so the anchor schedule of a column can
-differ between launches: results agree to the parity bar, not bit for bit."""
+differ between launches: results agree to the parity bar, not bit for bit (in the deterministic
+mode they agree bit for bit: test_gpu_deterministic.py)."""
 import numpy as np
 import pytest
 
