@@ -65,6 +65,9 @@ def parse():
                     help="most points of the CPU baseline's stratified sample (it is sized to ~15 s)")
     ap.add_argument("--acc-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="the library's deterministic mode (fixed chunk schedule; hopf_set_deterministic); "
+                         "the line's config then says so")
     ap.add_argument("--workload", default="c3",
                     choices=["c3", "c1s", "c2", "c4", "c5", "c2wl2", "pd16", "pa16", "t5n16", "lc16", "c3wl2"],
                     help="c3 (default): the metric workload.  Other hot-path workloads, one JSON line "
@@ -107,6 +110,9 @@ def main():
         return
     global SKIP_CPU
     SKIP_CPU = a.no_cpu
+    if a.deterministic:
+        from paper_1605_01799_amd import hopf as H
+        H.set_deterministic(True)
     if a.workload != "c3":
         bench_other(a)
         return
@@ -207,6 +213,8 @@ def main():
                 p.t, a.cpu_sample, "same tol (%g), FP64 oracle (triangular solves, compensated sums)" % tol)
     except Exception as e:  # the oracle is test infrastructure; its absence only drops these fields
         rec["accuracy_error"] = str(e)
+    if a.deterministic:
+        rec.setdefault("config", {})["deterministic"] = True
     print(json.dumps(rec), flush=True)
 
 
@@ -875,6 +883,8 @@ def bench_other(a):
                                  "kind": "oracle", **host_info(),
                                  "sample": "the same %d points (one problem per thread), same tol, FP64 "
                                            "oracle, %d threads (the GPU's CPU share)" % (cpu_n, threads)})
+    if a.deterministic:
+        rec.setdefault("config", {})["deterministic"] = True
     print(json.dumps(rec), flush=True)
 
 
