@@ -50,6 +50,25 @@ def measured_traffic(precision, npts, tol):
     return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
 
 
+# The same for the tile kernel of the n=256 union workload (c5; its profiles/ summary), valid for
+# the sources, the tuned launch shapes and the point count and tolerance it was measured on.
+C5_TRAFFIC = {"sources": ("dense.hip", "dense_shared.hpp", "common.hpp", "api.hip", "tune_table.inc"),
+              "source_sha256": "636a595d17c4cad03159e34201d42043b1770ae7b13c4ce67e6ca68730276ea0",
+              "read_bytes": 26.688e9, "write_bytes": 173.348e9, "npts": 1 << 18, "tol": 1e-12}
+
+
+def measured_traffic_c5(npts, tol):
+    import hashlib
+    h = hashlib.sha256()
+    for f in C5_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1605_01799_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (h.hexdigest() != C5_TRAFFIC["source_sha256"] or npts != C5_TRAFFIC["npts"] or tol != C5_TRAFFIC["tol"]
+            or "HOPF_DENSE_VARIANT" in os.environ or os.environ.get("HOPF_ANCHOR_EVERY", "32") != "32"):
+        return None
+    return C5_TRAFFIC["read_bytes"] + C5_TRAFFIC["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -733,7 +752,9 @@ def bench_other(a):
                                        "tol %g; step = forward + backward (x, t, A, centres)" % (npts, tol),
                            "npts": npts},
                    roofline={"bound": "mfma", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-                             "frac": achieved / 157.3, "traffic": None, "kernel": "dense_kernel<2, ...> (FP32 refined)",
+                             "frac": achieved / 157.3, "traffic": measured_traffic_c5(npts, tol),
+                             "traffic_unit": "HBM bytes read + written per launch (FETCH_SIZE, WRITE_SIZE scaled)",
+                             "kernel": "dense_kernel<2, ...> (FP32 refined)",
                              "algorithmic": "passes of every copy of every point (hopf_problem_iterations) x "
                                             "2 n^2 FLOP", "passes_per_step": passes, "launch_ms": kms},
                    backward={"ms": bms, "hbm_GBps": bw_bytes / (bms / 1e3) / 1e9,
