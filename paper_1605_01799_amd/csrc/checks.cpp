@@ -1,6 +1,7 @@
 // Host-side argument checks of the C ABI (declarations and rules in checks.hpp).
 #include "checks.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,16 +19,64 @@ static hopf_status say(hopf_status st, char* why, size_t len, const char* fmt, .
   return st;
 }
 
-static bool symmetric(const double* S, int n, int* bi, int* bj) {
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) {
-      const double a = S[(size_t)i * n + j], b = S[(size_t)j * n + i];
-      if (std::fabs(a - b) > 1e-12 * std::fmax(1.0, std::fmax(std::fabs(a), std::fabs(b)))) {
-        *bi = i; *bj = j;
-        return false;
+// Index of the first non-finite entry of a[0 .. m), or -1.  The scan accumulates a flag without
+// branching (it vectorises); the index is searched only when the flag is set.
+static int64_t first_nonfinite(const double* a, int64_t m) {
+  int bad = 0;
+  for (int64_t i = 0; i < m; ++i) bad |= std::isfinite(a[i]) ? 0 : 1;
+  if (!bad) return -1;
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(a[i])) return i;
+  return -1;
+}
+
+static bool differ(double a, double b) {
+  return std::fabs(a - b) > 1e-12 * std::fmax(1.0, std::fmax(std::fabs(a), std::fabs(b)));
+}
+
+// Checks the row-major n x n matrix S in one pass: every entry finite, and S symmetric to a
+// relative 1e-12.  The matrix is walked in 64 x 64 tiles of the lower block triangle; each
+// mirrored upper tile is first copied transposed into a local buffer (row reads), so both
+// operands of every comparison are read contiguously, every entry is read once, and the loops
+// vectorise (a row-by-row scan reads the upper triangle with a stride of n doubles).  Returns 0,
+// or 1 with *bad the first non-finite index, or 2 with (*bi, *bj) the first mismatch in
+// row-major order of the lower triangle.
+static int check_dense(const double* S, int n, int64_t* bad, int* bi, int* bj) {
+  constexpr int kT = 64;
+  double up[kT][kT];  // up[i - ib][j - jb] = S[j][i] (32 KiB)
+  int nonfinite = 0, asym = 0;
+  for (int ib = 0; ib < n; ib += kT) {
+    const int ie = std::min(n, ib + kT);
+    for (int jb = 0; jb <= ib; jb += kT) {
+      const int je = std::min(n, jb + kT);
+      if (jb < ib) {
+        for (int j = jb; j < je; ++j)
+          for (int i = ib; i < ie; ++i) up[i - ib][j - jb] = S[(size_t)j * n + i];
+        for (int i = ib; i < ie; ++i) {
+          const double* row = S + (size_t)i * n;
+          for (int j = jb; j < je; ++j) {
+            const double a = row[j], b = up[i - ib][j - jb];
+            nonfinite |= (std::isfinite(a) && std::isfinite(b)) ? 0 : 1;
+            asym |= differ(a, b) ? 1 : 0;
+          }
+        }
+      } else {  // a diagonal tile: both triangles are in it
+        for (int i = ib; i < ie; ++i) {
+          const double* row = S + (size_t)i * n;
+          for (int j = jb; j < je; ++j) {
+            nonfinite |= std::isfinite(row[j]) ? 0 : 1;
+            if (j < i) asym |= differ(row[j], S[(size_t)j * n + i]) ? 1 : 0;
+          }
+        }
       }
     }
-  return true;
+  }
+  if (nonfinite) { *bad = first_nonfinite(S, (int64_t)n * n); return 1; }
+  if (!asym) return 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (differ(S[(size_t)i * n + j], S[(size_t)j * n + i])) { *bi = i; *bj = j; return 2; }
+  return 0;
 }
 
 hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
@@ -62,15 +111,17 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
   const bool normsq = d->jkind != HOPF_J_QUADRATIC;
   const bool diag = normsq || d->A == nullptr || d->A_is_diagonal;
   if (d->A && !normsq) {
-    const int64_t m = d->A_is_diagonal ? n : (int64_t)n * n;
-    for (int64_t i = 0; i < m; ++i)
-      if (!std::isfinite(d->A[i])) return say(HOPF_EINVAL, why, len, "A[%lld] is not finite", (long long)i);
     if (d->A_is_diagonal) {
+      const int64_t bad = first_nonfinite(d->A, n);
+      if (bad >= 0) return say(HOPF_EINVAL, why, len, "A[%lld] is not finite", (long long)bad);
       for (int i = 0; i < n; ++i)
         if (!(d->A[i] > 0.0)) return say(HOPF_ENOTSPD, why, len, "diagonal A[%d] = %g is not > 0", i, d->A[i]);
     } else {
+      int64_t bad = -1;
       int bi = 0, bj = 0;
-      if (!symmetric(d->A, n, &bi, &bj)) return say(HOPF_EINVAL, why, len, "A is not symmetric at (%d, %d)", bi, bj);
+      const int r = check_dense(d->A, n, &bad, &bi, &bj);
+      if (r == 1) return say(HOPF_EINVAL, why, len, "A[%lld] is not finite", (long long)bad);
+      if (r == 2) return say(HOPF_EINVAL, why, len, "A is not symmetric at (%d, %d)", bi, bj);
     }
   }
   if (d->precision == HOPF_F64 && !(diag && n <= kDiagMaxN))
@@ -102,10 +153,11 @@ hopf_status check_desc(const hopf_problem_desc* d, char* why, size_t len) {
       return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 supports HOPF_F64 with diagonal A and n <= %d, or HOPF_F32 "
                  "and HOPF_BF16_REFINED with n <= %d", kDiagMaxN, kRotMaxN);
     if (!d->HA) return say(HOPF_EINVAL, why, len, "HOPF_H_AL2 needs the matrix HA");
-    for (int64_t i = 0; i < (int64_t)n * n; ++i)
-      if (!std::isfinite(d->HA[i])) return say(HOPF_EINVAL, why, len, "HA[%lld] is not finite", (long long)i);
+    int64_t bad = -1;
     int bi = 0, bj = 0;
-    if (!symmetric(d->HA, n, &bi, &bj)) return say(HOPF_EINVAL, why, len, "HA is not symmetric at (%d, %d)", bi, bj);
+    const int r = check_dense(d->HA, n, &bad, &bi, &bj);
+    if (r == 1) return say(HOPF_EINVAL, why, len, "HA[%lld] is not finite", (long long)bad);
+    if (r == 2) return say(HOPF_EINVAL, why, len, "HA is not symmetric at (%d, %d)", bi, bj);
   }
   return HOPF_OK;
 }

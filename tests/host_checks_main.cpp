@@ -20,6 +20,14 @@ static void expect(const char* name, hopf_status got, hopf_status want, const ch
   if (!ok) ++failures;
 }
 
+static void expect_msg(const char* name, hopf_status got, hopf_status want, const char* why, const char* part) {
+  expect(name, got, want, why);
+  if (!std::strstr(why, part)) {
+    std::printf("FAIL %s: the message does not name %s\n", name, part);
+    ++failures;
+  }
+}
+
 static hopf_problem_desc base(int n) {
   hopf_problem_desc d;
   std::memset(&d, 0, sizeof d);
@@ -64,6 +72,30 @@ int main() {
     A[63] = 2.0;
     d.A = Ad.data(); d.A_is_diagonal = 1; Ad[7] = 0.0; why[0] = 0;
     expect("diagonal A with a zero", check_desc(&d, why, sizeof why), HOPF_ENOTSPD, why);
+  }
+  {  // a dense A over several 64 x 64 tiles with a ragged last one (n = 200): the one-pass check
+     // finds every entry and reports the first offence in row-major order
+    const int n = 200;
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = (i == j) ? n : 1.0 / (1 + i + j);
+    hopf_problem_desc d = base(n);
+    d.A = A.data();
+    auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+    why[0] = 0; expect("symmetric A, n = 200", check_desc(&d, why, sizeof why), HOPF_OK, why);
+    at(150, 10) += 1e-6; why[0] = 0;
+    expect_msg("asymmetric lower entry (150, 10)", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "(150, 10)");
+    at(150, 10) = at(10, 150); at(10, 150) -= 1e-6; why[0] = 0;
+    expect_msg("asymmetric upper entry (10, 150)", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "(150, 10)");
+    at(199, 198) += 1.0; why[0] = 0;
+    expect_msg("two mismatches: the first in row order", check_desc(&d, why, sizeof why), HOPF_EINVAL, why,
+               "(150, 10)");
+    at(10, 150) = at(150, 10); at(199, 198) = at(198, 199); at(3, 190) = NAN; why[0] = 0;
+    expect_msg("NaN in the upper triangle", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "A[790]");
+    at(3, 190) = at(190, 3); at(130, 130) = INFINITY; why[0] = 0;
+    expect_msg("infinite diagonal entry", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "A[26130]");
+    at(130, 130) = n; why[0] = 0;
+    expect("symmetric A again, n = 200", check_desc(&d, why, sizeof why), HOPF_OK, why);
   }
   {  // (H, J, precision, n) combinations
     hopf_problem_desc d = base(33);
