@@ -6,7 +6,7 @@
 // iteration, so the inverse is formed once: block Gauss-Jordan elimination in
 // FP64 on S = A + lambda I (symmetric positive definite, so no pivoting is
 // needed and every pivot block is SPD), 32x32 blocks.  Each pivot block is
-// inverted through its Cholesky factor, which doubles as the positive-
+// inverted by Gauss-Jordan elimination, whose pivots double as the positive-
 // definiteness test.  Problems of a batch are sorted by size so that the
 // problems still active at step s form a prefix of the list.
 #include "common.hpp"
@@ -16,58 +16,54 @@ namespace hopf {
 
 constexpr int NB = 32;
 
-// Pivot block: P = S_KK^{-1} via Cholesky, one wave per problem, the block in registers: lane i
-// (< NB) holds row i, and every other lane's value is read with a broadcast from a compile-time
-// lane (readlane), so the three phases run without LDS or barriers.
-__device__ __forceinline__ double bcast(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
-__global__ void __launch_bounds__(64) gj_pivot_kernel(const SetupProb* probs, int nprob, int step) {
+// Pivot block: P = S_KK^{-1} by Gauss-Jordan elimination without pivoting on the SPD block, one
+// 256-thread workgroup per problem with the block in LDS (four entries per thread).  Step k turns
+// column k into a unit column: with p = a_kk, a_kk <- 1/p, a_kj <- a_kj/p, a_ik <- -a_ik/p and
+// a_ij <- a_ij - a_ik a_kj/p (i, j != k); after the NB steps the block holds its inverse.  The
+// pivots p are the diagonal of the block's LDL^T factorisation, so all of them are positive
+// exactly when the block is positive definite: that is the definiteness test (a failed pivot is
+// replaced by 1 so that the rest stays finite, and the problem is flagged).
+constexpr int kPivThreads = 256;
+__global__ void __launch_bounds__(kPivThreads) gj_pivot_kernel(const SetupProb* probs, int nprob, int step) {
   const int q = blockIdx.x;
   if (q >= nprob) return;
   const SetupProb pb = probs[q];
   if (step * NB >= pb.n_pad) return;
-  const int l = threadIdx.x;
-  const int k0 = step * NB;
-  const int row = l < NB ? l : NB - 1;  // lanes past NB mirror the last row; they store nothing
-  double r[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) r[k] = pb.S[(size_t)(k0 + row) * pb.n_pad + k0 + k];
-  // Cholesky, lower triangle in place: column j of L, then the trailing rows
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    double d = bcast(r[j], j);
-    if (!(d > 0.0)) { bad = true; d = 1.0; }
-    const double sj = sqrt(d);
-    r[j] = (row == j) ? sj : (row > j ? r[j] / sj : r[j]);
-#pragma unroll
-    for (int k = j + 1; k < NB; ++k) {
-      const double lkj = bcast(r[j], k);
-      if (row >= k) r[k] -= r[j] * lkj;
+  constexpr int kPer = NB * NB / kPivThreads;
+  __shared__ double a[NB][NB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x, k0 = step * NB;
+  for (int e = tid; e < NB * NB; e += kPivThreads) {
+    const int i = e / NB, j = e % NB;
+    a[i][j] = pb.S[(size_t)(k0 + i) * pb.n_pad + k0 + j];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < NB; ++k) {
+    double p = a[k][k];
+    if (!(p > 0.0)) {
+      p = 1.0;
+      if (tid == 0) bad = 1;
     }
+    const double ip = 1.0 / p;
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + kPivThreads * u, i = e / NB, j = e % NB;
+      if (i == k) v[u] = (j == k) ? ip : a[k][j] * ip;
+      else if (j == k) v[u] = -a[i][k] * ip;
+      else v[u] = fma(-a[i][k], a[k][j] * ip, a[i][j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + kPivThreads * u;
+      a[e / NB][e % NB] = v[u];
+    }
+    __syncthreads();
   }
-  // X = L^{-1}: lane c holds column c, X_ic = (delta_ic - sum_{m < i} L_im X_mc) / L_ii
-  double x[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    double s = (row == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = 0; m < i; ++m) s -= bcast(r[m], i) * x[m];
-    x[i] = (i < row) ? 0.0 : s / bcast(r[i], i);
-  }
-  // P = X^T X: lane j computes column j, P_ij = sum_m X_mi X_mj
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < NB; ++m) s += bcast(x[m], i) * x[m];
-    if (l < NB) pb.P[i * NB + l] = s;
-  }
-  if (l == 0 && bad) *pb.status = 1;
+  for (int e = tid; e < NB * NB; e += kPivThreads) pb.P[e] = a[e / NB][e % NB];
+  if (tid == 0 && bad) *pb.status = 1;
 }
 
 // Panels: T = S[:, K] (copy of the old column panel), R = P * S[K, :] (new row panel).
@@ -243,7 +239,7 @@ hipError_t run_gauss_jordan(const SetupProb* d_probs, const int* h_nblocks, int 
     const int* ht = hb + nprob + 1;
     const int* db = d_prefix + s * stride;
     const int* dt = db + nprob + 1;
-    hipLaunchKernelGGL(gj_pivot_kernel, dim3(nactive), dim3(64), 0, stream, d_probs, nactive, s);
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(nactive), dim3(kPivThreads), 0, stream, d_probs, nactive, s);
     hipLaunchKernelGGL(gj_panel_kernel, dim3(hb[nactive]), dim3(kBlock), 0, stream, d_probs, db,
                        nactive, s);
     hipLaunchKernelGGL(gj_update_kernel, dim3(ht[nactive]), dim3(kBlock), 0, stream, d_probs, dt,
