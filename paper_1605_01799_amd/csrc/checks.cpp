@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 namespace hopf {
 
@@ -38,14 +40,19 @@ static bool differ(double a, double b) {
 // relative 1e-12.  The matrix is walked in 64 x 64 tiles of the lower block triangle; each
 // mirrored upper tile is first copied transposed into a local buffer (row reads), so both
 // operands of every comparison are read contiguously, every entry is read once, and the loops
-// vectorise (a row-by-row scan reads the upper triangle with a stride of n doubles).  Returns 0,
-// or 1 with *bad the first non-finite index, or 2 with (*bi, *bj) the first mismatch in
-// row-major order of the lower triangle.
-static int check_dense(const double* S, int n, int64_t* bad, int* bi, int* bj) {
-  constexpr int kT = 64;
+// vectorise (a row-by-row scan reads the upper triangle with a stride of n doubles).  Block rows
+// are dealt round-robin to up to 8 host threads from n = 768 (the pass is bound by memory
+// bandwidth; below that the threads' start costs more than they save).  Returns 0, or 1 with *bad the first non-finite index, or 2 with (*bi, *bj) the
+// first mismatch in row-major order of the lower triangle.
+constexpr int kCheckTile = 64;
+
+// Tiles of the block rows first, first + stride, ...: bit 0 set if an entry is not finite, bit 1
+// if a pair differs.
+static int check_rows(const double* S, int n, int first, int stride) {
+  constexpr int kT = kCheckTile;
   double up[kT][kT];  // up[i - ib][j - jb] = S[j][i] (32 KiB)
   int nonfinite = 0, asym = 0;
-  for (int ib = 0; ib < n; ib += kT) {
+  for (int ib = first * kT; ib < n; ib += stride * kT) {
     const int ie = std::min(n, ib + kT);
     for (int jb = 0; jb <= ib; jb += kT) {
       const int je = std::min(n, jb + kT);
@@ -71,6 +78,29 @@ static int check_dense(const double* S, int n, int64_t* bad, int* bi, int* bj) {
       }
     }
   }
+  return nonfinite | (asym << 1);
+}
+
+static int check_dense(const double* S, int n, int64_t* bad, int* bi, int* bj) {
+  const int nbr = (n + kCheckTile - 1) / kCheckTile;  // block rows
+  int nt = 1;
+  if (n >= 768) {
+    const unsigned hc = std::thread::hardware_concurrency();
+    nt = std::max(1, std::min({8, nbr, hc > 0 ? (int)hc : 1}));
+  }
+  int flags = 0;
+  if (nt == 1) {
+    flags = check_rows(S, n, 0, 1);
+  } else {
+    std::vector<int> part(nt, 0);
+    std::vector<std::thread> pool;
+    pool.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) pool.emplace_back([&, t] { part[t] = check_rows(S, n, t, nt); });
+    part[0] = check_rows(S, n, 0, nt);
+    for (auto& th : pool) th.join();
+    for (int f : part) flags |= f;
+  }
+  const int nonfinite = flags & 1, asym = flags & 2;
   if (nonfinite) { *bad = first_nonfinite(S, (int64_t)n * n); return 1; }
   if (!asym) return 0;
   for (int i = 0; i < n; ++i)

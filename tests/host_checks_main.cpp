@@ -97,6 +97,22 @@ int main() {
     at(130, 130) = n; why[0] = 0;
     expect("symmetric A again, n = 200", check_desc(&d, why, sizeof why), HOPF_OK, why);
   }
+  {  // n = 1000: the block rows are split over host threads; offences in rows of different threads
+    const int n = 1000;
+    std::vector<double> A((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = (i == j) ? n : 1.0 / (1 + i + j);
+    hopf_problem_desc d = base(n);
+    d.A = A.data();
+    auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+    why[0] = 0; expect("symmetric A, n = 1000", check_desc(&d, why, sizeof why), HOPF_OK, why);
+    at(900, 700) += 1e-3; at(999, 5) -= 1e-3; why[0] = 0;
+    expect_msg("two mismatches, n = 1000", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "(900, 700)");
+    at(900, 700) = at(700, 900); at(999, 5) = at(5, 999); at(640, 641) = INFINITY; at(80, 3) = NAN; why[0] = 0;
+    expect_msg("two non-finite entries, n = 1000", check_desc(&d, why, sizeof why), HOPF_EINVAL, why, "A[80003]");
+    at(640, 641) = at(641, 640); at(80, 3) = at(3, 80); why[0] = 0;
+    expect("symmetric A again, n = 1000", check_desc(&d, why, sizeof why), HOPF_OK, why);
+  }
   {  // (H, J, precision, n) combinations
     hopf_problem_desc d = base(33);
     d.precision = HOPF_F64; why[0] = 0;
