@@ -159,7 +159,10 @@ hopf_status hopf_problem_create(const hopf_problem_desc* desc, void* stream, hop
 hopf_status hopf_problem_create_batch(int32_t nprob, const hopf_problem_desc* descs, void* stream,
                                       hopf_problem_t* out);
 
-/* Releases the device memory of a problem (synchronises the device first). */
+/* Releases the device memory of a problem (synchronises the device first).  The library keeps
+ * up to 1 GiB of such freed blocks per device and hands them out again to problems created later
+ * with the same buffer sizes (no hipMalloc for a repeated set-up); beyond that they go back to
+ * the device.  The kept blocks are held until the process ends. */
 hopf_status hopf_problem_destroy(hopf_problem_t problem);
 
 /* Evaluates npts points (eq. (3.3), split Bregman (3.4a)-(3.4c) with

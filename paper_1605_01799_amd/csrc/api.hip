@@ -10,6 +10,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -179,11 +181,83 @@ static hopf_status validate_columns(int64_t npts, int32_t K) {
   return st ? fail(st, "%s", why) : HOPF_OK;
 }
 
+// Device memory of problems (their matrices and set-up temporaries).  Freed blocks are kept per
+// device and exact size, up to kBlockCache bytes per device, and handed out again: creating a
+// problem of a size created before then costs no hipMalloc (a large one costs tens of
+// microseconds, and a problem takes about a dozen).  A block is cached only after the device has
+// finished its queued work (the implicit synchronisation of hipFree, kept), so no pending kernel
+// can still read it when it is handed out again.
+namespace {
+struct LiveBlock { int dev; size_t bytes; };
+std::mutex g_blk_mu;
+std::unordered_map<void*, LiveBlock> g_blk_live;
+std::multimap<std::pair<int, size_t>, void*> g_blk_free;
+size_t g_blk_cached[64] = {};
+constexpr size_t kBlockCache = size_t(1) << 30;
+}  // namespace
+
+static hipError_t dmalloc_raw(void** p, size_t bytes) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64 && bytes > 0) {
+    std::lock_guard<std::mutex> g(g_blk_mu);
+    auto it = g_blk_free.find({dev, bytes});
+    if (it != g_blk_free.end()) {
+      *p = it->second;
+      g_blk_free.erase(it);
+      g_blk_cached[dev] -= bytes;
+      g_blk_live[*p] = {dev, bytes};
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, bytes);
+  if (e != hipSuccess) { *p = nullptr; return e; }
+  if (*p && dev >= 0 && dev < 64) {
+    std::lock_guard<std::mutex> g(g_blk_mu);
+    g_blk_live[*p] = {dev, bytes};
+  }
+  return hipSuccess;
+}
+template <typename T>
+static hipError_t dmalloc(T** p, size_t bytes) {
+  void* v = nullptr;
+  const hipError_t e = dmalloc_raw(&v, bytes);
+  *p = (T*)v;
+  return e;
+}
+static void dfree(void* p) {
+  if (!p) return;
+  LiveBlock b{};
+  {
+    std::lock_guard<std::mutex> g(g_blk_mu);
+    auto it = g_blk_live.find(p);
+    if (it == g_blk_live.end()) { (void)hipFree(p); return; }
+    b = it->second;
+    g_blk_live.erase(it);
+  }
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = b.dev;
+  if (cur != b.dev) (void)hipSetDevice(b.dev);
+  const hipError_t e = hipDeviceSynchronize();
+  if (cur != b.dev) (void)hipSetDevice(cur);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> g(g_blk_mu);
+    if (g_blk_cached[b.dev] + b.bytes <= kBlockCache) {
+      g_blk_free.insert({{b.dev, b.bytes}, p});
+      g_blk_cached[b.dev] += b.bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 static void free_problem(hopf_problem* p) {
-  hipFree(p->d_w); hipFree(p->d_wf); hipFree(p->d_centres); hipFree(p->d_Md); hipFree(p->d_Mf); hipFree(p->d_Mb);
-  hipFree(p->d_Mq); hipFree(p->d_Mqe); hipFree(p->d_drift);
-  hipFree(p->d_adiag); hipFree(p->d_minv); hipFree(p->d_HP); hipFree(p->d_Af); hipFree(p->d_centres0);
-  hipFree(p->d_iter_total);
+  dfree(p->d_w); dfree(p->d_wf); dfree(p->d_centres); dfree(p->d_Md); dfree(p->d_Mf); dfree(p->d_Mb);
+  dfree(p->d_Mq); dfree(p->d_Mqe); dfree(p->d_drift);
+  dfree(p->d_adiag); dfree(p->d_minv); dfree(p->d_HP); dfree(p->d_Af); dfree(p->d_centres0);
+  dfree(p->d_iter_total);
   delete p;
 }
 
@@ -194,9 +268,9 @@ static hopf_status eig_HA(hopf_problem* p, const hopf_problem_desc* d, hipStream
   const size_t nn = (size_t)n * n;
   double *dHA = nullptr, *sig = nullptr;
   int* sweeps = nullptr;
-  auto cleanup = [&]() { hipFree(dHA); hipFree(sig); hipFree(sweeps); };
-  if (hipMalloc(&p->d_HP, sizeof(double) * nn) || hipMalloc(&dHA, sizeof(double) * nn) ||
-      hipMalloc(&sig, sizeof(double) * n) || hipMalloc(&sweeps, sizeof(int))) {
+  auto cleanup = [&]() { dfree(dHA); dfree(sig); dfree(sweeps); };
+  if (dmalloc(&p->d_HP, sizeof(double) * nn) || dmalloc(&dHA, sizeof(double) * nn) ||
+      dmalloc(&sig, sizeof(double) * n) || dmalloc(&sweeps, sizeof(int))) {
     cleanup();
     return fail(HOPF_ENOMEM, "hipMalloc HA eigenbasis");
   }
@@ -220,11 +294,11 @@ static hopf_status rotate_problem(hopf_problem* p, const hopf_problem_desc* d, d
   const int n = p->n;
   double *dHA = nullptr, *sig = nullptr, *T = nullptr, *A2 = nullptr, *C2 = nullptr;
   int* sweeps = nullptr;
-  auto cleanup = [&]() { hipFree(dHA); hipFree(sig); hipFree(T); hipFree(A2); hipFree(C2); hipFree(sweeps); };
+  auto cleanup = [&]() { dfree(dHA); dfree(sig); dfree(T); dfree(A2); dfree(C2); dfree(sweeps); };
   const size_t nn = (size_t)n * n;
-  if (hipMalloc(&p->d_HP, sizeof(double) * nn) || hipMalloc(&dHA, sizeof(double) * nn) ||
-      hipMalloc(&sig, sizeof(double) * n) || hipMalloc(&T, sizeof(double) * nn) ||
-      hipMalloc(&A2, sizeof(double) * nn) || hipMalloc(&sweeps, sizeof(int))) {
+  if (dmalloc(&p->d_HP, sizeof(double) * nn) || dmalloc(&dHA, sizeof(double) * nn) ||
+      dmalloc(&sig, sizeof(double) * n) || dmalloc(&T, sizeof(double) * nn) ||
+      dmalloc(&A2, sizeof(double) * nn) || dmalloc(&sweeps, sizeof(int))) {
     cleanup();
     return fail(HOPF_ENOMEM, "hipMalloc HA eigenbasis");
   }
@@ -235,7 +309,7 @@ static hopf_status rotate_problem(hopf_problem* p, const hopf_problem_desc* d, d
   if (!e) e = launch_set_weights(sig, n, p->n_pad, p->d_w, p->d_wf, stream);
   if (!e && p->d_centres) {
     const size_t cb = sizeof(double) * (size_t)p->K * p->n_pad;
-    if (hipMalloc(&C2, cb)) { cleanup(); return fail(HOPF_ENOMEM, "hipMalloc centres"); }
+    if (dmalloc(&C2, cb)) { cleanup(); return fail(HOPF_ENOMEM, "hipMalloc centres"); }
     e = hipMemsetAsync(C2, 0, cb, stream);
     if (!e) e = launch_rotate_centres(p->d_centres, C2, p->n_pad, p->d_HP, n, p->K, stream);
     if (!e) e = hipMemcpyAsync(p->d_centres, C2, cb, hipMemcpyDeviceToDevice, stream);
@@ -277,20 +351,20 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
   auto bail = [&](hopf_status s) { free_problem(p); return s; };
   std::vector<double> hw(n_pad, 0.0);
   for (int i = 0; i < n; ++i) hw[i] = d->w ? d->w[i] : 1.0;
-  hipError_t e = hipMalloc(&p->d_w, sizeof(double) * n_pad);
+  hipError_t e = dmalloc(&p->d_w, sizeof(double) * n_pad);
   if (e) return bail(fail(HOPF_ENOMEM, "hipMalloc w"));
   e = hipMemcpy(p->d_w, hw.data(), sizeof(double) * n_pad, hipMemcpyHostToDevice);
   if (e) return bail(fail(HOPF_EDEVICE, "copy w: %s", hipGetErrorString(e)));
   {
     std::vector<float> hwf(n_pad);
     for (int i = 0; i < n_pad; ++i) hwf[i] = (float)hw[i];
-    if (hipMalloc(&p->d_wf, sizeof(float) * n_pad)) return bail(fail(HOPF_ENOMEM, "hipMalloc wf"));
+    if (dmalloc(&p->d_wf, sizeof(float) * n_pad)) return bail(fail(HOPF_ENOMEM, "hipMalloc wf"));
     if (hipMemcpy(p->d_wf, hwf.data(), sizeof(float) * n_pad, hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy wf"));
   }
-  if (hipMalloc(&p->d_iter_total, sizeof(unsigned long long))) return bail(fail(HOPF_ENOMEM, "hipMalloc counter"));
+  if (dmalloc(&p->d_iter_total, sizeof(unsigned long long))) return bail(fail(HOPF_ENOMEM, "hipMalloc counter"));
   if (d->hkind == HOPF_H_LINCTRL) {
-    if (hipMalloc(&p->d_drift, sizeof(double) * n)) return bail(fail(HOPF_ENOMEM, "hipMalloc drift"));
+    if (dmalloc(&p->d_drift, sizeof(double) * n)) return bail(fail(HOPF_ENOMEM, "hipMalloc drift"));
     if (hipMemcpy(p->d_drift, d->drift, sizeof(double) * n, hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy drift"));
   }
@@ -299,26 +373,26 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     std::vector<double> hc((size_t)d->K * n_pad, 0.0);
     for (int k = 0; k < d->K; ++k)
       for (int i = 0; i < n; ++i) hc[(size_t)k * n_pad + i] = d->centres[(size_t)k * n + i];
-    if (hipMalloc(&p->d_centres, sizeof(double) * hc.size())) return bail(fail(HOPF_ENOMEM, "hipMalloc centres"));
+    if (dmalloc(&p->d_centres, sizeof(double) * hc.size())) return bail(fail(HOPF_ENOMEM, "hipMalloc centres"));
     if (hipMemcpy(p->d_centres, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy centres"));
   }
   const size_t mm = (size_t)n_pad * n_pad;
-  if (hipMalloc(&p->d_Md, sizeof(double) * mm)) return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP64)"));
-  if (d->precision != HOPF_BF16_REFINED && hipMalloc(&p->d_Mf, sizeof(float) * mm))
+  if (dmalloc(&p->d_Md, sizeof(double) * mm)) return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP64)"));
+  if (d->precision != HOPF_BF16_REFINED && dmalloc(&p->d_Mf, sizeof(float) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (FP32)"));
-  if (d->precision == HOPF_BF16_REFINED && hipMalloc(&p->d_Mb, sizeof(__bf16) * mm))
+  if (d->precision == HOPF_BF16_REFINED && dmalloc(&p->d_Mb, sizeof(__bf16) * mm))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (BF16)"));
   // integer slices of M for the exact anchor products of the refined tile solver (BF16 or FP32
   // increments); also for a diagonal problem that hopf_eval runs per thread, since a ragged batch
   // runs it in the dense kernels
   if (d->precision != HOPF_F64 &&
-      (hipMalloc(&p->d_Mq, (size_t)kSlices * n_pad * pad64(n_pad)) || hipMalloc(&p->d_Mqe, sizeof(int32_t) * n_pad)))
+      (dmalloc(&p->d_Mq, (size_t)kSlices * n_pad * pad64(n_pad)) || dmalloc(&p->d_Mqe, sizeof(int32_t) * n_pad)))
     return bail(fail(HOPF_ENOMEM, "hipMalloc M (slices)"));
   if (p->diagonal) {
     std::vector<double> a(n, 1.0);  // unused by the squared-norm initial data
     if (d->A && p->jkind == HOPF_J_QUADRATIC) for (int i = 0; i < n; ++i) a[i] = d->A[i];
-    if (hipMalloc(&p->d_adiag, sizeof(double) * n) || hipMalloc(&p->d_minv, sizeof(double) * n))
+    if (dmalloc(&p->d_adiag, sizeof(double) * n) || dmalloc(&p->d_minv, sizeof(double) * n))
       return bail(fail(HOPF_ENOMEM, "hipMalloc diagonal"));
     if (hipMemcpy(p->d_adiag, a.data(), sizeof(double) * n, hipMemcpyHostToDevice))
       return bail(fail(HOPF_EDEVICE, "copy A"));
@@ -332,8 +406,8 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
     // A + lambda I in FP64 on the device; the Gauss-Jordan batch is run by the caller
     double* dA = nullptr;
     double* S = nullptr;
-    if (hipMalloc(&dA, sizeof(double) * (size_t)n * n) || hipMalloc(&S, sizeof(double) * mm)) {
-      hipFree(dA);
+    if (dmalloc(&dA, sizeof(double) * (size_t)n * n) || dmalloc(&S, sizeof(double) * mm)) {
+      dfree(dA);
       return bail(fail(HOPF_ENOMEM, "hipMalloc setup"));
     }
     std::vector<double> hA;
@@ -344,31 +418,31 @@ static hopf_status create_one(const hopf_problem_desc* d, hipStream_t stream, ho
       srcA = hA.data();
     }
     if (hipMemcpy(dA, srcA, sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice)) {
-      hipFree(dA); hipFree(S);
+      dfree(dA); dfree(S);
       return bail(fail(HOPF_EDEVICE, "copy A"));
     }
     {  // FP32 copy of A in the caller's basis (before any rotation), for the control read-out
       const int64_t nn = (int64_t)n * n;
-      if (hipMalloc(&p->d_Af, sizeof(float) * nn) || launch_to_f32(dA, p->d_Af, nn, stream)) {
-        hipFree(dA); hipFree(S);
+      if (dmalloc(&p->d_Af, sizeof(float) * nn) || launch_to_f32(dA, p->d_Af, nn, stream)) {
+        dfree(dA); dfree(S);
         return bail(fail(HOPF_ENOMEM, "FP32 copy of A"));
       }
     }
     if (al2 && p->d_centres) {
       const size_t cb = sizeof(double) * (size_t)p->K * n_pad;
-      if (hipMalloc(&p->d_centres0, cb) || hipMemcpy(p->d_centres0, p->d_centres, cb, hipMemcpyDeviceToDevice)) {
-        hipFree(dA); hipFree(S);
+      if (dmalloc(&p->d_centres0, cb) || hipMemcpy(p->d_centres0, p->d_centres, cb, hipMemcpyDeviceToDevice)) {
+        dfree(dA); dfree(S);
         return bail(fail(HOPF_ENOMEM, "copy of the centres"));
       }
     }
     if (al2) {
       hopf_status rs = rotate_problem(p, d, dA, stream);
-      if (rs) { hipFree(dA); hipFree(S); return bail(rs); }
+      if (rs) { dfree(dA); dfree(S); return bail(rs); }
     }
     e = launch_build_shifted(dA, n, n_pad, d->lambda, S, stream);
     hipStreamSynchronize(stream);
-    hipFree(dA);
-    if (e) { hipFree(S); return bail(fail(HOPF_EDEVICE, "build A + lambda I: %s", hipGetErrorString(e))); }
+    dfree(dA);
+    if (e) { dfree(S); return bail(fail(HOPF_EDEVICE, "build A + lambda I: %s", hipGetErrorString(e))); }
     pending_S->push_back(S);
   }
   *out = p;
@@ -395,11 +469,11 @@ static hopf_status factor_batch(std::vector<hopf_problem*>& dense, std::vector<d
   int* d_prefix = nullptr;
   std::vector<int> h_prefix((size_t)steps * 2 * (np + 1));
   auto cleanup = [&]() {
-    hipFree(d_scr); hipFree(d_status); hipFree(d_probs); hipFree(d_prefix);
+    dfree(d_scr); dfree(d_status); dfree(d_probs); dfree(d_prefix);
   };
-  if (hipMalloc(&d_scr, sizeof(double) * scratch) || hipMalloc(&d_status, sizeof(int) * np) ||
-      hipMalloc(&d_probs, sizeof(SetupProb) * np) ||
-      hipMalloc(&d_prefix, sizeof(int) * h_prefix.size())) {
+  if (dmalloc(&d_scr, sizeof(double) * scratch) || dmalloc(&d_status, sizeof(int) * np) ||
+      dmalloc(&d_probs, sizeof(SetupProb) * np) ||
+      dmalloc(&d_prefix, sizeof(int) * h_prefix.size())) {
     cleanup();
     return fail(HOPF_ENOMEM, "hipMalloc setup scratch");
   }
@@ -445,7 +519,7 @@ extern "C" hopf_status hopf_problem_create_batch(int32_t nprob, const hopf_probl
   std::vector<double*> S;
   for (int i = 0; i < nprob; ++i) out[i] = nullptr;
   auto undo = [&]() {
-    for (double* x : S) hipFree(x);
+    for (double* x : S) dfree(x);
     for (hopf_problem* p : made) free_problem(p);
   };
   for (int i = 0; i < nprob; ++i) {
@@ -461,7 +535,7 @@ extern "C" hopf_status hopf_problem_create_batch(int32_t nprob, const hopf_probl
     if (S.size() > before) dense.push_back(p);
   }
   hopf_status st = factor_batch(dense, S, s);
-  for (double* x : S) hipFree(x);
+  for (double* x : S) dfree(x);
   S.clear();
   if (st) {
     std::string m = g_err;
