@@ -121,8 +121,8 @@ def copy_calibrate():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU only (the workload is one GPU's share; "
-              "see the sharding notes in DESIGN.md); --gpus %d is not supported" % a.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only (the workload is one GPU's share of the points); "
+              "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.copy_calibrate:
         copy_calibrate()
@@ -842,7 +842,7 @@ def bench_other(a):
         flops_q = passes * 2.0 * nall.astype(np.float64) ** 2      # per problem, every copy
         flops = float(flops_q.sum())
         flops_d = float((passes_d * 2.0 * nall.astype(np.float64) ** 2).sum())
-        # the survey's mixed roofline: per problem max(FLOP / FP32 MFMA peak, bytes / HBM), summed
+        # a mixed roofline: per problem max(FLOP / FP32 MFMA peak, bytes / HBM), summed
         off = out["offsets"]
         t_roof = 0.0
         for q in range(nprob):
