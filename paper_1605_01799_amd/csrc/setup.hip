@@ -129,12 +129,21 @@ __global__ void __launch_bounds__(kBlock) gj_update_kernel(const SetupProb* prob
     Rj[i][j] = (bj == K) ? pb.P[i * NB + j] : pb.R[(size_t)i * ld + bj * NB + j];
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    int i = e / NB, j = e % NB;
-    double s = 0.0;
-    for (int m = 0; m < NB; ++m) s += Ti[i][m] * Rj[m][j];
+  // T_i R_j by FP64 MFMA 16x16x4: wave w takes the 16 x 16 quadrant (w / 2, w % 2), eight k-steps.
+  // Operands: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the output's row i sits in lane
+  // j + 16 (i % 4), register i / 4.
+  static_assert(kBlock == 256 && NB == 32, "four waves, one 16 x 16 quadrant of the 32 x 32 tile each");
+  const int wave = tid >> 6, l = tid & 63, wi = wave >> 1, wj = wave & 1;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < NB / 4; ++ks)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ti[16 * wi + (l & 15)][4 * ks + (l >> 4)],
+                                              Rj[4 * ks + (l >> 4)][16 * wj + (l & 15)], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * wi + 4 * v + (l >> 4), j = 16 * wj + (l & 15);
     double* dst = &pb.S[(size_t)(bi * NB + i) * ld + bj * NB + j];
-    *dst = (bj == K) ? -s : (*dst - s);
+    *dst = (bj == K) ? -acc[v] : (*dst - acc[v]);
   }
 }
 
