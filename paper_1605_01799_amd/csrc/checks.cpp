@@ -95,8 +95,18 @@ static int check_dense(const double* S, int n, int64_t* bad, int* bi, int* bj) {
     std::vector<int> part(nt, 0);
     std::vector<std::thread> pool;
     pool.reserve(nt - 1);
-    for (int t = 1; t < nt; ++t) pool.emplace_back([&, t] { part[t] = check_rows(S, n, t, nt); });
+    // the block rows of a thread that could not be started are checked on this thread
+    std::vector<char> started(nt, 0);
+    for (int t = 1; t < nt; ++t) {
+      try {
+        pool.emplace_back([&part, S, n, t, nt] { part[t] = check_rows(S, n, t, nt); });
+        started[t] = 1;
+      } catch (...) {
+      }
+    }
     part[0] = check_rows(S, n, 0, nt);
+    for (int t = 1; t < nt; ++t)
+      if (!started[t]) part[t] = check_rows(S, n, t, nt);
     for (auto& th : pool) th.join();
     for (int f : part) flags |= f;
   }
