@@ -53,8 +53,8 @@ def measured_traffic(precision, npts, tol):
 # The same for the tile kernel of the n=256 union workload (c5; its profiles/ summary), valid for
 # the sources, the tuned launch shapes and the point count and tolerance it was measured on.
 C5_TRAFFIC = {"sources": ("dense.hip", "dense_shared.hpp", "common.hpp", "api.hip", "tune_table.inc"),
-              "source_sha256": "636a595d17c4cad03159e34201d42043b1770ae7b13c4ce67e6ca68730276ea0",
-              "read_bytes": 26.688e9, "write_bytes": 173.348e9, "npts": 1 << 18, "tol": 1e-12}
+              "source_sha256": "8a0b7392b9ed08e2772106bf0dbf65dc3065980c5c457d60dffa9b9d54fda650",
+              "read_bytes": 26.721e9, "write_bytes": 173.840e9, "npts": 1 << 18, "tol": 1e-12}
 
 
 def measured_traffic_c5(npts, tol):
